@@ -1,0 +1,237 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py, never by the GPU library or its binding.
+
+All arrays are numpy complex128 in the canonical layouts documented in
+oracle.h (U[V][4][3][3], psi[V][4][3], T[V][12][12]).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BUILD_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fcx-limited-range"]
+
+
+def build() -> str:
+    """Compile liboracle.so (plain gcc; no GPU code)."""
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc"] + BUILD_FLAGS + [_SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_P = C.c_void_p
+_I4 = C.c_int * 4
+
+
+def _declare(L):
+    L.or_set_threads.argtypes = [C.c_int]
+    L.or_get_threads.restype = C.c_int
+    L.or_gamma.argtypes = [C.c_int, _P]
+    L.or_sigma.argtypes = [C.c_int, C.c_int, _P]
+    L.or_clover_site.argtypes = [_I4, _P, C.c_double, C.c_double, C.c_long, _P]
+    L.or_clover_field.argtypes = [_I4, _P, C.c_double, C.c_double, _P]
+    L.or_leaf_sum.argtypes = [_I4, _P, C.c_long, C.c_int, C.c_int, _P]
+    L.or_apply_D.argtypes = [_I4, _P, _P, C.c_double, _P, _P]
+    L.or_apply_Ddag.argtypes = [_I4, _P, _P, C.c_double, _P, _P]
+    L.or_apply_D_sites.argtypes = [_I4, _P, C.c_double, C.c_double, _P, C.c_long, _P, _P]
+    L.or_residual_norm.argtypes = [_I4, _P, C.c_double, C.c_double, _P, _P]
+    L.or_residual_norm.restype = C.c_double
+    L.or_num_blocks.argtypes = [_I4, _I4]
+    L.or_num_blocks.restype = C.c_long
+    L.or_block_colour.argtypes = [_I4, _I4, C.c_long]
+    L.or_block_colour.restype = C.c_int
+    L.or_block_of_site.argtypes = [_I4, _I4, C.c_long]
+    L.or_block_of_site.restype = C.c_long
+    L.or_apply_D_block.argtypes = [_I4, _I4, C.c_long, _P, _P, C.c_double, _P, _P]
+    L.or_mr_block.argtypes = [_I4, _I4, C.c_long, _P, _P, C.c_double, C.c_int, _P, _P]
+    L.or_sap.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, _P, _P]
+    L.or_fgcr.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int,
+                          C.c_double, C.c_int, _P, _P, C.POINTER(C.c_int),
+                          C.POINTER(C.c_double), _P]
+    L.or_fgcr.restype = C.c_int
+    L.or_force.argtypes = [_I4, _P, C.c_double, C.c_double, _P, _P, _P, _P]
+    L.or_su3_generator.argtypes = [C.c_int, _P]
+
+
+def _dims(d):
+    return _I4(*[int(v) for v in d])
+
+
+def _c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return lib().or_get_threads()
+
+
+def gamma(mu: int) -> np.ndarray:
+    g = np.zeros((4, 4), np.complex128)
+    lib().or_gamma(mu, _ptr(g))
+    return g
+
+
+def sigma(mu: int, nu: int) -> np.ndarray:
+    s = np.zeros((4, 4), np.complex128)
+    lib().or_sigma(mu, nu, _ptr(s))
+    return s
+
+
+def su3_generator(a: int) -> np.ndarray:
+    t = np.zeros((3, 3), np.complex128)
+    lib().or_su3_generator(a, _ptr(t))
+    return t
+
+
+def volume(dims) -> int:
+    return int(np.prod([int(v) for v in dims]))
+
+
+def leaf_sum(dims, U, site, mu, nu) -> np.ndarray:
+    U = _c128(U)
+    q = np.zeros((3, 3), np.complex128)
+    lib().or_leaf_sum(_dims(dims), _ptr(U), int(site), mu, nu, _ptr(q))
+    return q
+
+
+def clover_site(dims, U, kappa, csw, site) -> np.ndarray:
+    U = _c128(U)
+    t = np.zeros((12, 12), np.complex128)
+    lib().or_clover_site(_dims(dims), _ptr(U), float(kappa), float(csw), int(site), _ptr(t))
+    return t
+
+
+def clover_field(dims, U, kappa, csw) -> np.ndarray:
+    U = _c128(U)
+    t = np.zeros((volume(dims), 12, 12), np.complex128)
+    lib().or_clover_field(_dims(dims), _ptr(U), float(kappa), float(csw), _ptr(t))
+    return t
+
+
+def apply_D(dims, U, T, kappa, psi) -> np.ndarray:
+    U, psi = _c128(U), _c128(psi)
+    T = None if T is None else _c128(T)
+    out = np.empty_like(psi)
+    lib().or_apply_D(_dims(dims), _ptr(U), _ptr(T), float(kappa), _ptr(psi), _ptr(out))
+    return out
+
+
+def apply_Ddag(dims, U, T, kappa, psi) -> np.ndarray:
+    U, psi = _c128(U), _c128(psi)
+    T = None if T is None else _c128(T)
+    out = np.empty_like(psi)
+    lib().or_apply_Ddag(_dims(dims), _ptr(U), _ptr(T), float(kappa), _ptr(psi), _ptr(out))
+    return out
+
+
+def apply_D_sites(dims, U, kappa, csw, psi, sites) -> np.ndarray:
+    U, psi = _c128(U), _c128(psi)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((len(sites), 4, 3), np.complex128)
+    lib().or_apply_D_sites(_dims(dims), _ptr(U), float(kappa), float(csw), _ptr(psi),
+                           len(sites), _ptr(sites), _ptr(out))
+    return out
+
+
+def residual_norm(dims, U, kappa, csw, b, x) -> float:
+    U, b, x = _c128(U), _c128(b), _c128(x)
+    return lib().or_residual_norm(_dims(dims), _ptr(U), float(kappa), float(csw),
+                                  _ptr(b), _ptr(x))
+
+
+def num_blocks(dims, bdim) -> int:
+    return lib().or_num_blocks(_dims(dims), _dims(bdim))
+
+
+def block_colour(dims, bdim, blk) -> int:
+    return lib().or_block_colour(_dims(dims), _dims(bdim), int(blk))
+
+
+def block_of_site(dims, bdim, site) -> int:
+    return lib().or_block_of_site(_dims(dims), _dims(bdim), int(site))
+
+
+def apply_D_block(dims, bdim, blk, U, T, kappa, psi) -> np.ndarray:
+    U, psi = _c128(U), _c128(psi)
+    T = None if T is None else _c128(T)
+    out = np.zeros_like(psi)
+    lib().or_apply_D_block(_dims(dims), _dims(bdim), int(blk), _ptr(U), _ptr(T),
+                           float(kappa), _ptr(psi), _ptr(out))
+    return out
+
+
+def mr_block(dims, bdim, blk, U, T, kappa, n_mr, r) -> np.ndarray:
+    U, r = _c128(U), _c128(r)
+    T = None if T is None else _c128(T)
+    delta = np.zeros_like(r)
+    lib().or_mr_block(_dims(dims), _dims(bdim), int(blk), _ptr(U), _ptr(T), float(kappa),
+                      int(n_mr), _ptr(r), _ptr(delta))
+    return delta
+
+
+def sap(dims, bdim, U, T, kappa, n_cy, n_mr, b, x0=None) -> np.ndarray:
+    U, b = _c128(U), _c128(b)
+    T = None if T is None else _c128(T)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    lib().or_sap(_dims(dims), _dims(bdim), _ptr(U), _ptr(T), float(kappa), int(n_cy),
+                 int(n_mr), _ptr(b), _ptr(x))
+    return x
+
+
+def fgcr(dims, bdim, U, T, kappa, b, n_cy=2, n_mr=4, restart=16, tol=1e-10,
+         max_iter=2000, x0=None):
+    """Returns (x, status, iterations, true_relres, history)."""
+    U, b = _c128(U), _c128(b)
+    T = None if T is None else _c128(T)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    it = C.c_int(0)
+    rel = C.c_double(0)
+    hist = np.zeros(max_iter + 1, np.float64)
+    st = lib().or_fgcr(_dims(dims), _dims(bdim), _ptr(U), _ptr(T), float(kappa), int(n_cy),
+                       int(n_mr), int(restart), float(tol), int(max_iter), _ptr(b), _ptr(x),
+                       C.byref(it), C.byref(rel), _ptr(hist))
+    return x, st, it.value, rel.value, hist[: it.value + 1].copy()
+
+
+def force(dims, U, kappa, csw, x, y, parts=("hop", "clov")):
+    """Gradient g[V][4][8] of Re(eta^dag D^-1 b); returns (g_hop, g_clov)."""
+    U, x, y = _c128(U), _c128(x), _c128(y)
+    V = volume(dims)
+    gh = np.zeros((V, 4, 8)) if "hop" in parts else None
+    gc = np.zeros((V, 4, 8)) if "clov" in parts else None
+    lib().or_force(_dims(dims), _ptr(U), float(kappa), float(csw), _ptr(x), _ptr(y),
+                   _ptr(gh), _ptr(gc))
+    return gh, gc

@@ -1,0 +1,165 @@
+"""Oracle pins for the clover-Wilson operator D (paper Section 2, Eq. (1)).
+
+  (D psi)(x) = (1 + T(x)) psi(x)
+               - kappa sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+                               + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)]
+
+Pins: free-field plane waves (closed-form symbol and its basis-independent
+spectrum), constant twisted links (which hop carries U and which U^dag),
+gamma5-hermiticity of D and of the Dirichlet block operator, gauge
+covariance, and agreement of the oracle's three evaluation routes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_00501_amd import synth
+from tests.oracle_helpers import (block_sites, coords, dense_D, dof_indices, g5_apply,
+                                  gauge_transform_links, gauge_transform_spinor)
+
+DIMS = (4, 6, 4, 8)  # unequal extents catch axis mix-ups
+PAULI = [np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]], complex),
+         np.array([[1, 0], [0, -1]], complex)]
+Z2 = np.zeros((2, 2), complex)
+GAMMA = [np.block([[Z2, -1j * PAULI[k]], [1j * PAULI[k], Z2]]) for k in range(3)] + \
+        [np.block([[Z2, np.eye(2)], [np.eye(2), Z2]])]
+
+
+def symbol(p, kappa):
+    """Free-field momentum-space D(p) on spin (4x4)."""
+    return (1 - 2 * kappa * np.sum(np.cos(p))) * np.eye(4) + \
+        2j * kappa * sum(np.sin(p[m]) * GAMMA[m] for m in range(4))
+
+
+def plane_wave(dims, p, u):
+    V = int(np.prod(dims))
+    ph = np.exp(1j * coords(dims, V) @ p)
+    return ph[:, None, None] * u[None, :, :], ph
+
+
+@pytest.mark.parametrize("n", [(0, 0, 0, 0), (1, 0, 0, 0), (0, 2, 1, 3), (3, 5, 2, 7), (2, 3, 2, 4)])
+def test_free_field_plane_wave(n):
+    kappa = 0.137
+    p = 2 * np.pi * np.array(n) / np.array(DIMS)
+    U = synth.unit_gauge(DIMS)
+    T = oracle.clover_field(DIMS, U, kappa, 1.3)
+    assert np.abs(T).max() == 0
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    psi, ph = plane_wave(DIMS, p, u)
+    out = oracle.apply_D(DIMS, U, T, kappa, psi)
+    ref = ph[:, None, None] * (symbol(p, kappa) @ u)[None]
+    assert np.abs(out - ref).max() < 1e-14
+
+
+def test_free_field_spectrum_basis_independent():
+    # eigenvalues 1 - 2 kappa sum cos p  +/-  2 i kappa sqrt(sum sin^2 p), six-fold each
+    kappa = 0.125
+    U = synth.unit_gauge(DIMS)
+    for n in [(1, 2, 3, 4), (0, 1, 0, 5), (2, 0, 1, 1)]:
+        p = 2 * np.pi * np.array(n) / np.array(DIMS)
+        M = np.empty((12, 12), complex)
+        for j in range(12):
+            u = np.zeros(12, complex)
+            u[j] = 1
+            psi, _ = plane_wave(DIMS, p, u.reshape(4, 3))
+            M[:, j] = oracle.apply_D(DIMS, U, None, kappa, psi)[0].reshape(-1)
+        ev = np.linalg.eigvals(M)
+        ev = ev[np.argsort(ev.imag)]
+        a = 1 - 2 * kappa * np.sum(np.cos(p))
+        b = 2 * kappa * np.sqrt(np.sum(np.sin(p) ** 2))
+        ref = np.array([a - 1j * b] * 6 + [a + 1j * b] * 6)
+        assert np.abs(ev - ref).max() < 1e-12
+
+
+def test_twisted_constant_links_shift_colour_momenta():
+    # U_mu = diag(e^{i th_1}, e^{i th_2}, e^{-i(th_1 + th_2)}): colour a sees p + th_a
+    kappa = 0.13
+    rng = np.random.default_rng(7)
+    th = rng.uniform(-np.pi, np.pi, size=(4, 2))
+    phases = np.concatenate([th, -th.sum(axis=1, keepdims=True)], axis=1)  # [mu][a]
+    V = int(np.prod(DIMS))
+    U = np.zeros((V, 4, 3, 3), complex)
+    for mu in range(4):
+        U[:, mu] = np.diag(np.exp(1j * phases[mu]))
+    T = oracle.clover_field(DIMS, U, kappa, 1.0)
+    assert np.abs(T).max() < 1e-15  # plaquettes of commuting links are 1
+    p = 2 * np.pi * np.array([1, 2, 0, 3]) / np.array(DIMS)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    psi, ph = plane_wave(DIMS, p, u)
+    out = oracle.apply_D(DIMS, U, T, kappa, psi)
+    ref = np.empty((4, 3), complex)
+    for a in range(3):
+        ref[:, a] = symbol(p + phases[:, a], kappa) @ u[:, a]
+    assert np.abs(out - ph[:, None, None] * ref[None]).max() < 1e-14
+
+
+@pytest.fixture(scope="module")
+def field():
+    U = synth.gauge_field(DIMS, 0.3, 11)
+    T = oracle.clover_field(DIMS, U, 0.1355, 1.0)
+    return U, T
+
+
+def test_gamma5_hermiticity(field):
+    U, T = field
+    kappa = 0.1355
+    x, y = synth.source(DIMS, 1), synth.source(DIMS, 2)
+    lhs = np.vdot(x, oracle.apply_D(DIMS, U, T, kappa, y))
+    rhs = np.vdot(g5_apply(oracle.apply_D(DIMS, U, T, kappa, g5_apply(x))), y)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-14
+    # Ddag is the adjoint: <x, D y> = <Ddag x, y>
+    rhs2 = np.vdot(oracle.apply_Ddag(DIMS, U, T, kappa, x), y)
+    assert abs(lhs - rhs2) / abs(lhs) < 1e-14
+
+
+def test_block_operator_is_dirichlet_restriction_and_g5_hermitian():
+    dims, bdim = (4, 4, 4, 8), (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 0.3, 12)
+    kappa = 0.13
+    T = oracle.clover_field(dims, U, kappa, 1.0)
+    M = dense_D(dims, U, T, kappa)
+    x, y = synth.source(dims, 3), synth.source(dims, 4)
+    for blk in (0, 5, 15):
+        idx = dof_indices(block_sites(dims, bdim, blk))
+        out = oracle.apply_D_block(dims, bdim, blk, U, T, kappa, y).reshape(-1)
+        assert np.abs(out[idx] - M[np.ix_(idx, idx)] @ y.reshape(-1)[idx]).max() < 1e-14
+        mask = np.ones(out.size, bool)
+        mask[idx] = False
+        assert np.abs(out[mask]).max() == 0
+        xb = np.zeros_like(x).reshape(-1)
+        xb[idx] = x.reshape(-1)[idx]
+        xb = xb.reshape(x.shape)
+        lhs = np.vdot(xb, oracle.apply_D_block(dims, bdim, blk, U, T, kappa, y))
+        rhs = np.vdot(g5_apply(oracle.apply_D_block(dims, bdim, blk, U, T, kappa, g5_apply(xb))), y)
+        assert abs(lhs - rhs) / abs(lhs) < 1e-13
+
+
+def test_gauge_covariance(field):
+    U, T = field
+    kappa, csw = 0.1355, 1.0
+    Om = synth.gauge_transform(DIMS, 4002)
+    Ug = gauge_transform_links(DIMS, U, Om)
+    Tg = oracle.clover_field(DIMS, Ug, kappa, csw)
+    # T' = Om T Om^dag (colour rotation on each spin block)
+    Tr = T.reshape(-1, 4, 3, 4, 3)
+    Tgr = np.einsum("vab,vsbtc,vdc->vsatd", Om, Tr, np.conj(Om))
+    assert np.abs(Tg.reshape(Tgr.shape) - Tgr).max() < 1e-14
+    psi = synth.source(DIMS, 5)
+    out = oracle.apply_D(DIMS, U, T, kappa, psi)
+    outg = oracle.apply_D(DIMS, Ug, Tg, kappa, gauge_transform_spinor(Om, psi))
+    assert np.abs(outg - gauge_transform_spinor(Om, out)).max() < 1e-13
+    assert np.isclose(np.linalg.norm(outg), np.linalg.norm(out), rtol=1e-14)
+
+
+def test_sitewise_and_residual_routes_agree(field):
+    U, T = field
+    kappa, csw = 0.1355, 1.0
+    psi = synth.source(DIMS, 6)
+    full = oracle.apply_D(DIMS, U, T, kappa, psi)
+    sites = np.array([0, 1, 23, 191, 500, 767])
+    part = oracle.apply_D_sites(DIMS, U, kappa, csw, psi, sites)
+    assert np.abs(part - full[sites]).max() < 1e-14
+    b = synth.source(DIMS, 7)
+    r = oracle.residual_norm(DIMS, U, kappa, csw, b, psi)
+    assert np.isclose(r, np.linalg.norm(b - full), rtol=1e-13)
