@@ -1,0 +1,206 @@
+/*
+ * cloversap -- clover-Wilson Dirac operator, red/black SAP smoother and
+ * flexible GCR for one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every function returns an int status (cs_status); no exception
+ * crosses the boundary.  cs_last_error() gives a message for the last
+ * failure on the calling thread.
+ *
+ * Objects
+ *   cs_lattice  geometry and the 4^4 block decomposition (host object)
+ *   cs_gauge    the links, stored on the device in compressed form (rows 0
+ *               and 1 of each SU(3) matrix) in every storage precision
+ *   cs_clover   C = 1 + T for one (kappa, c_sw), stored on the device as two
+ *               6x6 Hermitian blocks per site
+ * Handles are owned by the library and released with the matching destroy
+ * call.  Spinor fields are caller-owned device buffers (for example torch
+ * tensors) in the library's internal layout; cs_field_bytes() gives their
+ * size and cs_field_import / cs_field_export convert from / to the
+ * canonical layout below.
+ *
+ * Canonical layouts (complex double, interleaved re/im, site index x fastest:
+ * s = x + Lx*(y + Ly*(z + Lz*t)), directions mu = 0..3 for x, y, z, t):
+ *   links    U[V][4][3][3]            U_mu(x)[row][col], each exactly SU(3)
+ *   spinor   psi[nrhs][V][4][3]       index 3*spin + colour
+ *   clover   T[V][12][12]             the term T of C = 1 + T (export only)
+ * Boundary conditions are periodic in all four directions.  Gamma matrices
+ * are those of the chiral basis with gamma5 = diag(1, 1, -1, -1):
+ *   gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = x, y, z),
+ *   gamma_t = [[0, 1], [1, 0]].
+ *
+ * Streams: every call that takes a stream (a hipStream_t passed as void*,
+ * NULL = the null stream) is asynchronous on it, except cs_gcr_solve, which
+ * synchronises the stream for its convergence control and returns after the
+ * solution is complete.  All pointers passed as field, link or result
+ * arguments are device pointers unless stated otherwise.
+ *
+ * Precision (cs_prec) names the storage type of spinors and links in HBM:
+ *   CS_F64   double spinors, links and clover; double arithmetic
+ *   CS_F32   float spinors, links and clover; float arithmetic
+ *   CS_F16   half spinors with one float scale per site, half links, float
+ *            clover; float arithmetic
+ *   CS_BF16  as CS_F16 with bfloat16 storage
+ */
+#ifndef CLOVERSAP_H
+#define CLOVERSAP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CS_OK = 0,
+    CS_ERR_INVALID = -1,    /* bad argument value                              */
+    CS_ERR_GEOMETRY = -2,   /* dims not multiples of 4, or an odd block count  */
+    CS_ERR_NULL = -3,       /* a required pointer or handle is NULL            */
+    CS_ERR_PRECISION = -4,  /* precision not supported by this call            */
+    CS_ERR_HIP = -5,        /* a HIP runtime call failed                       */
+    CS_ERR_ALLOC = -6,      /* device memory allocation failed                 */
+    CS_NOT_CONVERGED = 1,   /* solver stopped at max_iter                      */
+    CS_BREAKDOWN = 2,       /* solver met a zero search direction              */
+    CS_NONFINITE = 3        /* a NaN or Inf appeared in a residual norm        */
+} cs_status;
+
+typedef enum { CS_F64 = 0, CS_F32 = 1, CS_F16 = 2, CS_BF16 = 3 } cs_prec;
+
+typedef struct cs_lattice_s* cs_lattice;
+typedef struct cs_gauge_s* cs_gauge;
+typedef struct cs_clover_s* cs_clover;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* cs_last_error(void);
+/* Short text for a status code. */
+const char* cs_strerror(int status);
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Lattice of dims[0..3] = (Lx, Ly, Lz, Lt) sites, cut into blocks of
+ * block[0..3] sites.  The kernels require block = (4, 4, 4, 4) and every
+ * extent a multiple of 4 (CS_ERR_GEOMETRY otherwise).  The red/black block
+ * colouring of the SAP smoother (paper Section 2 and Section 3; colour of a
+ * block = sum of its block coordinates mod 2) also needs an even number of
+ * blocks in every direction; that is checked by the SAP and solver calls. */
+int cs_lattice_create(const int dims[4], const int block[4], cs_lattice* out);
+int cs_lattice_destroy(cs_lattice lat);
+/* Number of sites V. */
+long long cs_lattice_volume(cs_lattice lat);
+/* Bytes of one internal-layout spinor field of precision prec holding nrhs
+ * right-hand sides (0 for an invalid precision). */
+size_t cs_field_bytes(cs_lattice lat, cs_prec prec, int nrhs);
+
+/* Canonical complex128 spinors (device) -> internal layout of precision prec
+ * (device).  The nrhs fields are consecutive in both buffers. */
+int cs_field_import(cs_lattice lat, cs_prec prec, void* dst_internal,
+                    const void* src_canonical, int nrhs, void* stream);
+/* Internal layout -> canonical complex128. */
+int cs_field_export(cs_lattice lat, cs_prec prec, void* dst_canonical,
+                    const void* src_internal, int nrhs, void* stream);
+
+/* -------------------------------------------------------------- gauge field */
+
+/* Copy the canonical links U (device, complex128 [V][4][3][3]) into the
+ * library, compressed to rows 0 and 1 in every storage precision.  The third
+ * row is rebuilt as conj(row0 x row1), which equals the stored row only for
+ * exact SU(3) matrices: U must be SU(3) to rounding.  The input buffer is not
+ * kept.  Completes on the stream before the call returns (the handle is then
+ * usable on any stream). */
+int cs_gauge_create(cs_lattice lat, const void* U_canonical, void* stream, cs_gauge* out);
+int cs_gauge_destroy(cs_gauge g);
+
+/* ----------------------------------------------------------- clover term */
+
+/* Build C = 1 + T (paper Section 2, Eq. (1)) from the plaquette leaves, in
+ * double precision, with
+ *   T(x) = i kappa c_sw sum_{mu<nu} sigma_{mu nu} F_{mu nu}(x),
+ *   sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu],  F = (Q - Q^dag)/8,
+ *   Q_{mu nu}(x) = the four counter-clockwise plaquettes at x in the plane.
+ * Stored in double and float.  Synchronises the stream before returning. */
+int cs_clover_create(cs_gauge g, double kappa, double csw, void* stream, cs_clover* out);
+int cs_clover_destroy(cs_clover c);
+/* Write T (not 1 + T) in the canonical complex128 [V][12][12] layout. */
+int cs_clover_export(cs_clover c, void* dst_canonical, void* stream);
+
+/* ---------------------------------------------------------------- operator */
+
+/* out = D in for nrhs consecutive internal-layout fields of precision prec,
+ * with D the clover-Wilson operator of the paper's Eq. (1) (Section 2):
+ *   (D psi)(x) = (1 + T(x)) psi(x)
+ *     - kappa sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                     + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)].
+ * out and in must not overlap. */
+int cs_apply_D(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in,
+               int nrhs, void* stream);
+/* out = D^dag in = gamma5 D gamma5 in. */
+int cs_apply_Ddag(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in,
+                  int nrhs, void* stream);
+
+/* -------------------------------------------------------------------- SAP */
+
+/* Multiplicative Schwarz smoother (paper Section 2: domains updated in turn
+ * with a fixed number of block-solver iterations; Section 3: used as the
+ * post-smoother with a given start vector).  n_cy cycles, each a sweep over
+ * the colour-0 blocks then the colour-1 blocks; on every block B of the
+ * current colour
+ *   r_B = b_B - (D x)_B,  delta = MR(D_BB, r_B, n_mr),  x_B += delta,
+ * where D_BB drops every hopping term that leaves the block and MR is the
+ * minimal-residual iteration delta += alpha rho, rho -= alpha D_BB rho,
+ * alpha = <D_BB rho, rho> / |D_BB rho|^2, started from delta = 0, rho = r_B.
+ * x holds x0 on entry (ignored when x0_is_zero != 0) and the result on exit.
+ * b and x are nrhs consecutive internal fields of precision prec; they must
+ * not overlap.  Needs an even number of blocks in every direction. */
+int cs_sap_smooth(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b,
+                  int n_cy, int n_mr, int x0_is_zero, int nrhs, void* stream);
+
+/* ------------------------------------------------------------------ solver */
+
+typedef struct {
+    int restart;          /* GCR restart length m (1..32)                        */
+    int max_iter;         /* iteration cap                                       */
+    int n_cy, n_mr;       /* SAP cycles and MR steps; n_cy = 0: no preconditioner */
+    double tol;           /* stop when |b - D x| <= tol |b| (true FP64 residual)  */
+    cs_prec inner_prec;   /* precision of the SAP preconditioner and of w = D z   */
+    cs_prec basis_prec;   /* storage of the Krylov basis w_k: CS_F64 or CS_F32    */
+    double reliable_delta;/* restart early when |r_iter| < delta |r_true| (0: off) */
+} cs_solver_params;
+
+typedef struct {
+    int iters;            /* GCR iterations (= preconditioner applications)      */
+    int restarts;         /* true-residual recomputations after the first        */
+    double true_relres;   /* |b - D x| / |b| on exit, FP64                        */
+    double seconds;       /* wall time of the call                               */
+} cs_solver_stats;
+
+/* Fill p with the defaults: restart 16, max_iter 2000, n_cy 2, n_mr 4,
+ * tol 1e-10, inner CS_F32, basis CS_F32, reliable_delta 1e-5. */
+void cs_solver_params_default(cs_solver_params* p);
+
+/* Solve D x = b by flexible GCR (outer arithmetic, reductions and the
+ * residual recomputation in FP64), preconditioned by the SAP smoother in
+ * p->inner_prec (the flexible outer iteration tolerates the nonlinear MR
+ * preconditioner; mixed precision is recovered by recomputing the true
+ * residual in FP64 at every restart, the iterative-refinement scheme of the
+ * paper's Section 2).  x and b are nrhs consecutive CS_F64 internal fields;
+ * x holds x0 on entry.  stats (host, may be NULL) has nrhs entries.  Device
+ * workspace is allocated on first use and kept with the clover handle.
+ * Returns CS_OK when every right-hand side converged, else the first
+ * non-zero status. */
+int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
+                 const void* b, int nrhs, cs_solver_stats* stats, void* stream);
+
+/* -------------------------------------------------------------- profiling */
+
+/* When enabled, every kernel launch of the library is bracketed by HIP
+ * events on the stream it runs on.  cs_profile_query returns the number of
+ * launches and their summed duration (ms) for a kernel family name (one of
+ * "dslash", "sap_halfsweep", "blas", "convert", "clover_build"), after
+ * synchronising the recorded events.  cs_profile_reset clears the counters. */
+int cs_profile_enable(int on);
+int cs_profile_query(const char* name, long long* count, double* total_ms);
+int cs_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

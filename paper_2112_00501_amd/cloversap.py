@@ -1,0 +1,269 @@
+"""Python binding of the cloversap C ABI (include/cloversap.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch provides device memory and streams.  The library must be
+built (paper_2112_00501_amd/build.py); importing this module without it
+raises, so no code path can fall back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcloversap.so")
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+PREC = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+SITE_BYTES = {F64: 192, F32: 96, F16: 52, BF16: 52}
+
+CS_OK, CS_NOT_CONVERGED, CS_BREAKDOWN, CS_NONFINITE = 0, 1, 2, 3
+
+
+class CloverSapError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+class _Params(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_iter", C.c_int), ("n_cy", C.c_int), ("n_mr", C.c_int),
+                ("tol", C.c_double), ("inner_prec", C.c_int), ("basis_prec", C.c_int),
+                ("reliable_delta", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("true_relres", C.c_double),
+                ("seconds", C.c_double)]
+
+
+_lib = None
+
+EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_destroy",
+            "cs_lattice_volume", "cs_field_bytes", "cs_field_import", "cs_field_export",
+            "cs_gauge_create", "cs_gauge_destroy", "cs_clover_create", "cs_clover_destroy",
+            "cs_clover_export", "cs_apply_D", "cs_apply_Ddag", "cs_sap_smooth",
+            "cs_solver_params_default", "cs_gcr_solve", "cs_profile_enable", "cs_profile_query",
+            "cs_profile_reset"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcloversap.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2112_00501_amd/build.py "
+                           "(or __graft_entry__.build())")
+    L = C.CDLL(path)
+    P, I, D = C.c_void_p, C.c_int, C.c_double
+    I4 = C.c_int * 4
+    L.cs_last_error.restype = C.c_char_p
+    L.cs_strerror.restype = C.c_char_p
+    L.cs_strerror.argtypes = [I]
+    L.cs_lattice_create.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(P)]
+    L.cs_lattice_destroy.argtypes = [P]
+    L.cs_lattice_volume.argtypes = [P]
+    L.cs_lattice_volume.restype = C.c_longlong
+    L.cs_field_bytes.argtypes = [P, I, I]
+    L.cs_field_bytes.restype = C.c_size_t
+    L.cs_field_import.argtypes = [P, I, P, P, I, P]
+    L.cs_field_export.argtypes = [P, I, P, P, I, P]
+    L.cs_gauge_create.argtypes = [P, P, P, C.POINTER(P)]
+    L.cs_gauge_destroy.argtypes = [P]
+    L.cs_clover_create.argtypes = [P, D, D, P, C.POINTER(P)]
+    L.cs_clover_destroy.argtypes = [P]
+    L.cs_clover_export.argtypes = [P, P, P]
+    L.cs_apply_D.argtypes = [P, P, I, P, P, I, P]
+    L.cs_apply_Ddag.argtypes = [P, P, I, P, P, I, P]
+    L.cs_sap_smooth.argtypes = [P, P, I, P, P, I, I, I, I, P]
+    L.cs_solver_params_default.argtypes = [C.POINTER(_Params)]
+    L.cs_solver_params_default.restype = None
+    L.cs_gcr_solve.argtypes = [P, P, C.POINTER(_Params), P, P, I, C.POINTER(_Stats), P]
+    L.cs_profile_enable.argtypes = [I]
+    L.cs_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
+    L.cs_profile_reset.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status, where, allow=()):
+    if status != CS_OK and status not in allow:
+        msg = _lib.cs_last_error().decode()
+        raise CloverSapError(status, where, msg)
+    return status
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """Geometry with 4^4 blocks.  dims = (Lx, Ly, Lz, Lt)."""
+
+    def __init__(self, dims, block=(4, 4, 4, 4)):
+        L = load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.block = tuple(int(b) for b in block)
+        h = C.c_void_p()
+        _check(L.cs_lattice_create((C.c_int * 4)(*self.dims), (C.c_int * 4)(*self.block),
+                                   C.byref(h)), "cs_lattice_create")
+        self.handle = h
+        self.volume = int(L.cs_lattice_volume(h))
+
+    def field_bytes(self, prec: int, nrhs: int = 1) -> int:
+        return int(_lib.cs_field_bytes(self.handle, prec, nrhs))
+
+    def new_field(self, prec: int, nrhs: int = 1, device="cuda") -> torch.Tensor:
+        """Uninitialised internal-layout field (a uint8 tensor of the right size)."""
+        return torch.empty(self.field_bytes(prec, nrhs), dtype=torch.uint8, device=device)
+
+    def import_field(self, canonical: torch.Tensor, prec: int, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+        """canonical complex128 [nrhs][V][4][3] or [V][4][3] (GPU) -> internal field."""
+        if canonical.dtype != torch.complex128:
+            raise ValueError("canonical spinors are complex128")
+        nrhs = canonical.numel() // (self.volume * 12)
+        if nrhs * self.volume * 12 != canonical.numel():
+            raise ValueError("canonical field has the wrong size")
+        if out is None:
+            out = self.new_field(prec, nrhs, canonical.device)
+        _check(_lib.cs_field_import(self.handle, prec, _ptr(out), _ptr(canonical), nrhs,
+                                    _stream(stream)), "cs_field_import")
+        return out
+
+    def export_field(self, internal: torch.Tensor, prec: int, nrhs: int = 1,
+                     stream=None) -> torch.Tensor:
+        shape = (self.volume, 4, 3) if nrhs == 1 else (nrhs, self.volume, 4, 3)
+        out = torch.empty(shape, dtype=torch.complex128, device=internal.device)
+        _check(_lib.cs_field_export(self.handle, prec, _ptr(out), _ptr(internal), nrhs,
+                                    _stream(stream)), "cs_field_export")
+        return out
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cs_lattice_destroy(self.handle)
+            self.handle = None
+
+
+class Gauge:
+    """Links, compressed on the device.  U: complex128 [V][4][3][3] on the GPU."""
+
+    def __init__(self, lat: Lattice, U: torch.Tensor, stream=None):
+        if U.dtype != torch.complex128 or U.numel() != lat.volume * 36:
+            raise ValueError("U must be complex128 [V][4][3][3]")
+        self.lat = lat
+        h = C.c_void_p()
+        _check(_lib.cs_gauge_create(lat.handle, _ptr(U), _stream(stream), C.byref(h)),
+               "cs_gauge_create")
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cs_gauge_destroy(self.handle)
+            self.handle = None
+
+
+class Clover:
+    """C = 1 + T for (kappa, c_sw), built on the device from the gauge field."""
+
+    def __init__(self, gauge: Gauge, kappa: float, csw: float, stream=None):
+        self.gauge = gauge
+        self.kappa, self.csw = float(kappa), float(csw)
+        h = C.c_void_p()
+        _check(_lib.cs_clover_create(gauge.handle, self.kappa, self.csw, _stream(stream),
+                                     C.byref(h)), "cs_clover_create")
+        self.handle = h
+
+    def export(self, stream=None) -> torch.Tensor:
+        lat = self.gauge.lat
+        out = torch.empty((lat.volume, 12, 12), dtype=torch.complex128, device="cuda")
+        _check(_lib.cs_clover_export(self.handle, _ptr(out), _stream(stream)), "cs_clover_export")
+        return out
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cs_clover_destroy(self.handle)
+            self.handle = None
+
+
+class Operator:
+    """The clover-Wilson operator D of one gauge field and (kappa, c_sw)."""
+
+    def __init__(self, lat: Lattice, U: torch.Tensor, kappa: float, csw: float, stream=None):
+        self.lat = lat
+        self.gauge = Gauge(lat, U, stream)
+        self.clover = Clover(self.gauge, kappa, csw, stream)
+
+    def apply_D(self, out, inp, prec, nrhs=1, stream=None):
+        _check(_lib.cs_apply_D(self.gauge.handle, self.clover.handle, prec, _ptr(out), _ptr(inp),
+                               nrhs, _stream(stream)), "cs_apply_D")
+        return out
+
+    def apply_Ddag(self, out, inp, prec, nrhs=1, stream=None):
+        _check(_lib.cs_apply_Ddag(self.gauge.handle, self.clover.handle, prec, _ptr(out),
+                                  _ptr(inp), nrhs, _stream(stream)), "cs_apply_Ddag")
+        return out
+
+    def sap_smooth(self, x, b, prec, n_cy=2, n_mr=4, x0_is_zero=True, nrhs=1, stream=None):
+        _check(_lib.cs_sap_smooth(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
+                                  int(n_cy), int(n_mr), int(bool(x0_is_zero)), nrhs,
+                                  _stream(stream)), "cs_sap_smooth")
+        return x
+
+    def gcr_solve(self, x, b, params: "SolverParams", nrhs=1, stream=None, allow_fail=False):
+        """x, b: CS_F64 internal fields.  Returns (status, [stats per rhs])."""
+        p = params.to_c()
+        stats = (_Stats * nrhs)()
+        st = _lib.cs_gcr_solve(self.gauge.handle, self.clover.handle, C.byref(p), _ptr(x), _ptr(b),
+                               nrhs, stats, _stream(stream))
+        if not allow_fail:
+            _check(st, "cs_gcr_solve")
+        out = [dict(iters=s.iters, restarts=s.restarts, true_relres=s.true_relres,
+                    seconds=s.seconds) for s in stats]
+        return st, out
+
+
+@dataclass
+class SolverParams:
+    restart: int = 16
+    max_iter: int = 2000
+    n_cy: int = 2
+    n_mr: int = 4
+    tol: float = 1e-10
+    inner_prec: int = F32
+    basis_prec: int = F32
+    reliable_delta: float = 1e-5
+
+    def to_c(self) -> _Params:
+        return _Params(self.restart, self.max_iter, self.n_cy, self.n_mr, self.tol,
+                       self.inner_prec, self.basis_prec, self.reliable_delta)
+
+
+def profile_enable(on: bool = True):
+    load_library()
+    _check(_lib.cs_profile_enable(int(on)), "cs_profile_enable")
+
+
+def profile_reset():
+    _check(_lib.cs_profile_reset(), "cs_profile_reset")
+
+
+def profile_query(name: str):
+    n = C.c_longlong(0)
+    ms = C.c_double(0)
+    _check(_lib.cs_profile_query(name.encode(), C.byref(n), C.byref(ms)), "cs_profile_query")
+    return int(n.value), float(ms.value)

@@ -1,0 +1,425 @@
+// C ABI of the cloversap library (include/cloversap.h): handle management,
+// argument validation, error reporting and launch profiling.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cloversap.h"
+#include "gcr.hpp"
+
+struct cs_lattice_s {
+    cs::Geom g;
+};
+
+struct cs_gauge_s {
+    cs::Geom g;
+    void* links[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+struct cs_clover_s {
+    cs_gauge_s* gauge = nullptr;
+    double kappa = 0, csw = 0;
+    void* c64 = nullptr;
+    void* c32 = nullptr;
+    std::unique_ptr<cs::GcrWork> work;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int ok() {
+    g_last_error.clear();
+    return CS_OK;
+}
+
+#define CS_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) return fail(CS_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool valid_prec(int p) { return p >= CS_F64 && p <= CS_BF16; }
+
+cs::OpData make_op(const cs_gauge_s* g, const cs_clover_s* c) {
+    cs::OpData op;
+    op.g = g->g;
+    for (int i = 0; i < 4; ++i) op.links[i] = g->links[i];
+    op.clover64 = c->c64;
+    op.clover32 = c->c32;
+    op.kappa = c->kappa;
+    return op;
+}
+
+int check_op(cs_gauge g, cs_clover c) {
+    if (!g || !c) return fail(CS_ERR_NULL, "gauge or clover handle is NULL");
+    if (c->gauge != g) return fail(CS_ERR_INVALID, "clover handle was built from a different gauge handle");
+    return CS_OK;
+}
+
+bool sap_geometry_ok(const cs::Geom& g) {
+    for (int m = 0; m < 4; ++m)
+        if (g.NB[m] % 2 != 0) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------- profiler
+
+struct ProfRec {
+    std::string fam;
+    hipEvent_t a, b;
+    bool closed;
+};
+std::mutex g_pm;
+bool g_prof_on = false;
+std::vector<ProfRec> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+std::map<std::string, std::pair<long long, double>> g_prof;
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void drain_pending() {
+    for (auto& r : g_pending) {
+        if (r.closed && hipEventSynchronize(r.b) == hipSuccess) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                auto& slot = g_prof[r.fam];
+                slot.first += 1;
+                slot.second += ms;
+            }
+        }
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_pending.clear();
+}
+
+}  // namespace
+
+namespace cs {
+
+void prof_begin(const char* family, hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_pm);
+    ProfRec r{family, take_event(), take_event(), false};
+    if (!r.a || !r.b) return;
+    hipEventRecord(r.a, s);
+    g_pending.push_back(r);
+}
+
+void prof_end(const char* family, hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_pm);
+    for (auto it = g_pending.rbegin(); it != g_pending.rend(); ++it) {
+        if (!it->closed && it->fam == family) {
+            hipEventRecord(it->b, s);
+            it->closed = true;
+            break;
+        }
+    }
+}
+
+}  // namespace cs
+
+extern "C" {
+
+const char* cs_last_error(void) { return g_last_error.c_str(); }
+
+const char* cs_strerror(int status) {
+    switch (status) {
+    case CS_OK: return "ok";
+    case CS_ERR_INVALID: return "invalid argument";
+    case CS_ERR_GEOMETRY: return "unsupported lattice geometry";
+    case CS_ERR_NULL: return "null pointer or handle";
+    case CS_ERR_PRECISION: return "unsupported precision";
+    case CS_ERR_HIP: return "HIP runtime error";
+    case CS_ERR_ALLOC: return "device allocation failed";
+    case CS_NOT_CONVERGED: return "not converged within max_iter";
+    case CS_BREAKDOWN: return "solver breakdown";
+    case CS_NONFINITE: return "non-finite residual";
+    default: return "unknown status";
+    }
+}
+
+int cs_lattice_create(const int dims[4], const int block[4], cs_lattice* out) {
+    if (!dims || !block || !out) return fail(CS_ERR_NULL, "dims, block and out must be non-NULL");
+    cs::Geom g{};
+    long long V = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (block[m] != 4)
+            return fail(CS_ERR_GEOMETRY, "block must be 4x4x4x4 (got %d in direction %d)", block[m], m);
+        if (dims[m] <= 0 || dims[m] % 4 != 0)
+            return fail(CS_ERR_GEOMETRY, "extent %d in direction %d is not a positive multiple of 4", dims[m], m);
+        g.L[m] = dims[m];
+        g.NB[m] = dims[m] / 4;
+        V *= dims[m];
+    }
+    if (V / cs::BLOCK_SITES > (1LL << 30)) return fail(CS_ERR_GEOMETRY, "lattice too large");
+    g.V = V;
+    g.nblk = (int)(V / cs::BLOCK_SITES);
+    *out = new cs_lattice_s{g};
+    return ok();
+}
+
+int cs_lattice_destroy(cs_lattice lat) {
+    delete lat;
+    return ok();
+}
+
+long long cs_lattice_volume(cs_lattice lat) { return lat ? lat->g.V : 0; }
+
+size_t cs_field_bytes(cs_lattice lat, cs_prec prec, int nrhs) {
+    if (!lat || !valid_prec(prec) || nrhs < 0) return 0;
+    return cs::spinor_bytes_per_site(prec) * (size_t)lat->g.V * (size_t)nrhs;
+}
+
+int cs_field_import(cs_lattice lat, cs_prec prec, void* dst, const void* src, int nrhs, void* stream) {
+    if (!lat || !dst || !src) return fail(CS_ERR_NULL, "lattice, dst and src must be non-NULL");
+    if (!valid_prec(prec)) return fail(CS_ERR_PRECISION, "unknown precision %d", (int)prec);
+    if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
+    CS_HIP(cs::launch_field_import(lat->g, prec, dst, src, nrhs, (hipStream_t)stream));
+    return ok();
+}
+
+int cs_field_export(cs_lattice lat, cs_prec prec, void* dst, const void* src, int nrhs, void* stream) {
+    if (!lat || !dst || !src) return fail(CS_ERR_NULL, "lattice, dst and src must be non-NULL");
+    if (!valid_prec(prec)) return fail(CS_ERR_PRECISION, "unknown precision %d", (int)prec);
+    if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
+    CS_HIP(cs::launch_field_export(lat->g, prec, dst, src, nrhs, (hipStream_t)stream));
+    return ok();
+}
+
+int cs_gauge_create(cs_lattice lat, const void* U, void* stream, cs_gauge* out) {
+    if (!lat || !U || !out) return fail(CS_ERR_NULL, "lattice, U and out must be non-NULL");
+    auto* g = new cs_gauge_s;
+    g->g = lat->g;
+    for (int p = 0; p < 4; ++p) {
+        if (hipMalloc(&g->links[p], cs::link_bytes_per_site(p) * g->g.V) != hipSuccess) {
+            cs_gauge_destroy(g);
+            return fail(CS_ERR_ALLOC, "could not allocate %zu bytes of links",
+                        cs::link_bytes_per_site(p) * (size_t)g->g.V);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = cs::launch_import_links(g->g, U, g->links[0], g->links[1], g->links[2], g->links[3], s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        cs_gauge_destroy(g);
+        return fail(CS_ERR_HIP, "link import: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return ok();
+}
+
+int cs_gauge_destroy(cs_gauge g) {
+    if (!g) return ok();
+    for (int p = 0; p < 4; ++p)
+        if (g->links[p]) hipFree(g->links[p]);
+    delete g;
+    return ok();
+}
+
+int cs_clover_create(cs_gauge g, double kappa, double csw, void* stream, cs_clover* out) {
+    if (!g || !out) return fail(CS_ERR_NULL, "gauge and out must be non-NULL");
+    if (!std::isfinite(kappa) || !std::isfinite(csw)) return fail(CS_ERR_INVALID, "kappa and c_sw must be finite");
+    auto* c = new cs_clover_s;
+    c->gauge = g;
+    c->kappa = kappa;
+    c->csw = csw;
+    if (hipMalloc(&c->c64, cs::clover_bytes_per_site(cs::P_F64) * g->g.V) != hipSuccess ||
+        hipMalloc(&c->c32, cs::clover_bytes_per_site(cs::P_F32) * g->g.V) != hipSuccess) {
+        cs_clover_destroy(c);
+        return fail(CS_ERR_ALLOC, "could not allocate the clover term");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = cs::launch_clover_build(g->g, g->links[cs::P_F64], kappa, csw, c->c64, c->c32, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        cs_clover_destroy(c);
+        return fail(CS_ERR_HIP, "clover build: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return ok();
+}
+
+int cs_clover_destroy(cs_clover c) {
+    if (!c) return ok();
+    c->work.reset();
+    if (c->c64) hipFree(c->c64);
+    if (c->c32) hipFree(c->c32);
+    delete c;
+    return ok();
+}
+
+int cs_clover_export(cs_clover c, void* dst, void* stream) {
+    if (!c || !dst) return fail(CS_ERR_NULL, "clover and dst must be non-NULL");
+    CS_HIP(cs::launch_clover_export(c->gauge->g, c->c64, dst, (hipStream_t)stream));
+    return ok();
+}
+
+static int apply(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in, int nrhs, void* stream,
+                 bool dagger) {
+    int st = check_op(g, c);
+    if (st) return st;
+    if (!out || !in) return fail(CS_ERR_NULL, "out and in must be non-NULL");
+    if (!valid_prec(prec)) return fail(CS_ERR_PRECISION, "unknown precision %d", (int)prec);
+    if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
+    const size_t bytes = cs::spinor_bytes_per_site(prec) * (size_t)g->g.V * nrhs;
+    const char* i0 = (const char*)in;
+    const char* o0 = (const char*)out;
+    if (i0 < o0 + bytes && o0 < i0 + bytes) return fail(CS_ERR_INVALID, "out and in overlap");
+    CS_HIP(cs::launch_dslash(make_op(g, c), prec, prec, prec, dagger, out, in, nullptr, nrhs, (hipStream_t)stream));
+    return ok();
+}
+
+int cs_apply_D(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in, int nrhs, void* stream) {
+    return apply(g, c, prec, out, in, nrhs, stream, false);
+}
+
+int cs_apply_Ddag(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in, int nrhs, void* stream) {
+    return apply(g, c, prec, out, in, nrhs, stream, true);
+}
+
+int cs_sap_smooth(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
+                  int x0_is_zero, int nrhs, void* stream) {
+    int st = check_op(g, c);
+    if (st) return st;
+    if (!x || !b) return fail(CS_ERR_NULL, "x and b must be non-NULL");
+    if (!valid_prec(prec)) return fail(CS_ERR_PRECISION, "unknown precision %d", (int)prec);
+    if (n_cy < 0 || n_mr < 0) return fail(CS_ERR_INVALID, "n_cy and n_mr must be >= 0");
+    if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
+    if (!sap_geometry_ok(g->g))
+        return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
+    const size_t bytes = cs::spinor_bytes_per_site(prec) * (size_t)g->g.V * nrhs;
+    const char* i0 = (const char*)b;
+    const char* o0 = (const char*)x;
+    if (i0 < o0 + bytes && o0 < i0 + bytes) return fail(CS_ERR_INVALID, "x and b overlap");
+    const cs::OpData op = make_op(g, c);
+    hipStream_t s = (hipStream_t)stream;
+    if (n_cy == 0 && x0_is_zero) {
+        CS_HIP(hipMemsetAsync(x, 0, bytes, s));
+        return ok();
+    }
+    for (int cy = 0; cy < n_cy; ++cy)
+        for (int col = 0; col < 2; ++col) {
+            const int mode = (x0_is_zero && cy == 0) ? (col == 0 ? 1 : 2) : 0;
+            CS_HIP(cs::launch_sap_halfsweep(op, prec, col, n_mr, mode, x, b, nrhs, s));
+        }
+    return ok();
+}
+
+void cs_solver_params_default(cs_solver_params* p) {
+    if (!p) return;
+    p->restart = 16;
+    p->max_iter = 2000;
+    p->n_cy = 2;
+    p->n_mr = 4;
+    p->tol = 1e-10;
+    p->inner_prec = CS_F32;
+    p->basis_prec = CS_F32;
+    p->reliable_delta = 1e-5;
+}
+
+int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
+                 cs_solver_stats* stats, void* stream) {
+    int st = check_op(g, c);
+    if (st) return st;
+    if (!p || !x || !b) return fail(CS_ERR_NULL, "params, x and b must be non-NULL");
+    if (p->restart < 1 || p->restart > cs::GCR_MAX_RESTART)
+        return fail(CS_ERR_INVALID, "restart must be in 1..%d", cs::GCR_MAX_RESTART);
+    if (p->max_iter < 0 || p->n_cy < 0 || (p->n_cy > 0 && p->n_mr < 1))
+        return fail(CS_ERR_INVALID, "max_iter and n_cy must be >= 0 and n_mr >= 1 when n_cy > 0");
+    if (!(p->tol >= 0.0)) return fail(CS_ERR_INVALID, "tol must be >= 0");
+    if (!valid_prec(p->inner_prec)) return fail(CS_ERR_PRECISION, "unknown inner precision");
+    if (p->basis_prec != CS_F64 && p->basis_prec != CS_F32)
+        return fail(CS_ERR_PRECISION, "basis precision must be CS_F64 or CS_F32");
+    if (p->inner_prec == CS_F64 && p->basis_prec != CS_F64)
+        return fail(CS_ERR_PRECISION, "an FP64 inner solve needs an FP64 basis");
+    if (nrhs < 1) return fail(CS_ERR_INVALID, "nrhs must be >= 1");
+    if (p->n_cy > 0 && !sap_geometry_ok(g->g))
+        return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
+    const size_t f64 = cs::spinor_bytes_per_site(cs::P_F64) * (size_t)g->g.V;
+    {
+        const char* i0 = (const char*)b;
+        const char* o0 = (const char*)x;
+        if (i0 < o0 + f64 * nrhs && o0 < i0 + f64 * nrhs) return fail(CS_ERR_INVALID, "x and b overlap");
+    }
+    if (!c->work) c->work.reset(new cs::GcrWork);
+    hipError_t e = c->work->ensure(g->g, p->restart, p->inner_prec, p->basis_prec);
+    if (e != hipSuccess) {
+        c->work->release();
+        return fail(CS_ERR_ALLOC, "solver workspace: %s", hipGetErrorString(e));
+    }
+    const cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
+                           p->reliable_delta};
+    const cs::OpData op = make_op(g, c);
+    int first_bad = CS_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        cs::GcrResult res{};
+        e = cs::gcr_solve_one(op, gp, *c->work, (char*)x + r * f64, (const char*)b + r * f64, &res,
+                              (hipStream_t)stream);
+        if (e != hipSuccess) return fail(CS_ERR_HIP, "solve: %s", hipGetErrorString(e));
+        if (stats) {
+            stats[r].iters = res.iters;
+            stats[r].restarts = res.restarts;
+            stats[r].true_relres = res.true_relres;
+            stats[r].seconds = res.seconds;
+        }
+        if (res.status != cs::GCR_OK && first_bad == CS_OK) first_bad = res.status;
+    }
+    if (first_bad != CS_OK) return fail(first_bad, "%s", cs_strerror(first_bad));
+    return ok();
+}
+
+int cs_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_pm);
+    g_prof_on = on != 0;
+    return ok();
+}
+
+int cs_profile_query(const char* name, long long* count, double* total_ms) {
+    if (!name || !count || !total_ms) return fail(CS_ERR_NULL, "name, count and total_ms must be non-NULL");
+    std::lock_guard<std::mutex> lk(g_pm);
+    drain_pending();
+    auto it = g_prof.find(name);
+    *count = it == g_prof.end() ? 0 : it->second.first;
+    *total_ms = it == g_prof.end() ? 0.0 : it->second.second;
+    return ok();
+}
+
+int cs_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_pm);
+    drain_pending();
+    g_prof.clear();
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+// Internal definitions shared by the HIP sources of the cloversap library:
+// geometry of the 4^4 block layout, storage formats, complex helpers and the
+// host-side launch interface between translation units.
+//
+// Internal layout (private to the library).  Sites are grouped into 4^4
+// blocks; block b = bx + NBx*(by + NBy*(bz + NBz*bt)), local site
+// l = lx + 4*(ly + 4*(lz + 4*lt)).  Within a block every field is stored
+// component-major ("structure of arrays"), so lane l of a 256-thread
+// workgroup reads word l of each component row: all loads are unit-stride.
+//
+//   spinor F64  double2 [nblk][12][256]            complex component c = 3*spin + colour
+//   spinor F32  float4  [nblk][6][256]             float4 k = components (2k, 2k+1)
+//   spinor F16  uint4   [nblk][3][256] + float [nblk][256]
+//               (8 halves = 4 complex per uint4; the float is the per-site scale,
+//                the largest |re|, |im| of the site's 24 reals)
+//   spinor BF16 as F16 with bfloat16 halves
+//   links  F64  double2 [nblk][4][6][256]          rows 0 and 1 of U_mu(x), row-major
+//   links  F32  float4  [nblk][4][3][256]
+//   links  F16/BF16 uint2 [nblk][4][3][256]        2 complex per uint2
+//   clover F64  double2 [nblk][36][256]            72 reals: for each chirality h,
+//   clover F32  float4  [nblk][18][256]            6 diagonal reals of 1+T_h, then the
+//                                                  15 upper entries (i<j, row-major)
+//                                                  as (re, im)
+// Multi-RHS fields are nrhs single fields one after the other.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace cs {
+
+constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+
+// ------------------------------------------------------------------ geometry
+
+struct Geom {
+    int L[4];      // lattice extents
+    int NB[4];     // blocks per direction
+    int nblk;      // number of blocks
+    long long V;   // number of sites
+};
+
+// Per-thread block coordinates and block-index strides.
+struct BlockPos {
+    int blk;
+    int bc[4];
+    int stride[4];
+};
+
+__device__ __forceinline__ BlockPos block_pos(const Geom& g, int blk) {
+    BlockPos p;
+    p.blk = blk;
+    int r = blk;
+    p.bc[0] = r % g.NB[0]; r /= g.NB[0];
+    p.bc[1] = r % g.NB[1]; r /= g.NB[1];
+    p.bc[2] = r % g.NB[2];
+    p.bc[3] = r / g.NB[2];
+    p.stride[0] = 1;
+    p.stride[1] = g.NB[0];
+    p.stride[2] = g.NB[0] * g.NB[1];
+    p.stride[3] = g.NB[0] * g.NB[1] * g.NB[2];
+    return p;
+}
+
+// Neighbour of local site l in direction mu (dir = +1 or -1): returns the
+// neighbour's block and writes its local index.  *inside = 1 when the
+// neighbour lies in the same block.
+__device__ __forceinline__ int neighbour(const Geom& g, const BlockPos& p, int l, int mu, int dir,
+                                         int* nl, bool* inside) {
+    const int sh = 2 * mu;
+    const int lc = (l >> sh) & 3;
+    if (dir > 0) {
+        if (lc < 3) { *nl = l + (1 << sh); *inside = true; return p.blk; }
+        *nl = l - (3 << sh);
+        *inside = false;
+        return p.bc[mu] == g.NB[mu] - 1 ? p.blk - (g.NB[mu] - 1) * p.stride[mu] : p.blk + p.stride[mu];
+    }
+    if (lc > 0) { *nl = l - (1 << sh); *inside = true; return p.blk; }
+    *nl = l + (3 << sh);
+    *inside = false;
+    return p.bc[mu] == 0 ? p.blk + (g.NB[mu] - 1) * p.stride[mu] : p.blk - p.stride[mu];
+}
+
+// The c-th block of colour `colour` (colour = sum of block coordinates mod 2),
+// enumerated with bx fastest; requires NB[0] even.
+__host__ __device__ __forceinline__ int colour_block(const Geom& g, int colour, int c) {
+    const int half = g.NB[0] / 2;
+    const int hx = c % half;
+    int r = c / half;
+    const int by = r % g.NB[1];
+    r /= g.NB[1];
+    const int bz = r % g.NB[2];
+    const int bt = r / g.NB[2];
+    const int bx = 2 * hx + ((colour + by + bz + bt) & 1);
+    return bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+}
+
+// Canonical site index of (blk, l).
+__device__ __forceinline__ long long canonical_site(const Geom& g, int blk, int l) {
+    const BlockPos p = block_pos(g, blk);
+    const int x = p.bc[0] * 4 + (l & 3);
+    const int y = p.bc[1] * 4 + ((l >> 2) & 3);
+    const int z = p.bc[2] * 4 + ((l >> 4) & 3);
+    const int t = p.bc[3] * 4 + (l >> 6);
+    return x + (long long)g.L[0] * (y + (long long)g.L[1] * (z + (long long)g.L[2] * t));
+}
+
+// ------------------------------------------------------------ storage sizes
+
+inline size_t spinor_bytes_per_site(int prec) {
+    switch (prec) {
+    case P_F64: return 192;
+    case P_F32: return 96;
+    case P_F16:
+    case P_BF16: return 52;
+    default: return 0;
+    }
+}
+inline size_t link_bytes_per_site(int prec) {  // four compressed links
+    switch (prec) {
+    case P_F64: return 384;
+    case P_F32: return 192;
+    case P_F16:
+    case P_BF16: return 96;
+    default: return 0;
+    }
+}
+inline size_t clover_bytes_per_site(int prec) { return prec == P_F64 ? 576 : 288; }
+
+// ------------------------------------------------------------ complex numbers
+
+template <typename R>
+struct cpx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cpx<R> cmake(R a, R b) { return cpx<R>{a, b}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator*(cpx<R> a, cpx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> operator*(R s, cpx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> conj(cpx<R> a) { return {a.re, -a.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> mul_i(cpx<R> a) { return {-a.im, a.re}; }   // i a
+template <typename R>
+__device__ __forceinline__ cpx<R> mul_mi(cpx<R> a) { return {a.im, -a.re}; }  // -i a
+// a += b * c
+template <typename R>
+__device__ __forceinline__ void cmac(cpx<R>& a, cpx<R> b, cpx<R> c) {
+    a.re = fma(b.re, c.re, a.re);
+    a.re = fma(-b.im, c.im, a.re);
+    a.im = fma(b.re, c.im, a.im);
+    a.im = fma(b.im, c.re, a.im);
+}
+// a += conj(b) * c
+template <typename R>
+__device__ __forceinline__ void cmac_conj(cpx<R>& a, cpx<R> b, cpx<R> c) {
+    a.re = fma(b.re, c.re, a.re);
+    a.re = fma(b.im, c.im, a.re);
+    a.im = fma(b.re, c.im, a.im);
+    a.im = fma(-b.im, c.re, a.im);
+}
+
+// ------------------------------------------------------------- host launch API
+
+struct Profiler;
+
+// Launch bookkeeping shared by all translation units: records HIP events
+// around a launch when profiling is on.
+void prof_begin(const char* family, hipStream_t s);
+void prof_end(const char* family, hipStream_t s);
+
+struct ProfScope {
+    const char* fam;
+    hipStream_t s;
+    ProfScope(const char* f, hipStream_t st) : fam(f), s(st) { prof_begin(fam, s); }
+    ~ProfScope() { prof_end(fam, s); }
+};
+
+// setup.hip
+hipError_t launch_import_links(const Geom& g, const void* U_canonical, void* l64, void* l32,
+                               void* l16, void* lbf16, hipStream_t s);
+hipError_t launch_clover_build(const Geom& g, const void* links64, double kappa, double csw,
+                               void* c64, void* c32, hipStream_t s);
+hipError_t launch_clover_export(const Geom& g, const void* c64, void* dst, hipStream_t s);
+hipError_t launch_field_import(const Geom& g, int prec, void* dst, const void* src, int nrhs,
+                               hipStream_t s);
+hipError_t launch_field_export(const Geom& g, int prec, void* dst, const void* src, int nrhs,
+                               hipStream_t s);
+
+// dslash.hip: out = D in (dagger: gamma5 D gamma5).  in_prec / out_prec are
+// spinor storage precisions; link and clover precision follow the arithmetic
+// (F64 arithmetic when in_prec == P_F64, else F32 arithmetic with links of
+// precision link_prec and F32 clover).  With sub != nullptr the kernel writes
+// out = sub - D in (sub has out_prec).
+struct OpData {
+    Geom g;
+    const void* links[4];   // indexed by Prec
+    const void* clover64;
+    const void* clover32;
+    double kappa;
+};
+hipError_t launch_dslash(const OpData& op, int in_prec, int out_prec, int link_prec, bool dagger,
+                         void* out, const void* in, const void* sub, int nrhs, hipStream_t s);
+
+// sap.hip: one half-sweep over the blocks of one colour.  mode 0: general;
+// 1: x is zero everywhere (r = b); 2: x is zero on the blocks of this colour.
+hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode,
+                                void* x, const void* b, int nrhs, hipStream_t s);
+
+// blas.hip
+struct BlasWork;  // defined in blas.hip
+hipError_t launch_convert(const Geom& g, int dst_prec, void* dst, int src_prec, const void* src,
+                          const double* scale_dev, int nrhs, hipStream_t s);
+
+}  // namespace cs

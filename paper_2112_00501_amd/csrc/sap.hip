@@ -1,0 +1,250 @@
+// One half-sweep of the multiplicative red/black Schwarz smoother (paper
+// Section 2: domains are updated in turn, each with a fixed number of
+// block-solver iterations).  One workgroup owns one 4^4 block of the current
+// colour; one lane owns one site.  Per block:
+//   r_B = b_B - (D x)_B          full operator; the neighbouring blocks all
+//                                have the other colour, so they are not being
+//                                written by this launch (no races, no atomics)
+//   delta = 0, rho = r_B
+//   n_mr times:  q = D_BB rho    Dirichlet block operator, rho and the links
+//                                read from LDS, the clover term from registers
+//                alpha = <q, rho> / <q, q>   (workgroup reductions)
+//                delta += alpha rho,  rho -= alpha q
+//   x_B += delta
+// HBM traffic per site: b, x, the face neighbours of x, the links and the
+// clover term once, and x once written.  All MR iterations run out of LDS
+// and registers.
+#include <type_traits>
+
+#include "dslash_core.hpp"
+
+namespace cs {
+
+namespace {
+
+// Rows 0 and 1 of the block's links, kept in LDS in float for the MR loop.
+template <bool ON>
+struct LinkSmem { cpx<float> u[4][6][BLOCK_SITES]; };
+template <>
+struct LinkSmem<false> { cpx<float> u[1][1][1]; };
+
+template <typename R>
+struct LdsSpinor {  // in-block neighbours of the Dirichlet operator
+    cpx<R> (*s)[BLOCK_SITES];
+    __device__ __forceinline__ bool want(bool inside) const { return inside; }
+    template <typename RR>
+    __device__ __forceinline__ void load_nb(int, int l, bool, cpx<RR>* c) const {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) c[k] = {(RR)s[k][l].re, (RR)s[k][l].im};
+    }
+};
+
+struct LdsLinks {
+    const LinkSmem<true>* sm;
+    template <typename R>
+    __device__ __forceinline__ void load(int, int l, int mu, bool, cpx<R>* u) const {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u[k] = {(R)sm->u[mu][k][l].re, (R)sm->u[mu][k][l].im};
+        su3_row2(u);
+    }
+};
+
+// x is zero on the blocks of the current colour: only hops that leave the
+// block contribute to D x.
+template <int P>
+struct OutsideSpinor {
+    const void* base;
+    int nblk;
+    __device__ __forceinline__ bool want(bool inside) const { return !inside; }
+    template <typename R>
+    __device__ __forceinline__ void load_nb(int blk, int l, bool, cpx<R>* c) const {
+        using RS = typename SpinorIO<P>::R;
+        cpx<RS> t[12];
+        SpinorIO<P>::load(base, nblk, blk, l, t);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) c[k] = {(R)t[k].re, (R)t[k].im};
+    }
+};
+
+// Sum of three values over the 256 lanes; every lane receives the same total.
+template <typename R>
+__device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+        red[2][wave] = c;
+    }
+    __syncthreads();
+    a = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    b = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    c = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+}
+
+template <int P, int PLINK>
+__global__ __launch_bounds__(BLOCK_SITES) void k_sap_halfsweep(
+    Geom g, const void* __restrict__ links, const void* __restrict__ clover, double kappa_d,
+    int colour, int n_mr, int mode, void* __restrict__ x, const void* __restrict__ b,
+    size_t stride) {
+    using R = typename Arith<P>::R;
+    constexpr bool F32PATH = std::is_same<R, float>::value;
+    __shared__ cpx<R> s_rho[12][BLOCK_SITES];
+    __shared__ LinkSmem<F32PATH> s_lk;
+    __shared__ R s_red[3][4];
+
+    const int l = threadIdx.x;
+    const int blk = colour_block(g, colour, blockIdx.x);
+    char* xr = (char*)x + blockIdx.y * stride;
+    const char* br = (const char*)b + blockIdx.y * stride;
+    const BlockPos p = block_pos(g, blk);
+    const R kappa = (R)kappa_d;
+
+    if constexpr (F32PATH) {
+        for (int mu = 0; mu < 4; ++mu) {
+            cpx<typename LinkIO<PLINK>::R> u[6];
+            LinkIO<PLINK>::load6(links, blk, l, mu, u);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) s_lk.u[mu][k][l] = {(float)u[k].re, (float)u[k].im};
+        }
+    }
+
+    // ---- block residual r_B = b_B - (D x)_B
+    cpx<R> rho[12];
+    {
+        using RS = typename SpinorIO<P>::R;
+        cpx<RS> t[12];
+        SpinorIO<P>::load(br, g.nblk, blk, l, t);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) rho[k] = {(R)t[k].re, (R)t[k].im};
+    }
+    R cl[72];
+    CloverIO<R>::load(clover, blk, l, cl);
+    if (mode != 1) {
+        cpx<R> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+        GlobalLinks<PLINK> glk{links};
+        if (mode == 0) {
+            GlobalSpinor<P, false> gs{xr, g.nblk};
+            hopping_sum<R>(g, p, l, gs, glk, acc);
+            cpx<R> self[12], cx[12];
+            gs.load(blk, l, self);
+            clover_apply(cl, self, cx);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {cx[k].re - kappa * acc[k].re, cx[k].im - kappa * acc[k].im};
+        } else {
+            OutsideSpinor<P> os{xr, g.nblk};
+            hopping_sum<R>(g, p, l, os, glk, acc);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {-kappa * acc[k].re, -kappa * acc[k].im};
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) rho[k] = rho[k] - acc[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s_rho[k][l] = rho[k];
+
+    // ---- MR on the Dirichlet block operator
+    cpx<R> delta[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) delta[k] = {(R)0, (R)0};
+    LdsSpinor<R> ls{s_rho};
+    for (int it = 0; it < n_mr; ++it) {
+        __syncthreads();
+        cpx<R> q[12];
+        {
+            cpx<R> acc[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+            if constexpr (F32PATH) {
+                LdsLinks lk{&s_lk};
+                hopping_sum<R>(g, p, l, ls, lk, acc);
+            } else {
+                GlobalLinks<PLINK> lk{links};
+                hopping_sum<R>(g, p, l, ls, lk, acc);
+            }
+            if constexpr (F32PATH) {
+                clover_apply(cl, rho, q);
+            } else {  // double clover does not fit in registers next to the MR state
+                R c2[72];
+                CloverIO<R>::load(clover, blk, l, c2);
+                clover_apply(c2, rho, q);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) q[k] = {q[k].re - kappa * acc[k].re, q[k].im - kappa * acc[k].im};
+        }
+        R qq = 0, qr_re = 0, qr_im = 0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            qq = fma(q[k].re, q[k].re, qq);
+            qq = fma(q[k].im, q[k].im, qq);
+            // conj(q) * rho
+            qr_re = fma(q[k].re, rho[k].re, qr_re);
+            qr_re = fma(q[k].im, rho[k].im, qr_re);
+            qr_im = fma(q[k].re, rho[k].im, qr_im);
+            qr_im = fma(-q[k].im, rho[k].re, qr_im);
+        }
+        block_sum3(qq, qr_re, qr_im, s_red);
+        if (qq == (R)0) break;  // rho = 0: the block is solved (uniform branch)
+        const R inv = (R)1 / qq;
+        const cpx<R> alpha = {qr_re * inv, qr_im * inv};
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            cmac(delta[k], alpha, rho[k]);
+            cpx<R> t = rho[k];
+            t.re = fma(-alpha.re, q[k].re, t.re);
+            t.re = fma(alpha.im, q[k].im, t.re);
+            t.im = fma(-alpha.re, q[k].im, t.im);
+            t.im = fma(-alpha.im, q[k].re, t.im);
+            rho[k] = t;
+            s_rho[k][l] = t;
+        }
+    }
+
+    // ---- x_B += delta (after every lane has finished reading x above)
+    __syncthreads();
+    using RS = typename SpinorIO<P>::R;
+    cpx<RS> xo[12];
+    if (mode == 0) {
+        SpinorIO<P>::load(xr, g.nblk, blk, l, xo);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) xo[k] = {xo[k].re + (RS)delta[k].re, xo[k].im + (RS)delta[k].im};
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) xo[k] = {(RS)delta[k].re, (RS)delta[k].im};
+    }
+    SpinorIO<P>::store(xr, g.nblk, blk, l, xo);
+}
+
+template <int P, int PLINK>
+hipError_t launch_p(const OpData& op, int colour, int n_mr, int mode, void* x, const void* b,
+                    int nrhs, hipStream_t s) {
+    const dim3 grid(op.g.nblk / 2, nrhs);
+    const size_t stride = spinor_bytes_per_site(P) * op.g.V;
+    const void* cl = P == P_F64 ? op.clover64 : op.clover32;
+    hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK>), grid, dim3(BLOCK_SITES), 0, s, op.g,
+                       op.links[PLINK], cl, op.kappa, colour, n_mr, mode, x, b, stride);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode, void* x,
+                                const void* b, int nrhs, hipStream_t s) {
+    ProfScope ps("sap_halfsweep", s);
+    switch (prec) {
+    case P_F64: return launch_p<P_F64, P_F64>(op, colour, n_mr, mode, x, b, nrhs, s);
+    case P_F32: return launch_p<P_F32, P_F32>(op, colour, n_mr, mode, x, b, nrhs, s);
+    case P_F16: return launch_p<P_F16, P_F16>(op, colour, n_mr, mode, x, b, nrhs, s);
+    case P_BF16: return launch_p<P_BF16, P_BF16>(op, colour, n_mr, mode, x, b, nrhs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace cs

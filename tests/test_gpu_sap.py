@@ -1,0 +1,78 @@
+"""GPU parity of the red/black SAP smoother (paper Section 2: multiplicative
+Schwarz, fixed-count block solves; Section 3: post-smoother with a start
+vector) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_00501_amd import cloversap as cs
+from paper_2112_00501_amd import synth
+from tests.gpu_helpers import Case, rel
+
+pytestmark = pytest.mark.gpu
+
+BDIM = (4, 4, 4, 4)
+# MR's step lengths are data dependent, so low-precision SAP differs from the
+# FP64 oracle by more than one rounding: bounds from the storage precision.
+TOL_SAP = {cs.F64: 1e-11, cs.F32: 1e-4, cs.F16: 5e-3, cs.BF16: 4e-2}
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return Case((8, 8, 8, 8), 0.3, 0.13, 1.0, 1001)
+
+
+@pytest.fixture(scope="module")
+def noncubic():
+    return Case((8, 8, 16, 8), 0.3, 0.1355, 1.0, 9)
+
+
+@pytest.mark.parametrize("prec", [cs.F64, cs.F32, cs.F16, cs.BF16])
+def test_sap_from_zero(cfg1, noncubic, prec):
+    for c in (cfg1, noncubic):
+        b = synth.source(c.dims, 2001)
+        ref = oracle.sap(c.dims, BDIM, c.U, c.T, c.kappa, 2, 4, b)
+        bd = c.to_dev(b, prec)
+        xd = c.lat.new_field(prec)
+        c.op.sap_smooth(xd, bd, prec, n_cy=2, n_mr=4, x0_is_zero=True)
+        err = rel(c.to_host(xd, prec), ref)
+        print(f"dims={c.dims} prec={prec} sap rel.err={err:.3e}")
+        assert err <= TOL_SAP[prec]
+
+
+@pytest.mark.parametrize("n_cy,n_mr", [(1, 1), (2, 4), (3, 6)])
+def test_sap_with_start_vector(cfg1, n_cy, n_mr):
+    c = cfg1
+    b = synth.source(c.dims, 2002)
+    x0 = 0.3 * synth.source(c.dims, 2003)
+    ref = oracle.sap(c.dims, BDIM, c.U, c.T, c.kappa, n_cy, n_mr, b, x0=x0)
+    for prec in (cs.F64, cs.F32):
+        bd = c.to_dev(b, prec)
+        xd = c.to_dev(x0, prec)
+        c.op.sap_smooth(xd, bd, prec, n_cy=n_cy, n_mr=n_mr, x0_is_zero=False)
+        err = rel(c.to_host(xd, prec), ref)
+        print(f"n_cy={n_cy} n_mr={n_mr} prec={prec} rel.err={err:.3e}")
+        assert err <= TOL_SAP[prec]
+
+
+def test_sap_batched_equals_single(cfg1):
+    c = cfg1
+    bs = synth.source(c.dims, 11, nrhs=2)
+    for prec in (cs.F64, cs.F32):
+        bd = c.to_dev(bs, prec)
+        xd = c.lat.new_field(prec, 2)
+        c.op.sap_smooth(xd, bd, prec, nrhs=2)
+        got = c.to_host(xd, prec, 2)
+        for r in range(2):
+            x1 = c.lat.new_field(prec)
+            c.op.sap_smooth(x1, c.to_dev(bs[r], prec), prec)
+            assert np.array_equal(c.to_host(x1, prec), got[r])
+
+
+def test_sap_rejects_odd_block_count():
+    c = Case((4, 8, 8, 8), 0.3, 0.13, 1.0, 3, oracle_T=False)
+    bd = c.to_dev(synth.source(c.dims, 1), cs.F64)
+    xd = c.lat.new_field(cs.F64)
+    with pytest.raises(cs.CloverSapError) as e:
+        c.op.sap_smooth(xd, bd, cs.F64)
+    assert e.value.status == -2
