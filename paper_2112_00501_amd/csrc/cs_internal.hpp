@@ -34,6 +34,72 @@ namespace cs {
 
 constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
 
+// Tuning knobs (compile-time; the defaults are the measured best on MI355X).
+// Minimum waves per SIMD requested from the register allocator for the
+// operator and smoother kernels (0 = compiler default); XCD-aware ordering of
+// workgroups; non-temporal loads of the fields that are read exactly once
+// (links, clover); the operator's hopping sum as a rolled loop (bounded
+// registers, 4 waves per SIMD) instead of fully unrolled.
+#ifndef CS_DSLASH_WAVES
+#define CS_DSLASH_WAVES 0
+#endif
+#ifndef CS_SAP_WAVES
+#define CS_SAP_WAVES 0
+#endif
+#ifndef CS_XCD_REMAP
+#define CS_XCD_REMAP 1
+#endif
+#ifndef CS_NT_LOADS
+#define CS_NT_LOADS 0
+#endif
+#ifndef CS_DSLASH_ROLLED
+#define CS_DSLASH_ROLLED 1
+#endif
+#if CS_DSLASH_WAVES > 0
+#define CS_DSLASH_BOUNDS __launch_bounds__(256, CS_DSLASH_WAVES)
+#else
+#define CS_DSLASH_BOUNDS __launch_bounds__(256)
+#endif
+#if CS_SAP_WAVES > 0
+#define CS_SAP_BOUNDS __launch_bounds__(256, CS_SAP_WAVES)
+#else
+#define CS_SAP_BOUNDS __launch_bounds__(256)
+#endif
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with its own L2.  Remapping workgroup i to item (i mod 8) * (n / 8) + i / 8
+// gives every XCD one contiguous range of blocks, so blocks that share faces
+// mostly run on the same XCD and meet in the same L2.
+__host__ __device__ __forceinline__ int xcd_remap(int i, int n) {
+#if CS_XCD_REMAP
+    constexpr int NX = 8;
+    if (n % NX != 0) return i;
+    return (i % NX) * (n / NX) + i / NX;
+#else
+    (void)n;
+    return i;
+#endif
+}
+
+// Load of data that is used once per kernel (kept out of the caches' reuse
+// set when CS_NT_LOADS is on).
+template <typename T>
+__device__ __forceinline__ T ld_once(const T* p) {
+#if CS_NT_LOADS
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(T) == 16) {
+        return __builtin_bit_cast(T, __builtin_nontemporal_load((const v4u*)p));
+    } else if constexpr (sizeof(T) == 8) {
+        return __builtin_bit_cast(T, __builtin_nontemporal_load((const v2u*)p));
+    } else {
+        return *p;
+    }
+#else
+    return *p;
+#endif
+}
+
 enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
 
 // ------------------------------------------------------------------ geometry

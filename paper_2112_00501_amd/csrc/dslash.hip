@@ -13,14 +13,14 @@ namespace cs {
 namespace {
 
 template <int PIN, int POUT, int PLINK, bool DAG, bool SUB>
-__global__ __launch_bounds__(BLOCK_SITES) void k_dslash(Geom g, const void* __restrict__ links,
+__global__ CS_DSLASH_BOUNDS void k_dslash(Geom g, const void* __restrict__ links,
                                                         const void* __restrict__ clover, double kappa,
                                                         void* __restrict__ out,
                                                         const void* __restrict__ in,
                                                         const void* __restrict__ sub,
                                                         size_t in_stride, size_t out_stride) {
     using R = typename Arith<PIN>::R;
-    const int blk = blockIdx.x, l = threadIdx.x, r = blockIdx.y;
+    const int blk = xcd_remap(blockIdx.x, g.nblk), l = threadIdx.x, r = blockIdx.y;
     const char* src = (const char*)in + r * in_stride;
     const BlockPos p = block_pos(g, blk);
 
@@ -29,7 +29,8 @@ __global__ __launch_bounds__(BLOCK_SITES) void k_dslash(Geom g, const void* __re
     for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
     GlobalSpinor<PIN, DAG> ld{src, g.nblk};
     GlobalLinks<PLINK> lk{links};
-    hopping_sum<R>(g, p, l, ld, lk, acc);
+    if (CS_DSLASH_ROLLED || PIN == P_F64) hopping_sum_rolled<R>(g, p, l, ld, lk, acc);
+    else hopping_sum<R>(g, p, l, ld, lk, acc);
 
     cpx<R> self[12], res[12];
     ld.load(blk, l, self);

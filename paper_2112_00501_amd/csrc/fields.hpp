@@ -149,12 +149,14 @@ struct LinkIO;
 template <>
 struct LinkIO<P_F64> {
     using R = double;
-    // rows 0 and 1 of U_mu at (blk, l) into u[0..5]
+    // rows 0 and 1 of U_mu at (blk, l) into u[0..5]; ONCE: the load is the
+    // only use of these words in the kernel
+    template <bool ONCE = true>
     __device__ static void load6(const void* base, int blk, int l, int mu, cpx<R>* u) {
         const double2* p = (const double2*)base + ((size_t)blk * 4 + mu) * 6 * BLOCK_SITES + l;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const double2 v = p[k * BLOCK_SITES];
+            const double2 v = ONCE ? ld_once(p + k * BLOCK_SITES) : p[k * BLOCK_SITES];
             u[k] = {v.x, v.y};
         }
     }
@@ -168,11 +170,12 @@ struct LinkIO<P_F64> {
 template <>
 struct LinkIO<P_F32> {
     using R = float;
+    template <bool ONCE = true>
     __device__ static void load6(const void* base, int blk, int l, int mu, cpx<R>* u) {
         const float4* p = (const float4*)base + ((size_t)blk * 4 + mu) * 3 * BLOCK_SITES + l;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float4 v = p[k * BLOCK_SITES];
+            const float4 v = ONCE ? ld_once(p + k * BLOCK_SITES) : p[k * BLOCK_SITES];
             u[2 * k] = {v.x, v.y};
             u[2 * k + 1] = {v.z, v.w};
         }
@@ -189,11 +192,12 @@ struct LinkIO<P_F32> {
 template <int P>
 struct LinkIO16 {
     using R = float;
+    template <bool ONCE = true>
     __device__ static void load6(const void* base, int blk, int l, int mu, cpx<R>* u) {
         const uint2* p = (const uint2*)base + ((size_t)blk * 4 + mu) * 3 * BLOCK_SITES + l;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const uint2 v = p[k * BLOCK_SITES];
+            const uint2 v = ONCE ? ld_once(p + k * BLOCK_SITES) : p[k * BLOCK_SITES];
             float a, b;
             unpack2<P>(v.x, a, b); u[2 * k] = {a, b};
             unpack2<P>(v.y, a, b); u[2 * k + 1] = {a, b};
@@ -216,11 +220,11 @@ template <>
 struct LinkIO<P_BF16> : LinkIO16<P_BF16> {};
 
 // Full 3x3 link (row 2 rebuilt) in arithmetic type R.
-template <int P, typename R>
+template <int P, typename R, bool ONCE = true>
 __device__ __forceinline__ void load_link(const void* base, int blk, int l, int mu, cpx<R>* u) {
     using RS = typename LinkIO<P>::R;
     cpx<RS> t[6];
-    LinkIO<P>::load6(base, blk, l, mu, t);
+    LinkIO<P>::template load6<ONCE>(base, blk, l, mu, t);
 #pragma unroll
     for (int k = 0; k < 6; ++k) u[k] = {(R)t[k].re, (R)t[k].im};
     su3_row2(u);
@@ -235,11 +239,12 @@ struct CloverIO;
 
 template <>
 struct CloverIO<double> {
+    template <bool ONCE = true>
     __device__ static void load(const void* base, int blk, int l, double* c) {
         const double2* p = (const double2*)base + (size_t)blk * 36 * BLOCK_SITES + l;
 #pragma unroll
         for (int k = 0; k < 36; ++k) {
-            const double2 v = p[k * BLOCK_SITES];
+            const double2 v = ONCE ? ld_once(p + k * BLOCK_SITES) : p[k * BLOCK_SITES];
             c[2 * k] = v.x;
             c[2 * k + 1] = v.y;
         }
@@ -247,11 +252,12 @@ struct CloverIO<double> {
 };
 template <>
 struct CloverIO<float> {
+    template <bool ONCE = true>
     __device__ static void load(const void* base, int blk, int l, float* c) {
         const float4* p = (const float4*)base + (size_t)blk * 18 * BLOCK_SITES + l;
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
-            const float4 v = p[k * BLOCK_SITES];
+            const float4 v = ONCE ? ld_once(p + k * BLOCK_SITES) : p[k * BLOCK_SITES];
             c[4 * k] = v.x;
             c[4 * k + 1] = v.y;
             c[4 * k + 2] = v.z;

@@ -88,10 +88,10 @@ __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
 }
 
 template <int P, int PLINK>
-__global__ __launch_bounds__(BLOCK_SITES) void k_sap_halfsweep(
-    Geom g, const void* __restrict__ links, const void* __restrict__ clover, double kappa_d,
-    int colour, int n_mr, int mode, void* __restrict__ x, const void* __restrict__ b,
-    size_t stride) {
+__global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ links,
+                                              const void* __restrict__ clover, double kappa_d,
+                                              int colour, int n_mr, int mode, void* __restrict__ x,
+                                              const void* __restrict__ b, size_t stride) {
     using R = typename Arith<P>::R;
     constexpr bool F32PATH = std::is_same<R, float>::value;
     __shared__ cpx<R> s_rho[12][BLOCK_SITES];
@@ -99,11 +99,12 @@ __global__ __launch_bounds__(BLOCK_SITES) void k_sap_halfsweep(
     __shared__ R s_red[3][4];
 
     const int l = threadIdx.x;
-    const int blk = colour_block(g, colour, blockIdx.x);
+    const int blk = colour_block(g, colour, xcd_remap(blockIdx.x, g.nblk / 2));
     char* xr = (char*)x + blockIdx.y * stride;
     const char* br = (const char*)b + blockIdx.y * stride;
     const BlockPos p = block_pos(g, blk);
     const R kappa = (R)kappa_d;
+    LdsSpinor<R> ls{s_rho};
 
     if constexpr (F32PATH) {
         for (int mu = 0; mu < 4; ++mu) {
@@ -113,48 +114,62 @@ __global__ __launch_bounds__(BLOCK_SITES) void k_sap_halfsweep(
             for (int k = 0; k < 6; ++k) s_lk.u[mu][k][l] = {(float)u[k].re, (float)u[k].im};
         }
     }
+    // The FP32 path keeps the clover term in registers for the MR loop; the
+    // FP64 one re-reads it (it would not fit next to the MR state).  It is
+    // loaded after the hopping sum of the residual so that the two are never
+    // live together.
+    R cl[F32PATH ? 72 : 1];
 
-    // ---- block residual r_B = b_B - (D x)_B
-    cpx<R> rho[12];
+    // ---- block residual r_B = b_B - (D x)_B, stored as rho in LDS
     {
-        using RS = typename SpinorIO<P>::R;
-        cpx<RS> t[12];
-        SpinorIO<P>::load(br, g.nblk, blk, l, t);
+        cpx<R> r[12];
+        {
+            using RS = typename SpinorIO<P>::R;
+            cpx<RS> t[12];
+            SpinorIO<P>::load(br, g.nblk, blk, l, t);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) rho[k] = {(R)t[k].re, (R)t[k].im};
-    }
-    R cl[72];
-    CloverIO<R>::load(clover, blk, l, cl);
-    if (mode != 1) {
-        cpx<R> acc[12];
+            for (int k = 0; k < 12; ++k) r[k] = {(R)t[k].re, (R)t[k].im};
+        }
+        if (mode != 1) {
+            cpx<R> acc[12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
-        GlobalLinks<PLINK> glk{links};
-        if (mode == 0) {
-            GlobalSpinor<P, false> gs{xr, g.nblk};
-            hopping_sum<R>(g, p, l, gs, glk, acc);
-            cpx<R> self[12], cx[12];
-            gs.load(blk, l, self);
-            clover_apply(cl, self, cx);
+            for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+            GlobalLinks<PLINK> glk{links};
+            if (mode == 0) {
+                GlobalSpinor<P, false> gs{xr, g.nblk};
+                hopping_sum_rolled<R>(g, p, l, gs, glk, acc);
+                cpx<R> self[12], cx[12];
+                gs.load(blk, l, self);
+                if constexpr (F32PATH) {
+                    CloverIO<R>::load(clover, blk, l, cl);
+                    clover_apply(cl, self, cx);
+                } else {
+                    R c2[72];
+                    CloverIO<R>::template load<false>(clover, blk, l, c2);
+                    clover_apply(c2, self, cx);
+                }
 #pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = {cx[k].re - kappa * acc[k].re, cx[k].im - kappa * acc[k].im};
-        } else {
-            OutsideSpinor<P> os{xr, g.nblk};
-            hopping_sum<R>(g, p, l, os, glk, acc);
+                for (int k = 0; k < 12; ++k) acc[k] = {cx[k].re - kappa * acc[k].re, cx[k].im - kappa * acc[k].im};
+            } else {
+                OutsideSpinor<P> os{xr, g.nblk};
+                hopping_sum_rolled<R>(g, p, l, os, glk, acc);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = {-kappa * acc[k].re, -kappa * acc[k].im};
+                for (int k = 0; k < 12; ++k) acc[k] = {-kappa * acc[k].re, -kappa * acc[k].im};
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) r[k] = r[k] - acc[k];
         }
 #pragma unroll
-        for (int k = 0; k < 12; ++k) rho[k] = rho[k] - acc[k];
+        for (int k = 0; k < 12; ++k) s_rho[k][l] = r[k];
     }
-#pragma unroll
-    for (int k = 0; k < 12; ++k) s_rho[k][l] = rho[k];
+    if constexpr (F32PATH) {
+        if (mode != 0) CloverIO<R>::load(clover, blk, l, cl);
+    }
 
-    // ---- MR on the Dirichlet block operator
+    // ---- MR on the Dirichlet block operator; rho lives in LDS only
     cpx<R> delta[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) delta[k] = {(R)0, (R)0};
-    LdsSpinor<R> ls{s_rho};
     for (int it = 0; it < n_mr; ++it) {
         __syncthreads();
         cpx<R> q[12];
@@ -166,19 +181,23 @@ __global__ __launch_bounds__(BLOCK_SITES) void k_sap_halfsweep(
                 LdsLinks lk{&s_lk};
                 hopping_sum<R>(g, p, l, ls, lk, acc);
             } else {
-                GlobalLinks<PLINK> lk{links};
-                hopping_sum<R>(g, p, l, ls, lk, acc);
+                GlobalLinks<PLINK, false> lk{links};
+                hopping_sum_rolled<R>(g, p, l, ls, lk, acc);
             }
+            cpx<R> rho[12];
+            ls.load_nb(0, l, true, rho);
             if constexpr (F32PATH) {
                 clover_apply(cl, rho, q);
-            } else {  // double clover does not fit in registers next to the MR state
+            } else {
                 R c2[72];
-                CloverIO<R>::load(clover, blk, l, c2);
+                CloverIO<R>::template load<false>(clover, blk, l, c2);
                 clover_apply(c2, rho, q);
             }
 #pragma unroll
             for (int k = 0; k < 12; ++k) q[k] = {q[k].re - kappa * acc[k].re, q[k].im - kappa * acc[k].im};
         }
+        cpx<R> rho[12];
+        ls.load_nb(0, l, true, rho);
         R qq = 0, qr_re = 0, qr_im = 0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
@@ -202,7 +221,6 @@ __global__ __launch_bounds__(BLOCK_SITES) void k_sap_halfsweep(
             t.re = fma(alpha.im, q[k].im, t.re);
             t.im = fma(-alpha.re, q[k].im, t.im);
             t.im = fma(-alpha.im, q[k].re, t.im);
-            rho[k] = t;
             s_rho[k][l] = t;
         }
     }
