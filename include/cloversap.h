@@ -189,13 +189,41 @@ void cs_solver_params_default(cs_solver_params* p);
 int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
                  const void* b, int nrhs, cs_solver_stats* stats, void* stream);
 
+/* Solve D^dag x = b (the adjoint system of the backward pass) with the same
+ * method: D^dag = gamma5 D gamma5, so D (gamma5 x) = gamma5 b is solved by
+ * cs_gcr_solve's algorithm.  Same arguments and ownership as cs_gcr_solve;
+ * one extra FP64 field of workspace is kept with the clover handle. */
+int cs_gcr_solve_dag(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
+                     const void* b, int nrhs, cs_solver_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------- gradient */
+
+/* Gradient with respect to the links of a real function L of x = D^{-1} b.
+ * Given x (the solution) and y = D^{-dag} eta, where eta is dL/dx in the
+ * convention dL = Re(eta^dag dx), every change dD of the operator changes L
+ * by -Re(y^dag dD x).  With links varied as U_mu(x) -> exp(i w T^a) U_mu(x),
+ * T^a = lambda^a / 2 (Gell-Mann), this computes g_{mu,a}(x) = dL/dw for the
+ * hopping term and the clover term of the paper's Eq. (1) (Section 2; the
+ * clover term through the derivative of every plaquette leaf of F).
+ *   x, y     CS_F64 internal fields (one right-hand side each)
+ *   g_lie    device, double [V][4][8] in canonical site order, or NULL
+ *   grad_U   device, complex128 [V][4][3][3], or NULL: the tangent-space
+ *            gradient G = 2 i (sum_a g_a T^a) U, which satisfies
+ *            dL = Re tr(G^dag dU) for every dU = i X U, X Hermitian
+ *            traceless (the gradient of any SU(3)-valued parametrisation).
+ * Needs 864 bytes per site of device workspace (kept with the clover
+ * handle).  Asynchronous on the stream. */
+int cs_force(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_lie,
+             void* grad_U, void* stream);
+
 /* -------------------------------------------------------------- profiling */
 
 /* When enabled, every kernel launch of the library is bracketed by HIP
  * events on the stream it runs on.  cs_profile_query returns the number of
  * launches and their summed duration (ms) for a kernel family name (one of
  * "dslash", "sap_halfsweep", "blas", "convert", "clover_build"), after
- * synchronising the recorded events.  cs_profile_reset clears the counters. */
+ * synchronising the recorded events ("force" covers cs_force).
+ * cs_profile_reset clears the counters. */
 int cs_profile_enable(int on);
 int cs_profile_query(const char* name, long long* count, double* total_ms);
 int cs_profile_reset(void);

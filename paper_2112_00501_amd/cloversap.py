@@ -46,8 +46,8 @@ EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_des
             "cs_lattice_volume", "cs_field_bytes", "cs_field_import", "cs_field_export",
             "cs_gauge_create", "cs_gauge_destroy", "cs_clover_create", "cs_clover_destroy",
             "cs_clover_export", "cs_apply_D", "cs_apply_Ddag", "cs_sap_smooth",
-            "cs_solver_params_default", "cs_gcr_solve", "cs_profile_enable", "cs_profile_query",
-            "cs_profile_reset"]
+            "cs_solver_params_default", "cs_gcr_solve", "cs_gcr_solve_dag", "cs_force",
+            "cs_profile_enable", "cs_profile_query", "cs_profile_reset"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -83,6 +83,8 @@ def load_library(path: str = LIB_PATH):
     L.cs_solver_params_default.argtypes = [C.POINTER(_Params)]
     L.cs_solver_params_default.restype = None
     L.cs_gcr_solve.argtypes = [P, P, C.POINTER(_Params), P, P, I, C.POINTER(_Stats), P]
+    L.cs_gcr_solve_dag.argtypes = [P, P, C.POINTER(_Params), P, P, I, C.POINTER(_Stats), P]
+    L.cs_force.argtypes = [P, P, P, P, P, P, P]
     L.cs_profile_enable.argtypes = [I]
     L.cs_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
     L.cs_profile_reset.argtypes = []
@@ -224,17 +226,32 @@ class Operator:
                                   _stream(stream)), "cs_sap_smooth")
         return x
 
-    def gcr_solve(self, x, b, params: "SolverParams", nrhs=1, stream=None, allow_fail=False):
-        """x, b: CS_F64 internal fields.  Returns (status, [stats per rhs])."""
+    def gcr_solve(self, x, b, params: "SolverParams", nrhs=1, stream=None, allow_fail=False,
+                  dagger=False):
+        """x, b: CS_F64 internal fields.  Solves D x = b (D^dag x = b with
+        dagger).  Returns (status, [stats per rhs])."""
         p = params.to_c()
         stats = (_Stats * nrhs)()
-        st = _lib.cs_gcr_solve(self.gauge.handle, self.clover.handle, C.byref(p), _ptr(x), _ptr(b),
-                               nrhs, stats, _stream(stream))
+        fn = _lib.cs_gcr_solve_dag if dagger else _lib.cs_gcr_solve
+        st = fn(self.gauge.handle, self.clover.handle, C.byref(p), _ptr(x), _ptr(b), nrhs, stats,
+                _stream(stream))
         if not allow_fail:
-            _check(st, "cs_gcr_solve")
+            _check(st, "cs_gcr_solve_dag" if dagger else "cs_gcr_solve")
         out = [dict(iters=s.iters, restarts=s.restarts, true_relres=s.true_relres,
                     seconds=s.seconds) for s in stats]
         return st, out
+
+    def force(self, x, y, want_lie=True, want_grad=False, stream=None):
+        """Link gradient of L given x = D^-1 b and y = D^-dag dL/dx (CS_F64
+        internal fields).  Returns (g_lie [V][4][8] float64 or None,
+        grad_U [V][4][3][3] complex128 or None), on the GPU."""
+        V = self.lat.volume
+        g = torch.empty((V, 4, 8), dtype=torch.float64, device="cuda") if want_lie else None
+        G = torch.empty((V, 4, 3, 3), dtype=torch.complex128, device="cuda") if want_grad else None
+        _check(_lib.cs_force(self.gauge.handle, self.clover.handle, _ptr(x), _ptr(y),
+                             None if g is None else _ptr(g), None if G is None else _ptr(G),
+                             _stream(stream)), "cs_force")
+        return g, G
 
 
 @dataclass
@@ -267,3 +284,39 @@ def profile_query(name: str):
     ms = C.c_double(0)
     _check(_lib.cs_profile_query(name.encode(), C.byref(n), C.byref(ms)), "cs_profile_query")
     return int(n.value), float(ms.value)
+
+
+class CloverSolve(torch.autograd.Function):
+    """x = D(U)^{-1} b as a differentiable torch operation.
+
+    forward(U, b, lat, kappa, csw, params): U complex128 [V][4][3][3] (SU(3)),
+    b complex128 [V][4][3], both on the GPU; returns x (complex128).
+    backward: the adjoint solve y = D^{-dag} grad_x (D^dag = gamma5 D gamma5,
+    same solver), grad_b = y, and grad_U from the force kernel: the
+    tangent-space gradient 2 i (sum_a g_a T^a) U, exact for any SU(3)-valued
+    parametrisation of U.  The forward solution is kept (one FP64 field) for
+    the backward pass.
+    """
+
+    @staticmethod
+    def forward(ctx, U, b, lat, kappa, csw, params=None):
+        params = params or SolverParams(inner_prec=F32, basis_prec=F32)
+        op = Operator(lat, U.detach().contiguous(), kappa, csw)
+        bd = lat.import_field(b.detach().contiguous(), F64)
+        xd = lat.new_field(F64).zero_()
+        op.gcr_solve(xd, bd, params)
+        ctx.op, ctx.lat, ctx.params = op, lat, params
+        ctx.xd = xd
+        return lat.export_field(xd, F64)
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        op, lat = ctx.op, ctx.lat
+        gd = lat.import_field(grad_x.detach().contiguous().to(torch.complex128), F64)
+        yd = lat.new_field(F64).zero_()
+        op.gcr_solve(yd, gd, ctx.params, dagger=True)
+        grad_b = lat.export_field(yd, F64) if ctx.needs_input_grad[1] else None
+        grad_U = None
+        if ctx.needs_input_grad[0]:
+            _, grad_U = op.force(ctx.xd, yd, want_lie=False, want_grad=True)
+        return grad_U, grad_b, None, None, None, None

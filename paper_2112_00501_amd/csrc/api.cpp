@@ -31,6 +31,8 @@ struct cs_clover_s {
     void* c64 = nullptr;
     void* c32 = nullptr;
     std::unique_ptr<cs::GcrWork> work;
+    void* force_H = nullptr;   // insertion matrices of the force, 864 B/site
+    void* dag_tmp = nullptr;   // one FP64 field for the adjoint solve
 };
 
 namespace {
@@ -273,6 +275,8 @@ int cs_clover_create(cs_gauge g, double kappa, double csw, void* stream, cs_clov
 int cs_clover_destroy(cs_clover c) {
     if (!c) return ok();
     c->work.reset();
+    if (c->force_H) hipFree(c->force_H);
+    if (c->dag_tmp) hipFree(c->dag_tmp);
     if (c->c64) hipFree(c->c64);
     if (c->c32) hipFree(c->c32);
     delete c;
@@ -348,8 +352,8 @@ void cs_solver_params_default(cs_solver_params* p) {
     p->reliable_delta = 1e-5;
 }
 
-int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
-                 cs_solver_stats* stats, void* stream) {
+static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
+                      cs_solver_stats* stats, void* stream, bool dagger) {
     int st = check_op(g, c);
     if (st) return st;
     if (!p || !x || !b) return fail(CS_ERR_NULL, "params, x and b must be non-NULL");
@@ -378,14 +382,21 @@ int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, co
         c->work->release();
         return fail(CS_ERR_ALLOC, "solver workspace: %s", hipGetErrorString(e));
     }
+    if (dagger && !c->dag_tmp && hipMalloc(&c->dag_tmp, f64) != hipSuccess) {
+        c->dag_tmp = nullptr;
+        return fail(CS_ERR_ALLOC, "adjoint-solve workspace");
+    }
     const cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
                            p->reliable_delta};
     const cs::OpData op = make_op(g, c);
     int first_bad = CS_OK;
     for (int r = 0; r < nrhs; ++r) {
         cs::GcrResult res{};
-        e = cs::gcr_solve_one(op, gp, *c->work, (char*)x + r * f64, (const char*)b + r * f64, &res,
-                              (hipStream_t)stream);
+        void* xr = (char*)x + r * f64;
+        const void* br = (const char*)b + r * f64;
+        e = dagger ? cs::gcr_solve_one_dag(op, gp, *c->work, xr, br, c->dag_tmp, &res, (hipStream_t)stream)
+                   : cs::gcr_solve_one(op, gp, *c->work, xr, br, &res, (hipStream_t)stream);
+        if (e == hipSuccess && dagger) e = hipStreamSynchronize((hipStream_t)stream);
         if (e != hipSuccess) return fail(CS_ERR_HIP, "solve: %s", hipGetErrorString(e));
         if (stats) {
             stats[r].iters = res.iters;
@@ -396,6 +407,30 @@ int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, co
         if (res.status != cs::GCR_OK && first_bad == CS_OK) first_bad = res.status;
     }
     if (first_bad != CS_OK) return fail(first_bad, "%s", cs_strerror(first_bad));
+    return ok();
+}
+
+int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
+                 cs_solver_stats* stats, void* stream) {
+    return gcr_common(g, c, p, x, b, nrhs, stats, stream, false);
+}
+
+int cs_gcr_solve_dag(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
+                     cs_solver_stats* stats, void* stream) {
+    return gcr_common(g, c, p, x, b, nrhs, stats, stream, true);
+}
+
+int cs_force(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_lie, void* grad_U, void* stream) {
+    int st = check_op(g, c);
+    if (st) return st;
+    if (!x || !y) return fail(CS_ERR_NULL, "x and y must be non-NULL");
+    if (!g_lie && !grad_U) return fail(CS_ERR_NULL, "at least one of g_lie and grad_U must be non-NULL");
+    if (!c->force_H && hipMalloc(&c->force_H, (size_t)864 * g->g.V) != hipSuccess) {
+        c->force_H = nullptr;
+        return fail(CS_ERR_ALLOC, "force workspace (%zu bytes)", (size_t)864 * g->g.V);
+    }
+    CS_HIP(cs::launch_force(g->g, g->links[cs::P_F64], c->kappa, c->csw, x, y, c->force_H, g_lie, grad_U,
+                            (hipStream_t)stream));
     return ok();
 }
 

@@ -71,6 +71,15 @@ __global__ __launch_bounds__(TPB) void k_convert(Geom g, void* dst, const void* 
     }
 }
 
+__global__ __launch_bounds__(TPB) void k_gamma5(Geom g, void* dst, const void* src) {
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> c[12];
+        ld64<P_F64>(src, g.nblk, blk, threadIdx.x, c);
+        negate_lower(c);
+        st64<P_F64>(dst, g.nblk, blk, threadIdx.x, c);
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_norm2_f64(Geom g, const void* v, double2* partials) {
     cpx<double> acc[1] = {{0.0, 0.0}};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
@@ -253,6 +262,12 @@ hipError_t blas_convert(const BlasCtx& c, int dst_prec, void* dst, int src_prec,
     case P_BF16: return convert_from<P_BF16>(c, dst, src_prec, src, scale, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t blas_gamma5(const BlasCtx& c, void* dst, const void* src, hipStream_t s) {
+    ProfScope ps("blas", s);
+    hipLaunchKernelGGL(k_gamma5, dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, dst, src);
+    return hipGetLastError();
 }
 
 hipError_t blas_norm_to_scalars(const BlasCtx& c, const void* v, hipStream_t s) {

@@ -35,6 +35,8 @@ struct BlasCtx {
 // dst = scale * src (scale: device pointer, or nullptr for 1)
 hipError_t blas_convert(const BlasCtx& c, int dst_prec, void* dst, int src_prec, const void* src,
                         const double* scale, hipStream_t s);
+// dst = gamma5 src (F64 fields; dst may equal src)
+hipError_t blas_gamma5(const BlasCtx& c, void* dst, const void* src, hipStream_t s);
 // |v|^2 -> sc->rnorm2 and sc->inv_rnorm (v is F64)
 hipError_t blas_norm_to_scalars(const BlasCtx& c, const void* v, hipStream_t s);
 // beta_jk = <w_j_hat, w_k> for j < k (W stored unnormalised, w_j_hat = W_j * inv_nu_j);

@@ -166,6 +166,25 @@ __host__ __device__ __forceinline__ int colour_block(const Geom& g, int colour, 
     return bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
 }
 
+// Internal (blk, l) of the site with global coordinates c (already wrapped).
+__device__ __forceinline__ void site_to_internal(const Geom& g, const int* c, int* blk, int* l) {
+    *blk = (c[0] >> 2) + g.NB[0] * ((c[1] >> 2) + g.NB[1] * ((c[2] >> 2) + g.NB[2] * (c[3] >> 2)));
+    *l = (c[0] & 3) + 4 * ((c[1] & 3) + 4 * ((c[2] & 3) + 4 * (c[3] & 3)));
+}
+
+// Global coordinates of (blk, l).
+__device__ __forceinline__ void internal_coords(const Geom& g, int blk, int l, int* c) {
+    int r = blk;
+    const int bx = r % g.NB[0]; r /= g.NB[0];
+    const int by = r % g.NB[1]; r /= g.NB[1];
+    const int bz = r % g.NB[2];
+    const int bt = r / g.NB[2];
+    c[0] = bx * 4 + (l & 3);
+    c[1] = by * 4 + ((l >> 2) & 3);
+    c[2] = bz * 4 + ((l >> 4) & 3);
+    c[3] = bt * 4 + (l >> 6);
+}
+
 // Canonical site index of (blk, l).
 __device__ __forceinline__ long long canonical_site(const Geom& g, int blk, int l) {
     const BlockPos p = block_pos(g, blk);
@@ -286,6 +305,11 @@ hipError_t launch_dslash(const OpData& op, int in_prec, int out_prec, int link_p
 // 1: x is zero everywhere (r = b); 2: x is zero on the blocks of this colour.
 hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode,
                                 void* x, const void* b, int nrhs, hipStream_t s);
+
+// force.hip: g_{mu,a}(x) = dL/dw of L with dL = -Re(y^dag dD x); either output
+// may be null.  Hbuf holds 864 bytes per site (insertion matrices).
+hipError_t launch_force(const Geom& g, const void* links64, double kappa, double csw, const void* x,
+                        const void* y, void* Hbuf, double* glie, void* gradU, hipStream_t s);
 
 // blas.hip
 struct BlasWork;  // defined in blas.hip

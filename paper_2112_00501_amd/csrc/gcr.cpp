@@ -200,4 +200,14 @@ hipError_t gcr_solve_one(const OpData& op, const GcrParams& p, GcrWork& w, void*
     return hipSuccess;
 }
 
+hipError_t gcr_solve_one_dag(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b,
+                             void* tmp, GcrResult* res, hipStream_t s) {
+    // D^dag = g5 D g5:  D^dag x = b  <=>  D (g5 x) = g5 b
+    const BlasCtx bc{op.g, w.partials, w.sc};
+    GCR_CHK(blas_gamma5(bc, tmp, b, s));
+    GCR_CHK(blas_gamma5(bc, x, x, s));  // start vector g5 x0
+    GCR_CHK(gcr_solve_one(op, p, w, x, tmp, res, s));
+    return blas_gamma5(bc, x, x, s);
+}
+
 }  // namespace cs

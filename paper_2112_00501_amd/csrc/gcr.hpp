@@ -39,5 +39,8 @@ struct GcrWork {
 
 hipError_t gcr_solve_one(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b,
                          GcrResult* res, hipStream_t s);
+// Solve D^dag x = b as D (g5 x) = g5 b; tmp is one F64 field of workspace.
+hipError_t gcr_solve_one_dag(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b,
+                             void* tmp, GcrResult* res, hipStream_t s);
 
 }  // namespace cs

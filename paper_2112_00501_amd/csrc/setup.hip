@@ -3,26 +3,13 @@
 // paper leaves building C from the gauge field to the user), and conversion
 // of spinors between the canonical and the internal layouts.
 #include "fields.hpp"
+#include "su3.hpp"
 
 namespace cs {
 
 namespace {
 
 constexpr int TPB = BLOCK_SITES;
-
-// Internal (blk, l) of the site with global coordinates c (already wrapped).
-__device__ __forceinline__ void site_to_internal(const Geom& g, const int* c, int* blk, int* l) {
-    *blk = (c[0] >> 2) + g.NB[0] * ((c[1] >> 2) + g.NB[1] * ((c[2] >> 2) + g.NB[2] * (c[3] >> 2)));
-    *l = (c[0] & 3) + 4 * ((c[1] & 3) + 4 * ((c[2] & 3) + 4 * (c[3] & 3)));
-}
-
-__device__ __forceinline__ void internal_coords(const Geom& g, int blk, int l, int* c) {
-    const BlockPos p = block_pos(g, blk);
-    c[0] = p.bc[0] * 4 + (l & 3);
-    c[1] = p.bc[1] * 4 + ((l >> 2) & 3);
-    c[2] = p.bc[2] * 4 + ((l >> 4) & 3);
-    c[3] = p.bc[3] * 4 + (l >> 6);
-}
 
 __global__ __launch_bounds__(TPB) void k_import_links(Geom g, const double2* __restrict__ U,
                                                       void* l64, void* l32, void* l16, void* lbf) {
@@ -40,55 +27,7 @@ __global__ __launch_bounds__(TPB) void k_import_links(Geom g, const double2* __r
     }
 }
 
-// 3x3 complex helpers (double)
 using C64 = cpx<double>;
-
-__device__ __forceinline__ void m3_mul(const C64* a, const C64* b, C64* c) {
-    C64 t[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            C64 s = {0.0, 0.0};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac(s, a[i * 3 + k], b[k * 3 + j]);
-            t[i * 3 + j] = s;
-        }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) c[i] = t[i];
-}
-
-// c = a * b^dag
-__device__ __forceinline__ void m3_mul_nd(const C64* a, const C64* b, C64* c) {
-    C64 t[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            C64 s = {0.0, 0.0};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac(s, a[i * 3 + k], conj(b[j * 3 + k]));
-            t[i * 3 + j] = s;
-        }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) c[i] = t[i];
-}
-
-// c = a^dag * b
-__device__ __forceinline__ void m3_mul_dn(const C64* a, const C64* b, C64* c) {
-    C64 t[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            C64 s = {0.0, 0.0};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac_conj(s, a[k * 3 + i], b[k * 3 + j]);
-            t[i * 3 + j] = s;
-        }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) c[i] = t[i];
-}
 
 __device__ __forceinline__ void link_at(const Geom& g, const void* links, const int* x, int da,
                                         int db, int mu, int nu, int dir, C64* u) {
@@ -131,15 +70,7 @@ __device__ void leaf_sum(const Geom& g, const void* links, const int* x, int mu,
     link_at(g, links, x, -1, 0, mu, nu, mu, a);
     link_at(g, links, x, -1, -1, mu, nu, nu, b);
     m3_mul(b, a, p);  // (U_nu U_mu)^dag = U_mu^dag U_nu^dag
-    {
-        C64 t[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) t[i * 3 + j] = conj(p[j * 3 + i]);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) p[i] = t[i];
-    }
+    m3_dag(p, p);
     link_at(g, links, x, -1, -1, mu, nu, mu, a);
     m3_mul(p, a, p);
     link_at(g, links, x, 0, -1, mu, nu, nu, a);
