@@ -136,6 +136,26 @@ int cs_apply_D(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in,
 int cs_apply_Ddag(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in,
                   int nrhs, void* stream);
 
+/* ------------------------------------------------- multi-RHS launch shapes */
+
+/* Launch shape of the multi-right-hand-side operator and SAP kernels:
+ * rhs_tile right-hand sides per workgroup (the block's links and clover term
+ * are read once per tile), and, when persistent_wgs > 0, a persistent launch
+ * of that many workgroups striding over the (block, tile) work items. */
+typedef struct {
+    int rhs_tile;
+    int persistent_wgs;
+} cs_launch_config;
+
+/* Time the SAP half-sweep and the operator for rhs_tile in {1, 4, 8, 12}
+ * (up to nrhs) and for grid and persistent launches, on nrhs right-hand
+ * sides of precision prec, and return the fastest shapes (either pointer may
+ * be NULL).  The result is cached with the clover handle and used by
+ * cs_gcr_solve when params.rhs_tile is 0.  Allocates and frees scratch
+ * fields; synchronises the stream. */
+int cs_autotune(cs_gauge g, cs_clover c, cs_prec prec, int nrhs, cs_launch_config* sap,
+                cs_launch_config* dslash, void* stream);
+
 /* -------------------------------------------------------------------- SAP */
 
 /* Multiplicative Schwarz smoother (paper Section 2: domains updated in turn
@@ -153,6 +173,15 @@ int cs_apply_Ddag(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* 
 int cs_sap_smooth(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b,
                   int n_cy, int n_mr, int x0_is_zero, int nrhs, void* stream);
 
+/* cs_sap_smooth and cs_apply_D with an explicit multi-right-hand-side launch
+ * shape (cfg NULL: one right-hand side per workgroup).  Results are bitwise
+ * identical to the untiled calls. */
+int cs_sap_smooth_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b,
+                      int n_cy, int n_mr, int x0_is_zero, int nrhs,
+                      const cs_launch_config* cfg, void* stream);
+int cs_apply_D_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in,
+                   int nrhs, const cs_launch_config* cfg, void* stream);
+
 /* ------------------------------------------------------------------ solver */
 
 typedef struct {
@@ -163,6 +192,10 @@ typedef struct {
     cs_prec inner_prec;   /* precision of the SAP preconditioner and of w = D z   */
     cs_prec basis_prec;   /* storage of the Krylov basis w_k: CS_F64 or CS_F32    */
     double reliable_delta;/* restart early when |r_iter| < delta |r_true| (0: off) */
+    int rhs_tile;         /* right-hand sides per workgroup in the batched SAP and
+                             operator launches (0: autotuned, see cs_autotune)    */
+    int use_graph;        /* 1: capture each iteration's kernels as a HIP graph
+                             once and replay it (ignored while profiling)         */
 } cs_solver_params;
 
 typedef struct {
@@ -173,7 +206,8 @@ typedef struct {
 } cs_solver_stats;
 
 /* Fill p with the defaults: restart 16, max_iter 2000, n_cy 2, n_mr 4,
- * tol 1e-10, inner CS_F32, basis CS_F32, reliable_delta 1e-5. */
+ * tol 1e-10, inner CS_F32, basis CS_F32, reliable_delta 1e-5, rhs_tile 0,
+ * use_graph 1. */
 void cs_solver_params_default(cs_solver_params* p);
 
 /* Solve D x = b by flexible GCR (outer arithmetic, reductions and the
@@ -182,10 +216,15 @@ void cs_solver_params_default(cs_solver_params* p);
  * preconditioner; mixed precision is recovered by recomputing the true
  * residual in FP64 at every restart, the iterative-refinement scheme of the
  * paper's Section 2).  x and b are nrhs consecutive CS_F64 internal fields;
- * x holds x0 on entry.  stats (host, may be NULL) has nrhs entries.  Device
- * workspace is allocated on first use and kept with the clover handle.
- * Returns CS_OK when every right-hand side converged, else the first
- * non-zero status. */
+ * x holds x0 on entry.  The right-hand sides advance together through
+ * batched SAP and operator launches (links and clover read once per tile of
+ * right-hand sides); each keeps its own scalars and stopping decisions, so
+ * every column follows the iterations of a single-right-hand-side solve.
+ * stats (host, may be NULL) has nrhs entries; seconds is the wall time of the
+ * whole call.  Device workspace (2 m nrhs fields plus scalars) is allocated on
+ * first use and kept with the clover handle.  The work runs on a private
+ * stream after the caller's stream has been synchronised.  Returns CS_OK when
+ * every right-hand side converged, else the first non-zero status. */
 int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
                  const void* b, int nrhs, cs_solver_stats* stats, void* stream);
 

@@ -32,7 +32,15 @@ class CloverSapError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iter", C.c_int), ("n_cy", C.c_int), ("n_mr", C.c_int),
                 ("tol", C.c_double), ("inner_prec", C.c_int), ("basis_prec", C.c_int),
-                ("reliable_delta", C.c_double)]
+                ("reliable_delta", C.c_double), ("rhs_tile", C.c_int), ("use_graph", C.c_int)]
+
+
+class LaunchConfig(C.Structure):
+    """Multi-right-hand-side launch shape (cs_launch_config)."""
+    _fields_ = [("rhs_tile", C.c_int), ("persistent_wgs", C.c_int)]
+
+    def __repr__(self):
+        return f"LaunchConfig(rhs_tile={self.rhs_tile}, persistent_wgs={self.persistent_wgs})"
 
 
 class _Stats(C.Structure):
@@ -45,9 +53,10 @@ _lib = None
 EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_destroy",
             "cs_lattice_volume", "cs_field_bytes", "cs_field_import", "cs_field_export",
             "cs_gauge_create", "cs_gauge_destroy", "cs_clover_create", "cs_clover_destroy",
-            "cs_clover_export", "cs_apply_D", "cs_apply_Ddag", "cs_sap_smooth",
-            "cs_solver_params_default", "cs_gcr_solve", "cs_gcr_solve_dag", "cs_force",
-            "cs_profile_enable", "cs_profile_query", "cs_profile_reset"]
+            "cs_clover_export", "cs_apply_D", "cs_apply_Ddag", "cs_apply_D_cfg", "cs_sap_smooth",
+            "cs_sap_smooth_cfg", "cs_autotune", "cs_solver_params_default", "cs_gcr_solve",
+            "cs_gcr_solve_dag", "cs_force", "cs_profile_enable", "cs_profile_query",
+            "cs_profile_reset"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -80,6 +89,9 @@ def load_library(path: str = LIB_PATH):
     L.cs_apply_D.argtypes = [P, P, I, P, P, I, P]
     L.cs_apply_Ddag.argtypes = [P, P, I, P, P, I, P]
     L.cs_sap_smooth.argtypes = [P, P, I, P, P, I, I, I, I, P]
+    L.cs_sap_smooth_cfg.argtypes = [P, P, I, P, P, I, I, I, I, C.POINTER(LaunchConfig), P]
+    L.cs_apply_D_cfg.argtypes = [P, P, I, P, P, I, C.POINTER(LaunchConfig), P]
+    L.cs_autotune.argtypes = [P, P, I, I, C.POINTER(LaunchConfig), C.POINTER(LaunchConfig), P]
     L.cs_solver_params_default.argtypes = [C.POINTER(_Params)]
     L.cs_solver_params_default.restype = None
     L.cs_gcr_solve.argtypes = [P, P, C.POINTER(_Params), P, P, I, C.POINTER(_Stats), P]
@@ -215,6 +227,25 @@ class Operator:
                                nrhs, _stream(stream)), "cs_apply_D")
         return out
 
+    def apply_D_cfg(self, out, inp, prec, nrhs, cfg: "LaunchConfig", stream=None):
+        _check(_lib.cs_apply_D_cfg(self.gauge.handle, self.clover.handle, prec, _ptr(out), _ptr(inp),
+                                   nrhs, C.byref(cfg), _stream(stream)), "cs_apply_D_cfg")
+        return out
+
+    def sap_smooth_cfg(self, x, b, prec, nrhs, cfg: "LaunchConfig", n_cy=2, n_mr=4,
+                       x0_is_zero=True, stream=None):
+        _check(_lib.cs_sap_smooth_cfg(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
+                                      int(n_cy), int(n_mr), int(bool(x0_is_zero)), nrhs,
+                                      C.byref(cfg), _stream(stream)), "cs_sap_smooth_cfg")
+        return x
+
+    def autotune(self, prec, nrhs, stream=None):
+        """Fastest (SAP, operator) launch shapes for nrhs right-hand sides."""
+        a, b = LaunchConfig(), LaunchConfig()
+        _check(_lib.cs_autotune(self.gauge.handle, self.clover.handle, prec, nrhs, C.byref(a),
+                                C.byref(b), _stream(stream)), "cs_autotune")
+        return a, b
+
     def apply_Ddag(self, out, inp, prec, nrhs=1, stream=None):
         _check(_lib.cs_apply_Ddag(self.gauge.handle, self.clover.handle, prec, _ptr(out),
                                   _ptr(inp), nrhs, _stream(stream)), "cs_apply_Ddag")
@@ -264,10 +295,13 @@ class SolverParams:
     inner_prec: int = F32
     basis_prec: int = F32
     reliable_delta: float = 1e-5
+    rhs_tile: int = 0
+    use_graph: bool = True
 
     def to_c(self) -> _Params:
         return _Params(self.restart, self.max_iter, self.n_cy, self.n_mr, self.tol,
-                       self.inner_prec, self.basis_prec, self.reliable_delta)
+                       self.inner_prec, self.basis_prec, self.reliable_delta, self.rhs_tile,
+                       int(bool(self.use_graph)))
 
 
 def profile_enable(on: bool = True):

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/cloversap.h"
+#include "blas.hpp"
 #include "gcr.hpp"
 
 struct cs_lattice_s {
@@ -32,7 +33,10 @@ struct cs_clover_s {
     void* c32 = nullptr;
     std::unique_ptr<cs::GcrWork> work;
     void* force_H = nullptr;   // insertion matrices of the force, 864 B/site
-    void* dag_tmp = nullptr;   // one FP64 field for the adjoint solve
+    void* dag_tmp = nullptr;   // FP64 fields for the adjoint solve
+    int dag_tmp_nrhs = 0;
+    // autotuned multi-right-hand-side launch shapes, keyed by (precision, nrhs)
+    std::map<std::pair<int, int>, std::pair<cs::LaunchCfg, cs::LaunchCfg>> tuned;
 };
 
 namespace {
@@ -289,31 +293,53 @@ int cs_clover_export(cs_clover c, void* dst, void* stream) {
     return ok();
 }
 
-static int apply(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in, int nrhs, void* stream,
-                 bool dagger) {
+static bool overlap(const void* a, const void* b, size_t bytes) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+static cs::LaunchCfg to_cfg(const cs_launch_config* c) {
+    cs::LaunchCfg r;
+    if (c) {
+        r.rhs_tile = c->rhs_tile < 1 ? 1 : c->rhs_tile;
+        r.persistent_wgs = c->persistent_wgs < 0 ? 0 : c->persistent_wgs;
+    }
+    return r;
+}
+
+static int apply(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in, int nrhs,
+                 const cs_launch_config* cfg, void* stream, bool dagger) {
     int st = check_op(g, c);
     if (st) return st;
     if (!out || !in) return fail(CS_ERR_NULL, "out and in must be non-NULL");
     if (!valid_prec(prec)) return fail(CS_ERR_PRECISION, "unknown precision %d", (int)prec);
     if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
     const size_t bytes = cs::spinor_bytes_per_site(prec) * (size_t)g->g.V * nrhs;
-    const char* i0 = (const char*)in;
-    const char* o0 = (const char*)out;
-    if (i0 < o0 + bytes && o0 < i0 + bytes) return fail(CS_ERR_INVALID, "out and in overlap");
-    CS_HIP(cs::launch_dslash(make_op(g, c), prec, prec, prec, dagger, out, in, nullptr, nrhs, (hipStream_t)stream));
+    if (overlap(in, out, bytes)) return fail(CS_ERR_INVALID, "out and in overlap");
+    const cs::LaunchCfg lc = to_cfg(cfg);
+    if (lc.rhs_tile > 1 || lc.persistent_wgs > 0)
+        CS_HIP(cs::launch_dslash_tiled(make_op(g, c), prec, dagger, out, in, nrhs, lc, (hipStream_t)stream));
+    else
+        CS_HIP(cs::launch_dslash(make_op(g, c), prec, prec, prec, dagger, out, in, nullptr, nrhs, (hipStream_t)stream));
     return ok();
 }
 
 int cs_apply_D(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in, int nrhs, void* stream) {
-    return apply(g, c, prec, out, in, nrhs, stream, false);
+    return apply(g, c, prec, out, in, nrhs, nullptr, stream, false);
 }
 
 int cs_apply_Ddag(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in, int nrhs, void* stream) {
-    return apply(g, c, prec, out, in, nrhs, stream, true);
+    return apply(g, c, prec, out, in, nrhs, nullptr, stream, true);
 }
 
-int cs_sap_smooth(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
-                  int x0_is_zero, int nrhs, void* stream) {
+int cs_apply_D_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in, int nrhs,
+                   const cs_launch_config* cfg, void* stream) {
+    return apply(g, c, prec, out, in, nrhs, cfg, stream, false);
+}
+
+int cs_sap_smooth_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
+                      int x0_is_zero, int nrhs, const cs_launch_config* cfg, void* stream) {
     int st = check_op(g, c);
     if (st) return st;
     if (!x || !b) return fail(CS_ERR_NULL, "x and b must be non-NULL");
@@ -323,10 +349,9 @@ int cs_sap_smooth(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b,
     if (!sap_geometry_ok(g->g))
         return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
     const size_t bytes = cs::spinor_bytes_per_site(prec) * (size_t)g->g.V * nrhs;
-    const char* i0 = (const char*)b;
-    const char* o0 = (const char*)x;
-    if (i0 < o0 + bytes && o0 < i0 + bytes) return fail(CS_ERR_INVALID, "x and b overlap");
+    if (overlap(b, x, bytes)) return fail(CS_ERR_INVALID, "x and b overlap");
     const cs::OpData op = make_op(g, c);
+    const cs::LaunchCfg lc = to_cfg(cfg);
     hipStream_t s = (hipStream_t)stream;
     if (n_cy == 0 && x0_is_zero) {
         CS_HIP(hipMemsetAsync(x, 0, bytes, s));
@@ -335,8 +360,105 @@ int cs_sap_smooth(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b,
     for (int cy = 0; cy < n_cy; ++cy)
         for (int col = 0; col < 2; ++col) {
             const int mode = (x0_is_zero && cy == 0) ? (col == 0 ? 1 : 2) : 0;
-            CS_HIP(cs::launch_sap_halfsweep(op, prec, col, n_mr, mode, x, b, nrhs, s));
+            CS_HIP(cs::launch_sap_halfsweep(op, prec, col, n_mr, mode, x, b, nrhs, lc, s));
         }
+    return ok();
+}
+
+int cs_sap_smooth(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
+                  int x0_is_zero, int nrhs, void* stream) {
+    return cs_sap_smooth_cfg(g, c, prec, x, b, n_cy, n_mr, x0_is_zero, nrhs, nullptr, stream);
+}
+
+// Autotuner: time one SAP application (the four half-sweeps of n_cy = 2 from
+// x = 0, n_mr = 4) and one operator application per candidate launch shape.
+static int autotune(cs_gauge g, cs_clover c, int prec, int nrhs, hipStream_t s, cs::LaunchCfg* best_sap,
+                    cs::LaunchCfg* best_d) {
+    const auto key = std::make_pair(prec, nrhs);
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+        *best_sap = it->second.first;
+        *best_d = it->second.second;
+        return ok();
+    }
+    const cs::OpData op = make_op(g, c);
+    const size_t bytes = cs::spinor_bytes_per_site(prec) * (size_t)g->g.V * nrhs;
+    void *xb = nullptr, *bb = nullptr;
+    if (hipMalloc(&xb, bytes) != hipSuccess || hipMalloc(&bb, bytes) != hipSuccess) {
+        if (xb) hipFree(xb);
+        return fail(CS_ERR_ALLOC, "autotune scratch (%zu bytes)", 2 * bytes);
+    }
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    cs::BlasCtx bc{g->g, nrhs, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipError_t err = cs::blas_fill_pattern(bc, prec, bb, s);
+    std::vector<cs::LaunchCfg> cands;
+    for (int t : {1, 4, 8, 12}) {
+        if (t > nrhs) continue;
+        for (int pw : {0, 2 * cus}) {
+            cs::LaunchCfg lc;
+            lc.rhs_tile = t;
+            lc.persistent_wgs = pw;
+            cands.push_back(lc);
+        }
+    }
+    float best_s = 1e30f, best_dd = 1e30f;
+    cs::LaunchCfg bs, bd;
+    for (const cs::LaunchCfg& lc : cands) {
+        if (err != hipSuccess) break;
+        for (int kind = 0; kind < 2 && err == hipSuccess; ++kind) {
+            auto run = [&]() -> hipError_t {
+                if (kind == 0) {
+                    for (int h = 0; h < 4; ++h) {
+                        hipError_t e2 = cs::launch_sap_halfsweep(op, prec, h & 1, 4, h == 0 ? 1 : (h == 1 ? 2 : 0),
+                                                                 xb, bb, nrhs, lc, s);
+                        if (e2 != hipSuccess) return e2;
+                    }
+                    return hipSuccess;
+                }
+                if (lc.rhs_tile > 1 || lc.persistent_wgs > 0) return cs::launch_dslash_tiled(op, prec, false, xb, bb, nrhs, lc, s);
+                return cs::launch_dslash(op, prec, prec, prec, false, xb, bb, nullptr, nrhs, s);
+            };
+            err = run();  // warm-up
+            if (err != hipSuccess) break;
+            hipEventRecord(e0, s);
+            for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) err = run();
+            hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
+            if (kind == 0 && ms < best_s) { best_s = ms; bs = lc; }
+            if (kind == 1 && ms < best_dd) { best_dd = ms; bd = lc; }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(xb);
+    hipFree(bb);
+    if (err != hipSuccess) return fail(CS_ERR_HIP, "autotune: %s", hipGetErrorString(err));
+    c->tuned[key] = std::make_pair(bs, bd);
+    *best_sap = bs;
+    *best_d = bd;
+    return ok();
+}
+
+int cs_autotune(cs_gauge g, cs_clover c, cs_prec prec, int nrhs, cs_launch_config* sap, cs_launch_config* dslash,
+                void* stream) {
+    int st = check_op(g, c);
+    if (st) return st;
+    if (!valid_prec(prec)) return fail(CS_ERR_PRECISION, "unknown precision %d", (int)prec);
+    if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
+    if (!sap_geometry_ok(g->g))
+        return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
+    cs::LaunchCfg a, b;
+    st = autotune(g, c, prec, nrhs, (hipStream_t)stream, &a, &b);
+    if (st) return st;
+    if (sap) *sap = cs_launch_config{a.rhs_tile, a.persistent_wgs};
+    if (dslash) *dslash = cs_launch_config{b.rhs_tile, b.persistent_wgs};
     return ok();
 }
 
@@ -350,6 +472,8 @@ void cs_solver_params_default(cs_solver_params* p) {
     p->inner_prec = CS_F32;
     p->basis_prec = CS_F32;
     p->reliable_delta = 1e-5;
+    p->rhs_tile = 0;
+    p->use_graph = 1;
 }
 
 static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
@@ -367,44 +491,60 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         return fail(CS_ERR_PRECISION, "basis precision must be CS_F64 or CS_F32");
     if (p->inner_prec == CS_F64 && p->basis_prec != CS_F64)
         return fail(CS_ERR_PRECISION, "an FP64 inner solve needs an FP64 basis");
-    if (nrhs < 1) return fail(CS_ERR_INVALID, "nrhs must be >= 1");
+    if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
+    if (p->rhs_tile < 0) return fail(CS_ERR_INVALID, "rhs_tile must be >= 0");
     if (p->n_cy > 0 && !sap_geometry_ok(g->g))
         return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
     const size_t f64 = cs::spinor_bytes_per_site(cs::P_F64) * (size_t)g->g.V;
-    {
-        const char* i0 = (const char*)b;
-        const char* o0 = (const char*)x;
-        if (i0 < o0 + f64 * nrhs && o0 < i0 + f64 * nrhs) return fail(CS_ERR_INVALID, "x and b overlap");
+    if (overlap(b, x, f64 * nrhs)) return fail(CS_ERR_INVALID, "x and b overlap");
+    hipStream_t s = (hipStream_t)stream;
+    cs::LaunchCfg sap_cfg, d_cfg;
+    if (nrhs > 1) {
+        if (p->rhs_tile == 0) {
+            st = autotune(g, c, p->inner_prec, nrhs, s, &sap_cfg, &d_cfg);
+            if (st) return st;
+        } else {
+            sap_cfg.rhs_tile = d_cfg.rhs_tile = p->rhs_tile;
+        }
     }
     if (!c->work) c->work.reset(new cs::GcrWork);
-    hipError_t e = c->work->ensure(g->g, p->restart, p->inner_prec, p->basis_prec);
+    hipError_t e = c->work->ensure(g->g, p->restart, p->inner_prec, p->basis_prec, nrhs);
     if (e != hipSuccess) {
         c->work->release();
         return fail(CS_ERR_ALLOC, "solver workspace: %s", hipGetErrorString(e));
     }
-    if (dagger && !c->dag_tmp && hipMalloc(&c->dag_tmp, f64) != hipSuccess) {
+    if (dagger && c->dag_tmp_nrhs < nrhs) {
+        if (c->dag_tmp) hipFree(c->dag_tmp);
         c->dag_tmp = nullptr;
-        return fail(CS_ERR_ALLOC, "adjoint-solve workspace");
+        c->dag_tmp_nrhs = 0;
+        if (hipMalloc(&c->dag_tmp, f64 * nrhs) != hipSuccess) {
+            c->dag_tmp = nullptr;
+            return fail(CS_ERR_ALLOC, "adjoint-solve workspace");
+        }
+        c->dag_tmp_nrhs = nrhs;
+    }
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_pm);
+        prof = g_prof_on;
     }
     const cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
-                           p->reliable_delta};
-    const cs::OpData op = make_op(g, c);
+                           p->reliable_delta, sap_cfg, d_cfg, p->use_graph != 0 && !prof};
+    std::vector<cs::GcrResult> res(nrhs);
+    e = cs::gcr_solve(make_op(g, c), gp, *c->work, x, b, nrhs, dagger, c->dag_tmp, res.data(), s);
+    if (e != hipSuccess) {
+        c->work->drop_graphs();
+        return fail(CS_ERR_HIP, "solve: %s", hipGetErrorString(e));
+    }
     int first_bad = CS_OK;
     for (int r = 0; r < nrhs; ++r) {
-        cs::GcrResult res{};
-        void* xr = (char*)x + r * f64;
-        const void* br = (const char*)b + r * f64;
-        e = dagger ? cs::gcr_solve_one_dag(op, gp, *c->work, xr, br, c->dag_tmp, &res, (hipStream_t)stream)
-                   : cs::gcr_solve_one(op, gp, *c->work, xr, br, &res, (hipStream_t)stream);
-        if (e == hipSuccess && dagger) e = hipStreamSynchronize((hipStream_t)stream);
-        if (e != hipSuccess) return fail(CS_ERR_HIP, "solve: %s", hipGetErrorString(e));
         if (stats) {
-            stats[r].iters = res.iters;
-            stats[r].restarts = res.restarts;
-            stats[r].true_relres = res.true_relres;
-            stats[r].seconds = res.seconds;
+            stats[r].iters = res[r].iters;
+            stats[r].restarts = res[r].restarts;
+            stats[r].true_relres = res[r].true_relres;
+            stats[r].seconds = res[r].seconds;
         }
-        if (res.status != cs::GCR_OK && first_bad == CS_OK) first_bad = res.status;
+        if (res[r].status != cs::GCR_OK && first_bad == CS_OK) first_bad = res[r].status;
     }
     if (first_bad != CS_OK) return fail(first_bad, "%s", cs_strerror(first_bad));
     return ok();

@@ -2,6 +2,12 @@
 // reductions are FP64 whatever the storage precision of the operands.
 // Reductions are deterministic: each workgroup writes its partial sums and a
 // single-workgroup kernel adds them in a fixed order.
+//
+// Every kernel works on nrhs right-hand sides at once (grid.y = right-hand
+// side), each with its own solver scalars; right-hand sides whose entry in the
+// device mask `active` is zero are skipped (no mask: all active).  Fields of
+// one right-hand side are `stride` bytes apart; basis vectors are stored
+// [k][rhs].
 #pragma once
 
 #include "cs_internal.hpp"
@@ -12,46 +18,58 @@ constexpr int GCR_MAX_RESTART = 32;
 constexpr int BLAS_MAX_WG = 1024;
 constexpr int MULTIDOT_CHUNK = 16;
 
-// Solver scalars kept on the device between kernels, so one GCR iteration
-// needs a single device-to-host read (of `status`).
+// Solver scalars of one right-hand side, kept on the device between kernels.
 struct GcrScalars {
-    double2 dots[MULTIDOT_CHUNK + 2];        // finalize output
+    double2 dots[MULTIDOT_CHUNK + 2];             // finalize output
     double2 R[GCR_MAX_RESTART][GCR_MAX_RESTART];  // R[j][k] = beta_jk (j < k), nu_k (j = k)
     double inv_nu[GCR_MAX_RESTART];
     double2 c[GCR_MAX_RESTART];
-    double2 coef[GCR_MAX_RESTART];           // coefficients of the next update kernel
-    double2 gamma[GCR_MAX_RESTART];          // back-substitution result (host -> device)
-    double rnorm2;                           // |r|^2 of the current residual
-    double inv_rnorm;                        // 1 / |r| (scale of the low-precision copy)
-    double nu;                               // norm of the newest orthogonalised w
+    double2 coef[GCR_MAX_RESTART];                // coefficients of the next update kernel
+    double2 gamma[GCR_MAX_RESTART];               // back-substitution result (host -> device)
+    int nk;                                       // number of gamma_k (host -> device)
+    int pad;
+    double rnorm2;                                // |r|^2 of the current residual
+    double inv_rnorm;                             // 1 / |r| (scale of the low-precision copy)
+    double nu;                                    // norm of the newest orthogonalised w
+};
+
+// Compact per-right-hand-side results the host reads every iteration.
+struct GcrTail {
+    double rnorm2, nu;
 };
 
 struct BlasCtx {
     Geom g;
-    double2* partials;   // [BLAS_MAX_WG][MULTIDOT_CHUNK + 2]
-    GcrScalars* sc;      // device
+    int nrhs;
+    const int* active;   // device mask [nrhs] or nullptr
+    double2* partials;   // [nrhs][BLAS_MAX_WG][MULTIDOT_CHUNK + 2]
+    GcrScalars* sc;      // device [nrhs]
+    GcrTail* tail;       // device [nrhs]
 };
 
-// dst = scale * src (scale: device pointer, or nullptr for 1)
+// dst = scale * src per right-hand side; scale_from_sc: use sc[r].inv_rnorm,
+// else 1.  dst / src strides follow their precisions.
 hipError_t blas_convert(const BlasCtx& c, int dst_prec, void* dst, int src_prec, const void* src,
-                        const double* scale, hipStream_t s);
+                        bool scale_from_sc, hipStream_t s);
 // dst = gamma5 src (F64 fields; dst may equal src)
 hipError_t blas_gamma5(const BlasCtx& c, void* dst, const void* src, hipStream_t s);
-// |v|^2 -> sc->rnorm2 and sc->inv_rnorm (v is F64)
+// |v|^2 -> sc[r].rnorm2, inv_rnorm and tail[r].rnorm2 (v is F64)
 hipError_t blas_norm_to_scalars(const BlasCtx& c, const void* v, hipStream_t s);
-// beta_jk = <w_j_hat, w_k> for j < k (W stored unnormalised, w_j_hat = W_j * inv_nu_j);
-// sets R[j][k] = beta_jk and coef[j] = beta_jk * inv_nu_j.
+// beta_jk = <w_j_hat, w_k> for j < k (W_j stored unnormalised, w_j_hat =
+// W_j inv_nu_j); sets R[j][k] = beta_jk and coef[j] = beta_jk inv_nu_j.
 hipError_t blas_gcr_project(const BlasCtx& c, int basis_prec, const void* W, size_t wstride, int k,
                             hipStream_t s);
 // W_k -= sum_j coef_j W_j, then nu = |W_k|, c_k = <W_k, r> / nu, R[k][k] = nu,
-// inv_nu[k] = 1/nu, coef[0] = c_k / nu.
+// inv_nu[k] = 1/nu, coef[0] = c_k / nu, tail.nu = nu.
 hipError_t blas_gcr_orthonormalise(const BlasCtx& c, int basis_prec, void* W, size_t wstride, int k,
                                    const void* r, hipStream_t s);
-// r -= coef[0] W_k, then |r|^2 -> rnorm2 / inv_rnorm.
-hipError_t blas_gcr_residual_update(const BlasCtx& c, int basis_prec, const void* Wk, void* r,
-                                    hipStream_t s);
-// x += sum_{j < k} gamma_j Z_j
-hipError_t blas_gcr_solution_update(const BlasCtx& c, int zprec, const void* Z, size_t zstride, int k,
+// r -= coef[0] W_k, then |r|^2 -> rnorm2 / inv_rnorm / tail.
+hipError_t blas_gcr_residual_update(const BlasCtx& c, int basis_prec, const void* W, size_t wstride,
+                                    int k, void* r, hipStream_t s);
+// x += sum_{j < sc.nk} gamma_j Z_j
+hipError_t blas_gcr_solution_update(const BlasCtx& c, int zprec, const void* Z, size_t zstride,
                                     void* x, hipStream_t s);
+// Deterministic non-zero test pattern (for timing runs).
+hipError_t blas_fill_pattern(const BlasCtx& c, int prec, void* dst, hipStream_t s);
 
 }  // namespace cs

@@ -54,6 +54,100 @@ __global__ CS_DSLASH_BOUNDS void k_dslash(Geom g, const void* __restrict__ links
     SpinorIO<POUT>::store((char*)out + r * out_stride, g.nblk, blk, l, o);
 }
 
+// Multi-right-hand-side variant: work item = (block, tile of right-hand
+// sides).  The block's links go to LDS once and its clover term to registers
+// once per item; every right-hand side of the tile reuses them.  Backward
+// links of neighbours outside the block come from HBM (cache).  With
+// gridDim.x < nitems the workgroups stride over the items (persistent).
+template <bool ON>
+struct DLinkSmem { cpx<float> u[4][6][BLOCK_SITES]; };
+template <>
+struct DLinkSmem<false> { cpx<double> u[4][6][BLOCK_SITES]; };
+
+template <typename RS, int PLINK>
+struct MixedLinks {
+    const cpx<RS> (*sm)[6][BLOCK_SITES];
+    const void* base;
+    template <typename R>
+    __device__ __forceinline__ void load(int blk, int l, int mu, bool inside, cpx<R>* u) const {
+        if (inside) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) u[k] = {(R)sm[mu][k][l].re, (R)sm[mu][k][l].im};
+            su3_row2(u);
+        } else {
+            load_link<PLINK, R, false>(base, blk, l, mu, u);
+        }
+    }
+};
+
+template <int PIN, int POUT, int PLINK, bool DAG>
+__global__ CS_DSLASH_BOUNDS void k_dslash_tiled(Geom g, const void* __restrict__ links,
+                                                const void* __restrict__ clover, double kappa,
+                                                void* __restrict__ out, const void* __restrict__ in,
+                                                size_t in_stride, size_t out_stride, int nrhs, int tile,
+                                                int nitems) {
+    using R = typename Arith<PIN>::R;
+    using RS = typename LinkIO<PLINK>::R;
+    __shared__ cpx<RS> s_lk[4][6][BLOCK_SITES];
+    const int l = threadIdx.x;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int w = xcd_remap(item, nitems);
+        const int blk = w % g.nblk;
+        const int r0 = (w / g.nblk) * tile;
+        const int r1 = r0 + tile < nrhs ? r0 + tile : nrhs;
+        const BlockPos p = block_pos(g, blk);
+        __syncthreads();
+        for (int mu = 0; mu < 4; ++mu) {
+            cpx<RS> u[6];
+            LinkIO<PLINK>::load6(links, blk, l, mu, u);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) s_lk[mu][k][l] = u[k];
+        }
+        R cl[72];
+        CloverIO<R>::load(clover, blk, l, cl);
+        __syncthreads();
+        MixedLinks<RS, PLINK> lk{s_lk, links};
+        const R k = (R)kappa;
+        for (int r = r0; r < r1; ++r) {
+            const char* src = (const char*)in + (size_t)r * in_stride;
+            cpx<R> acc[12];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) acc[i] = {(R)0, (R)0};
+            GlobalSpinor<PIN, DAG> ld{src, g.nblk};
+            hopping_sum_rolled<R>(g, p, l, ld, lk, acc);
+            cpx<R> self[12], res[12];
+            ld.load(blk, l, self);
+            clover_apply(cl, self, res);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) res[i] = {res[i].re - k * acc[i].re, res[i].im - k * acc[i].im};
+            if (DAG) negate_lower(res);
+            using RO = typename SpinorIO<POUT>::R;
+            cpx<RO> o[12];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) o[i] = {(RO)res[i].re, (RO)res[i].im};
+            SpinorIO<POUT>::store((char*)out + (size_t)r * out_stride, g.nblk, blk, l, o);
+        }
+    }
+}
+
+template <int PIN, int POUT, int PLINK>
+hipError_t launch_tiled(const OpData& op, bool dagger, void* out, const void* in, int nrhs,
+                        const LaunchCfg& cfg, hipStream_t s) {
+    const int tile = cfg.rhs_tile > nrhs ? nrhs : cfg.rhs_tile;
+    const int nitems = op.g.nblk * ((nrhs + tile - 1) / tile);
+    const int grid = cfg.persistent_wgs > 0 && cfg.persistent_wgs < nitems ? cfg.persistent_wgs : nitems;
+    const size_t is = spinor_bytes_per_site(PIN) * op.g.V, os = spinor_bytes_per_site(POUT) * op.g.V;
+    const void* cl = PIN == P_F64 ? op.clover64 : op.clover32;
+    const void* lk = op.links[PLINK];
+    if (dagger)
+        hipLaunchKernelGGL((k_dslash_tiled<PIN, POUT, PLINK, true>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g, lk, cl,
+                           op.kappa, out, in, is, os, nrhs, tile, nitems);
+    else
+        hipLaunchKernelGGL((k_dslash_tiled<PIN, POUT, PLINK, false>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g, lk, cl,
+                           op.kappa, out, in, is, os, nrhs, tile, nitems);
+    return hipGetLastError();
+}
+
 template <int PIN, int POUT, int PLINK>
 hipError_t launch3(const OpData& op, bool dagger, void* out, const void* in, const void* sub,
                    int nrhs, hipStream_t s) {
@@ -72,6 +166,18 @@ hipError_t launch3(const OpData& op, bool dagger, void* out, const void* in, con
 }
 
 }  // namespace
+
+hipError_t launch_dslash_tiled(const OpData& op, int prec, bool dagger, void* out, const void* in, int nrhs,
+                               const LaunchCfg& cfg, hipStream_t s) {
+    ProfScope ps("dslash", s);
+    switch (prec) {
+    case P_F64: return launch_tiled<P_F64, P_F64, P_F64>(op, dagger, out, in, nrhs, cfg, s);
+    case P_F32: return launch_tiled<P_F32, P_F32, P_F32>(op, dagger, out, in, nrhs, cfg, s);
+    case P_F16: return launch_tiled<P_F16, P_F16, P_F16>(op, dagger, out, in, nrhs, cfg, s);
+    case P_BF16: return launch_tiled<P_BF16, P_BF16, P_BF16>(op, dagger, out, in, nrhs, cfg, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_dslash(const OpData& op, int in_prec, int out_prec, int link_prec, bool dagger,
                          void* out, const void* in, const void* sub, int nrhs, hipStream_t s) {

@@ -14,11 +14,17 @@
 //   beta_jk = <w_j_hat, w_k>, j < k    classical Gram-Schmidt, FP64
 //   w_k -= sum_j beta_jk w_j_hat; nu_k = |w_k|; c_k = <w_k_hat, r>
 //   r -= c_k w_k_hat
-// followed by one 24-byte device-to-host read of |r|^2 for the stopping
-// test.  At the end of a cycle R gamma = c is solved on the host (R upper
-// triangular, R_jk = beta_jk, R_kk = nu_k), x += sum_k gamma_k z_k, and the
-// true residual r = b - D x is recomputed in FP64.  Convergence is only ever
-// declared on that true residual.
+// followed by one small device-to-host read of |r|^2 and nu_k per right-hand
+// side for the stopping test.  At the end of a cycle R gamma = c is solved on
+// the host (R upper triangular, R_jk = beta_jk, R_kk = nu_k),
+// x += sum_k gamma_k z_k, and the true residual r = b - D x is recomputed in
+// FP64.  Convergence is only ever declared on that true residual.
+//
+// Several right-hand sides advance in lock step through batched kernels
+// (multi-right-hand-side SAP and operator launches that reuse links and
+// clover); each keeps its own scalars and stops, freezes or restarts on its
+// own criteria.  The kernels of one iteration can be captured once per k as a
+// HIP graph and replayed.
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -35,179 +41,326 @@ namespace {
 int natural_out(int inner) { return inner == P_F64 ? P_F64 : P_F32; }
 int link_for_w(int inner) { return inner == P_F64 ? P_F64 : P_F32; }
 
-}  // namespace
-
-void GcrWork::release() {
-    for (void** p : {&r, &rlo, &Z, &W, &wtmp}) {
-        if (*p) hipFree(*p);
-        *p = nullptr;
-    }
-    if (partials) hipFree(partials);
-    if (sc) hipFree(sc);
-    if (host_sc) hipHostFree(host_sc);
-    partials = nullptr;
-    sc = nullptr;
-    host_sc = nullptr;
-    m = 0;
-}
-
-hipError_t GcrWork::ensure(const Geom& g, int m_, int inner_, int basis_) {
-    if (m_ == m && inner_ == inner && basis_ == basis && W) return hipSuccess;
-    release();
-    m = m_;
-    inner = inner_;
-    basis = basis_;
-    const size_t f64 = spinor_bytes_per_site(P_F64) * g.V;
-    zstride = spinor_bytes_per_site(inner) * g.V;
-    wstride = spinor_bytes_per_site(basis) * g.V;
-    hipError_t e;
-    if ((e = hipMalloc(&r, f64)) != hipSuccess) return e;
-    if ((e = hipMalloc(&rlo, zstride)) != hipSuccess) return e;
-    if ((e = hipMalloc(&Z, zstride * m)) != hipSuccess) return e;
-    if ((e = hipMalloc(&W, wstride * m)) != hipSuccess) return e;
-    if (natural_out(inner) != basis) {
-        if ((e = hipMalloc(&wtmp, spinor_bytes_per_site(natural_out(inner)) * g.V)) != hipSuccess) return e;
-    }
-    if ((e = hipMalloc((void**)&partials, sizeof(double2) * BLAS_MAX_WG * (MULTIDOT_CHUNK + 2))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&sc, sizeof(GcrScalars))) != hipSuccess) return e;
-    if ((e = hipHostMalloc((void**)&host_sc, sizeof(GcrScalars), hipHostMallocDefault)) != hipSuccess) return e;
-    return hipSuccess;
-}
-
 #define GCR_CHK(x)                           \
     do {                                     \
         hipError_t e_ = (x);                 \
         if (e_ != hipSuccess) return e_;     \
     } while (0)
 
-// Read the three trailing scalars (rnorm2, inv_rnorm, nu).
-static hipError_t read_tail(GcrWork& w, hipStream_t s) {
-    const size_t off = offsetof(GcrScalars, rnorm2);
-    GCR_CHK(hipMemcpyAsync((char*)w.host_sc + off, (char*)w.sc + off, 3 * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    return hipStreamSynchronize(s);
+}  // namespace
+
+void GcrWork::drop_graphs() {
+    for (hipGraphExec_t g : graphs)
+        if (g) hipGraphExecDestroy(g);
+    graphs.clear();
+    graph_key.clear();
 }
 
-hipError_t gcr_solve_one(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b,
-                         GcrResult* res, hipStream_t s) {
-    const auto t0 = std::chrono::steady_clock::now();
-    const Geom& g = op.g;
-    const BlasCtx bc{g, w.partials, w.sc};
-    res->status = GCR_NOT_CONVERGED;
-    res->iters = 0;
-    res->restarts = 0;
+void GcrWork::release() {
+    drop_graphs();
+    for (void** p : {&r, &rlo, &Z, &W, &wtmp}) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    if (partials) hipFree(partials);
+    if (sc) hipFree(sc);
+    if (tail) hipFree(tail);
+    if (active) hipFree(active);
+    if (host_sc) hipHostFree(host_sc);
+    if (host_tail) hipHostFree(host_tail);
+    if (host_active) hipHostFree(host_active);
+    if (stream) hipStreamDestroy(stream);
+    partials = nullptr;
+    sc = nullptr;
+    tail = nullptr;
+    active = nullptr;
+    host_sc = nullptr;
+    host_tail = nullptr;
+    host_active = nullptr;
+    stream = nullptr;
+    m = 0;
+    nrhs = 0;
+}
 
-    GCR_CHK(blas_norm_to_scalars(bc, b, s));
-    GCR_CHK(read_tail(w, s));
-    const double bnorm = std::sqrt(w.host_sc->rnorm2);
-    if (!std::isfinite(bnorm)) {
-        res->status = GCR_NONFINITE;
-        res->true_relres = bnorm;
-        return hipSuccess;
+hipError_t GcrWork::ensure(const Geom& g, int m_, int inner_, int basis_, int nrhs_) {
+    if (m_ == m && inner_ == inner && basis_ == basis && nrhs_ == nrhs && W) return hipSuccess;
+    release();
+    m = m_;
+    inner = inner_;
+    basis = basis_;
+    nrhs = nrhs_;
+    const size_t f64 = spinor_bytes_per_site(P_F64) * g.V;
+    zstride = spinor_bytes_per_site(inner) * g.V;
+    wstride = spinor_bytes_per_site(basis) * g.V;
+    hipError_t e;
+    if ((e = hipMalloc(&r, f64 * nrhs)) != hipSuccess) return e;
+    if ((e = hipMalloc(&rlo, zstride * nrhs)) != hipSuccess) return e;
+    if ((e = hipMalloc(&Z, zstride * m * nrhs)) != hipSuccess) return e;
+    if ((e = hipMalloc(&W, wstride * m * nrhs)) != hipSuccess) return e;
+    if (natural_out(inner) != basis) {
+        if ((e = hipMalloc(&wtmp, spinor_bytes_per_site(natural_out(inner)) * g.V * nrhs)) != hipSuccess) return e;
     }
-    if (bnorm == 0.0) {  // D x = 0 has the unique solution x = 0
-        GCR_CHK(hipMemsetAsync(x, 0, spinor_bytes_per_site(P_F64) * g.V, s));
-        GCR_CHK(hipStreamSynchronize(s));
-        res->status = GCR_OK;
-        res->true_relres = 0.0;
-        res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        return hipSuccess;
-    }
-    // true residual r = b - D x
-    GCR_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, b, 1, s));
-    GCR_CHK(blas_norm_to_scalars(bc, w.r, s));
-    GCR_CHK(read_tail(w, s));
-    double rel = std::sqrt(w.host_sc->rnorm2) / bnorm;
-    int iters = 0, cycles = 0;
-    const int nout = natural_out(p.inner);
-
-    for (;;) {
-        if (!std::isfinite(rel)) { res->status = GCR_NONFINITE; break; }
-        if (rel <= p.tol) { res->status = GCR_OK; break; }
-        if (iters >= p.max_iter) { res->status = GCR_NOT_CONVERGED; break; }
-        const double r_true = rel * bnorm;
-        int k_used = 0;
-        bool breakdown = false;
-        for (int k = 0; k < p.restart; ++k) {
-            char* zk = (char*)w.Z + (size_t)k * w.zstride;
-            char* wk = (char*)w.W + (size_t)k * w.wstride;
-            // z_k = SAP(r / |r|)
-            if (p.n_cy > 0) {
-                GCR_CHK(blas_convert(bc, p.inner, w.rlo, P_F64, w.r, &w.sc->inv_rnorm, s));
-                for (int cy = 0; cy < p.n_cy; ++cy)
-                    for (int col = 0; col < 2; ++col) {
-                        const int mode = cy == 0 ? (col == 0 ? 1 : 2) : 0;
-                        GCR_CHK(launch_sap_halfsweep(op, p.inner, col, p.n_mr, mode, zk, w.rlo, 1, s));
-                    }
-            } else {
-                GCR_CHK(blas_convert(bc, p.inner, zk, P_F64, w.r, &w.sc->inv_rnorm, s));
-            }
-            // w_k = D z_k
-            if (nout == w.basis) {
-                GCR_CHK(launch_dslash(op, p.inner, nout, link_for_w(p.inner), false, wk, zk, nullptr, 1, s));
-            } else {
-                GCR_CHK(launch_dslash(op, p.inner, nout, link_for_w(p.inner), false, w.wtmp, zk, nullptr, 1, s));
-                GCR_CHK(blas_convert(bc, w.basis, wk, nout, w.wtmp, nullptr, s));
-            }
-            if (k > 0) GCR_CHK(blas_gcr_project(bc, w.basis, w.W, w.wstride, k, s));
-            GCR_CHK(blas_gcr_orthonormalise(bc, w.basis, w.W, w.wstride, k, w.r, s));
-            GCR_CHK(blas_gcr_residual_update(bc, w.basis, wk, w.r, s));
-            GCR_CHK(read_tail(w, s));
-            if (!(w.host_sc->nu > 0.0)) {
-                breakdown = true;
-                break;
-            }
-            ++iters;
-            k_used = k + 1;
-            const double rr = std::sqrt(w.host_sc->rnorm2);
-            if (!std::isfinite(rr)) break;
-            if (rr <= p.tol * bnorm || iters >= p.max_iter) break;
-            if (p.reliable_delta > 0.0 && rr < p.reliable_delta * r_true) break;
-        }
-        if (k_used > 0) {
-            // back substitution R gamma = c on the host
-            GCR_CHK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(GcrScalars), hipMemcpyDeviceToHost, s));
-            GCR_CHK(hipStreamSynchronize(s));
-            GcrScalars& h = *w.host_sc;
-            std::vector<std::complex<double>> gam(k_used);
-            for (int k = k_used - 1; k >= 0; --k) {
-                std::complex<double> acc(h.c[k].x, h.c[k].y);
-                for (int j = k + 1; j < k_used; ++j)
-                    acc -= std::complex<double>(h.R[k][j].x, h.R[k][j].y) * gam[j];
-                gam[k] = acc / std::complex<double>(h.R[k][k].x, h.R[k][k].y);
-            }
-            for (int k = 0; k < k_used; ++k) h.gamma[k] = make_double2(gam[k].real(), gam[k].imag());
-            const size_t goff = offsetof(GcrScalars, gamma);
-            GCR_CHK(hipMemcpyAsync((char*)w.sc + goff, (char*)w.host_sc + goff,
-                                   sizeof(double2) * k_used, hipMemcpyHostToDevice, s));
-            GCR_CHK(blas_gcr_solution_update(bc, p.inner, w.Z, w.zstride, k_used, x, s));
-        }
-        // reliable update: true FP64 residual
-        GCR_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, b, 1, s));
-        GCR_CHK(blas_norm_to_scalars(bc, w.r, s));
-        GCR_CHK(read_tail(w, s));
-        rel = std::sqrt(w.host_sc->rnorm2) / bnorm;
-        ++cycles;
-        if (breakdown) {
-            res->status = rel <= p.tol ? GCR_OK : GCR_BREAKDOWN;
-            break;
-        }
-    }
-    res->iters = iters;
-    res->restarts = cycles;
-    res->true_relres = rel;
-    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if ((e = hipMalloc((void**)&partials, sizeof(double2) * BLAS_MAX_WG * (MULTIDOT_CHUNK + 2) * nrhs)) != hipSuccess)
+        return e;
+    if ((e = hipMalloc((void**)&sc, sizeof(GcrScalars) * nrhs)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&tail, sizeof(GcrTail) * nrhs)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&active, sizeof(int) * nrhs)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&host_sc, sizeof(GcrScalars) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&host_tail, sizeof(GcrTail) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&host_active, sizeof(int) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
+    if ((e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking)) != hipSuccess) return e;
     return hipSuccess;
 }
 
-hipError_t gcr_solve_one_dag(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b,
-                             void* tmp, GcrResult* res, hipStream_t s) {
-    // D^dag = g5 D g5:  D^dag x = b  <=>  D (g5 x) = g5 b
-    const BlasCtx bc{op.g, w.partials, w.sc};
-    GCR_CHK(blas_gamma5(bc, tmp, b, s));
-    GCR_CHK(blas_gamma5(bc, x, x, s));  // start vector g5 x0
-    GCR_CHK(gcr_solve_one(op, p, w, x, tmp, res, s));
-    return blas_gamma5(bc, x, x, s);
+namespace {
+
+struct Solver {
+    const OpData& op;
+    const GcrParams& p;
+    GcrWork& w;
+    BlasCtx bc;
+    hipStream_t s;
+    int n;
+
+    Solver(const OpData& op_, const GcrParams& p_, GcrWork& w_, int nrhs)
+        : op(op_), p(p_), w(w_), s(w_.stream), n(nrhs) {
+        bc = BlasCtx{op.g, nrhs, w.active, w.partials, w.sc, w.tail};
+    }
+
+    size_t f64() const { return spinor_bytes_per_site(P_F64) * op.g.V; }
+
+    hipError_t upload_mask(const std::vector<char>& m) {
+        for (int r = 0; r < n; ++r) w.host_active[r] = m[r] ? 1 : 0;
+        return hipMemcpyAsync(w.active, w.host_active, sizeof(int) * n, hipMemcpyHostToDevice, s);
+    }
+
+    hipError_t read_tails() {
+        GCR_CHK(hipMemcpyAsync(w.host_tail, w.tail, sizeof(GcrTail) * n, hipMemcpyDeviceToHost, s));
+        return hipStreamSynchronize(s);
+    }
+
+    // w = D z for all right-hand sides
+    hipError_t apply_w(void* wk, const void* zk) {
+        const int nout = natural_out(p.inner);
+        const bool tiled = n > 1 && p.dslash_cfg.rhs_tile > 1 && p.inner == nout;
+        void* dst = nout == w.basis ? wk : w.wtmp;
+        if (tiled) GCR_CHK(launch_dslash_tiled(op, p.inner, false, dst, zk, n, p.dslash_cfg, s));
+        else GCR_CHK(launch_dslash(op, p.inner, nout, link_for_w(p.inner), false, dst, zk, nullptr, n, s));
+        if (nout != w.basis) GCR_CHK(blas_convert(bc, w.basis, wk, nout, w.wtmp, false, s));
+        return hipSuccess;
+    }
+
+    // The kernels of iteration k (the part that is graph-captured).
+    hipError_t iteration(int k) {
+        char* zk = (char*)w.Z + (size_t)k * n * w.zstride;
+        char* wk = (char*)w.W + (size_t)k * n * w.wstride;
+        if (p.n_cy > 0) {
+            GCR_CHK(blas_convert(bc, p.inner, w.rlo, P_F64, w.r, true, s));
+            for (int cy = 0; cy < p.n_cy; ++cy)
+                for (int col = 0; col < 2; ++col) {
+                    const int mode = cy == 0 ? (col == 0 ? 1 : 2) : 0;
+                    GCR_CHK(launch_sap_halfsweep(op, p.inner, col, p.n_mr, mode, zk, w.rlo, n, p.sap_cfg, s));
+                }
+        } else {
+            GCR_CHK(blas_convert(bc, p.inner, zk, P_F64, w.r, true, s));
+        }
+        GCR_CHK(apply_w(wk, zk));
+        if (k > 0) GCR_CHK(blas_gcr_project(bc, w.basis, w.W, w.wstride, k, s));
+        GCR_CHK(blas_gcr_orthonormalise(bc, w.basis, w.W, w.wstride, k, w.r, s));
+        GCR_CHK(blas_gcr_residual_update(bc, w.basis, w.W, w.wstride, k, w.r, s));
+        return hipSuccess;
+    }
+
+    std::vector<char> key() const {
+        std::vector<char> kbuf(256, 0);
+        const int vals[] = {p.restart, p.n_cy, p.n_mr, p.inner, p.basis, p.sap_cfg.rhs_tile,
+                            p.sap_cfg.persistent_wgs, p.dslash_cfg.rhs_tile, p.dslash_cfg.persistent_wgs, n};
+        std::memcpy(kbuf.data(), vals, sizeof vals);
+        const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32};
+        std::memcpy(kbuf.data() + sizeof vals, ptrs, sizeof ptrs);
+        std::memcpy(kbuf.data() + sizeof vals + sizeof ptrs, &op.kappa, sizeof op.kappa);
+        return kbuf;
+    }
+
+    hipError_t run_iteration(int k) {
+        if (!p.use_graph) return iteration(k);
+        const std::vector<char> kk = key();
+        if (w.graph_key != kk) {
+            w.drop_graphs();
+            w.graph_key = kk;
+        }
+        if ((int)w.graphs.size() < p.restart) w.graphs.resize(p.restart, nullptr);
+        if (!w.graphs[k]) {
+            hipGraph_t graph;
+            GCR_CHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t e = iteration(k);
+            hipError_t e2 = hipStreamEndCapture(s, &graph);
+            if (e != hipSuccess) return e;
+            if (e2 != hipSuccess) return e2;
+            hipGraphExec_t exec;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) return e;
+            w.graphs[k] = exec;
+        }
+        return hipGraphLaunch(w.graphs[k], s);
+    }
+};
+
+}  // namespace
+
+hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b, int nrhs,
+                     bool dagger, void* tmp, GcrResult* res, hipStream_t user_stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    GCR_CHK(hipStreamSynchronize(user_stream));  // inputs written on the caller's stream
+    Solver S(op, p, w, nrhs);
+    hipStream_t s = S.s;
+    const size_t f64 = S.f64();
+    const int n = nrhs;
+    std::vector<char> all(n, 1);
+
+    const void* rhs = b;
+    if (dagger) {  // D^dag x = b  <=>  D (g5 x) = g5 b
+        BlasCtx bc0 = S.bc;
+        bc0.active = nullptr;
+        GCR_CHK(blas_gamma5(bc0, tmp, b, s));
+        GCR_CHK(blas_gamma5(bc0, x, x, s));
+        rhs = tmp;
+    }
+
+    std::vector<double> bnorm(n), rel(n), r_true(n);
+    std::vector<int> status(n, GCR_NOT_CONVERGED), iters(n, 0), cycles(n, 0), k_used(n, 0);
+    std::vector<char> done(n, 0), cyc(n, 0), brk(n, 0);
+
+    GCR_CHK(S.upload_mask(all));
+    GCR_CHK(blas_norm_to_scalars(S.bc, rhs, s));
+    GCR_CHK(S.read_tails());
+    for (int r = 0; r < n; ++r) {
+        bnorm[r] = std::sqrt(w.host_tail[r].rnorm2);
+        if (!std::isfinite(bnorm[r])) {
+            status[r] = GCR_NONFINITE;
+            rel[r] = bnorm[r];
+            done[r] = 1;
+        } else if (bnorm[r] == 0.0) {  // D x = 0 has the unique solution x = 0
+            GCR_CHK(hipMemsetAsync((char*)x + r * f64, 0, f64, s));
+            status[r] = GCR_OK;
+            rel[r] = 0.0;
+            done[r] = 1;
+        }
+    }
+    auto not_done = [&]() {
+        std::vector<char> m(n);
+        for (int r = 0; r < n; ++r) m[r] = !done[r];
+        return m;
+    };
+    auto true_residual = [&]() -> hipError_t {
+        GCR_CHK(S.upload_mask(not_done()));
+        GCR_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, rhs, n, s));
+        GCR_CHK(blas_norm_to_scalars(S.bc, w.r, s));
+        GCR_CHK(S.read_tails());
+        for (int r = 0; r < n; ++r)
+            if (!done[r]) rel[r] = std::sqrt(w.host_tail[r].rnorm2) / bnorm[r];
+        return hipSuccess;
+    };
+    GCR_CHK(true_residual());
+
+    for (;;) {
+        bool any = false;
+        for (int r = 0; r < n; ++r) {
+            if (done[r]) continue;
+            if (!std::isfinite(rel[r])) { status[r] = GCR_NONFINITE; done[r] = 1; }
+            else if (rel[r] <= p.tol) { status[r] = GCR_OK; done[r] = 1; }
+            else if (iters[r] >= p.max_iter) { status[r] = GCR_NOT_CONVERGED; done[r] = 1; }
+            else any = true;
+        }
+        if (!any) break;
+        for (int r = 0; r < n; ++r) {
+            cyc[r] = !done[r];
+            k_used[r] = 0;
+            brk[r] = 0;
+            r_true[r] = rel[r] * bnorm[r];
+        }
+        GCR_CHK(S.upload_mask(cyc));
+        for (int k = 0; k < p.restart; ++k) {
+            GCR_CHK(S.run_iteration(k));
+            GCR_CHK(S.read_tails());
+            bool changed = false, left = false;
+            for (int r = 0; r < n; ++r) {
+                if (!cyc[r]) continue;
+                const GcrTail& t = w.host_tail[r];
+                if (!(t.nu > 0.0)) {
+                    brk[r] = 1;
+                    cyc[r] = 0;
+                    changed = true;
+                    continue;
+                }
+                ++iters[r];
+                k_used[r] = k + 1;
+                const double rr = std::sqrt(t.rnorm2);
+                if (!std::isfinite(rr) || rr <= p.tol * bnorm[r] || iters[r] >= p.max_iter ||
+                    (p.reliable_delta > 0.0 && rr < p.reliable_delta * r_true[r])) {
+                    cyc[r] = 0;
+                    changed = true;
+                }
+                left = left || cyc[r];
+            }
+            if (!left) break;
+            if (changed) GCR_CHK(S.upload_mask(cyc));
+        }
+        // back substitution R gamma = c on the host, then x += sum gamma_k z_k
+        std::vector<char> upd(n, 0);
+        bool any_upd = false;
+        for (int r = 0; r < n; ++r) any_upd = any_upd || k_used[r] > 0;
+        if (any_upd) {
+            GCR_CHK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(GcrScalars) * n, hipMemcpyDeviceToHost, s));
+            GCR_CHK(hipStreamSynchronize(s));
+            for (int r = 0; r < n; ++r) {
+                const int ku = k_used[r];
+                if (ku == 0) continue;
+                upd[r] = 1;
+                GcrScalars& h = w.host_sc[r];
+                std::vector<std::complex<double>> gam(ku);
+                for (int k = ku - 1; k >= 0; --k) {
+                    std::complex<double> acc(h.c[k].x, h.c[k].y);
+                    for (int j = k + 1; j < ku; ++j) acc -= std::complex<double>(h.R[k][j].x, h.R[k][j].y) * gam[j];
+                    gam[k] = acc / std::complex<double>(h.R[k][k].x, h.R[k][k].y);
+                }
+                for (int k = 0; k < ku; ++k) h.gamma[k] = make_double2(gam[k].real(), gam[k].imag());
+                h.nk = ku;
+                const size_t goff = offsetof(GcrScalars, gamma);
+                const size_t glen = offsetof(GcrScalars, pad) - goff;
+                GCR_CHK(hipMemcpyAsync((char*)(w.sc + r) + goff, (char*)(w.host_sc + r) + goff, glen,
+                                       hipMemcpyHostToDevice, s));
+            }
+            GCR_CHK(S.upload_mask(upd));
+            GCR_CHK(blas_gcr_solution_update(S.bc, p.inner, w.Z, w.zstride, x, s));
+        }
+        // reliable update: true FP64 residual
+        GCR_CHK(true_residual());
+        for (int r = 0; r < n; ++r) {
+            if (done[r]) continue;
+            ++cycles[r];
+            if (brk[r]) {
+                status[r] = rel[r] <= p.tol ? GCR_OK : GCR_BREAKDOWN;
+                done[r] = 1;
+            }
+        }
+    }
+    if (dagger) {
+        BlasCtx bc0 = S.bc;
+        bc0.active = nullptr;
+        GCR_CHK(blas_gamma5(bc0, x, x, s));
+    }
+    GCR_CHK(hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < n; ++r) {
+        res[r].status = status[r];
+        res[r].iters = iters[r];
+        res[r].restarts = cycles[r];
+        res[r].true_relres = rel[r];
+        res[r].seconds = secs;
+    }
+    return hipSuccess;
 }
 
 }  // namespace cs

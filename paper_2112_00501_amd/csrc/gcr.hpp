@@ -1,6 +1,8 @@
 // Host-side flexible GCR driver (see gcr.cpp).
 #pragma once
 
+#include <vector>
+
 #include "blas.hpp"
 #include "cs_internal.hpp"
 
@@ -13,6 +15,8 @@ struct GcrParams {
     double tol;
     int inner, basis;
     double reliable_delta;
+    LaunchCfg sap_cfg, dslash_cfg;  // multi-right-hand-side launch shapes
+    bool use_graph;                 // replay each iteration as a captured HIP graph
 };
 
 struct GcrResult {
@@ -21,26 +25,36 @@ struct GcrResult {
 };
 
 // Device workspace of one solver configuration, owned by a clover handle.
+// Right-hand sides advance in lock step; each has its own scalars and stops
+// (freezes) on its own criteria, so every column follows exactly the
+// iterations a single-right-hand-side solve would make.
 struct GcrWork {
-    int m = 0, inner = -1, basis = -1;
-    size_t zstride = 0, wstride = 0;
-    void* r = nullptr;     // FP64 residual
-    void* rlo = nullptr;   // residual in the inner precision
-    void* Z = nullptr;     // m preconditioned directions, inner precision
-    void* W = nullptr;     // m basis vectors D z, basis precision
-    void* wtmp = nullptr;  // D z before conversion to the basis precision
+    int m = 0, inner = -1, basis = -1, nrhs = 0;
+    size_t zstride = 0, wstride = 0;  // bytes of one field (one right-hand side)
+    void* r = nullptr;     // FP64 residuals [nrhs]
+    void* rlo = nullptr;   // residuals in the inner precision [nrhs]
+    void* Z = nullptr;     // preconditioned directions [m][nrhs], inner precision
+    void* W = nullptr;     // basis vectors D z [m][nrhs], basis precision
+    void* wtmp = nullptr;  // D z before conversion to the basis precision [nrhs]
     double2* partials = nullptr;
     GcrScalars* sc = nullptr;
     GcrScalars* host_sc = nullptr;  // pinned
-    hipError_t ensure(const Geom& g, int m, int inner, int basis);
+    GcrTail* tail = nullptr;
+    GcrTail* host_tail = nullptr;   // pinned
+    int* active = nullptr;
+    int* host_active = nullptr;     // pinned
+    hipStream_t stream = nullptr;   // private stream (graph capture needs a non-null stream)
+    std::vector<hipGraphExec_t> graphs;
+    std::vector<char> graph_key;
+    hipError_t ensure(const Geom& g, int m, int inner, int basis, int nrhs);
+    void drop_graphs();
     void release();
     ~GcrWork() { release(); }
 };
 
-hipError_t gcr_solve_one(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b,
-                         GcrResult* res, hipStream_t s);
-// Solve D^dag x = b as D (g5 x) = g5 b; tmp is one F64 field of workspace.
-hipError_t gcr_solve_one_dag(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b,
-                             void* tmp, GcrResult* res, hipStream_t s);
+// Solve D x = b for nrhs right-hand sides (consecutive CS_F64 fields).
+// With dagger, solve D^dag x = b as D (g5 x) = g5 b (tmp: nrhs F64 fields).
+hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, const void* b, int nrhs,
+                     bool dagger, void* tmp, GcrResult* res, hipStream_t user_stream);
 
 }  // namespace cs

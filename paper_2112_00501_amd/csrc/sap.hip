@@ -87,11 +87,18 @@ __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
     c = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
 }
 
+// Work item = (block of the current colour, tile of right-hand sides).  One
+// workgroup stages the block's links in LDS and loads its clover term once,
+// then runs the visit for each right-hand side of the tile, so links and
+// clover are read from HBM once per tile instead of once per right-hand side.
+// With gridDim.x < nitems the launch is persistent: workgroups stride over
+// the work items.
 template <int P, int PLINK>
 __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ links,
                                               const void* __restrict__ clover, double kappa_d,
                                               int colour, int n_mr, int mode, void* __restrict__ x,
-                                              const void* __restrict__ b, size_t stride) {
+                                              const void* __restrict__ b, size_t stride, int nrhs,
+                                              int tile, int nitems) {
     using R = typename Arith<P>::R;
     constexpr bool F32PATH = std::is_same<R, float>::value;
     __shared__ cpx<R> s_rho[12][BLOCK_SITES];
@@ -99,168 +106,170 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
     __shared__ R s_red[3][4];
 
     const int l = threadIdx.x;
-    const int blk = colour_block(g, colour, xcd_remap(blockIdx.x, g.nblk / 2));
-    char* xr = (char*)x + blockIdx.y * stride;
-    const char* br = (const char*)b + blockIdx.y * stride;
-    const BlockPos p = block_pos(g, blk);
+    const int ncb = g.nblk / 2;
     const R kappa = (R)kappa_d;
     LdsSpinor<R> ls{s_rho};
 
-    if constexpr (F32PATH) {
-        for (int mu = 0; mu < 4; ++mu) {
-            cpx<typename LinkIO<PLINK>::R> u[6];
-            LinkIO<PLINK>::load6(links, blk, l, mu, u);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) s_lk.u[mu][k][l] = {(float)u[k].re, (float)u[k].im};
-        }
-    }
-    // The FP32 path keeps the clover term in registers for the MR loop; the
-    // FP64 one re-reads it (it would not fit next to the MR state).  It is
-    // loaded after the hopping sum of the residual so that the two are never
-    // live together.
-    R cl[F32PATH ? 72 : 1];
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int w = xcd_remap(item, nitems);
+        const int blk = colour_block(g, colour, w % ncb);
+        const int r0 = (w / ncb) * tile;
+        const int r1 = r0 + tile < nrhs ? r0 + tile : nrhs;
+        const BlockPos p = block_pos(g, blk);
 
-    // ---- block residual r_B = b_B - (D x)_B, stored as rho in LDS
-    {
-        cpx<R> r[12];
-        {
-            using RS = typename SpinorIO<P>::R;
-            cpx<RS> t[12];
-            SpinorIO<P>::load(br, g.nblk, blk, l, t);
+        __syncthreads();  // the previous item's readers of s_lk are done
+        if constexpr (F32PATH) {
+            for (int mu = 0; mu < 4; ++mu) {
+                cpx<typename LinkIO<PLINK>::R> u[6];
+                LinkIO<PLINK>::load6(links, blk, l, mu, u);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) r[k] = {(R)t[k].re, (R)t[k].im};
+                for (int k = 0; k < 6; ++k) s_lk.u[mu][k][l] = {(float)u[k].re, (float)u[k].im};
+            }
         }
-        if (mode != 1) {
-            cpx<R> acc[12];
+        // The FP32 path keeps the clover term in registers for the whole
+        // tile; the FP64 one re-reads it (it would not fit next to the MR
+        // state).
+        R cl[F32PATH ? 72 : 1];
+        if constexpr (F32PATH) CloverIO<R>::load(clover, blk, l, cl);
+
+        for (int r = r0; r < r1; ++r) {
+            char* xr = (char*)x + (size_t)r * stride;
+            const char* br = (const char*)b + (size_t)r * stride;
+
+            // ---- block residual r_B = b_B - (D x)_B, stored as rho in LDS
+            {
+                cpx<R> acc[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
-            GlobalLinks<PLINK> glk{links};
-            if (mode == 0) {
-                GlobalSpinor<P, false> gs{xr, g.nblk};
-                hopping_sum_rolled<R>(g, p, l, gs, glk, acc);
-                cpx<R> self[12], cx[12];
-                gs.load(blk, l, self);
-                if constexpr (F32PATH) {
-                    CloverIO<R>::load(clover, blk, l, cl);
-                    clover_apply(cl, self, cx);
-                } else {
-                    R c2[72];
-                    CloverIO<R>::template load<false>(clover, blk, l, c2);
-                    clover_apply(c2, self, cx);
+                for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+                if (mode != 1) {
+                    GlobalLinks<PLINK> glk{links};
+                    if (mode == 0) {
+                        GlobalSpinor<P, false> gs{xr, g.nblk};
+                        hopping_sum_rolled<R>(g, p, l, gs, glk, acc);
+                        cpx<R> self[12], cx[12];
+                        gs.load(blk, l, self);
+                        if constexpr (F32PATH) {
+                            clover_apply(cl, self, cx);
+                        } else {
+                            R c2[72];
+                            CloverIO<R>::template load<false>(clover, blk, l, c2);
+                            clover_apply(c2, self, cx);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) acc[k] = {cx[k].re - kappa * acc[k].re, cx[k].im - kappa * acc[k].im};
+                    } else {
+                        OutsideSpinor<P> os{xr, g.nblk};
+                        hopping_sum_rolled<R>(g, p, l, os, glk, acc);
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) acc[k] = {-kappa * acc[k].re, -kappa * acc[k].im};
+                    }
                 }
+                using RS = typename SpinorIO<P>::R;
+                cpx<RS> t[12];
+                SpinorIO<P>::load(br, g.nblk, blk, l, t);
 #pragma unroll
-                for (int k = 0; k < 12; ++k) acc[k] = {cx[k].re - kappa * acc[k].re, cx[k].im - kappa * acc[k].im};
-            } else {
-                OutsideSpinor<P> os{xr, g.nblk};
-                hopping_sum_rolled<R>(g, p, l, os, glk, acc);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) acc[k] = {-kappa * acc[k].re, -kappa * acc[k].im};
+                for (int k = 0; k < 12; ++k) s_rho[k][l] = {(R)t[k].re - acc[k].re, (R)t[k].im - acc[k].im};
             }
-#pragma unroll
-            for (int k = 0; k < 12; ++k) r[k] = r[k] - acc[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 12; ++k) s_rho[k][l] = r[k];
-    }
-    if constexpr (F32PATH) {
-        if (mode != 0) CloverIO<R>::load(clover, blk, l, cl);
-    }
 
-    // ---- MR on the Dirichlet block operator; rho lives in LDS only
-    cpx<R> delta[12];
+            // ---- MR on the Dirichlet block operator; rho lives in LDS only
+            cpx<R> delta[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) delta[k] = {(R)0, (R)0};
-    for (int it = 0; it < n_mr; ++it) {
-        __syncthreads();
-        cpx<R> q[12];
-        {
-            cpx<R> acc[12];
+            for (int k = 0; k < 12; ++k) delta[k] = {(R)0, (R)0};
+            for (int it = 0; it < n_mr; ++it) {
+                __syncthreads();
+                cpx<R> q[12];
+                {
+                    cpx<R> acc[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
-            if constexpr (F32PATH) {
-                LdsLinks lk{&s_lk};
-                hopping_sum<R>(g, p, l, ls, lk, acc);
-            } else {
-                GlobalLinks<PLINK, false> lk{links};
-                hopping_sum_rolled<R>(g, p, l, ls, lk, acc);
+                    for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+                    if constexpr (F32PATH) {
+                        LdsLinks lk{&s_lk};
+                        hopping_sum<R>(g, p, l, ls, lk, acc);
+                    } else {
+                        GlobalLinks<PLINK, false> lk{links};
+                        hopping_sum_rolled<R>(g, p, l, ls, lk, acc);
+                    }
+                    cpx<R> rho[12];
+                    ls.load_nb(0, l, true, rho);
+                    if constexpr (F32PATH) {
+                        clover_apply(cl, rho, q);
+                    } else {
+                        R c2[72];
+                        CloverIO<R>::template load<false>(clover, blk, l, c2);
+                        clover_apply(c2, rho, q);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) q[k] = {q[k].re - kappa * acc[k].re, q[k].im - kappa * acc[k].im};
+                }
+                cpx<R> rho[12];
+                ls.load_nb(0, l, true, rho);
+                R qq = 0, qr_re = 0, qr_im = 0;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    qq = fma(q[k].re, q[k].re, qq);
+                    qq = fma(q[k].im, q[k].im, qq);
+                    // conj(q) * rho
+                    qr_re = fma(q[k].re, rho[k].re, qr_re);
+                    qr_re = fma(q[k].im, rho[k].im, qr_re);
+                    qr_im = fma(q[k].re, rho[k].im, qr_im);
+                    qr_im = fma(-q[k].im, rho[k].re, qr_im);
+                }
+                block_sum3(qq, qr_re, qr_im, s_red);
+                if (qq == (R)0) break;  // rho = 0: the block is solved (uniform branch)
+                const R inv = (R)1 / qq;
+                const cpx<R> alpha = {qr_re * inv, qr_im * inv};
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    cmac(delta[k], alpha, rho[k]);
+                    cpx<R> t = rho[k];
+                    t.re = fma(-alpha.re, q[k].re, t.re);
+                    t.re = fma(alpha.im, q[k].im, t.re);
+                    t.im = fma(-alpha.re, q[k].im, t.im);
+                    t.im = fma(-alpha.im, q[k].re, t.im);
+                    s_rho[k][l] = t;
+                }
             }
-            cpx<R> rho[12];
-            ls.load_nb(0, l, true, rho);
-            if constexpr (F32PATH) {
-                clover_apply(cl, rho, q);
-            } else {
-                R c2[72];
-                CloverIO<R>::template load<false>(clover, blk, l, c2);
-                clover_apply(c2, rho, q);
-            }
-#pragma unroll
-            for (int k = 0; k < 12; ++k) q[k] = {q[k].re - kappa * acc[k].re, q[k].im - kappa * acc[k].im};
-        }
-        cpx<R> rho[12];
-        ls.load_nb(0, l, true, rho);
-        R qq = 0, qr_re = 0, qr_im = 0;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            qq = fma(q[k].re, q[k].re, qq);
-            qq = fma(q[k].im, q[k].im, qq);
-            // conj(q) * rho
-            qr_re = fma(q[k].re, rho[k].re, qr_re);
-            qr_re = fma(q[k].im, rho[k].im, qr_re);
-            qr_im = fma(q[k].re, rho[k].im, qr_im);
-            qr_im = fma(-q[k].im, rho[k].re, qr_im);
-        }
-        block_sum3(qq, qr_re, qr_im, s_red);
-        if (qq == (R)0) break;  // rho = 0: the block is solved (uniform branch)
-        const R inv = (R)1 / qq;
-        const cpx<R> alpha = {qr_re * inv, qr_im * inv};
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            cmac(delta[k], alpha, rho[k]);
-            cpx<R> t = rho[k];
-            t.re = fma(-alpha.re, q[k].re, t.re);
-            t.re = fma(alpha.im, q[k].im, t.re);
-            t.im = fma(-alpha.re, q[k].im, t.im);
-            t.im = fma(-alpha.im, q[k].re, t.im);
-            s_rho[k][l] = t;
-        }
-    }
 
-    // ---- x_B += delta (after every lane has finished reading x above)
-    __syncthreads();
-    using RS = typename SpinorIO<P>::R;
-    cpx<RS> xo[12];
-    if (mode == 0) {
-        SpinorIO<P>::load(xr, g.nblk, blk, l, xo);
+            // ---- x_B += delta (after every lane has finished reading x and rho)
+            __syncthreads();
+            using RS = typename SpinorIO<P>::R;
+            cpx<RS> xo[12];
+            if (mode == 0) {
+                SpinorIO<P>::load(xr, g.nblk, blk, l, xo);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) xo[k] = {xo[k].re + (RS)delta[k].re, xo[k].im + (RS)delta[k].im};
-    } else {
+                for (int k = 0; k < 12; ++k) xo[k] = {xo[k].re + (RS)delta[k].re, xo[k].im + (RS)delta[k].im};
+            } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) xo[k] = {(RS)delta[k].re, (RS)delta[k].im};
+                for (int k = 0; k < 12; ++k) xo[k] = {(RS)delta[k].re, (RS)delta[k].im};
+            }
+            SpinorIO<P>::store(xr, g.nblk, blk, l, xo);
+        }
     }
-    SpinorIO<P>::store(xr, g.nblk, blk, l, xo);
 }
 
 template <int P, int PLINK>
 hipError_t launch_p(const OpData& op, int colour, int n_mr, int mode, void* x, const void* b,
-                    int nrhs, hipStream_t s) {
-    const dim3 grid(op.g.nblk / 2, nrhs);
+                    int nrhs, const LaunchCfg& cfg, hipStream_t s) {
+    const int tile = cfg.rhs_tile < 1 ? 1 : (cfg.rhs_tile > nrhs ? nrhs : cfg.rhs_tile);
+    const int nitems = (op.g.nblk / 2) * ((nrhs + tile - 1) / tile);
+    const int grid = cfg.persistent_wgs > 0 && cfg.persistent_wgs < nitems ? cfg.persistent_wgs : nitems;
     const size_t stride = spinor_bytes_per_site(P) * op.g.V;
     const void* cl = P == P_F64 ? op.clover64 : op.clover32;
-    hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK>), grid, dim3(BLOCK_SITES), 0, s, op.g,
-                       op.links[PLINK], cl, op.kappa, colour, n_mr, mode, x, b, stride);
+    hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
+                       op.links[PLINK], cl, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode, void* x,
-                                const void* b, int nrhs, hipStream_t s) {
+                                const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s) {
     ProfScope ps("sap_halfsweep", s);
     switch (prec) {
-    case P_F64: return launch_p<P_F64, P_F64>(op, colour, n_mr, mode, x, b, nrhs, s);
-    case P_F32: return launch_p<P_F32, P_F32>(op, colour, n_mr, mode, x, b, nrhs, s);
-    case P_F16: return launch_p<P_F16, P_F16>(op, colour, n_mr, mode, x, b, nrhs, s);
-    case P_BF16: return launch_p<P_BF16, P_BF16>(op, colour, n_mr, mode, x, b, nrhs, s);
+    case P_F64: return launch_p<P_F64, P_F64>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
+    case P_F32: return launch_p<P_F32, P_F32>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
+    case P_F16: return launch_p<P_F16, P_F16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
+    case P_BF16: return launch_p<P_BF16, P_BF16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }

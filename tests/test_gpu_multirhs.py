@@ -1,0 +1,118 @@
+"""Multi-right-hand-side path: tiled SAP and operator launches (links and
+clover read once per tile), persistent launches, the autotuner, the batched
+lock-step FGCR and its HIP-graph replay.  Every column must reproduce the
+single-right-hand-side result bit for bit (same arithmetic, same reduction
+order)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2112_00501_amd import cloversap as cs
+from paper_2112_00501_amd import synth
+from tests.gpu_helpers import Case
+
+pytestmark = pytest.mark.gpu
+
+NRHS = 6
+
+
+@pytest.fixture(scope="module")
+def case():
+    return Case((8, 8, 8, 16), 0.3, 0.1355, 1.0, 1004, oracle_T=False)
+
+
+CFGS = [(1, 0), (4, 0), (6, 0), (4, 16), (1, 7), (12, 0)]
+
+
+@pytest.mark.parametrize("prec", [cs.F32, cs.F64, cs.F16])
+@pytest.mark.parametrize("tile,pers", CFGS)
+def test_tiled_sap_and_dslash_equal_untiled(case, prec, tile, pers):
+    c = case
+    bs = synth.source(c.dims, 7, nrhs=NRHS)
+    bd = c.to_dev(bs, prec)
+    cfg = cs.LaunchConfig(tile, pers)
+    # operator
+    ref = c.lat.new_field(prec, NRHS)
+    c.op.apply_D(ref, bd, prec, nrhs=NRHS)
+    got = c.lat.new_field(prec, NRHS)
+    c.op.apply_D_cfg(got, bd, prec, NRHS, cfg)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, got)
+    # smoother, from zero and from a start vector
+    for x0z in (True, False):
+        x0 = c.to_dev(0.1 * synth.source(c.dims, 8, nrhs=NRHS), prec)
+        xr = x0.clone()
+        xg = x0.clone()
+        c.op.sap_smooth(xr, bd, prec, nrhs=NRHS, x0_is_zero=x0z)
+        c.op.sap_smooth_cfg(xg, bd, prec, NRHS, cfg, x0_is_zero=x0z)
+        torch.cuda.synchronize()
+        assert torch.equal(xr, xg)
+
+
+def test_autotune_returns_valid_shapes(case):
+    sap, d = case.op.autotune(cs.F32, NRHS)
+    print("autotuned", sap, d)
+    assert sap.rhs_tile in (1, 4) and d.rhs_tile in (1, 4)
+    assert sap.persistent_wgs >= 0 and d.persistent_wgs >= 0
+
+
+@pytest.mark.parametrize("inner", [cs.F32, cs.F64])
+def test_batched_gcr_columns_equal_single_solves(case, inner):
+    c = case
+    bs = synth.source(c.dims, 9, nrhs=NRHS)
+    bs[2] = 0.0  # a zero right-hand side is solved by x = 0 without iterations
+    basis = cs.F64 if inner == cs.F64 else cs.F32
+    p_batch = cs.SolverParams(inner_prec=inner, basis_prec=basis, rhs_tile=4, use_graph=False)
+    bd = c.to_dev(bs, cs.F64)
+    xd = c.lat.new_field(cs.F64, NRHS).zero_()
+    st, stats = c.op.gcr_solve(xd, bd, p_batch, nrhs=NRHS)
+    xb = c.to_host(xd, cs.F64, NRHS)
+    assert st == 0 and stats[2]["iters"] == 0 and np.abs(xb[2]).max() == 0
+    for r in (0, 3, 5):
+        x1 = c.lat.new_field(cs.F64).zero_()
+        st1, s1 = c.op.gcr_solve(x1, c.to_dev(bs[r], cs.F64),
+                                 cs.SolverParams(inner_prec=inner, basis_prec=basis, use_graph=False))
+        assert s1[0]["iters"] == stats[r]["iters"]
+        assert np.array_equal(c.to_host(x1, cs.F64), xb[r])
+        rel = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, bs[r], xb[r]) / np.linalg.norm(bs[r])
+        assert rel <= 1e-10
+
+
+def test_graph_replay_equals_eager(case):
+    c = case
+    bs = synth.source(c.dims, 10, nrhs=NRHS)
+    bd = c.to_dev(bs, cs.F64)
+    eager = c.lat.new_field(cs.F64, NRHS).zero_()
+    c.op.gcr_solve(eager, bd, cs.SolverParams(rhs_tile=4, use_graph=False), nrhs=NRHS)
+    for rep in range(3):
+        xg = c.lat.new_field(cs.F64, NRHS).zero_()
+        c.op.gcr_solve(xg, bd, cs.SolverParams(rhs_tile=4, use_graph=True), nrhs=NRHS)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, eager), rep
+        # eager work between replays
+        tmp = c.lat.new_field(cs.F32, NRHS)
+        c.op.sap_smooth(tmp, c.to_dev(bs, cs.F32), cs.F32, nrhs=NRHS)
+        torch.cuda.synchronize()
+    # single right-hand side through graphs too
+    x1 = c.lat.new_field(cs.F64).zero_()
+    x2 = c.lat.new_field(cs.F64).zero_()
+    b1 = c.to_dev(bs[1], cs.F64)
+    c.op.gcr_solve(x1, b1, cs.SolverParams(use_graph=False))
+    c.op.gcr_solve(x2, b1, cs.SolverParams(use_graph=True))
+    c.op.gcr_solve(x2.zero_(), b1, cs.SolverParams(use_graph=True))
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2)
+
+
+def test_batched_adjoint_solve(case):
+    c = case
+    bs = synth.source(c.dims, 12, nrhs=3)
+    bd = c.to_dev(bs, cs.F64)
+    yd = c.lat.new_field(cs.F64, 3).zero_()
+    c.op.gcr_solve(yd, bd, cs.SolverParams(rhs_tile=0), nrhs=3, dagger=True)
+    y = c.to_host(yd, cs.F64, 3)
+    T = oracle.clover_field(c.dims, c.U, c.kappa, c.csw)
+    for r in range(3):
+        res = oracle.apply_Ddag(c.dims, c.U, T, c.kappa, y[r]) - bs[r]
+        assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(bs[r])
