@@ -90,14 +90,16 @@ def cpu_baseline(dims, U, b, kappa, csw):
 
 def hbm_resident_measurement(cs, synth, torch, reps_d=20, reps_sap=10):
     """Dslash and SAP bandwidth on 32^3 x 64 (working set far above the
-    256 MB last-level cache), FP32 storage, HIP events per launch."""
+    256 MB last-level cache), FP32 storage, HIP events per launch; then
+    time-to-1e-10 for the FP32, FP16 and BF16 smoothers and the FP64-only
+    solve on the same field (low-precision storage: iteration penalty)."""
+    import numpy as np
     c = synth.CONFIGS["lowprec_32x32x32x64"]
     dims = c["dims"]
     U = synth.gauge_field(dims, c["eps"], c["gauge_seed"])
     b = synth.source(dims, c["src_seed"])
     lat = cs.Lattice(dims)
     op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
-    del U
     V = lat.volume
     bin32 = lat.import_field(torch.from_numpy(b).cuda(), cs.F32)
     out32 = lat.new_field(cs.F32)
@@ -119,22 +121,169 @@ def hbm_resident_measurement(cs, synth, torch, reps_d=20, reps_sap=10):
     sap_app_us = mss / reps_sap * 1e3
     d_gbs = DSLASH_BYTES_F32 * V / (d_us * 1e-6) / 1e9
     s_gbs = sap_bytes_per_application(V, 2) / (sap_app_us * 1e-6) / 1e9
-    res = dict(lattice="32x32x32x64", storage="f32",
+    res = dict(lattice="32x32x32x64", eps=c["eps"], kappa=c["kappa"], csw=c["csw"], storage="f32",
                dslash_us=round(d_us, 2), dslash_GBps=round(d_gbs, 1),
                dslash_frac_hbm_peak=round(d_gbs / HBM_PEAK_GBS, 4),
                sap_application_us=round(sap_app_us, 2), sap_GBps=round(s_gbs, 1),
                sap_frac_hbm_peak=round(s_gbs / HBM_PEAK_GBS, 4))
-    # time to 1e-10 at this size, mixed FP32 and FP64-only
+    del bin32, out32
     bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
     xd = lat.new_field(cs.F64)
-    for name, inner, basis in (("mixed_f32", cs.F32, cs.F32), ("fp64", cs.F64, cs.F64)):
+    import oracle
+    for name, inner, basis in (("mixed_f32", cs.F32, cs.F32), ("mixed_f16", cs.F16, cs.F32),
+                               ("mixed_bf16", cs.BF16, cs.F32), ("fp64", cs.F64, cs.F64)):
+        p = cs.SolverParams(inner_prec=inner, basis_prec=basis)
         xd.zero_()
-        st, stats = op.gcr_solve(xd, bd, cs.SolverParams(inner_prec=inner, basis_prec=basis),
-                                 allow_fail=True)
-        res[f"{name}_time_to_1e-10_s"] = round(stats[0]["seconds"], 4)
+        op.gcr_solve(xd, bd, p, allow_fail=True)  # warm-up (workspace, graphs)
+        xd.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats = op.gcr_solve(xd, bd, p, allow_fail=True)
+        torch.cuda.synchronize()
+        res[f"{name}_time_to_1e-10_s"] = round(time.perf_counter() - t, 4)
         res[f"{name}_iterations"] = stats[0]["iters"]
         res[f"{name}_status"] = st
+        if name == "mixed_f32":
+            x = lat.export_field(xd, cs.F64).cpu().numpy()
+            res["mixed_f32_oracle_checked_relres"] = float(
+                f"{oracle.residual_norm(dims, U, c['kappa'], c['csw'], b, x) / np.linalg.norm(b):.3e}")
+    res["speedup_mixed_f32_vs_fp64"] = round(res["fp64_time_to_1e-10_s"] / res["mixed_f32_time_to_1e-10_s"], 3)
     return res
+
+
+def lowprec_subrun(cs, synth, torch):
+    """16^4 sub-run of the low-precision configuration: FP16 / BF16 smoother
+    solutions against the FP64 oracle's solution, and the iteration penalty."""
+    import numpy as np
+
+    import oracle
+    c = synth.CONFIGS["lowprec_sub_16x16x16x16"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["eps"], c["gauge_seed"])
+    b = synth.source(dims, c["src_seed"])
+    oracle.set_threads(min(16, len(os.sched_getaffinity(0))))
+    T = oracle.clover_field(dims, U, c["kappa"], c["csw"])
+    xo, st, ito, relo, _ = oracle.fgcr(dims, (4, 4, 4, 4), U, T, c["kappa"], b, tol=1e-12)
+    lat = cs.Lattice(dims)
+    op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
+    bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
+    xd = lat.new_field(cs.F64)
+    res = dict(lattice="16x16x16x16", oracle_iterations=ito, oracle_relres=float(f"{relo:.2e}"))
+    for name, inner in (("f32", cs.F32), ("f16", cs.F16), ("bf16", cs.BF16), ("f64", cs.F64)):
+        xd.zero_()
+        st, stats = op.gcr_solve(xd, bd, cs.SolverParams(inner_prec=inner,
+                                                         basis_prec=cs.F64 if inner == cs.F64 else cs.F32),
+                                 allow_fail=True)
+        x = lat.export_field(xd, cs.F64).cpu().numpy()
+        res[f"{name}_iterations"] = stats[0]["iters"]
+        res[f"{name}_rel_error_vs_oracle"] = float(f"{np.linalg.norm(x - xo) / np.linalg.norm(xo):.3e}")
+        res[f"{name}_oracle_checked_relres"] = float(
+            f"{oracle.residual_norm(dims, U, c['kappa'], c['csw'], b, x) / np.linalg.norm(b):.3e}")
+    return res
+
+
+def multirhs_measurement(cs, synth, torch, nrhs=24):
+    """24 right-hand sides on 24^3 x 48: autotuned tile and launch shape,
+    bandwidth per right-hand side of the batched operator and smoother, and
+    time to 1e-10 for all 24 (batched, graph-replayed) against 24 one-by-one
+    solves."""
+    import numpy as np
+    c = synth.CONFIGS["multirhs_24x24x24x48"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["eps"], c["gauge_seed"])
+    lat = cs.Lattice(dims)
+    op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
+    del U
+    V = lat.volume
+    B = torch.empty((nrhs, V, 4, 3), dtype=torch.complex128)
+    for j in range(nrhs):
+        B[j] = torch.from_numpy(synth.source(dims, c["src_seed"] + 100 * j))
+    Bd = B.cuda()
+    del B
+    sap_cfg, d_cfg = op.autotune(cs.F32, nrhs)
+    b32 = lat.import_field(Bd, cs.F32)
+    x32 = lat.new_field(cs.F32, nrhs)
+    op.apply_D_cfg(x32, b32, cs.F32, nrhs, d_cfg)
+    op.sap_smooth_cfg(x32, b32, cs.F32, nrhs, sap_cfg)
+    torch.cuda.synchronize()
+    cs.profile_reset()
+    cs.profile_enable(True)
+    for _ in range(5):
+        op.apply_D_cfg(x32, b32, cs.F32, nrhs, d_cfg)
+    for _ in range(3):
+        op.sap_smooth_cfg(x32, b32, cs.F32, nrhs, sap_cfg)
+    torch.cuda.synchronize()
+    cs.profile_enable(False)
+    nd, msd = cs.profile_query("dslash")
+    ns, mss = cs.profile_query("sap_halfsweep")
+    d_us = msd / nd * 1e3
+    s_us = mss / 3 * 1e3
+    t = sap_cfg.rhs_tile
+    td = d_cfg.rhs_tile
+    # algorithmic bytes with link and clover reuse over a tile of t right-hand sides
+    d_bytes = (192 + 480 / td) * V * nrhs
+    # own links (192) and clover (288) are read once per tile of t right-hand sides
+    s_bytes = sum((SAP_BYTES_F32[m] - 480 + 480 / t) for m in (1, 2, 0, 0)) * V / 2 * nrhs
+    res = dict(lattice="24x24x24x48", nrhs=nrhs, sap_rhs_tile=t, sap_persistent_wgs=sap_cfg.persistent_wgs,
+               dslash_rhs_tile=td, dslash_persistent_wgs=d_cfg.persistent_wgs,
+               dslash_us_all_rhs=round(d_us, 1), dslash_GBps=round(d_bytes / (d_us * 1e-6) / 1e9, 1),
+               dslash_us_per_rhs=round(d_us / nrhs, 2),
+               sap_application_us_all_rhs=round(s_us, 1), sap_GBps=round(s_bytes / (s_us * 1e-6) / 1e9, 1),
+               sap_application_us_per_rhs=round(s_us / nrhs, 2))
+    del b32, x32
+    bd = lat.import_field(Bd, cs.F64)
+    del Bd
+    xd = lat.new_field(cs.F64, nrhs)
+    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, rhs_tile=0, use_graph=True)
+    xd.zero_()
+    op.gcr_solve(xd, bd, p, nrhs=nrhs, allow_fail=True)  # warm-up: workspace, graphs
+    xd.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stats = op.gcr_solve(xd, bd, p, nrhs=nrhs, allow_fail=True)
+    torch.cuda.synchronize()
+    res["batched_time_to_1e-10_all_rhs_s"] = round(time.perf_counter() - t0, 4)
+    res["batched_status"] = st
+    res["iterations_min_max"] = [min(s["iters"] for s in stats), max(s["iters"] for s in stats)]
+    res["worst_true_relres"] = float(f"{max(s['true_relres'] for s in stats):.3e}")
+    # the same 24 right-hand sides one by one (single-RHS path, graphs on)
+    fbytes = lat.field_bytes(cs.F64)
+    x1 = lat.new_field(cs.F64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(nrhs):
+        x1.zero_()
+        op.gcr_solve(x1, bd[j * fbytes:(j + 1) * fbytes], cs.SolverParams(), allow_fail=True)
+    torch.cuda.synchronize()
+    res["sequential_time_to_1e-10_all_rhs_s"] = round(time.perf_counter() - t0, 4)
+    res["batched_speedup"] = round(res["sequential_time_to_1e-10_all_rhs_s"] / res["batched_time_to_1e-10_all_rhs_s"], 3)
+    return res
+
+
+def gradient_measurement(cs, synth, torch):
+    """Forward solve and backward pass (adjoint solve + force) of
+    L = Re(eta^dag D^-1 b) on 32^3 x 64 through torch.autograd."""
+    import numpy as np
+    c = synth.CONFIGS["grad_32x32x32x64"]
+    dims = c["dims"]
+    U = torch.from_numpy(synth.gauge_field(dims, c["eps"], c["gauge_seed"])).cuda().requires_grad_(True)
+    b = torch.from_numpy(synth.source(dims, c["src_seed"])).cuda().requires_grad_(True)
+    eta = torch.from_numpy(synth.source(dims, c["eta_seed"])).cuda()
+    lat = cs.Lattice(dims)
+    params = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = cs.CloverSolve.apply(U, b, lat, c["kappa"], c["csw"], params)
+    L = (torch.conj(eta) * x).sum().real
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gn = float(U.grad.abs().max())
+    return dict(lattice="32x32x32x64", forward_s=round(t1 - t0, 4), backward_s=round(t2 - t1, 4),
+                note="forward includes gauge import and clover build; backward = adjoint solve + force",
+                grad_U_maxabs=float(f"{gn:.4e}"), loss=float(f"{float(L):.6e}"))
 
 
 def main():
@@ -144,6 +293,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm", action="store_true", help="skip the 32^3x64 side measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the low-precision, multi-RHS and gradient side measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB five times (counter calibration)")
     args = ap.parse_args()
@@ -190,8 +341,6 @@ def main():
     torch.cuda.synchronize()
 
     log(f"[bench] timing {args.steps} mixed-precision solves")
-    cs.profile_reset()
-    cs.profile_enable(True)
     iters = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -201,12 +350,26 @@ def main():
         iters.append(stats[0]["iters"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    cs.profile_enable(False)
-    fam = {k: cs.profile_query(k) for k in ("sap_halfsweep", "dslash", "blas")}
     ms_per_step = (t1 - t0) / args.steps * 1e3
     x_gpu = lat.export_field(xd, cs.F64).cpu().numpy()
 
-    # dominant kernel: the SAP half-sweep (largest summed time in the timed region)
+    # The same steps again with HIP events recorded around every kernel launch
+    # on the stream it runs on (per-launch events cannot be placed inside the
+    # captured graphs of the timed pass, so this pass runs the kernels eagerly).
+    log(f"[bench] profiled pass of {args.steps} solves")
+    cs.profile_reset()
+    cs.profile_enable(True)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        xd.zero_()
+        op.gcr_solve(xd, bd, mixed)
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    cs.profile_enable(False)
+    fam = {k: cs.profile_query(k) for k in ("sap_halfsweep", "dslash", "blas")}
+
+    # dominant kernel: the SAP half-sweep (largest summed time)
     n_sap, ms_sap = fam["sap_halfsweep"]
     n_apps = n_sap // 4
     alg_bytes = sap_bytes_per_application(V, 2) * n_apps
@@ -220,12 +383,14 @@ def main():
                     kernel="k_sap_halfsweep<f32>", avg_launch_us=round(avg_us, 2),
                     alg_bytes_per_launch=int(per_launch_bytes), launches=n_sap,
                     dominant_by_time=dominant,
-                    note=("working set ~90 MB fits the 256 MB last-level cache at this lattice; "
-                          "the HBM-resident figure is hbm_resident_32x32x32x64.sap_GBps"))
+                    profiled_pass_ms_per_step=round((tp1 - tp0) / args.steps * 1e3, 3),
+                    note=("kernel durations from HIP events around every launch in a profiled pass of "
+                          "the same steps (eager); working set ~90 MB fits the 256 MB last-level cache "
+                          "at this lattice; the HBM-resident figure is hbm_resident_32x32x32x64.sap_GBps"))
 
     log("[bench] FP64-only GPU solves")
     fp64_times, fp64_iters = [], []
-    for _ in range(3):
+    for _ in range(4):
         xd.zero_()
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -233,7 +398,7 @@ def main():
         torch.cuda.synchronize()
         fp64_times.append(time.perf_counter() - ta)
         fp64_iters.append(st64[0]["iters"])
-    fp64_ms = float(np.median(fp64_times)) * 1e3
+    fp64_ms = float(np.median(fp64_times[1:])) * 1e3
 
     import oracle
     rel_or = oracle.residual_norm(dims, U, kappa, csw, b, x_gpu) / np.linalg.norm(b)
@@ -243,7 +408,7 @@ def main():
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32/f64",
                data="synthetic",
                config=dict(workload=("mixed_16x16x16x32: SAP(2 cycles x 4 MR, 4^4 blocks, FP32)-"
-                                     "preconditioned FP64 flexible GCR(16) to 1e-10"),
+                                     "preconditioned FP64 flexible GCR(16) to 1e-10, HIP-graph replay"),
                            lattice="16x16x16x32", eps=cfg["eps"], kappa=kappa, csw=csw,
                            gauge_seed=cfg["gauge_seed"], source_seed=cfg["src_seed"]),
                time_to_1e10_ms=round(ms_per_step, 3), iterations=int(np.median(iters)),
@@ -254,9 +419,20 @@ def main():
                                 avg_us=round(v[1] / max(v[0], 1) * 1e3, 2))
                         for k, v in fam.items()},
                roofline=roofline)
+    del op, lat, bd, xd
+    torch.cuda.empty_cache()
     if not args.no_hbm:
         log("[bench] 32^3x64 HBM-resident measurement")
         out["hbm_resident_32x32x32x64"] = hbm_resident_measurement(cs, synth, torch)
+        torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("[bench] 16^4 low-precision sub-run against the oracle")
+        out["lowprec_sub_16x16x16x16"] = lowprec_subrun(cs, synth, torch)
+        log("[bench] 24 right-hand sides on 24^3x48")
+        out["multirhs_24x24x24x48"] = multirhs_measurement(cs, synth, torch)
+        torch.cuda.empty_cache()
+        log("[bench] gradient on 32^3x64")
+        out["grad_32x32x32x64"] = gradient_measurement(cs, synth, torch)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         cb, _ = cpu_baseline(dims, U, b, kappa, csw)
