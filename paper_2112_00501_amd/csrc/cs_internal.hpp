@@ -55,6 +55,9 @@ constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
 #ifndef CS_DSLASH_ROLLED
 #define CS_DSLASH_ROLLED 1
 #endif
+#ifndef CS_SAP_LDS_RESIDUAL
+#define CS_SAP_LDS_RESIDUAL 1
+#endif
 #if CS_DSLASH_WAVES > 0
 #define CS_DSLASH_BOUNDS __launch_bounds__(256, CS_DSLASH_WAVES)
 #else

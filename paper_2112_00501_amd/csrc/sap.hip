@@ -66,6 +66,59 @@ struct OutsideSpinor {
     }
 };
 
+// Hops that leave the block, for the directions MU0 and MU1 together (a lane
+// has at most one face neighbour per direction).  All lanes issue the loads
+// (lanes without a face neighbour read their own site, which is in cache) so
+// that the loads of both directions are in flight at once.
+template <int MU, int P, typename R>
+__device__ __forceinline__ void face_load(const Geom& g, const BlockPos& p, int l, const void* xr,
+                                          const void* links, cpx<R>* psi, cpx<R>* ug, int* kind) {
+    const int sh = 2 * MU;
+    const int lc = (l >> sh) & 3;
+    int nb = p.blk, nl = l;
+    *kind = 0;
+    if (lc == 3) {
+        *kind = 1;
+        nl = l - (3 << sh);
+        nb = p.bc[MU] == g.NB[MU] - 1 ? p.blk - (g.NB[MU] - 1) * p.stride[MU] : p.blk + p.stride[MU];
+    } else if (lc == 0) {
+        *kind = 2;
+        nl = l + (3 << sh);
+        nb = p.bc[MU] == 0 ? p.blk + (g.NB[MU] - 1) * p.stride[MU] : p.blk - p.stride[MU];
+    }
+    using RS = typename SpinorIO<P>::R;
+    cpx<RS> t[12];
+    SpinorIO<P>::load(xr, g.nblk, nb, nl, t);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = {(R)t[k].re, (R)t[k].im};
+    load_link<P == P_F64 ? P_F64 : (P == P_F32 ? P_F32 : P), R, false>(links, nb, nl, MU, ug);
+}
+
+template <int MU, typename R>
+__device__ __forceinline__ void face_apply(int l, int kind, const cpx<R>* psi, const cpx<R>* ug,
+                                           const LinkSmem<true>& sm, cpx<R>* acc) {
+    if (kind == 1) {  // forward: own link U_mu(x) from LDS
+        cpx<R> u[9];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u[k] = {(R)sm.u[MU][k][l].re, (R)sm.u[MU][k][l].im};
+        su3_row2(u);
+        hop_term<MU, -1>(u, psi, acc);
+    } else if (kind == 2) {  // backward: U_mu(x - mu) of the neighbour block
+        hop_term<MU, +1>(ug, psi, acc);
+    }
+}
+
+template <int MA, int MB, int P, typename R>
+__device__ __forceinline__ void face_pair(const Geom& g, const BlockPos& p, int l, const void* xr,
+                                          const void* links, const LinkSmem<true>& sm, cpx<R>* acc) {
+    cpx<R> pa[12], ua[9], pb[12], ub[9];
+    int ka, kb;
+    face_load<MA, P>(g, p, l, xr, links, pa, ua, &ka);
+    face_load<MB, P>(g, p, l, xr, links, pb, ub, &kb);
+    face_apply<MA>(l, ka, pa, ua, sm, acc);
+    face_apply<MB>(l, kb, pb, ub, sm, acc);
+}
+
 // Sum of three values over the 256 lanes; every lane receives the same total.
 template <typename R>
 __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
@@ -137,7 +190,46 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
             const char* br = (const char*)b + (size_t)r * stride;
 
             // ---- block residual r_B = b_B - (D x)_B, stored as rho in LDS
-            {
+            if constexpr (F32PATH && CS_SAP_LDS_RESIDUAL) {
+                // own x staged in LDS: the hops inside the block read it (and
+                // the links) from LDS; the face hops read HBM two directions
+                // at a time
+                cpx<R> acc[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+                if (mode == 0) {
+                    using RS = typename SpinorIO<P>::R;
+                    cpx<RS> t[12];
+                    SpinorIO<P>::load(xr, g.nblk, blk, l, t);
+                    __syncthreads();  // the previous right-hand side's readers of rho are done
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) s_rho[k][l] = {(R)t[k].re, (R)t[k].im};
+                    __syncthreads();
+                    LdsLinks lk{&s_lk};
+                    hopping_sum<R>(g, p, l, ls, lk, acc);
+                }
+                if (mode != 1) {
+                    face_pair<0, 1, P, R>(g, p, l, xr, links, s_lk, acc);
+                    face_pair<2, 3, P, R>(g, p, l, xr, links, s_lk, acc);
+                }
+                cpx<R> cx[12];
+                if (mode == 0) {
+                    cpx<R> self[12];
+                    ls.load_nb(0, l, true, self);
+                    clover_apply(cl, self, cx);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) cx[k] = {(R)0, (R)0};
+                }
+                using RS = typename SpinorIO<P>::R;
+                cpx<RS> t[12];
+                SpinorIO<P>::load(br, g.nblk, blk, l, t);
+                __syncthreads();  // every lane has read x from rho
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    s_rho[k][l] = {(R)t[k].re - (cx[k].re - kappa * acc[k].re),
+                                   (R)t[k].im - (cx[k].im - kappa * acc[k].im)};
+            } else {
                 cpx<R> acc[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
@@ -167,6 +259,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 using RS = typename SpinorIO<P>::R;
                 cpx<RS> t[12];
                 SpinorIO<P>::load(br, g.nblk, blk, l, t);
+                __syncthreads();  // the previous right-hand side's readers of rho are done
 #pragma unroll
                 for (int k = 0; k < 12; ++k) s_rho[k][l] = {(R)t[k].re - acc[k].re, (R)t[k].im - acc[k].im};
             }
