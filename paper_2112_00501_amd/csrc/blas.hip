@@ -2,6 +2,8 @@
 // reductions on operands stored in any precision).  Each kernel walks the
 // lattice block by block with one lane per site, so operands of different
 // storage precisions line up site by site; grid.y runs over right-hand sides.
+#include <type_traits>
+
 #include "blas.hpp"
 #include "fields.hpp"
 
@@ -12,7 +14,7 @@ namespace {
 constexpr int NVS = MULTIDOT_CHUNK + 2;  // partial-sum slots per workgroup
 constexpr int TPB = BLOCK_SITES;
 
-enum Step { STEP_NONE = 0, STEP_PROJECT = 1, STEP_ORTHO = 2, STEP_NORM = 3 };
+enum Step { STEP_NONE = 0, STEP_PROJECT = 1, STEP_NORM = 2 };
 
 template <int P>
 __device__ __forceinline__ void ld64(const void* base, int nblk, int blk, int l, cpx<double>* c) {
@@ -40,10 +42,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ bool skip(const int* active) { return active && !active[blockIdx.y]; }
 
-// Reduce NV complex values over the workgroup; lane j < nv writes slot j of
-// this workgroup's partials of right-hand side blockIdx.y.
+// Reduce NV complex values over the workgroup; lane j < nv writes slot v0 + j
+// of this workgroup's partials of right-hand side blockIdx.y.
 template <int NV>
-__device__ __forceinline__ void wg_reduce_store(cpx<double>* acc, int nv, double2* partials) {
+__device__ __forceinline__ void wg_reduce_store(cpx<double>* acc, int nv, double2* partials, int v0 = 0) {
     __shared__ double2 red[4][NV];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -57,7 +59,80 @@ __device__ __forceinline__ void wg_reduce_store(cpx<double>* acc, int nv, double
         double2 t;
         t.x = (red[0][j].x + red[1][j].x) + (red[2][j].x + red[3][j].x);
         t.y = (red[0][j].y + red[1][j].y) + (red[2][j].y + red[3][j].y);
-        partials[((size_t)blockIdx.y * BLAS_MAX_WG + blockIdx.x) * NVS + j] = t;
+        partials[((size_t)blockIdx.y * BLAS_MAX_WG + blockIdx.x) * NVS + v0 + j] = t;
+    }
+}
+
+// Sum slots v0 .. v0 + NVP - 1 of nwg workgroup partials (one right-hand side)
+// in a fixed order: lane t takes slot t % NVP and every (TPB / NVP)-th
+// workgroup from t / NVP, then a fixed tree adds the chunks.  The total of
+// slot v ends in red[v].  Any workgroup running this on the same partials
+// gets bitwise the same sums.
+template <int NVP>
+__device__ __forceinline__ void sum_partials(const double2* part, int nwg, int v0, double2* red) {
+    constexpr int G = TPB / NVP;
+    const int t = threadIdx.x, v = t % NVP, c = t / NVP;
+    double2 s = make_double2(0.0, 0.0);
+    for (int i = c; i < nwg; i += G) {
+        const double2 q = part[(size_t)i * NVS + v0 + v];
+        s.x += q.x;
+        s.y += q.y;
+    }
+    red[t] = s;
+    __syncthreads();
+#pragma unroll
+    for (int w = G / 2; w > 0; w >>= 1) {
+        if (c < w) {
+            red[t].x += red[t + w * NVP].x;
+            red[t].y += red[t + w * NVP].y;
+        }
+        __syncthreads();
+    }
+}
+
+// GCR scalars of the orthonormalisation step from |W_k|^2 and <W_k, r>.
+struct OrthoScalars {
+    double nu, inv_nu;
+    double2 ck, coef;
+};
+
+__device__ __forceinline__ OrthoScalars ortho_scalars(double2 ww, double2 wr) {
+    OrthoScalars o;
+    o.nu = sqrt(ww.x);
+    o.inv_nu = o.nu > 0.0 ? 1.0 / o.nu : 0.0;
+    o.ck = make_double2(wr.x * o.inv_nu, wr.y * o.inv_nu);
+    o.coef = make_double2(o.ck.x * o.inv_nu, o.ck.y * o.inv_nu);
+    return o;
+}
+
+// Slots of the partials: a projection uses 0 .. MULTIDOT_CHUNK - 1, the
+// orthonormalisation 0 and 1 (|W_k|^2, <W_k, r>), a norm NORM_SLOT, so the
+// residual update can read the orthonormalisation sums while it writes its own.
+constexpr int NORM_SLOT = MULTIDOT_CHUNK;
+
+// Sum the partials and apply one solver step (one workgroup per right-hand side).
+template <int NVP>
+__global__ __launch_bounds__(TPB) void k_finalize(const double2* partials, int nwg, int nv, int v0, GcrScalars* scs,
+                                                  GcrTail* tails, const int* active, int step, int k, int j0) {
+    const int r = blockIdx.x;
+    if (active && !active[r]) return;
+    GcrScalars* sc = scs + r;
+    __shared__ double2 red[TPB];
+    sum_partials<NVP>(partials + (size_t)r * BLAS_MAX_WG * NVS, nwg, v0, red);
+    if (threadIdx.x != 0) return;
+    for (int v = 0; v < nv; ++v) sc->dots[v] = red[v];
+    if (step == STEP_PROJECT) {
+        for (int j = 0; j < nv; ++j) {
+            const double in = sc->inv_nu[j0 + j];
+            const double2 beta = make_double2(red[j].x * in, red[j].y * in);
+            sc->R[j0 + j][k] = beta;
+            sc->coef[j0 + j] = make_double2(beta.x * in, beta.y * in);
+        }
+    } else if (step == STEP_NORM) {
+        const double r2 = red[0].x;
+        sc->rnorm2 = r2;
+        tails[r].rnorm2 = r2;
+        sc->inv_rnorm = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
     }
 }
 
@@ -105,18 +180,34 @@ __global__ __launch_bounds__(TPB) void k_fill(Geom g, void* dst, size_t fs) {
     }
 }
 
-__global__ __launch_bounds__(TPB) void k_norm2_f64(Geom g, const void* v, size_t fs, const int* active,
-                                                   double2* partials) {
+// Scale of the low-precision residual copy: 1 / |r| of the residual before
+// this update (the preconditioner is homogeneous, so any positive scale gives
+// the same direction; this one keeps the copy near unit norm).
+__device__ __forceinline__ double lo_scale(const GcrScalars& S) {
+    return S.inv_rnorm > 0.0 ? S.inv_rnorm : 1.0;
+}
+
+// |v|^2; optionally also writes lo_scale * v in precision PL to lo (PL < 0: no copy)
+template <int PL>
+__global__ __launch_bounds__(TPB) void k_norm2_f64(Geom g, const void* v, size_t fs, void* lo, size_t ls,
+                                                   const GcrScalars* sc, const int* active, double2* partials) {
     if (skip(active)) return;
     const char* q = (const char*)v + blockIdx.y * fs;
+    double sl = 1.0;
+    if constexpr (PL >= 0) sl = lo_scale(sc[blockIdx.y]);
     cpx<double> acc[1] = {{0.0, 0.0}};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> c[12];
         ld64<P_F64>(q, g.nblk, blk, threadIdx.x, c);
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[0].re += c[k].re * c[k].re + c[k].im * c[k].im;
+        if constexpr (PL >= 0) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) c[k] = sl * c[k];
+            st64<PL>((char*)lo + blockIdx.y * ls, g.nblk, blk, threadIdx.x, c);
+        }
     }
-    wg_reduce_store<1>(acc, 1, partials);
+    wg_reduce_store<1>(acc, 1, partials, NORM_SLOT);
 }
 
 // partial <W_{j0 + j}, W_k> for j < n (n <= MULTIDOT_CHUNK); W stored [k][rhs]
@@ -176,14 +267,34 @@ __global__ __launch_bounds__(TPB) void k_ortho(Geom g, char* W, size_t ws, int n
     wg_reduce_store<2>(acc, 2, partials);
 }
 
-// r -= coef[0] W_k; partial |r|^2
-template <int PB>
+// Completes the orthonormalisation step from its partials (every workgroup
+// sums them in the same fixed order; workgroup 0 stores nu_k, c_k, R[k][k]),
+// then r -= (c_k / nu_k) W_k, partial |r|^2 and optionally
+// lo_scale * (new r) in precision PL to lo.
+template <int PB, int PL>
 __global__ __launch_bounds__(TPB) void k_residual_update(Geom g, const char* W, size_t ws, int nrhs, int k,
-                                                         void* rv, size_t rs, const GcrScalars* sc,
-                                                         const int* active, double2* partials) {
+                                                         void* rv, size_t rs, void* lo, size_t los,
+                                                         GcrScalars* sc, GcrTail* tails, const int* active,
+                                                         double2* partials, int nwg) {
     if (skip(active)) return;
     const int r = blockIdx.y;
-    const cpx<double> cf = {sc[r].coef[0].x, sc[r].coef[0].y};
+    __shared__ double2 red[TPB];
+    sum_partials<2>(partials + (size_t)r * BLAS_MAX_WG * NVS, nwg, 0, red);
+    const OrthoScalars o = ortho_scalars(red[0], red[1]);
+    double sl = 1.0;
+    if constexpr (PL >= 0) sl = lo_scale(sc[r]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        GcrScalars* S = sc + r;
+        S->dots[0] = red[0];
+        S->dots[1] = red[1];
+        S->nu = o.nu;
+        tails[r].nu = o.nu;
+        S->R[k][k] = make_double2(o.nu, 0.0);
+        S->inv_nu[k] = o.inv_nu;
+        S->c[k] = o.ck;
+        S->coef[0] = o.coef;
+    }
+    const cpx<double> cf = {o.coef.x, o.coef.y};
     const char* wk = W + ((size_t)k * nrhs + r) * ws;
     char* rr_base = (char*)rv + r * rs;
     cpx<double> acc[1] = {{0.0, 0.0}};
@@ -197,8 +308,13 @@ __global__ __launch_bounds__(TPB) void k_residual_update(Geom g, const char* W, 
             acc[0].re += rr[c].re * rr[c].re + rr[c].im * rr[c].im;
         }
         st64<P_F64>(rr_base, g.nblk, blk, threadIdx.x, rr);
+        if constexpr (PL >= 0) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) rr[c] = sl * rr[c];
+            st64<PL>((char*)lo + r * los, g.nblk, blk, threadIdx.x, rr);
+        }
     }
-    wg_reduce_store<1>(acc, 1, partials);
+    wg_reduce_store<1>(acc, 1, partials, NORM_SLOT);
 }
 
 // x += sum_{j < nk} gamma_j Z_j
@@ -224,65 +340,16 @@ __global__ __launch_bounds__(TPB) void k_solution_update(Geom g, const char* Z, 
     }
 }
 
-// Sum the partials of nv values in a fixed order and apply one solver step
-// (one workgroup per right-hand side).
-__global__ __launch_bounds__(TPB) void k_finalize(const double2* partials, int nwg, int nv, GcrScalars* scs,
-                                                  GcrTail* tails, const int* active, int step, int k, int j0) {
-    const int r = blockIdx.x;
-    if (active && !active[r]) return;
-    GcrScalars* sc = scs + r;
-    const double2* part = partials + (size_t)r * BLAS_MAX_WG * NVS;
-    __shared__ double2 red[TPB];
-    const int t = threadIdx.x;
-    for (int v = 0; v < nv; ++v) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int i = t; i < nwg; i += TPB) {
-            s.x += part[(size_t)i * NVS + v].x;
-            s.y += part[(size_t)i * NVS + v].y;
-        }
-        red[t] = s;
-        __syncthreads();
-        for (int w = TPB / 2; w > 0; w >>= 1) {
-            if (t < w) {
-                red[t].x += red[t + w].x;
-                red[t].y += red[t + w].y;
-            }
-            __syncthreads();
-        }
-        if (t == 0) sc->dots[v] = red[0];
-        __syncthreads();
-    }
-    if (t != 0) return;
-    if (step == STEP_PROJECT) {
-        for (int j = 0; j < nv; ++j) {
-            const double in = sc->inv_nu[j0 + j];
-            const double2 beta = make_double2(sc->dots[j].x * in, sc->dots[j].y * in);
-            sc->R[j0 + j][k] = beta;
-            sc->coef[j0 + j] = make_double2(beta.x * in, beta.y * in);
-        }
-    } else if (step == STEP_ORTHO) {
-        const double nu = sqrt(sc->dots[0].x);
-        const double in = nu > 0.0 ? 1.0 / nu : 0.0;
-        sc->nu = nu;
-        tails[r].nu = nu;
-        sc->R[k][k] = make_double2(nu, 0.0);
-        sc->inv_nu[k] = in;
-        const double2 ck = make_double2(sc->dots[1].x * in, sc->dots[1].y * in);
-        sc->c[k] = ck;
-        sc->coef[0] = make_double2(ck.x * in, ck.y * in);
-    } else if (step == STEP_NORM) {
-        const double r2 = sc->dots[0].x;
-        sc->rnorm2 = r2;
-        tails[r].rnorm2 = r2;
-        sc->inv_rnorm = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
-    }
-}
-
 int nwg_for(const Geom& g) { return g.nblk < BLAS_MAX_WG ? g.nblk : BLAS_MAX_WG; }
 
-hipError_t finalize(const BlasCtx& c, int nv, int step, int k, int j0, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(c.nrhs), dim3(TPB), 0, s, c.partials, nwg_for(c.g), nv, c.sc, c.tail,
-                       c.active, step, k, j0);
+hipError_t finalize(const BlasCtx& c, int nv, int v0, int step, int k, int j0, hipStream_t s) {
+    const int nwg = nwg_for(c.g);
+    if (nv == 1)
+        hipLaunchKernelGGL((k_finalize<1>), dim3(c.nrhs), dim3(TPB), 0, s, c.partials, nwg, nv, v0, c.sc, c.tail,
+                           c.active, step, k, j0);
+    else
+        hipLaunchKernelGGL((k_finalize<MULTIDOT_CHUNK>), dim3(c.nrhs), dim3(TPB), 0, s, c.partials, nwg, nv, v0,
+                           c.sc, c.tail, c.active, step, k, j0);
     return hipGetLastError();
 }
 
@@ -333,13 +400,18 @@ hipError_t blas_fill_pattern(const BlasCtx& c, int prec, void* dst, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t blas_norm_to_scalars(const BlasCtx& c, const void* v, hipStream_t s) {
+hipError_t blas_norm_to_scalars(const BlasCtx& c, const void* v, int lo_prec, void* lo, hipStream_t s) {
     ProfScope ps("blas", s);
-    hipLaunchKernelGGL(k_norm2_f64, dim3(nwg_for(c.g), c.nrhs), dim3(TPB), 0, s, c.g, v, f64_stride(c.g),
-                       c.active, c.partials);
+    const dim3 grid(nwg_for(c.g), c.nrhs);
+    const size_t ls = lo_prec >= 0 ? spinor_bytes_per_site(lo_prec) * c.g.V : 0;
+    if (lo_prec < 0) {
+        hipLaunchKernelGGL((k_norm2_f64<-1>), grid, dim3(TPB), 0, s, c.g, v, f64_stride(c.g), lo, ls, c.sc, c.active, c.partials);
+    } else {
+        CS_DISPATCH_P(lo_prec, hipLaunchKernelGGL((k_norm2_f64<PP>), grid, dim3(TPB), 0, s, c.g, v, f64_stride(c.g), lo, ls, c.sc, c.active, c.partials));
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return finalize(c, 1, STEP_NORM, 0, 0, s);
+    return finalize(c, 1, NORM_SLOT, STEP_NORM, 0, 0, s);
 }
 
 hipError_t blas_gcr_project(const BlasCtx& c, int pb, const void* W, size_t ws, int k, hipStream_t s) {
@@ -350,7 +422,7 @@ hipError_t blas_gcr_project(const BlasCtx& c, int pb, const void* W, size_t ws, 
         CS_DISPATCH_P(pb, hipLaunchKernelGGL((k_multidot<PP>), grid, dim3(TPB), 0, s, c.g, (const char*)W, ws, c.nrhs, j0, n, k, c.active, c.partials));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = finalize(c, n, STEP_PROJECT, k, j0, s);
+        e = finalize(c, n, 0, STEP_PROJECT, k, j0, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -361,19 +433,38 @@ hipError_t blas_gcr_orthonormalise(const BlasCtx& c, int pb, void* W, size_t ws,
     ProfScope ps("blas", s);
     const dim3 grid(nwg_for(c.g), c.nrhs);
     CS_DISPATCH_P(pb, hipLaunchKernelGGL((k_ortho<PP>), grid, dim3(TPB), 0, s, c.g, (char*)W, ws, c.nrhs, k, r, f64_stride(c.g), c.sc, c.active, c.partials));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return finalize(c, 2, STEP_ORTHO, k, 0, s);
+    return hipGetLastError();
 }
 
 hipError_t blas_gcr_residual_update(const BlasCtx& c, int pb, const void* W, size_t ws, int k, void* r,
-                                    hipStream_t s) {
+                                    int lo_prec, void* lo, hipStream_t s) {
     ProfScope ps("blas", s);
     const dim3 grid(nwg_for(c.g), c.nrhs);
-    CS_DISPATCH_P(pb, hipLaunchKernelGGL((k_residual_update<PP>), grid, dim3(TPB), 0, s, c.g, (const char*)W, ws, c.nrhs, k, r, f64_stride(c.g), c.sc, c.active, c.partials));
-    hipError_t e = hipGetLastError();
+    const size_t los = lo_prec >= 0 ? spinor_bytes_per_site(lo_prec) * c.g.V : 0;
+    hipError_t e = hipSuccess;
+    auto go = [&](auto pbt, auto plt) {
+        constexpr int PB = decltype(pbt)::value, PL = decltype(plt)::value;
+        hipLaunchKernelGGL((k_residual_update<PB, PL>), grid, dim3(TPB), 0, s, c.g, (const char*)W, ws, c.nrhs, k, r,
+                           f64_stride(c.g), lo, los, c.sc, c.tail, c.active, c.partials, nwg_for(c.g));
+        e = hipGetLastError();
+    };
+    auto with_lo = [&](auto pbt) {
+        switch (lo_prec) {
+        case -1: go(pbt, std::integral_constant<int, -1>{}); break;
+        case P_F64: go(pbt, std::integral_constant<int, P_F64>{}); break;
+        case P_F32: go(pbt, std::integral_constant<int, P_F32>{}); break;
+        case P_F16: go(pbt, std::integral_constant<int, P_F16>{}); break;
+        case P_BF16: go(pbt, std::integral_constant<int, P_BF16>{}); break;
+        default: e = hipErrorInvalidValue;
+        }
+    };
+    switch (pb) {
+    case P_F64: with_lo(std::integral_constant<int, P_F64>{}); break;
+    case P_F32: with_lo(std::integral_constant<int, P_F32>{}); break;
+    default: return hipErrorInvalidValue;
+    }
     if (e != hipSuccess) return e;
-    return finalize(c, 1, STEP_NORM, 0, 0, s);
+    return finalize(c, 1, NORM_SLOT, STEP_NORM, 0, 0, s);
 }
 
 hipError_t blas_gcr_solution_update(const BlasCtx& c, int pz, const void* Z, size_t zs, void* x, hipStream_t s) {

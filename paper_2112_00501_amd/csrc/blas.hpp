@@ -1,7 +1,8 @@
 // Level-1 kernels of the flexible GCR outer solver.  All arithmetic and all
 // reductions are FP64 whatever the storage precision of the operands.
 // Reductions are deterministic: each workgroup writes its partial sums and a
-// single-workgroup kernel adds them in a fixed order.
+// later kernel adds them in a fixed order (a one-workgroup-per-right-hand-side
+// finalize, or every workgroup of the consuming kernel).
 //
 // Every kernel works on nrhs right-hand sides at once (grid.y = right-hand
 // side), each with its own solver scalars; right-hand sides whose entry in the
@@ -20,7 +21,7 @@ constexpr int MULTIDOT_CHUNK = 16;
 
 // Solver scalars of one right-hand side, kept on the device between kernels.
 struct GcrScalars {
-    double2 dots[MULTIDOT_CHUNK + 2];             // finalize output
+    double2 dots[MULTIDOT_CHUNK + 2];             // reduced sums of the last reduction
     double2 R[GCR_MAX_RESTART][GCR_MAX_RESTART];  // R[j][k] = beta_jk (j < k), nu_k (j = k)
     double inv_nu[GCR_MAX_RESTART];
     double2 c[GCR_MAX_RESTART];
@@ -29,7 +30,7 @@ struct GcrScalars {
     int nk;                                       // number of gamma_k (host -> device)
     int pad;
     double rnorm2;                                // |r|^2 of the current residual
-    double inv_rnorm;                             // 1 / |r| (scale of the low-precision copy)
+    double inv_rnorm;                             // 1 / |r| (0 when r = 0)
     double nu;                                    // norm of the newest orthogonalised w
 };
 
@@ -53,19 +54,24 @@ hipError_t blas_convert(const BlasCtx& c, int dst_prec, void* dst, int src_prec,
                         bool scale_from_sc, hipStream_t s);
 // dst = gamma5 src (F64 fields; dst may equal src)
 hipError_t blas_gamma5(const BlasCtx& c, void* dst, const void* src, hipStream_t s);
-// |v|^2 -> sc[r].rnorm2, inv_rnorm and tail[r].rnorm2 (v is F64)
-hipError_t blas_norm_to_scalars(const BlasCtx& c, const void* v, hipStream_t s);
+// |v|^2 -> sc[r].rnorm2, inv_rnorm and tail[r].rnorm2 (v is F64); with
+// lo_prec >= 0 also writes v / |previous residual| in that precision to lo
+// (scale 1 when no previous norm is set).
+hipError_t blas_norm_to_scalars(const BlasCtx& c, const void* v, int lo_prec, void* lo, hipStream_t s);
 // beta_jk = <w_j_hat, w_k> for j < k (W_j stored unnormalised, w_j_hat =
 // W_j inv_nu_j); sets R[j][k] = beta_jk and coef[j] = beta_jk inv_nu_j.
 hipError_t blas_gcr_project(const BlasCtx& c, int basis_prec, const void* W, size_t wstride, int k,
                             hipStream_t s);
-// W_k -= sum_j coef_j W_j, then nu = |W_k|, c_k = <W_k, r> / nu, R[k][k] = nu,
-// inv_nu[k] = 1/nu, coef[0] = c_k / nu, tail.nu = nu.
+// W_k -= sum_j coef_j W_j and the partial sums of |W_k|^2 and <W_k, r>; the
+// scalars of this step are completed by blas_gcr_residual_update, which must
+// follow it.
 hipError_t blas_gcr_orthonormalise(const BlasCtx& c, int basis_prec, void* W, size_t wstride, int k,
                                    const void* r, hipStream_t s);
-// r -= coef[0] W_k, then |r|^2 -> rnorm2 / inv_rnorm / tail.
+// nu = |W_k|, c_k = <W_k, r> / nu -> R[k][k] = nu, inv_nu[k] = 1/nu, c[k],
+// tail.nu; then r -= (c_k / nu) W_k and |r|^2 -> rnorm2 / inv_rnorm / tail.
+// With lo_prec >= 0 also writes the new r / |old r| in that precision to lo.
 hipError_t blas_gcr_residual_update(const BlasCtx& c, int basis_prec, const void* W, size_t wstride,
-                                    int k, void* r, hipStream_t s);
+                                    int k, void* r, int lo_prec, void* lo, hipStream_t s);
 // x += sum_{j < sc.nk} gamma_j Z_j
 hipError_t blas_gcr_solution_update(const BlasCtx& c, int zprec, const void* Z, size_t zstride,
                                     void* x, hipStream_t s);

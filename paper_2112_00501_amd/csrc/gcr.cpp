@@ -128,6 +128,8 @@ struct Solver {
     }
 
     size_t f64() const { return spinor_bytes_per_site(P_F64) * op.g.V; }
+    // precision of the residual copy the smoother reads (none without smoother)
+    int lo_prec() const { return p.n_cy > 0 ? p.inner : -1; }
 
     hipError_t upload_mask(const std::vector<char>& m) {
         for (int r = 0; r < n; ++r) w.host_active[r] = m[r] ? 1 : 0;
@@ -155,7 +157,8 @@ struct Solver {
         char* zk = (char*)w.Z + (size_t)k * n * w.zstride;
         char* wk = (char*)w.W + (size_t)k * n * w.wstride;
         if (p.n_cy > 0) {
-            GCR_CHK(blas_convert(bc, p.inner, w.rlo, P_F64, w.r, true, s));
+            // w.rlo holds the residual in the inner precision, written by the
+            // kernel that last updated w.r
             for (int cy = 0; cy < p.n_cy; ++cy)
                 for (int col = 0; col < 2; ++col) {
                     const int mode = cy == 0 ? (col == 0 ? 1 : 2) : 0;
@@ -167,7 +170,7 @@ struct Solver {
         GCR_CHK(apply_w(wk, zk));
         if (k > 0) GCR_CHK(blas_gcr_project(bc, w.basis, w.W, w.wstride, k, s));
         GCR_CHK(blas_gcr_orthonormalise(bc, w.basis, w.W, w.wstride, k, w.r, s));
-        GCR_CHK(blas_gcr_residual_update(bc, w.basis, w.W, w.wstride, k, w.r, s));
+        GCR_CHK(blas_gcr_residual_update(bc, w.basis, w.W, w.wstride, k, w.r, lo_prec(), w.rlo, s));
         return hipSuccess;
     }
 
@@ -233,7 +236,7 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
     std::vector<char> done(n, 0), cyc(n, 0), brk(n, 0);
 
     GCR_CHK(S.upload_mask(all));
-    GCR_CHK(blas_norm_to_scalars(S.bc, rhs, s));
+    GCR_CHK(blas_norm_to_scalars(S.bc, rhs, -1, nullptr, s));
     GCR_CHK(S.read_tails());
     for (int r = 0; r < n; ++r) {
         bnorm[r] = std::sqrt(w.host_tail[r].rnorm2);
@@ -256,7 +259,7 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
     auto true_residual = [&]() -> hipError_t {
         GCR_CHK(S.upload_mask(not_done()));
         GCR_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, rhs, n, s));
-        GCR_CHK(blas_norm_to_scalars(S.bc, w.r, s));
+        GCR_CHK(blas_norm_to_scalars(S.bc, w.r, S.lo_prec(), w.rlo, s));
         GCR_CHK(S.read_tails());
         for (int r = 0; r < n; ++r)
             if (!done[r]) rel[r] = std::sqrt(w.host_tail[r].rnorm2) / bnorm[r];
