@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Dslash/SAP HBM GB/s (% peak); time-to-1e-10 residual, mixed vs FP64, 1 GPU"
-SAP_KERNEL_SOURCES = ["sap.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp"]
+SAP_KERNEL_SOURCES = ["sap.hip", "sap_pair.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp"]
 
 # Algorithmic bytes per visited site of one SAP half-sweep, FP32 storage:
 # every field the visit needs, counted once per site: b (96), x (96), the two
@@ -61,6 +61,12 @@ def load_traffic(kernel: str, per_launch_alg_bytes: float):
     if rec.get("source_hash") != source_hash(SAP_KERNEL_SOURCES):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def sap_kernel_name(nblk: int) -> str:
+    """The FP32 SAP kernel the library launches by default: the lane-pair
+    kernel while a colour has at most 256 blocks (one per compute unit)."""
+    return "k_sap_pair<f32>" if nblk // 2 <= 256 else "k_sap_halfsweep<f32>"
 
 
 def sap_bytes_per_application(V: int, n_cy: int) -> float:
@@ -295,6 +301,8 @@ def main():
     ap.add_argument("--no-hbm", action="store_true", help="skip the 32^3x64 side measurement")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the low-precision, multi-RHS and gradient side measurements")
+    ap.add_argument("--hbm-only", action="store_true",
+                    help="only the 32^3x64 HBM-resident operator, smoother and solve measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB five times (counter calibration)")
     args = ap.parse_args()
@@ -318,6 +326,11 @@ def main():
 
     from paper_2112_00501_amd import cloversap as cs
     from paper_2112_00501_amd import synth
+
+    if args.hbm_only:
+        log("[bench] 32^3x64 HBM-resident measurement")
+        print(json.dumps(dict(hbm_resident_32x32x32x64=hbm_resident_measurement(cs, synth, torch))), flush=True)
+        return
 
     cfg = synth.CONFIGS["mixed_16x16x16x32"]
     dims, kappa, csw = cfg["dims"], cfg["kappa"], cfg["csw"]
@@ -380,7 +393,7 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=load_traffic("sap_halfsweep_16x16x16x32", per_launch_bytes),
-                    kernel="k_sap_halfsweep<f32>", avg_launch_us=round(avg_us, 2),
+                    kernel=sap_kernel_name(V // 256), avg_launch_us=round(avg_us, 2),
                     alg_bytes_per_launch=int(per_launch_bytes), launches=n_sap,
                     dominant_by_time=dominant,
                     profiled_pass_ms_per_step=round((tp1 - tp0) / args.steps * 1e3, 3),

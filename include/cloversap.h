@@ -140,15 +140,22 @@ int cs_apply_Ddag(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* 
 
 /* Launch shape of the multi-right-hand-side operator and SAP kernels:
  * rhs_tile right-hand sides per workgroup (the block's links and clover term
- * are read once per tile), and, when persistent_wgs > 0, a persistent launch
- * of that many workgroups striding over the (block, tile) work items. */
+ * are read once per tile); when persistent_wgs > 0, a persistent launch of
+ * that many workgroups striding over the (block, tile) work items; and
+ * lanes_per_site of the FP32 / FP16 / BF16 SAP kernel: 1 (one lane per site),
+ * 2 (a lane pair per site: forward and backward hops on separate lanes, one
+ * chirality each), or 0 (the library chooses from the number of blocks).
+ * Values other than 0, 1, 2 mean 0; the operator ignores lanes_per_site and
+ * FP64 SAP always uses one lane per site. */
 typedef struct {
     int rhs_tile;
     int persistent_wgs;
+    int lanes_per_site;
 } cs_launch_config;
 
 /* Time the SAP half-sweep and the operator for rhs_tile in {1, 4, 8, 12}
- * (up to nrhs) and for grid and persistent launches, on nrhs right-hand
+ * (up to nrhs), for grid and persistent launches and (SAP below FP64) for
+ * one and two lanes per site, on nrhs right-hand
  * sides of precision prec, and return the fastest shapes (either pointer may
  * be NULL).  The result is cached with the clover handle and used by
  * cs_gcr_solve when params.rhs_tile is 0.  Allocates and frees scratch

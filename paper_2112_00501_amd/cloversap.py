@@ -37,10 +37,11 @@ class _Params(C.Structure):
 
 class LaunchConfig(C.Structure):
     """Multi-right-hand-side launch shape (cs_launch_config)."""
-    _fields_ = [("rhs_tile", C.c_int), ("persistent_wgs", C.c_int)]
+    _fields_ = [("rhs_tile", C.c_int), ("persistent_wgs", C.c_int), ("lanes_per_site", C.c_int)]
 
     def __repr__(self):
-        return f"LaunchConfig(rhs_tile={self.rhs_tile}, persistent_wgs={self.persistent_wgs})"
+        return (f"LaunchConfig(rhs_tile={self.rhs_tile}, persistent_wgs={self.persistent_wgs}, "
+                f"lanes_per_site={self.lanes_per_site})")
 
 
 class _Stats(C.Structure):

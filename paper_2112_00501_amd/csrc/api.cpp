@@ -304,6 +304,7 @@ static cs::LaunchCfg to_cfg(const cs_launch_config* c) {
     if (c) {
         r.rhs_tile = c->rhs_tile < 1 ? 1 : c->rhs_tile;
         r.persistent_wgs = c->persistent_wgs < 0 ? 0 : c->persistent_wgs;
+        r.lanes_per_site = c->lanes_per_site == 1 || c->lanes_per_site == 2 ? c->lanes_per_site : 0;
     }
     return r;
 }
@@ -399,12 +400,15 @@ static int autotune(cs_gauge g, cs_clover c, int prec, int nrhs, hipStream_t s, 
     std::vector<cs::LaunchCfg> cands;
     for (int t : {1, 4, 8, 12}) {
         if (t > nrhs) continue;
-        for (int pw : {0, 2 * cus}) {
-            cs::LaunchCfg lc;
-            lc.rhs_tile = t;
-            lc.persistent_wgs = pw;
-            cands.push_back(lc);
-        }
+        for (int pw : {0, 2 * cus})
+            for (int lanes : {1, 2}) {
+                if (lanes == 2 && prec == CS_F64) continue;
+                cs::LaunchCfg lc;
+                lc.rhs_tile = t;
+                lc.persistent_wgs = pw;
+                lc.lanes_per_site = lanes;
+                cands.push_back(lc);
+            }
     }
     float best_s = 1e30f, best_dd = 1e30f;
     cs::LaunchCfg bs, bd;
@@ -432,7 +436,7 @@ static int autotune(cs_gauge g, cs_clover c, int prec, int nrhs, hipStream_t s, 
             float ms = 0.f;
             if (err == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
             if (kind == 0 && ms < best_s) { best_s = ms; bs = lc; }
-            if (kind == 1 && ms < best_dd) { best_dd = ms; bd = lc; }
+            if (kind == 1 && ms < best_dd) { best_dd = ms; bd = lc; bd.lanes_per_site = 0; }
         }
     }
     hipEventDestroy(e0);
@@ -457,8 +461,8 @@ int cs_autotune(cs_gauge g, cs_clover c, cs_prec prec, int nrhs, cs_launch_confi
     cs::LaunchCfg a, b;
     st = autotune(g, c, prec, nrhs, (hipStream_t)stream, &a, &b);
     if (st) return st;
-    if (sap) *sap = cs_launch_config{a.rhs_tile, a.persistent_wgs};
-    if (dslash) *dslash = cs_launch_config{b.rhs_tile, b.persistent_wgs};
+    if (sap) *sap = cs_launch_config{a.rhs_tile, a.persistent_wgs, a.lanes_per_site};
+    if (dslash) *dslash = cs_launch_config{b.rhs_tile, b.persistent_wgs, 0};
     return ok();
 }
 

@@ -64,17 +64,31 @@ __device__ __forceinline__ void wg_reduce_store(cpx<double>* acc, int nv, double
 }
 
 // Sum slots v0 .. v0 + NVP - 1 of nwg workgroup partials (one right-hand side)
-// in a fixed order: lane t takes slot t % NVP and every (TPB / NVP)-th
-// workgroup from t / NVP, then a fixed tree adds the chunks.  The total of
-// slot v ends in red[v].  Any workgroup running this on the same partials
-// gets bitwise the same sums.
-template <int NVP>
+// in a fixed order with NT threads: lane t takes slot t % NVP and every
+// (NT / NVP)-th workgroup from t / NVP in increasing order (loads issued eight
+// at a time), then a fixed tree adds the chunks.  The total of slot v ends in
+// red[v].  Any workgroup running this on the same partials gets bitwise the
+// same sums.
+template <int NVP, int NT>
 __device__ __forceinline__ void sum_partials(const double2* part, int nwg, int v0, double2* red) {
-    constexpr int G = TPB / NVP;
+    constexpr int G = NT / NVP;
+    constexpr int U = 8;
     const int t = threadIdx.x, v = t % NVP, c = t / NVP;
+    const double2* p = part + v0 + v;
     double2 s = make_double2(0.0, 0.0);
-    for (int i = c; i < nwg; i += G) {
-        const double2 q = part[(size_t)i * NVS + v0 + v];
+    int i = c;
+    for (; i + (U - 1) * G < nwg; i += U * G) {
+        double2 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = p[(size_t)(i + u * G) * NVS];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s.x += q[u].x;
+            s.y += q[u].y;
+        }
+    }
+    for (; i < nwg; i += G) {
+        const double2 q = p[(size_t)i * NVS];
         s.x += q.x;
         s.y += q.y;
     }
@@ -111,14 +125,17 @@ __device__ __forceinline__ OrthoScalars ortho_scalars(double2 ww, double2 wr) {
 constexpr int NORM_SLOT = MULTIDOT_CHUNK;
 
 // Sum the partials and apply one solver step (one workgroup per right-hand side).
+constexpr int FIN_TPB = 1024;
+
 template <int NVP>
-__global__ __launch_bounds__(TPB) void k_finalize(const double2* partials, int nwg, int nv, int v0, GcrScalars* scs,
-                                                  GcrTail* tails, const int* active, int step, int k, int j0) {
+__global__ __launch_bounds__(FIN_TPB) void k_finalize(const double2* partials, int nwg, int nv, int v0,
+                                                      GcrScalars* scs, GcrTail* tails, const int* active, int step,
+                                                      int k, int j0) {
     const int r = blockIdx.x;
     if (active && !active[r]) return;
     GcrScalars* sc = scs + r;
-    __shared__ double2 red[TPB];
-    sum_partials<NVP>(partials + (size_t)r * BLAS_MAX_WG * NVS, nwg, v0, red);
+    __shared__ double2 red[FIN_TPB];
+    sum_partials<NVP, FIN_TPB>(partials + (size_t)r * BLAS_MAX_WG * NVS, nwg, v0, red);
     if (threadIdx.x != 0) return;
     for (int v = 0; v < nv; ++v) sc->dots[v] = red[v];
     if (step == STEP_PROJECT) {
@@ -279,7 +296,7 @@ __global__ __launch_bounds__(TPB) void k_residual_update(Geom g, const char* W, 
     if (skip(active)) return;
     const int r = blockIdx.y;
     __shared__ double2 red[TPB];
-    sum_partials<2>(partials + (size_t)r * BLAS_MAX_WG * NVS, nwg, 0, red);
+    sum_partials<2, TPB>(partials + (size_t)r * BLAS_MAX_WG * NVS, nwg, 0, red);
     const OrthoScalars o = ortho_scalars(red[0], red[1]);
     double sl = 1.0;
     if constexpr (PL >= 0) sl = lo_scale(sc[r]);
@@ -345,11 +362,11 @@ int nwg_for(const Geom& g) { return g.nblk < BLAS_MAX_WG ? g.nblk : BLAS_MAX_WG;
 hipError_t finalize(const BlasCtx& c, int nv, int v0, int step, int k, int j0, hipStream_t s) {
     const int nwg = nwg_for(c.g);
     if (nv == 1)
-        hipLaunchKernelGGL((k_finalize<1>), dim3(c.nrhs), dim3(TPB), 0, s, c.partials, nwg, nv, v0, c.sc, c.tail,
-                           c.active, step, k, j0);
+        hipLaunchKernelGGL((k_finalize<1>), dim3(c.nrhs), dim3(FIN_TPB), 0, s, c.partials, nwg, nv, v0, c.sc,
+                           c.tail, c.active, step, k, j0);
     else
-        hipLaunchKernelGGL((k_finalize<MULTIDOT_CHUNK>), dim3(c.nrhs), dim3(TPB), 0, s, c.partials, nwg, nv, v0,
-                           c.sc, c.tail, c.active, step, k, j0);
+        hipLaunchKernelGGL((k_finalize<MULTIDOT_CHUNK>), dim3(c.nrhs), dim3(FIN_TPB), 0, s, c.partials, nwg, nv,
+                           v0, c.sc, c.tail, c.active, step, k, j0);
     return hipGetLastError();
 }
 

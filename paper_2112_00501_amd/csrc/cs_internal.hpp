@@ -305,11 +305,13 @@ hipError_t launch_dslash(const OpData& op, int in_prec, int out_prec, int link_p
                          void* out, const void* in, const void* sub, int nrhs, hipStream_t s);
 
 // Launch configuration of the multi-right-hand-side kernels: right-hand
-// sides per workgroup (links and clover are loaded once per tile) and, when
-// positive, the number of workgroups of a persistent launch.
+// sides per workgroup (links and clover are loaded once per tile), when
+// positive the number of workgroups of a persistent launch, and the lanes per
+// site of the low-precision SAP kernel (1 or 2; 0: chosen from the lattice).
 struct LaunchCfg {
     int rhs_tile = 1;
     int persistent_wgs = 0;
+    int lanes_per_site = 0;
 };
 
 // dslash.hip, multi-right-hand-side form (input, output and links of one
@@ -321,6 +323,9 @@ hipError_t launch_dslash_tiled(const OpData& op, int prec, bool dagger, void* ou
 // 1: x is zero everywhere (r = b); 2: x is zero on the blocks of this colour.
 hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode,
                                 void* x, const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s);
+// sap_pair.hip: the same half-sweep with two lanes per site (FP32, FP16, BF16).
+hipError_t launch_sap_pair(const OpData& op, int prec, int colour, int n_mr, int mode, void* x, const void* b,
+                           int nrhs, const LaunchCfg& cfg, hipStream_t s);
 
 // force.hip: g_{mu,a}(x) = dL/dw of L with dL = -Re(y^dag dD x); either output
 // may be null.  Hbuf holds 864 bytes per site (insertion matrices).

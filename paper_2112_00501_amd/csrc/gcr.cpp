@@ -177,7 +177,8 @@ struct Solver {
     std::vector<char> key() const {
         std::vector<char> kbuf(256, 0);
         const int vals[] = {p.restart, p.n_cy, p.n_mr, p.inner, p.basis, p.sap_cfg.rhs_tile,
-                            p.sap_cfg.persistent_wgs, p.dslash_cfg.rhs_tile, p.dslash_cfg.persistent_wgs, n};
+                            p.sap_cfg.persistent_wgs, p.sap_cfg.lanes_per_site, p.dslash_cfg.rhs_tile,
+                            p.dslash_cfg.persistent_wgs, n};
         std::memcpy(kbuf.data(), vals, sizeof vals);
         const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32};
         std::memcpy(kbuf.data() + sizeof vals, ptrs, sizeof ptrs);

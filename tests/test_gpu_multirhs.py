@@ -25,13 +25,13 @@ def case():
 CFGS = [(1, 0), (4, 0), (6, 0), (4, 16), (1, 7), (12, 0)]
 
 
-@pytest.mark.parametrize("prec", [cs.F32, cs.F64, cs.F16])
+@pytest.mark.parametrize("prec,lanes", [(cs.F32, 1), (cs.F32, 2), (cs.F64, 1), (cs.F16, 1), (cs.F16, 2)])
 @pytest.mark.parametrize("tile,pers", CFGS)
-def test_tiled_sap_and_dslash_equal_untiled(case, prec, tile, pers):
+def test_tiled_sap_and_dslash_equal_untiled(case, prec, lanes, tile, pers):
     c = case
     bs = synth.source(c.dims, 7, nrhs=NRHS)
     bd = c.to_dev(bs, prec)
-    cfg = cs.LaunchConfig(tile, pers)
+    cfg = cs.LaunchConfig(tile, pers, lanes)
     # operator
     ref = c.lat.new_field(prec, NRHS)
     c.op.apply_D(ref, bd, prec, nrhs=NRHS)
@@ -44,7 +44,7 @@ def test_tiled_sap_and_dslash_equal_untiled(case, prec, tile, pers):
         x0 = c.to_dev(0.1 * synth.source(c.dims, 8, nrhs=NRHS), prec)
         xr = x0.clone()
         xg = x0.clone()
-        c.op.sap_smooth(xr, bd, prec, nrhs=NRHS, x0_is_zero=x0z)
+        c.op.sap_smooth_cfg(xr, bd, prec, NRHS, cs.LaunchConfig(1, 0, lanes), x0_is_zero=x0z)
         c.op.sap_smooth_cfg(xg, bd, prec, NRHS, cfg, x0_is_zero=x0z)
         torch.cuda.synchronize()
         assert torch.equal(xr, xg)

@@ -60,24 +60,3 @@ def test_dslash_batched_equals_single(cfg1):
             o1 = c.lat.new_field(prec)
             c.op.apply_D(o1, f1, prec)
             assert np.array_equal(c.to_host(o1, prec), got[r])
-
-
-def test_dslash_full_size_sampled():
-    """32^3 x 64 at the benchmark's launch configuration; the oracle evaluates
-    D on sampled sites (block faces and corners included)."""
-    dims, kappa, csw = (32, 32, 32, 64), 0.1370, 1.1
-    c = Case(dims, 0.25, kappa, csw, 1003, oracle_T=False)
-    psi = synth.source(dims, 2003)
-    rng = np.random.default_rng(0)
-    V = int(np.prod(dims))
-    corners = [0, 3, 4, 31, 32 * 32 * 32 * 63 + 31, V - 1]
-    sites = np.unique(np.concatenate([rng.choice(V, 500, replace=False), corners]))
-    ref = oracle.apply_D_sites(dims, c.U, kappa, csw, psi, sites)
-    for prec in (cs.F64, cs.F32):
-        fin = c.to_dev(psi, prec)
-        fout = c.lat.new_field(prec)
-        c.op.apply_D(fout, fin, prec)
-        got = c.to_host(fout, prec)[sites]
-        err = rel(got, ref)
-        print(f"32^3x64 prec={prec} sampled rel.err={err:.3e}")
-        assert err <= TOL_D[prec]

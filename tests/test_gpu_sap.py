@@ -27,16 +27,20 @@ def noncubic():
     return Case((8, 8, 16, 8), 0.3, 0.1355, 1.0, 9)
 
 
-@pytest.mark.parametrize("prec", [cs.F64, cs.F32, cs.F16, cs.BF16])
-def test_sap_from_zero(cfg1, noncubic, prec):
+# one lane per site, and (below FP64) the lane-pair kernel
+PREC_LANES = [(cs.F64, 1), (cs.F32, 1), (cs.F32, 2), (cs.F16, 1), (cs.F16, 2), (cs.BF16, 1), (cs.BF16, 2)]
+
+
+@pytest.mark.parametrize("prec,lanes", PREC_LANES)
+def test_sap_from_zero(cfg1, noncubic, prec, lanes):
     for c in (cfg1, noncubic):
         b = synth.source(c.dims, 2001)
         ref = oracle.sap(c.dims, BDIM, c.U, c.T, c.kappa, 2, 4, b)
         bd = c.to_dev(b, prec)
         xd = c.lat.new_field(prec)
-        c.op.sap_smooth(xd, bd, prec, n_cy=2, n_mr=4, x0_is_zero=True)
+        c.op.sap_smooth_cfg(xd, bd, prec, 1, cs.LaunchConfig(1, 0, lanes), n_cy=2, n_mr=4, x0_is_zero=True)
         err = rel(c.to_host(xd, prec), ref)
-        print(f"dims={c.dims} prec={prec} sap rel.err={err:.3e}")
+        print(f"dims={c.dims} prec={prec} lanes={lanes} sap rel.err={err:.3e}")
         assert err <= TOL_SAP[prec]
 
 
@@ -46,13 +50,31 @@ def test_sap_with_start_vector(cfg1, n_cy, n_mr):
     b = synth.source(c.dims, 2002)
     x0 = 0.3 * synth.source(c.dims, 2003)
     ref = oracle.sap(c.dims, BDIM, c.U, c.T, c.kappa, n_cy, n_mr, b, x0=x0)
-    for prec in (cs.F64, cs.F32):
+    for prec, lanes in [(cs.F64, 1), (cs.F32, 1), (cs.F32, 2), (cs.F16, 2)]:
         bd = c.to_dev(b, prec)
         xd = c.to_dev(x0, prec)
-        c.op.sap_smooth(xd, bd, prec, n_cy=n_cy, n_mr=n_mr, x0_is_zero=False)
+        c.op.sap_smooth_cfg(xd, bd, prec, 1, cs.LaunchConfig(1, 0, lanes), n_cy=n_cy, n_mr=n_mr,
+                            x0_is_zero=False)
         err = rel(c.to_host(xd, prec), ref)
-        print(f"n_cy={n_cy} n_mr={n_mr} prec={prec} rel.err={err:.3e}")
+        print(f"n_cy={n_cy} n_mr={n_mr} prec={prec} lanes={lanes} rel.err={err:.3e}")
         assert err <= TOL_SAP[prec]
+
+
+def test_sap_lane_pair_matches_single_lane(noncubic):
+    """The two kernels compute the same visit with a different summation
+    order of the hops: they agree to FP32 rounding."""
+    c = noncubic
+    b = synth.source(c.dims, 2004)
+    x0 = 0.2 * synth.source(c.dims, 2005)
+    outs = []
+    for lanes in (1, 2):
+        xd = c.to_dev(x0, cs.F32)
+        c.op.sap_smooth_cfg(xd, c.to_dev(b, cs.F32), cs.F32, 1, cs.LaunchConfig(1, 0, lanes), n_cy=2,
+                            n_mr=4, x0_is_zero=False)
+        outs.append(c.to_host(xd, cs.F32))
+    err = rel(outs[1], outs[0])
+    print(f"lane pair vs single lane rel.diff={err:.3e}")
+    assert err <= 1e-5
 
 
 def test_sap_batched_equals_single(cfg1):
