@@ -36,7 +36,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        hdr = os.path.join(os.path.dirname(_SRC), "oracle.h")
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                    os.path.getmtime(hdr)):
             build()
         _lib = C.CDLL(_LIB)
         _declare(_lib)
@@ -73,6 +75,10 @@ def _declare(L):
                           C.c_double, C.c_int, _P, _P, C.POINTER(C.c_int),
                           C.POINTER(C.c_double), _P]
     L.or_fgcr.restype = C.c_int
+    L.or_fbicgstab.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, C.c_double,
+                               C.c_int, C.c_double, _P, _P, C.POINTER(C.c_int),
+                               C.POINTER(C.c_int), C.POINTER(C.c_double), _P]
+    L.or_fbicgstab.restype = C.c_int
     L.or_force.argtypes = [_I4, _P, C.c_double, C.c_double, _P, _P, _P, _P]
     L.or_su3_generator.argtypes = [C.c_int, _P]
 
@@ -224,6 +230,22 @@ def fgcr(dims, bdim, U, T, kappa, b, n_cy=2, n_mr=4, restart=16, tol=1e-10,
                        int(n_mr), int(restart), float(tol), int(max_iter), _ptr(b), _ptr(x),
                        C.byref(it), C.byref(rel), _ptr(hist))
     return x, st, it.value, rel.value, hist[: it.value + 1].copy()
+
+
+def fbicgstab(dims, bdim, U, T, kappa, b, n_cy=2, n_mr=4, tol=1e-10, max_iter=2000,
+              delta=0.0, x0=None):
+    """Flexible BiCGStab with the SAP preconditioner.  Returns (x, status,
+    iterations, restarts, true_relres, history)."""
+    U, b = _c128(U), _c128(b)
+    T = None if T is None else _c128(T)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    it, rs = C.c_int(0), C.c_int(0)
+    rel = C.c_double(0)
+    hist = np.zeros(max_iter + 1, np.float64)
+    st = lib().or_fbicgstab(_dims(dims), _dims(bdim), _ptr(U), _ptr(T), float(kappa), int(n_cy),
+                            int(n_mr), float(tol), int(max_iter), float(delta), _ptr(b), _ptr(x),
+                            C.byref(it), C.byref(rs), C.byref(rel), _ptr(hist))
+    return x, st, it.value, rs.value, rel.value, hist[: it.value + 1].copy()
 
 
 def force(dims, U, kappa, csw, x, y, parts=("hop", "clov")):

@@ -656,6 +656,99 @@ done:
     return status;
 }
 
+/* --------------------------------------------------------------- BiCGStab */
+
+/* Flexible BiCGStab with the SAP preconditioner on the right (the outer
+ * solver of the paper's multigrid code, Section 3; flexible because SAP with
+ * MR is not a fixed linear map), FP64.  z = M v means n_cy SAP cycles from
+ * zero on v (z = v when n_cy = 0).  One iteration:
+ *   rho' = <rh, r>;  beta = (rho' / rho)(alpha / omega);  p = r + beta (p - omega v)
+ *   ph = M p;  v = D ph;  alpha = rho' / <rh, v>;  s = r - alpha v
+ *   sh = M s;  t = D sh;  omega = <t, s> / <t, t>
+ *   x += alpha ph + omega sh;  r = s - omega t;  rho = rho'
+ * The recursive residual r stops the iteration at tol ||b|| or, when delta >
+ * 0, once it falls below delta times the last true residual; then the true
+ * residual b - D x is recomputed and, unless it meets tol, the iteration
+ * restarts from the current x with rh = r, p = v = 0, rho = alpha = omega = 1.
+ * A zero <rh, v>, <t, t> or omega also restarts; a restart whose true
+ * residual has not decreased since the previous one is a breakdown.
+ * hist[k] = recursive relative residual after iteration k (hist[0] the
+ * initial true one).  Returns 0 converged, 1 iteration cap, 2 breakdown. */
+int or_fbicgstab(const int d[4], const int b[4], const ocplx* U, const ocplx* T, double kappa,
+                 int n_cy, int n_mr, double tol, int max_iter, double delta, const ocplx* bsrc,
+                 ocplx* x, int* iters_out, int* restarts_out, double* relres_out, double* hist) {
+    long n = vol4(d) * 12;
+    ocplx *r = malloc(sizeof(ocplx) * n), *rh = malloc(sizeof(ocplx) * n);
+    ocplx *p = malloc(sizeof(ocplx) * n), *v = malloc(sizeof(ocplx) * n);
+    ocplx *s = malloc(sizeof(ocplx) * n), *t = malloc(sizeof(ocplx) * n);
+    ocplx *ph = malloc(sizeof(ocplx) * n), *sh = malloc(sizeof(ocplx) * n);
+    int status = 1, iters = 0, restarts = 0;
+    double bnorm = sqrt(vnorm2(n, bsrc)), rel = 0, last_true = 0;
+    if (bnorm == 0.0) {
+        memset(x, 0, sizeof(ocplx) * n);
+        status = 0;
+        if (hist) hist[0] = 0;
+        goto done;
+    }
+    for (;;) {
+        /* (re)start: true residual */
+        or_apply_D(d, U, T, kappa, x, t);
+        for (long i = 0; i < n; ++i) r[i] = bsrc[i] - t[i];
+        double rt = sqrt(vnorm2(n, r));
+        rel = rt / bnorm;
+        if (iters == 0 && hist) hist[0] = rel;
+        if (rel <= tol) { status = 0; break; }
+        if (iters >= max_iter) { status = 1; break; }
+        if (iters > 0 && !(rt < last_true)) { status = 2; break; }
+        if (iters > 0) ++restarts;
+        last_true = rt;
+        memcpy(rh, r, sizeof(ocplx) * n);
+        memset(p, 0, sizeof(ocplx) * n);
+        memset(v, 0, sizeof(ocplx) * n);
+        ocplx rho = 1, alpha = 1, omega = 1;
+        while (iters < max_iter) {
+            ocplx rho_new = vdot(n, rh, r);
+            ocplx beta = (rho_new / rho) * (alpha / omega);
+            for (long i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            if (n_cy > 0) {
+                memset(ph, 0, sizeof(ocplx) * n);
+                or_sap(d, b, U, T, kappa, n_cy, n_mr, p, ph);
+            } else {
+                memcpy(ph, p, sizeof(ocplx) * n);
+            }
+            or_apply_D(d, U, T, kappa, ph, v);
+            ocplx rv = vdot(n, rh, v);
+            if (rv == 0) break;
+            alpha = rho_new / rv;
+            for (long i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+            if (n_cy > 0) {
+                memset(sh, 0, sizeof(ocplx) * n);
+                or_sap(d, b, U, T, kappa, n_cy, n_mr, s, sh);
+            } else {
+                memcpy(sh, s, sizeof(ocplx) * n);
+            }
+            or_apply_D(d, U, T, kappa, sh, t);
+            double tt = vnorm2(n, t);
+            omega = tt > 0 ? vdot(n, t, s) / tt : 0;
+            for (long i = 0; i < n; ++i) {
+                x[i] += alpha * ph[i] + omega * sh[i];
+                r[i] = s[i] - omega * t[i];
+            }
+            rho = rho_new;
+            ++iters;
+            double rr = sqrt(vnorm2(n, r));
+            if (hist) hist[iters] = rr / bnorm;
+            if (rr <= tol * bnorm || omega == 0 || (delta > 0 && rr < delta * last_true)) break;
+        }
+    }
+done:
+    if (iters_out) *iters_out = iters;
+    if (restarts_out) *restarts_out = restarts;
+    if (relres_out) *relres_out = rel;
+    free(r); free(rh); free(p); free(v); free(s); free(t); free(ph); free(sh);
+    return status;
+}
+
 /* -------------------------------------------------------------------- force */
 
 /* tr(A B) for 3x3 */

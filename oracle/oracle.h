@@ -91,6 +91,11 @@ void or_sap(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T
 int or_fgcr(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T,
             double kappa, int n_cy, int n_mr, int restart, double tol, int max_iter,
             const ocplx* b, ocplx* x, int* iters, double* true_relres, double* hist);
+/* Flexible BiCGStab, SAP preconditioner on the right; see oracle.c. */
+int or_fbicgstab(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T,
+                 double kappa, int n_cy, int n_mr, double tol, int max_iter, double delta,
+                 const ocplx* b, ocplx* x, int* iters, int* restarts, double* relres,
+                 double* hist);
 
 /* Gradient of L = Re(eta^dag D^{-1} b) with respect to the left Lie-algebra
  * coordinates of every link, U -> exp(i w T^a) U, given x = D^{-1} b and

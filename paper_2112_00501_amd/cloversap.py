@@ -56,7 +56,7 @@ EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_des
             "cs_gauge_create", "cs_gauge_destroy", "cs_clover_create", "cs_clover_destroy",
             "cs_clover_export", "cs_apply_D", "cs_apply_Ddag", "cs_apply_D_cfg", "cs_sap_smooth",
             "cs_sap_smooth_cfg", "cs_autotune", "cs_solver_params_default", "cs_gcr_solve",
-            "cs_gcr_solve_dag", "cs_force", "cs_profile_enable", "cs_profile_query",
+            "cs_gcr_solve_dag", "cs_bicgstab_solve", "cs_force", "cs_profile_enable", "cs_profile_query",
             "cs_profile_reset"]
 
 
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     L.cs_solver_params_default.restype = None
     L.cs_gcr_solve.argtypes = [P, P, C.POINTER(_Params), P, P, I, C.POINTER(_Stats), P]
     L.cs_gcr_solve_dag.argtypes = [P, P, C.POINTER(_Params), P, P, I, C.POINTER(_Stats), P]
+    L.cs_bicgstab_solve.argtypes = [P, P, C.POINTER(_Params), P, P, C.POINTER(_Stats), P]
     L.cs_force.argtypes = [P, P, P, P, P, P, P]
     L.cs_profile_enable.argtypes = [I]
     L.cs_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
@@ -272,6 +273,18 @@ class Operator:
         out = [dict(iters=s.iters, restarts=s.restarts, true_relres=s.true_relres,
                     seconds=s.seconds) for s in stats]
         return st, out
+
+    def bicgstab_solve(self, x, b, params: "SolverParams", stream=None, allow_fail=False):
+        """x, b: one CS_F64 internal field each.  Solves D x = b with flexible
+        BiCGStab (SAP on the right).  Returns (status, stats)."""
+        p = params.to_c()
+        st_ = _Stats()
+        st = _lib.cs_bicgstab_solve(self.gauge.handle, self.clover.handle, C.byref(p), _ptr(x), _ptr(b),
+                                    C.byref(st_), _stream(stream))
+        if not allow_fail:
+            _check(st, "cs_bicgstab_solve")
+        return st, dict(iters=st_.iters, restarts=st_.restarts, true_relres=st_.true_relres,
+                        seconds=st_.seconds)
 
     def force(self, x, y, want_lie=True, want_grad=False, stream=None):
         """Link gradient of L given x = D^-1 b and y = D^-dag dL/dx (CS_F64

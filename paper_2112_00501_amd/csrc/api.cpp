@@ -15,6 +15,7 @@
 
 #include "../../include/cloversap.h"
 #include "blas.hpp"
+#include "bicgstab.hpp"
 #include "gcr.hpp"
 
 struct cs_lattice_s {
@@ -32,6 +33,7 @@ struct cs_clover_s {
     void* c64 = nullptr;
     void* c32 = nullptr;
     std::unique_ptr<cs::GcrWork> work;
+    std::unique_ptr<cs::BicgWork> bicg;
     void* force_H = nullptr;   // insertion matrices of the force, 864 B/site
     void* dag_tmp = nullptr;   // FP64 fields for the adjoint solve
     int dag_tmp_nrhs = 0;
@@ -551,6 +553,48 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         if (res[r].status != cs::GCR_OK && first_bad == CS_OK) first_bad = res[r].status;
     }
     if (first_bad != CS_OK) return fail(first_bad, "%s", cs_strerror(first_bad));
+    return ok();
+}
+
+int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b,
+                      cs_solver_stats* stats, void* stream) {
+    int st = check_op(g, c);
+    if (st) return st;
+    if (!p || !x || !b) return fail(CS_ERR_NULL, "params, x and b must be non-NULL");
+    if (p->max_iter < 0 || p->n_cy < 0 || (p->n_cy > 0 && p->n_mr < 1))
+        return fail(CS_ERR_INVALID, "max_iter and n_cy must be >= 0 and n_mr >= 1 when n_cy > 0");
+    if (!(p->tol >= 0.0)) return fail(CS_ERR_INVALID, "tol must be >= 0");
+    if (!valid_prec(p->inner_prec)) return fail(CS_ERR_PRECISION, "unknown inner precision");
+    if (p->n_cy > 0 && !sap_geometry_ok(g->g))
+        return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
+    const size_t f64 = cs::spinor_bytes_per_site(cs::P_F64) * (size_t)g->g.V;
+    if (overlap(b, x, f64)) return fail(CS_ERR_INVALID, "x and b overlap");
+    if (!c->bicg) c->bicg.reset(new cs::BicgWork);
+    hipError_t e = c->bicg->ensure(g->g, p->inner_prec);
+    if (e != hipSuccess) {
+        c->bicg->release();
+        return fail(CS_ERR_ALLOC, "solver workspace: %s", hipGetErrorString(e));
+    }
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_pm);
+        prof = g_prof_on;
+    }
+    const cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
+                           p->reliable_delta, cs::LaunchCfg{}, cs::LaunchCfg{}, p->use_graph != 0 && !prof};
+    cs::GcrResult res{};
+    e = cs::bicgstab_solve(make_op(g, c), gp, *c->bicg, x, b, &res, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        c->bicg->drop_graph();
+        return fail(CS_ERR_HIP, "solve: %s", hipGetErrorString(e));
+    }
+    if (stats) {
+        stats->iters = res.iters;
+        stats->restarts = res.restarts;
+        stats->true_relres = res.true_relres;
+        stats->seconds = res.seconds;
+    }
+    if (res.status != cs::GCR_OK) return fail(res.status, "%s", cs_strerror(res.status));
     return ok();
 }
 

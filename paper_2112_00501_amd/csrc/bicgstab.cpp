@@ -1,0 +1,238 @@
+// Flexible BiCGStab with the SAP preconditioner on the right (host driver):
+// the outer solver of the paper's multigrid code (Section 3), in the
+// mixed-precision form of Section 2 (low-precision smoother and w = D z,
+// FP64 everything else).  One iteration, all on the device:
+//   p = r + beta (p - omega v)               FP64, plus p in the inner precision
+//   ph = SAP(p);  v = D ph                   inner precision
+//   alpha = rho / <rh, v>;  s = r - alpha v
+//   sh = SAP(s);  t = D sh
+//   omega = <t, s> / <t, t>
+//   x += alpha ph + omega sh;  r = s - omega t
+//   rho' = <rh, r>;  beta = (rho' / rho)(alpha / omega)
+// followed by a 16-byte read of |r|^2 for the stopping test.  The true
+// residual b - D x is recomputed in FP64 when the recursive one meets the
+// tolerance, drops below reliable_delta times the last true one, or the
+// iteration breaks down (<rh, v> = 0 or omega = 0); unless it meets the
+// tolerance the iteration restarts from x with rh = r.  A restart whose true
+// residual has not decreased since the previous restart is a breakdown.
+// The kernels of one iteration are the same every time, so they are captured
+// once as a HIP graph and replayed.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "bicgstab.hpp"
+
+namespace cs {
+
+namespace {
+
+#define BI_CHK(x)                            \
+    do {                                     \
+        hipError_t e_ = (x);                 \
+        if (e_ != hipSuccess) return e_;     \
+    } while (0)
+
+int natural_out(int inner) { return inner == P_F64 ? P_F64 : P_F32; }
+
+}  // namespace
+
+void BicgWork::drop_graph() {
+    if (graph) hipGraphExecDestroy(graph);
+    graph = nullptr;
+    graph_key.clear();
+}
+
+void BicgWork::release() {
+    drop_graph();
+    for (void** q : {&r, &rh, &p, &v, &s, &t, &plo, &slo, &zp, &zs, &w}) {
+        if (*q) hipFree(*q);
+        *q = nullptr;
+    }
+    if (partials) hipFree(partials);
+    if (sc) hipFree(sc);
+    if (tail) hipFree(tail);
+    if (host_tail) hipHostFree(host_tail);
+    if (stream) hipStreamDestroy(stream);
+    partials = nullptr;
+    sc = nullptr;
+    tail = nullptr;
+    host_tail = nullptr;
+    stream = nullptr;
+    inner = -1;
+    V = 0;
+}
+
+hipError_t BicgWork::ensure(const Geom& g, int inner_) {
+    if (inner_ == inner && (size_t)g.V == V && r) return hipSuccess;
+    release();
+    inner = inner_;
+    V = g.V;
+    const size_t f64 = spinor_bytes_per_site(P_F64) * g.V;
+    const size_t lo = spinor_bytes_per_site(inner) * g.V;
+    const size_t nat = spinor_bytes_per_site(natural_out(inner)) * g.V;
+    hipError_t e;
+    for (void** q : {&r, &rh, &p, &v, &s, &t})
+        if ((e = hipMalloc(q, f64)) != hipSuccess) return e;
+    for (void** q : {&plo, &slo, &zp, &zs})
+        if ((e = hipMalloc(q, lo)) != hipSuccess) return e;
+    if ((e = hipMalloc(&w, nat)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&partials, sizeof(double2) * BLAS_MAX_WG * (MULTIDOT_CHUNK + 2))) != hipSuccess)
+        return e;
+    if ((e = hipMalloc((void**)&sc, sizeof(BiScalars))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&tail, sizeof(BiTail))) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&host_tail, sizeof(BiTail), hipHostMallocDefault)) != hipSuccess) return e;
+    if ((e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+namespace {
+
+struct Bicg {
+    const OpData& op;
+    const GcrParams& p;
+    BicgWork& w;
+    BlasCtx bc;
+    BiFields f;
+    hipStream_t s;
+
+    Bicg(const OpData& op_, const GcrParams& p_, BicgWork& w_, void* x) : op(op_), p(p_), w(w_), s(w_.stream) {
+        bc = BlasCtx{op.g, 1, nullptr, w.partials, nullptr, nullptr};
+        // without smoothing the preconditioner is the identity: z is the
+        // inner-precision copy itself
+        void* zp = p.n_cy > 0 ? w.zp : w.plo;
+        void* zs = p.n_cy > 0 ? w.zs : w.slo;
+        f = BiFields{x, w.r, w.rh, w.p, w.v, w.s, w.t, w.plo, w.slo, zp, zs, w.w};
+    }
+
+    hipError_t read_tail() {
+        BI_CHK(hipMemcpyAsync(w.host_tail, w.tail, sizeof(BiTail), hipMemcpyDeviceToHost, s));
+        return hipStreamSynchronize(s);
+    }
+
+    // z = SAP(v) from zero (z is v itself without smoothing), then w = D z
+    hipError_t precondition_apply(void* lo, void* z) {
+        for (int cy = 0; cy < p.n_cy; ++cy)
+            for (int col = 0; col < 2; ++col) {
+                const int mode = cy == 0 ? (col == 0 ? 1 : 2) : 0;
+                BI_CHK(launch_sap_halfsweep(op, p.inner, col, p.n_mr, mode, z, lo, 1, p.sap_cfg, s));
+            }
+        const int nout = natural_out(p.inner);
+        return launch_dslash(op, p.inner, nout, nout, false, w.w, z, nullptr, 1, s);
+    }
+
+    hipError_t iteration() {
+        BI_CHK(bicg_update_p(bc, w.sc, f, p.inner, s));
+        BI_CHK(precondition_apply(f.plo, f.zp));
+        BI_CHK(bicg_alpha(bc, w.sc, f, natural_out(p.inner), s));
+        BI_CHK(bicg_update_s(bc, w.sc, f, p.inner, s));
+        BI_CHK(precondition_apply(f.slo, f.zs));
+        BI_CHK(bicg_omega(bc, w.sc, f, natural_out(p.inner), s));
+        return bicg_update_xr(bc, w.sc, w.tail, f, p.inner, s);
+    }
+
+    std::vector<char> key(const void* x) const {
+        std::vector<char> k(256, 0);
+        const int vals[] = {p.n_cy, p.n_mr, p.inner, p.sap_cfg.rhs_tile, p.sap_cfg.persistent_wgs,
+                            p.sap_cfg.lanes_per_site};
+        std::memcpy(k.data(), vals, sizeof vals);
+        const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32, x};
+        std::memcpy(k.data() + sizeof vals, ptrs, sizeof ptrs);
+        std::memcpy(k.data() + sizeof vals + sizeof ptrs, &op.kappa, sizeof op.kappa);
+        return k;
+    }
+
+    hipError_t run_iteration(const void* x) {
+        if (!p.use_graph) return iteration();
+        const std::vector<char> kk = key(x);
+        if (w.graph_key != kk) {
+            w.drop_graph();
+            hipGraph_t graph;
+            BI_CHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t e = iteration();
+            hipError_t e2 = hipStreamEndCapture(s, &graph);
+            if (e != hipSuccess) return e;
+            if (e2 != hipSuccess) return e2;
+            e = hipGraphInstantiate(&w.graph, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                w.graph = nullptr;
+                return e;
+            }
+            w.graph_key = kk;
+        }
+        return hipGraphLaunch(w.graph, s);
+    }
+
+    // r = b - D x (FP64), rh = r, p = v = 0, scalars reset; returns |r|
+    hipError_t restart(const void* b, const void* x, double* rnorm) {
+        const size_t f64 = spinor_bytes_per_site(P_F64) * op.g.V;
+        BI_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, b, 1, s));
+        BI_CHK(hipMemsetAsync(w.p, 0, f64, s));
+        BI_CHK(hipMemsetAsync(w.v, 0, f64, s));
+        BI_CHK(bicg_restart(bc, w.sc, w.tail, f, s));
+        BI_CHK(read_tail());
+        *rnorm = std::sqrt(w.host_tail->rr);
+        return hipSuccess;
+    }
+};
+
+}  // namespace
+
+hipError_t bicgstab_solve(const OpData& op, const GcrParams& p, BicgWork& w, void* x, const void* b,
+                          GcrResult* res, hipStream_t user_stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    BI_CHK(hipStreamSynchronize(user_stream));  // inputs written on the caller's stream
+    Bicg B(op, p, w, x);
+    hipStream_t s = B.s;
+    const size_t f64 = spinor_bytes_per_site(P_F64) * op.g.V;
+    int status = GCR_NOT_CONVERGED, iters = 0, restarts = 0;
+    double rel = 0.0;
+
+    BI_CHK(bicg_norm2(B.bc, w.sc, w.tail, b, s));
+    BI_CHK(B.read_tail());
+    const double bnorm = std::sqrt(w.host_tail->rr);
+    if (!std::isfinite(bnorm)) {
+        status = GCR_NONFINITE;
+        rel = bnorm;
+    } else if (bnorm == 0.0) {  // D x = 0 has the unique solution x = 0
+        BI_CHK(hipMemsetAsync(x, 0, f64, s));
+        status = GCR_OK;
+    } else {
+        double last_true = 0.0;
+        for (;;) {
+            double rt;
+            BI_CHK(B.restart(b, x, &rt));
+            rel = rt / bnorm;
+            if (!std::isfinite(rel)) { status = GCR_NONFINITE; break; }
+            if (rel <= p.tol) { status = GCR_OK; break; }
+            if (iters >= p.max_iter) { status = GCR_NOT_CONVERGED; break; }
+            if (iters > 0 && !(rt < last_true)) { status = GCR_BREAKDOWN; break; }
+            if (iters > 0) ++restarts;
+            last_true = rt;
+            while (iters < p.max_iter) {
+                BI_CHK(B.run_iteration(x));
+                BI_CHK(B.read_tail());
+                const BiTail t = *w.host_tail;
+                if (t.flag & 1) break;  // abandoned: <rh, v> = 0, x and r unchanged
+                ++iters;
+                const double rr = std::sqrt(t.rr);
+                if (!std::isfinite(rr) || rr <= p.tol * bnorm || (t.flag & 2) ||
+                    (p.reliable_delta > 0.0 && rr < p.reliable_delta * last_true))
+                    break;
+            }
+        }
+    }
+    BI_CHK(hipStreamSynchronize(s));
+    if (res) {
+        res->status = status;
+        res->iters = iters;
+        res->restarts = restarts;
+        res->true_relres = rel;
+        res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return hipSuccess;
+}
+
+}  // namespace cs

@@ -357,6 +357,180 @@ __global__ __launch_bounds__(TPB) void k_solution_update(Geom g, const char* Z, 
     }
 }
 
+
+// ------------------------------------------------------------- BiCGStab
+
+enum BiStep { BI_ALPHA = 1, BI_OMEGA = 2, BI_RHO = 3, BI_RESTART = 4, BI_NORM = 5 };
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <int PI>
+__global__ __launch_bounds__(TPB) void k_bi_p(Geom g, const BiScalars* sc, BiFields f) {
+    const cpx<double> beta = {sc->beta.x, sc->beta.y}, omega = {sc->omega.x, sc->omega.y};
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> r[12], p[12], v[12];
+        ld64<P_F64>(f.r, g.nblk, blk, threadIdx.x, r);
+        ld64<P_F64>(f.p, g.nblk, blk, threadIdx.x, p);
+        ld64<P_F64>(f.v, g.nblk, blk, threadIdx.x, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
+        st64<P_F64>(f.p, g.nblk, blk, threadIdx.x, p);
+        st64<PI>(f.plo, g.nblk, blk, threadIdx.x, p);
+    }
+}
+
+// dst = w (precision PW) as FP64; partials <a, dst> (slot 0) and, with TWO,
+// <dst, b2> (slot 0) and |dst|^2 (slot 1) instead
+template <int PW, bool TWO>
+__global__ __launch_bounds__(TPB) void k_bi_take(Geom g, const BiScalars* sc, const void* w, void* dst,
+                                                 const void* a, const void* b2, double2* partials) {
+    if (sc->flag & 1) return;
+    cpx<double> acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> v[12];
+        ld64<PW>(w, g.nblk, blk, threadIdx.x, v);
+        st64<P_F64>(dst, g.nblk, blk, threadIdx.x, v);
+        cpx<double> o[12];
+        if (TWO) {
+            ld64<P_F64>(b2, g.nblk, blk, threadIdx.x, o);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                cmac_conj(acc[0], v[k], o[k]);
+                acc[1].re += v[k].re * v[k].re + v[k].im * v[k].im;
+            }
+        } else {
+            ld64<P_F64>(a, g.nblk, blk, threadIdx.x, o);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) cmac_conj(acc[0], o[k], v[k]);
+        }
+    }
+    wg_reduce_store<2>(acc, TWO ? 2 : 1, partials);
+}
+
+template <int PI>
+__global__ __launch_bounds__(TPB) void k_bi_s(Geom g, const BiScalars* sc, BiFields f) {
+    if (sc->flag & 1) return;
+    const cpx<double> alpha = {sc->alpha.x, sc->alpha.y};
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> r[12], v[12];
+        ld64<P_F64>(f.r, g.nblk, blk, threadIdx.x, r);
+        ld64<P_F64>(f.v, g.nblk, blk, threadIdx.x, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) r[k] = r[k] - alpha * v[k];
+        st64<P_F64>(f.s, g.nblk, blk, threadIdx.x, r);
+        st64<PI>(f.slo, g.nblk, blk, threadIdx.x, r);
+    }
+}
+
+template <int PI>
+__global__ __launch_bounds__(TPB) void k_bi_xr(Geom g, const BiScalars* sc, BiFields f, double2* partials) {
+    if (sc->flag & 1) return;
+    const cpx<double> alpha = {sc->alpha.x, sc->alpha.y}, omega = {sc->omega.x, sc->omega.y};
+    cpx<double> acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> x[12], zp[12], zs[12];
+        ld64<P_F64>(f.x, g.nblk, blk, threadIdx.x, x);
+        ld64<PI>(f.zp, g.nblk, blk, threadIdx.x, zp);
+        ld64<PI>(f.zs, g.nblk, blk, threadIdx.x, zs);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) x[k] = x[k] + alpha * zp[k] + omega * zs[k];
+        st64<P_F64>(f.x, g.nblk, blk, threadIdx.x, x);
+        cpx<double> s[12], t[12], rh[12];
+        ld64<P_F64>(f.s, g.nblk, blk, threadIdx.x, s);
+        ld64<P_F64>(f.t, g.nblk, blk, threadIdx.x, t);
+        ld64<P_F64>(f.rh, g.nblk, blk, threadIdx.x, rh);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            s[k] = s[k] - omega * t[k];
+            cmac_conj(acc[0], rh[k], s[k]);
+            acc[1].re += s[k].re * s[k].re + s[k].im * s[k].im;
+        }
+        st64<P_F64>(f.r, g.nblk, blk, threadIdx.x, s);
+    }
+    wg_reduce_store<2>(acc, 2, partials);
+}
+
+// rh = r; partial |r|^2 (slot 0)
+__global__ __launch_bounds__(TPB) void k_bi_restart(Geom g, BiFields f, double2* partials) {
+    cpx<double> acc[1] = {{0.0, 0.0}};
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> r[12];
+        ld64<P_F64>(f.r, g.nblk, blk, threadIdx.x, r);
+        st64<P_F64>(f.rh, g.nblk, blk, threadIdx.x, r);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[0].re += r[k].re * r[k].re + r[k].im * r[k].im;
+    }
+    wg_reduce_store<1>(acc, 1, partials);
+}
+
+__global__ __launch_bounds__(TPB) void k_bi_norm2(Geom g, const void* v, double2* partials) {
+    cpx<double> acc[1] = {{0.0, 0.0}};
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> r[12];
+        ld64<P_F64>(v, g.nblk, blk, threadIdx.x, r);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[0].re += r[k].re * r[k].re + r[k].im * r[k].im;
+    }
+    wg_reduce_store<1>(acc, 1, partials);
+}
+
+__global__ __launch_bounds__(FIN_TPB) void k_bi_finalize(const double2* partials, int nwg, BiScalars* sc,
+                                                         BiTail* tail, int step) {
+    if ((sc->flag & 1) && step != BI_RESTART && step != BI_NORM) {
+        // an abandoned iteration: x and r are unchanged, the host restarts
+        if (step == BI_RHO && threadIdx.x == 0) {
+            tail->rr = sc->rr;
+            tail->flag = sc->flag;
+        }
+        return;
+    }
+    __shared__ double2 red[FIN_TPB];
+    sum_partials<2, FIN_TPB>(partials, nwg, 0, red);
+    if (threadIdx.x != 0) return;
+    const double2 d0 = red[0], d1 = red[1];
+    if (step == BI_ALPHA) {
+        if (d0.x == 0.0 && d0.y == 0.0) {
+            sc->flag = 1;
+            sc->alpha = make_double2(0.0, 0.0);
+        } else {
+            sc->alpha = cdiv(sc->rho, d0);
+        }
+    } else if (step == BI_OMEGA) {
+        if (d1.x > 0.0) {
+            sc->omega = make_double2(d0.x / d1.x, d0.y / d1.x);
+        } else {
+            sc->omega = make_double2(0.0, 0.0);
+            sc->flag |= 2;
+        }
+        if (sc->omega.x == 0.0 && sc->omega.y == 0.0) sc->flag |= 2;
+    } else if (step == BI_RHO) {
+        const double2 rho_new = d0;
+        if (sc->flag & 2) sc->beta = make_double2(0.0, 0.0);
+        else sc->beta = cmul2(cdiv(rho_new, sc->rho), cdiv(sc->alpha, sc->omega));
+        sc->rho = rho_new;
+        sc->rr = d1.x;
+        tail->rr = d1.x;
+        tail->flag = sc->flag;
+    } else if (step == BI_RESTART) {
+        sc->rho = make_double2(d0.x, 0.0);
+        sc->rr = d0.x;
+        sc->alpha = sc->omega = make_double2(1.0, 0.0);
+        sc->beta = make_double2(0.0, 0.0);
+        sc->flag = 0;
+        tail->rr = d0.x;
+        tail->flag = 0;
+    } else {  // BI_NORM
+        tail->rr = d0.x;
+        tail->flag = 0;
+    }
+}
+
 int nwg_for(const Geom& g) { return g.nblk < BLAS_MAX_WG ? g.nblk : BLAS_MAX_WG; }
 
 hipError_t finalize(const BlasCtx& c, int nv, int v0, int step, int k, int j0, hipStream_t s) {
@@ -489,6 +663,74 @@ hipError_t blas_gcr_solution_update(const BlasCtx& c, int pz, const void* Z, siz
     const dim3 grid(nwg_for(c.g), c.nrhs);
     CS_DISPATCH_P(pz, hipLaunchKernelGGL((k_solution_update<PP>), grid, dim3(TPB), 0, s, c.g, (const char*)Z, zs, c.nrhs, x, f64_stride(c.g), c.sc, c.active));
     return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------- BiCGStab
+
+#define CS_DISPATCH_NAT(P, CALL)                                 \
+    switch (P) {                                                 \
+    case P_F64: { constexpr int PP = P_F64; CALL; } break;       \
+    case P_F32: { constexpr int PP = P_F32; CALL; } break;       \
+    default: return hipErrorInvalidValue;                        \
+    }
+
+static hipError_t bi_fin(const BlasCtx& c, BiScalars* sc, BiTail* tail, int step, hipStream_t s) {
+    hipLaunchKernelGGL(k_bi_finalize, dim3(1), dim3(FIN_TPB), 0, s, c.partials, nwg_for(c.g), sc, tail, step);
+    return hipGetLastError();
+}
+
+hipError_t bicg_update_p(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pi, hipStream_t s) {
+    ProfScope ps("blas", s);
+    CS_DISPATCH_P(pi, hipLaunchKernelGGL((k_bi_p<PP>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f));
+    return hipGetLastError();
+}
+
+hipError_t bicg_alpha(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pw, hipStream_t s) {
+    ProfScope ps("blas", s);
+    CS_DISPATCH_NAT(pw, hipLaunchKernelGGL((k_bi_take<PP, false>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f.w, f.v, f.rh, nullptr, c.partials));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return bi_fin(c, sc, nullptr, BI_ALPHA, s);
+}
+
+hipError_t bicg_update_s(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pi, hipStream_t s) {
+    ProfScope ps("blas", s);
+    CS_DISPATCH_P(pi, hipLaunchKernelGGL((k_bi_s<PP>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f));
+    return hipGetLastError();
+}
+
+hipError_t bicg_omega(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pw, hipStream_t s) {
+    ProfScope ps("blas", s);
+    CS_DISPATCH_NAT(pw, hipLaunchKernelGGL((k_bi_take<PP, true>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f.w, f.t, nullptr, f.s, c.partials));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return bi_fin(c, sc, nullptr, BI_OMEGA, s);
+}
+
+hipError_t bicg_update_xr(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, int pi,
+                          hipStream_t s) {
+    ProfScope ps("blas", s);
+    CS_DISPATCH_P(pi, hipLaunchKernelGGL((k_bi_xr<PP>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f, c.partials));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return bi_fin(c, sc, tail, BI_RHO, s);
+}
+
+hipError_t bicg_restart(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, hipStream_t s) {
+    ProfScope ps("blas", s);
+    hipLaunchKernelGGL(k_bi_restart, dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, f, c.partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return bi_fin(c, sc, tail, BI_RESTART, s);
+}
+
+hipError_t bicg_norm2(const BlasCtx& c, BiScalars* sc, BiTail* tail, const void* v, hipStream_t s) {
+    ProfScope ps("blas", s);
+    hipLaunchKernelGGL(k_bi_norm2, dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, v, c.partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return bi_fin(c, sc, tail, BI_NORM, s);
 }
 
 }  // namespace cs

@@ -78,4 +78,46 @@ hipError_t blas_gcr_solution_update(const BlasCtx& c, int zprec, const void* Z, 
 // Deterministic non-zero test pattern (for timing runs).
 hipError_t blas_fill_pattern(const BlasCtx& c, int prec, void* dst, hipStream_t s);
 
+// ---------------------------------------------------------------- BiCGStab
+// Scalars of the flexible BiCGStab iteration (one right-hand side), kept on
+// the device between kernels.
+struct BiScalars {
+    double2 rho;    // <rh, r> of the current residual
+    double2 alpha, omega, beta;
+    double rr;      // |r|^2
+    int flag;       // 1: <rh, v> = 0 (iteration abandoned); 2: omega = 0
+    int pad;
+};
+
+struct BiTail {
+    double rr;
+    int flag, pad;
+};
+
+// Fields of one BiCGStab solve: FP64 x, r, rh (shadow), p, v, s, t; inner
+// precision plo / slo (smoother inputs) and zp / zs (smoother outputs); w
+// (the operator's output, precision pw).
+struct BiFields {
+    void *x, *r, *rh, *p, *v, *s, *t;
+    void *plo, *slo, *zp, *zs, *w;
+};
+
+// p = r + beta (p - omega v), plo = p in precision pi
+hipError_t bicg_update_p(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pi, hipStream_t s);
+// v = w; alpha = rho / <rh, v> (flag 1 and alpha = 0 when <rh, v> = 0)
+hipError_t bicg_alpha(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pw, hipStream_t s);
+// s = r - alpha v, slo = s in precision pi (nothing under flag 1)
+hipError_t bicg_update_s(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pi, hipStream_t s);
+// t = w; omega = <t, s> / <t, t> (0 and flag 2 when t = 0)
+hipError_t bicg_omega(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pw, hipStream_t s);
+// x += alpha zp + omega zs, r = s - omega t; rho' = <rh, r>,
+// beta = (rho' / rho)(alpha / omega), rho = rho', rr = |r|^2 -> tail
+// (nothing under flag 1)
+hipError_t bicg_update_xr(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, int pi,
+                          hipStream_t s);
+// restart: rh = r, rho = rr = |r|^2, alpha = omega = 1, beta = 0, flag = 0 -> tail
+hipError_t bicg_restart(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, hipStream_t s);
+// |v|^2 -> tail.rr (v FP64)
+hipError_t bicg_norm2(const BlasCtx& c, BiScalars* sc, BiTail* tail, const void* v, hipStream_t s);
+
 }  // namespace cs

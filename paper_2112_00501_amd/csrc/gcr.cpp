@@ -9,7 +9,8 @@
 // Section 3).
 //
 // One iteration k (all on the device; solver scalars stay in device memory):
-//   z_k = SAP(r / |r|)                 inner precision
+//   z_k = SAP(r / |r_prev|)            inner precision (r_prev: the residual
+//                                      before the update that produced r)
 //   w_k = D z_k                        inner precision arithmetic
 //   beta_jk = <w_j_hat, w_k>, j < k    classical Gram-Schmidt, FP64
 //   w_k -= sum_j beta_jk w_j_hat; nu_k = |w_k|; c_k = <w_k_hat, r>

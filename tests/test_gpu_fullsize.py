@@ -163,3 +163,16 @@ def test_batched_24_rhs_full_size():
         r = oracle.residual_norm(dims, c.U, c.kappa, c.csw, bs[j], x[j]) / np.linalg.norm(bs[j])
         print(f"24^3x48 rhs {j} iters={stats[j]['iters']} oracle relres={r:.3e}")
         assert r <= 1e-10 * (1 + 1e-6)
+
+
+def test_bicgstab_full_size_oracle_residual(big):
+    c = big
+    bd = c.to_dev(c.b, cs.F64)
+    xd = c.lat.new_field(cs.F64).zero_()
+    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10)
+    st, stats = c.op.bicgstab_solve(xd, bd, p)
+    x = c.to_host(xd, cs.F64)
+    r = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, c.b, x) / np.linalg.norm(c.b)
+    print(f"32^3x64 BiCGStab iters={stats['iters']} restarts={stats['restarts']} oracle relres={r:.3e}")
+    assert st == 0
+    assert r <= 1e-10 * (1 + 1e-6)

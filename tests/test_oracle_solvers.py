@@ -184,3 +184,60 @@ def test_sap_and_gcr_gauge_covariant(system):
     sg, stg, itg, _, _ = oracle.fgcr(DIMS, BDIM, Ug, Tg, KAPPA, bg)
     assert it == itg
     assert np.abs(sg - gauge_transform_spinor(Om, s)).max() < 1e-9
+
+
+# ---- flexible BiCGStab (the paper's outer solver, Section 3)
+
+@pytest.mark.parametrize("n_cy", [0, 2])
+def test_fbicgstab_matches_dense_lu(system, cond2, n_cy):
+    U, T, M = system
+    b = synth.source(DIMS, 41)
+    x_lu = np.linalg.solve(M, b.reshape(-1))
+    x, st, it, rs, rel, hist = oracle.fbicgstab(DIMS, BDIM, U, T, KAPPA, b, n_cy=n_cy, tol=1e-10)
+    assert st == 0 and rel <= 1e-10
+    assert np.linalg.norm(x.reshape(-1) - x_lu) <= cond2 * 1e-10 * np.linalg.norm(x_lu)
+    assert np.linalg.norm(b.reshape(-1) - M @ x.reshape(-1)) <= 1e-10 * np.linalg.norm(b)
+    if n_cy:  # the preconditioner pays: fewer iterations than without
+        _, _, it0, _, _, _ = oracle.fbicgstab(DIMS, BDIM, U, T, KAPPA, b, n_cy=0, tol=1e-10)
+        assert it < it0
+
+
+def test_fbicgstab_recursive_residual_is_the_true_one(system):
+    """Stopped by the iteration cap, the recursive residual of the last
+    iteration must equal b - D x of the returned x: the x and r recurrences
+    use the same alpha, omega, p-hat, s-hat."""
+    U, T, M = system
+    b = synth.source(DIMS, 42)
+    for n_cy in (0, 2):
+        x, st, it, rs, rel, hist = oracle.fbicgstab(DIMS, BDIM, U, T, KAPPA, b, n_cy=n_cy,
+                                                    max_iter=3, tol=1e-14)
+        assert st == 1 and it == 3 and rs == 0
+        true = np.linalg.norm(b.reshape(-1) - M @ x.reshape(-1)) / np.linalg.norm(b)
+        assert abs(rel - true) <= 1e-12 * true
+        assert abs(hist[-1] - true) <= 1e-9 * true
+
+
+def test_fbicgstab_exact_in_one_step_at_kappa_zero():
+    U = synth.gauge_field(DIMS, 0.3, 23)
+    T = oracle.clover_field(DIMS, U, 0.0, CSW)
+    b = synth.source(DIMS, 43)
+    x, st, it, rs, rel, _ = oracle.fbicgstab(DIMS, BDIM, U, T, 0.0, b, n_cy=0, tol=1e-12)
+    assert st == 0 and it == 1 and rel == 0.0
+    assert np.abs(x - b).max() < 1e-15
+
+
+def test_fbicgstab_reliable_restarts_zero_rhs_and_covariance(system):
+    U, T, M = system
+    b = synth.source(DIMS, 44)
+    x, st, it, rs, rel, _ = oracle.fbicgstab(DIMS, BDIM, U, T, KAPPA, b, n_cy=2, tol=1e-10, delta=1e-3)
+    assert st == 0 and rel <= 1e-10 and rs >= 2
+    z = np.zeros_like(b)
+    x0, st0, it0, _, _, _ = oracle.fbicgstab(DIMS, BDIM, U, T, KAPPA, z, x0=b)
+    assert st0 == 0 and it0 == 0 and np.abs(x0).max() == 0
+    Om = synth.gauge_transform(DIMS, 4004)
+    Ug = gauge_transform_links(DIMS, U, Om)
+    Tg = oracle.clover_field(DIMS, Ug, KAPPA, CSW)
+    s, _, its, _, _, _ = oracle.fbicgstab(DIMS, BDIM, U, T, KAPPA, b, n_cy=2)
+    sg, _, itg, _, _, _ = oracle.fbicgstab(DIMS, BDIM, Ug, Tg, KAPPA, gauge_transform_spinor(Om, b), n_cy=2)
+    assert its == itg
+    assert np.abs(sg - gauge_transform_spinor(Om, s)).max() < 1e-9
