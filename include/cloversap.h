@@ -242,26 +242,33 @@ int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
 int cs_gcr_solve_dag(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
                      const void* b, int nrhs, cs_solver_stats* stats, void* stream);
 
-/* Solve D x = b with flexible BiCGStab preconditioned on the right by SAP
- * (the outer solver of the paper's multigrid code, Section 3; flexible
- * because SAP with MR is not a fixed linear map).  Per iteration: two SAP
- * applications (n_cy cycles from zero, n_mr MR steps, in inner_prec; none
- * when n_cy = 0) and two operator applications in inner_prec; every vector
- * update and inner product in FP64.  The true FP64 residual is recomputed
- * when the recursive one meets tol, drops below reliable_delta times the
- * last true one, or the iteration breaks down (<rh, v> = 0 or omega = 0);
- * unless it meets tol the iteration restarts from x.  Convergence is only
- * declared on the true residual.
+/* Solve D x = b with BiCGStab preconditioned on the right by SAP (the outer
+ * solver of the paper's multigrid code is flexible BiCGStab, Section 3;
+ * flexible because SAP with MR is not a fixed linear map).  Per iteration:
+ * two SAP applications (n_cy cycles from zero, n_mr MR steps, in inner_prec;
+ * none when n_cy = 0) and two operator applications in inner_prec; every
+ * inner product is accumulated in FP64.  basis_prec selects the form:
+ *   CS_F64  flexible BiCGStab with FP64 vectors.  The true FP64 residual is
+ *           recomputed when the recursive one meets tol, drops below
+ *           reliable_delta times the last true one (0 disables), or the
+ *           iteration breaks down (<rh, v> = 0 or omega = 0); unless it meets
+ *           tol the iteration restarts from x.
+ *   CS_F32  the QWS scheme of the paper's Section 2: BiCGStab with FP32
+ *           vectors solves D e = r / |r| to the relative tolerance
+ *           reliable_delta (0 < reliable_delta < 1), inside an FP64
+ *           Richardson iteration x += |r| e, r = b - D x.
+ * Convergence is only declared on the true FP64 residual.
  *   params  tol, max_iter (BiCGStab iterations), n_cy, n_mr, inner_prec,
- *           reliable_delta, use_graph; restart, basis_prec and rhs_tile are
- *           ignored
+ *           basis_prec (CS_F64 or CS_F32; CS_F64 when inner_prec is CS_F64),
+ *           reliable_delta, use_graph; restart and rhs_tile are ignored
  *   x, b    one CS_F64 internal field each (x holds the start vector)
  *   stats   optional; iters counts BiCGStab iterations, restarts the
- *           restarts after the first start
+ *           restarts (Richardson steps) after the first
  * Returns CS_OK, CS_NOT_CONVERGED (max_iter reached), CS_BREAKDOWN (a
  * restart without progress) or CS_NONFINITE; the same argument errors as
- * cs_gcr_solve.  Synchronises the stream; the workspace (eleven fields) is
- * kept with the clover handle. */
+ * cs_gcr_solve, and CS_ERR_INVALID for reliable_delta outside (0, 1) with
+ * CS_F32 vectors.  Synchronises the stream; the workspace (eleven or, with
+ * CS_F32 vectors, fourteen fields) is kept with the clover handle. */
 int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
                       const void* b, cs_solver_stats* stats, void* stream);
 

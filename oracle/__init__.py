@@ -79,6 +79,10 @@ def _declare(L):
                                C.c_int, C.c_double, _P, _P, C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double), _P]
     L.or_fbicgstab.restype = C.c_int
+    L.or_richardson_bicgstab.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, C.c_double,
+                                         C.c_int, C.c_double, _P, _P, C.POINTER(C.c_int),
+                                         C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.or_richardson_bicgstab.restype = C.c_int
     L.or_force.argtypes = [_I4, _P, C.c_double, C.c_double, _P, _P, _P, _P]
     L.or_su3_generator.argtypes = [C.c_int, _P]
 
@@ -246,6 +250,21 @@ def fbicgstab(dims, bdim, U, T, kappa, b, n_cy=2, n_mr=4, tol=1e-10, max_iter=20
                             int(n_mr), float(tol), int(max_iter), float(delta), _ptr(b), _ptr(x),
                             C.byref(it), C.byref(rs), C.byref(rel), _ptr(hist))
     return x, st, it.value, rs.value, rel.value, hist[: it.value + 1].copy()
+
+
+def richardson_bicgstab(dims, bdim, U, T, kappa, b, n_cy=2, n_mr=4, tol=1e-10, max_iter=2000,
+                        inner_tol=1e-5, x0=None):
+    """Richardson iteration around inner BiCGStab solves.  Returns (x, status,
+    inner iterations, outer steps, true_relres)."""
+    U, b = _c128(U), _c128(b)
+    T = None if T is None else _c128(T)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    it, outer = C.c_int(0), C.c_int(0)
+    rel = C.c_double(0)
+    st = lib().or_richardson_bicgstab(_dims(dims), _dims(bdim), _ptr(U), _ptr(T), float(kappa), int(n_cy),
+                                      int(n_mr), float(tol), int(max_iter), float(inner_tol), _ptr(b),
+                                      _ptr(x), C.byref(it), C.byref(outer), C.byref(rel))
+    return x, st, it.value, outer.value, rel.value
 
 
 def force(dims, U, kappa, csw, x, y, parts=("hop", "clov")):

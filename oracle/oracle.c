@@ -749,6 +749,54 @@ done:
     return status;
 }
 
+/* The scheme the paper's Section 2 describes for QWS: a Richardson
+ * iteration in double precision around an inner BiCGStab solve.  Each outer
+ * step recomputes r = b - D x, solves D e = r / |r| with the flexible
+ * BiCGStab above to the relative tolerance inner_tol (from e = 0, no
+ * reliable restarts), and sets x += |r| e.  Stops when the true residual
+ * meets tol; an outer step without progress is a breakdown.  iters counts
+ * inner BiCGStab iterations, outer the Richardson steps taken. */
+int or_richardson_bicgstab(const int d[4], const int b[4], const ocplx* U, const ocplx* T, double kappa,
+                           int n_cy, int n_mr, double tol, int max_iter, double inner_tol,
+                           const ocplx* bsrc, ocplx* x, int* iters_out, int* outer_out,
+                           double* relres_out) {
+    long n = vol4(d) * 12;
+    ocplx *r = malloc(sizeof(ocplx) * n), *e = malloc(sizeof(ocplx) * n);
+    int status = 1, iters = 0, outer = 0;
+    double bnorm = sqrt(vnorm2(n, bsrc)), rel = 0, last = 0;
+    if (bnorm == 0.0) {
+        memset(x, 0, sizeof(ocplx) * n);
+        status = 0;
+        goto done;
+    }
+    for (;;) {
+        or_apply_D(d, U, T, kappa, x, r);
+        for (long i = 0; i < n; ++i) r[i] = bsrc[i] - r[i];
+        double rt = sqrt(vnorm2(n, r));
+        rel = rt / bnorm;
+        if (rel <= tol) { status = 0; break; }
+        if (iters >= max_iter) { status = 1; break; }
+        if (outer > 0 && !(rt < last)) { status = 2; break; }
+        last = rt;
+        for (long i = 0; i < n; ++i) r[i] /= rt;
+        memset(e, 0, sizeof(ocplx) * n);
+        int it = 0, rs = 0;
+        double rr = 0;
+        or_fbicgstab(d, b, U, T, kappa, n_cy, n_mr, inner_tol, max_iter - iters, 0.0, r, e, &it, &rs, &rr,
+                     NULL);
+        iters += it;
+        ++outer;
+        for (long i = 0; i < n; ++i) x[i] += rt * e[i];
+    }
+done:
+    if (iters_out) *iters_out = iters;
+    if (outer_out) *outer_out = outer;
+    if (relres_out) *relres_out = rel;
+    free(r);
+    free(e);
+    return status;
+}
+
 /* -------------------------------------------------------------------- force */
 
 /* tr(A B) for 3x3 */

@@ -96,6 +96,11 @@ int or_fbicgstab(const int dims[4], const int bdim[4], const ocplx* U, const ocp
                  double kappa, int n_cy, int n_mr, double tol, int max_iter, double delta,
                  const ocplx* b, ocplx* x, int* iters, int* restarts, double* relres,
                  double* hist);
+/* FP64 Richardson iteration around inner BiCGStab solves; see oracle.c. */
+int or_richardson_bicgstab(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T,
+                           double kappa, int n_cy, int n_mr, double tol, int max_iter,
+                           double inner_tol, const ocplx* b, ocplx* x, int* iters, int* outer,
+                           double* relres);
 
 /* Gradient of L = Re(eta^dag D^{-1} b) with respect to the left Lie-algebra
  * coordinates of every link, U -> exp(i w T^a) U, given x = D^{-1} b and

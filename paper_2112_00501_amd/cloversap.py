@@ -275,8 +275,10 @@ class Operator:
         return st, out
 
     def bicgstab_solve(self, x, b, params: "SolverParams", stream=None, allow_fail=False):
-        """x, b: one CS_F64 internal field each.  Solves D x = b with flexible
-        BiCGStab (SAP on the right).  Returns (status, stats)."""
+        """x, b: one CS_F64 internal field each.  Solves D x = b with BiCGStab
+        (SAP on the right): flexible BiCGStab with FP64 vectors when
+        params.basis_prec is F64, FP32 inner solves inside an FP64 Richardson
+        iteration when it is F32.  Returns (status, stats)."""
         p = params.to_c()
         st_ = _Stats()
         st = _lib.cs_bicgstab_solve(self.gauge.handle, self.clover.handle, C.byref(p), _ptr(x), _ptr(b),

@@ -569,8 +569,14 @@ int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
     const size_t f64 = cs::spinor_bytes_per_site(cs::P_F64) * (size_t)g->g.V;
     if (overlap(b, x, f64)) return fail(CS_ERR_INVALID, "x and b overlap");
+    if (p->basis_prec != CS_F64 && p->basis_prec != CS_F32)
+        return fail(CS_ERR_PRECISION, "vector precision (basis_prec) must be CS_F64 or CS_F32");
+    if (p->inner_prec == CS_F64 && p->basis_prec != CS_F64)
+        return fail(CS_ERR_PRECISION, "an FP64 inner solve needs FP64 vectors");
+    if (p->basis_prec == CS_F32 && !(p->reliable_delta > 0.0 && p->reliable_delta < 1.0))
+        return fail(CS_ERR_INVALID, "the single-precision form needs 0 < reliable_delta < 1");
     if (!c->bicg) c->bicg.reset(new cs::BicgWork);
-    hipError_t e = c->bicg->ensure(g->g, p->inner_prec);
+    hipError_t e = c->bicg->ensure(g->g, p->inner_prec, p->basis_prec);
     if (e != hipSuccess) {
         c->bicg->release();
         return fail(CS_ERR_ALLOC, "solver workspace: %s", hipGetErrorString(e));

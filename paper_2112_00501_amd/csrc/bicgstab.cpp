@@ -17,6 +17,12 @@
 // residual has not decreased since the previous restart is a breakdown.
 // The kernels of one iteration are the same every time, so they are captured
 // once as a HIP graph and replayed.
+//
+// Single-precision form (the scheme of the paper's Section 2 for QWS): the
+// iteration vectors are FP32 and BiCGStab solves D e = r / |r| to the
+// relative tolerance reliable_delta; an FP64 Richardson iteration around it
+// recomputes r = b - D x in FP64 and adds |r| e to x until the true residual
+// meets the tolerance.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -46,7 +52,7 @@ void BicgWork::drop_graph() {
 
 void BicgWork::release() {
     drop_graph();
-    for (void** q : {&r, &rh, &p, &v, &s, &t, &plo, &slo, &zp, &zs, &w}) {
+    for (void** q : {&r, &rh, &p, &v, &s, &t, &plo, &slo, &zp, &zs, &w, &r64, &bin, &e}) {
         if (*q) hipFree(*q);
         *q = nullptr;
     }
@@ -61,29 +67,37 @@ void BicgWork::release() {
     host_tail = nullptr;
     stream = nullptr;
     inner = -1;
+    pv = -1;
     V = 0;
 }
 
-hipError_t BicgWork::ensure(const Geom& g, int inner_) {
-    if (inner_ == inner && (size_t)g.V == V && r) return hipSuccess;
+hipError_t BicgWork::ensure(const Geom& g, int inner_, int pv_) {
+    if (inner_ == inner && pv_ == pv && (size_t)g.V == V && r) return hipSuccess;
     release();
     inner = inner_;
+    pv = pv_;
     V = g.V;
     const size_t f64 = spinor_bytes_per_site(P_F64) * g.V;
+    const size_t vec = spinor_bytes_per_site(pv) * g.V;
     const size_t lo = spinor_bytes_per_site(inner) * g.V;
     const size_t nat = spinor_bytes_per_site(natural_out(inner)) * g.V;
-    hipError_t e;
-    for (void** q : {&r, &rh, &p, &v, &s, &t})
-        if ((e = hipMalloc(q, f64)) != hipSuccess) return e;
-    for (void** q : {&plo, &slo, &zp, &zs})
-        if ((e = hipMalloc(q, lo)) != hipSuccess) return e;
-    if ((e = hipMalloc(&w, nat)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&partials, sizeof(double2) * BLAS_MAX_WG * (MULTIDOT_CHUNK + 2))) != hipSuccess)
-        return e;
-    if ((e = hipMalloc((void**)&sc, sizeof(BiScalars))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&tail, sizeof(BiTail))) != hipSuccess) return e;
-    if ((e = hipHostMalloc((void**)&host_tail, sizeof(BiTail), hipHostMallocDefault)) != hipSuccess) return e;
-    if ((e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking)) != hipSuccess) return e;
+    hipError_t err;
+#define E_(x)                                   \
+    if ((err = (x)) != hipSuccess) return err
+    for (void** q : {&r, &rh, &p, &v, &s, &t}) E_(hipMalloc(q, vec));
+    for (void** q : {&plo, &slo, &zp, &zs}) E_(hipMalloc(q, lo));
+    E_(hipMalloc(&w, nat));
+    if (pv != P_F64) {
+        E_(hipMalloc(&r64, f64));
+        E_(hipMalloc(&bin, vec));
+        E_(hipMalloc(&e, vec));
+    }
+    E_(hipMalloc((void**)&partials, sizeof(double2) * BLAS_MAX_WG * (MULTIDOT_CHUNK + 2)));
+    E_(hipMalloc((void**)&sc, sizeof(BiScalars)));
+    E_(hipMalloc((void**)&tail, sizeof(BiTail)));
+    E_(hipHostMalloc((void**)&host_tail, sizeof(BiTail), hipHostMallocDefault));
+    E_(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+#undef E_
     return hipSuccess;
 }
 
@@ -97,7 +111,10 @@ struct Bicg {
     BiFields f;
     hipStream_t s;
 
-    Bicg(const OpData& op_, const GcrParams& p_, BicgWork& w_, void* x) : op(op_), p(p_), w(w_), s(w_.stream) {
+    int pv;
+
+    Bicg(const OpData& op_, const GcrParams& p_, BicgWork& w_, void* x)
+        : op(op_), p(p_), w(w_), s(w_.stream), pv(w_.pv) {
         bc = BlasCtx{op.g, 1, nullptr, w.partials, nullptr, nullptr};
         // without smoothing the preconditioner is the identity: z is the
         // inner-precision copy itself
@@ -123,18 +140,18 @@ struct Bicg {
     }
 
     hipError_t iteration() {
-        BI_CHK(bicg_update_p(bc, w.sc, f, p.inner, s));
+        BI_CHK(bicg_update_p(bc, w.sc, f, pv, p.inner, s));
         BI_CHK(precondition_apply(f.plo, f.zp));
-        BI_CHK(bicg_alpha(bc, w.sc, f, natural_out(p.inner), s));
-        BI_CHK(bicg_update_s(bc, w.sc, f, p.inner, s));
+        BI_CHK(bicg_alpha(bc, w.sc, f, pv, natural_out(p.inner), s));
+        BI_CHK(bicg_update_s(bc, w.sc, f, pv, p.inner, s));
         BI_CHK(precondition_apply(f.slo, f.zs));
-        BI_CHK(bicg_omega(bc, w.sc, f, natural_out(p.inner), s));
-        return bicg_update_xr(bc, w.sc, w.tail, f, p.inner, s);
+        BI_CHK(bicg_omega(bc, w.sc, f, pv, natural_out(p.inner), s));
+        return bicg_update_xr(bc, w.sc, w.tail, f, pv, p.inner, s);
     }
 
     std::vector<char> key(const void* x) const {
         std::vector<char> k(256, 0);
-        const int vals[] = {p.n_cy, p.n_mr, p.inner, p.sap_cfg.rhs_tile, p.sap_cfg.persistent_wgs,
+        const int vals[] = {p.n_cy, p.n_mr, p.inner, pv, p.sap_cfg.rhs_tile, p.sap_cfg.persistent_wgs,
                             p.sap_cfg.lanes_per_site};
         std::memcpy(k.data(), vals, sizeof vals);
         const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32, x};
@@ -165,15 +182,35 @@ struct Bicg {
         return hipGraphLaunch(w.graph, s);
     }
 
-    // r = b - D x (FP64), rh = r, p = v = 0, scalars reset; returns |r|
+    // r = b - D x (precision pv), rh = r, p = v = 0, scalars reset; returns |r|
     hipError_t restart(const void* b, const void* x, double* rnorm) {
-        const size_t f64 = spinor_bytes_per_site(P_F64) * op.g.V;
-        BI_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, b, 1, s));
-        BI_CHK(hipMemsetAsync(w.p, 0, f64, s));
-        BI_CHK(hipMemsetAsync(w.v, 0, f64, s));
-        BI_CHK(bicg_restart(bc, w.sc, w.tail, f, s));
+        const size_t vec = spinor_bytes_per_site(pv) * op.g.V;
+        BI_CHK(launch_dslash(op, pv, pv, pv, false, w.r, x, b, 1, s));
+        BI_CHK(hipMemsetAsync(w.p, 0, vec, s));
+        BI_CHK(hipMemsetAsync(w.v, 0, vec, s));
+        BI_CHK(bicg_restart(bc, w.sc, w.tail, f, pv, s));
         BI_CHK(read_tail());
         *rnorm = std::sqrt(w.host_tail->rr);
+        return hipSuccess;
+    }
+
+    // BiCGStab iterations from the current restart state until the recursive
+    // residual |r| is <= stop_le or < stop_lt, omega = 0, or iters reaches
+    // max_iter; *abandoned: stopped at <rh, v> = 0 (x and r unchanged)
+    hipError_t iterate(const void* x, double stop_le, double stop_lt, int* iters, bool* abandoned) {
+        *abandoned = false;
+        while (*iters < p.max_iter) {
+            BI_CHK(run_iteration(x));
+            BI_CHK(read_tail());
+            const BiTail t = *w.host_tail;
+            if (t.flag & 1) {  // x and r unchanged
+                *abandoned = true;
+                break;
+            }
+            ++*iters;
+            const double rr = std::sqrt(t.rr);
+            if (!std::isfinite(rr) || rr <= stop_le || rr < stop_lt || (t.flag & 2)) break;
+        }
         return hipSuccess;
     }
 };
@@ -184,13 +221,14 @@ hipError_t bicgstab_solve(const OpData& op, const GcrParams& p, BicgWork& w, voi
                           GcrResult* res, hipStream_t user_stream) {
     const auto t0 = std::chrono::steady_clock::now();
     BI_CHK(hipStreamSynchronize(user_stream));  // inputs written on the caller's stream
-    Bicg B(op, p, w, x);
+    const bool single = w.pv != P_F64;
+    Bicg B(op, p, w, single ? w.e : x);
     hipStream_t s = B.s;
     const size_t f64 = spinor_bytes_per_site(P_F64) * op.g.V;
     int status = GCR_NOT_CONVERGED, iters = 0, restarts = 0;
     double rel = 0.0;
 
-    BI_CHK(bicg_norm2(B.bc, w.sc, w.tail, b, s));
+    BI_CHK(bicg_norm2(B.bc, w.sc, w.tail, b, P_F64, s));
     BI_CHK(B.read_tail());
     const double bnorm = std::sqrt(w.host_tail->rr);
     if (!std::isfinite(bnorm)) {
@@ -201,26 +239,36 @@ hipError_t bicgstab_solve(const OpData& op, const GcrParams& p, BicgWork& w, voi
         status = GCR_OK;
     } else {
         double last_true = 0.0;
-        for (;;) {
+        for (int outer = 0;; ++outer) {
+            // true FP64 residual
             double rt;
-            BI_CHK(B.restart(b, x, &rt));
+            if (single) {
+                BI_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r64, x, b, 1, s));
+                BI_CHK(bicg_norm2(B.bc, w.sc, w.tail, w.r64, P_F64, s));
+                BI_CHK(B.read_tail());
+                rt = std::sqrt(w.host_tail->rr);
+            } else {
+                BI_CHK(B.restart(b, x, &rt));
+            }
             rel = rt / bnorm;
             if (!std::isfinite(rel)) { status = GCR_NONFINITE; break; }
             if (rel <= p.tol) { status = GCR_OK; break; }
             if (iters >= p.max_iter) { status = GCR_NOT_CONVERGED; break; }
-            if (iters > 0 && !(rt < last_true)) { status = GCR_BREAKDOWN; break; }
-            if (iters > 0) ++restarts;
+            if (outer > 0 && !(rt < last_true)) { status = GCR_BREAKDOWN; break; }
+            if (outer > 0) ++restarts;
             last_true = rt;
-            while (iters < p.max_iter) {
-                BI_CHK(B.run_iteration(x));
-                BI_CHK(B.read_tail());
-                const BiTail t = *w.host_tail;
-                if (t.flag & 1) break;  // abandoned: <rh, v> = 0, x and r unchanged
-                ++iters;
-                const double rr = std::sqrt(t.rr);
-                if (!std::isfinite(rr) || rr <= p.tol * bnorm || (t.flag & 2) ||
-                    (p.reliable_delta > 0.0 && rr < p.reliable_delta * last_true))
-                    break;
+            bool abandoned;
+            if (single) {
+                // FP32 BiCGStab on D e = r / |r| to reliable_delta, then x += |r| e
+                BI_CHK(bicg_demote(B.bc, w.r64, w.bin, 1.0 / rt, s));
+                BI_CHK(hipMemsetAsync(w.e, 0, spinor_bytes_per_site(w.pv) * op.g.V, s));
+                double r0;
+                BI_CHK(B.restart(w.bin, w.e, &r0));
+                BI_CHK(B.iterate(w.e, p.reliable_delta * r0, 0.0, &iters, &abandoned));
+                BI_CHK(bicg_promote_add(B.bc, x, w.e, rt, s));
+            } else {
+                BI_CHK(B.iterate(x, p.tol * bnorm, p.reliable_delta > 0.0 ? p.reliable_delta * last_true : 0.0,
+                                 &iters, &abandoned));
             }
         }
     }

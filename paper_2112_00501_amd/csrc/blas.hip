@@ -370,24 +370,27 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-template <int PI>
+// Vectors of the iteration are stored in precision PV (FP64, or FP32 for
+// the single-precision inner solve of the Richardson form); arithmetic and
+// reductions are FP64 either way.
+template <int PV, int PI>
 __global__ __launch_bounds__(TPB) void k_bi_p(Geom g, const BiScalars* sc, BiFields f) {
     const cpx<double> beta = {sc->beta.x, sc->beta.y}, omega = {sc->omega.x, sc->omega.y};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> r[12], p[12], v[12];
-        ld64<P_F64>(f.r, g.nblk, blk, threadIdx.x, r);
-        ld64<P_F64>(f.p, g.nblk, blk, threadIdx.x, p);
-        ld64<P_F64>(f.v, g.nblk, blk, threadIdx.x, v);
+        ld64<PV>(f.r, g.nblk, blk, threadIdx.x, r);
+        ld64<PV>(f.p, g.nblk, blk, threadIdx.x, p);
+        ld64<PV>(f.v, g.nblk, blk, threadIdx.x, v);
 #pragma unroll
         for (int k = 0; k < 12; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
-        st64<P_F64>(f.p, g.nblk, blk, threadIdx.x, p);
+        st64<PV>(f.p, g.nblk, blk, threadIdx.x, p);
         st64<PI>(f.plo, g.nblk, blk, threadIdx.x, p);
     }
 }
 
-// dst = w (precision PW) as FP64; partials <a, dst> (slot 0) and, with TWO,
-// <dst, b2> (slot 0) and |dst|^2 (slot 1) instead
-template <int PW, bool TWO>
+// dst = w (precision PW) stored in PV; partials <a, dst> (slot 0) or, with
+// TWO, <dst, b2> (slot 0) and |dst|^2 (slot 1)
+template <int PW, bool TWO, int PV>
 __global__ __launch_bounds__(TPB) void k_bi_take(Geom g, const BiScalars* sc, const void* w, void* dst,
                                                  const void* a, const void* b2, double2* partials) {
     if (sc->flag & 1) return;
@@ -395,17 +398,22 @@ __global__ __launch_bounds__(TPB) void k_bi_take(Geom g, const BiScalars* sc, co
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> v[12];
         ld64<PW>(w, g.nblk, blk, threadIdx.x, v);
-        st64<P_F64>(dst, g.nblk, blk, threadIdx.x, v);
+        if constexpr (PV != PW) {
+            st64<PV>(dst, g.nblk, blk, threadIdx.x, v);
+            ld64<PV>(dst, g.nblk, blk, threadIdx.x, v);  // the value every later use sees
+        } else {
+            st64<PV>(dst, g.nblk, blk, threadIdx.x, v);
+        }
         cpx<double> o[12];
         if (TWO) {
-            ld64<P_F64>(b2, g.nblk, blk, threadIdx.x, o);
+            ld64<PV>(b2, g.nblk, blk, threadIdx.x, o);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 cmac_conj(acc[0], v[k], o[k]);
                 acc[1].re += v[k].re * v[k].re + v[k].im * v[k].im;
             }
         } else {
-            ld64<P_F64>(a, g.nblk, blk, threadIdx.x, o);
+            ld64<PV>(a, g.nblk, blk, threadIdx.x, o);
 #pragma unroll
             for (int k = 0; k < 12; ++k) cmac_conj(acc[0], o[k], v[k]);
         }
@@ -413,71 +421,98 @@ __global__ __launch_bounds__(TPB) void k_bi_take(Geom g, const BiScalars* sc, co
     wg_reduce_store<2>(acc, TWO ? 2 : 1, partials);
 }
 
-template <int PI>
+template <int PV, int PI>
 __global__ __launch_bounds__(TPB) void k_bi_s(Geom g, const BiScalars* sc, BiFields f) {
     if (sc->flag & 1) return;
     const cpx<double> alpha = {sc->alpha.x, sc->alpha.y};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> r[12], v[12];
-        ld64<P_F64>(f.r, g.nblk, blk, threadIdx.x, r);
-        ld64<P_F64>(f.v, g.nblk, blk, threadIdx.x, v);
+        ld64<PV>(f.r, g.nblk, blk, threadIdx.x, r);
+        ld64<PV>(f.v, g.nblk, blk, threadIdx.x, v);
 #pragma unroll
         for (int k = 0; k < 12; ++k) r[k] = r[k] - alpha * v[k];
-        st64<P_F64>(f.s, g.nblk, blk, threadIdx.x, r);
+        st64<PV>(f.s, g.nblk, blk, threadIdx.x, r);
         st64<PI>(f.slo, g.nblk, blk, threadIdx.x, r);
     }
 }
 
-template <int PI>
+template <int PV, int PI>
 __global__ __launch_bounds__(TPB) void k_bi_xr(Geom g, const BiScalars* sc, BiFields f, double2* partials) {
     if (sc->flag & 1) return;
     const cpx<double> alpha = {sc->alpha.x, sc->alpha.y}, omega = {sc->omega.x, sc->omega.y};
     cpx<double> acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> x[12], zp[12], zs[12];
-        ld64<P_F64>(f.x, g.nblk, blk, threadIdx.x, x);
+        ld64<PV>(f.x, g.nblk, blk, threadIdx.x, x);
         ld64<PI>(f.zp, g.nblk, blk, threadIdx.x, zp);
         ld64<PI>(f.zs, g.nblk, blk, threadIdx.x, zs);
 #pragma unroll
         for (int k = 0; k < 12; ++k) x[k] = x[k] + alpha * zp[k] + omega * zs[k];
-        st64<P_F64>(f.x, g.nblk, blk, threadIdx.x, x);
+        st64<PV>(f.x, g.nblk, blk, threadIdx.x, x);
         cpx<double> s[12], t[12], rh[12];
-        ld64<P_F64>(f.s, g.nblk, blk, threadIdx.x, s);
-        ld64<P_F64>(f.t, g.nblk, blk, threadIdx.x, t);
-        ld64<P_F64>(f.rh, g.nblk, blk, threadIdx.x, rh);
+        ld64<PV>(f.s, g.nblk, blk, threadIdx.x, s);
+        ld64<PV>(f.t, g.nblk, blk, threadIdx.x, t);
+        ld64<PV>(f.rh, g.nblk, blk, threadIdx.x, rh);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s[k] = s[k] - omega * t[k];
+        st64<PV>(f.r, g.nblk, blk, threadIdx.x, s);
+        if constexpr (PV != P_F64) ld64<PV>(f.r, g.nblk, blk, threadIdx.x, s);  // the stored residual
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            s[k] = s[k] - omega * t[k];
             cmac_conj(acc[0], rh[k], s[k]);
             acc[1].re += s[k].re * s[k].re + s[k].im * s[k].im;
         }
-        st64<P_F64>(f.r, g.nblk, blk, threadIdx.x, s);
     }
     wg_reduce_store<2>(acc, 2, partials);
 }
 
 // rh = r; partial |r|^2 (slot 0)
+template <int PV>
 __global__ __launch_bounds__(TPB) void k_bi_restart(Geom g, BiFields f, double2* partials) {
     cpx<double> acc[1] = {{0.0, 0.0}};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> r[12];
-        ld64<P_F64>(f.r, g.nblk, blk, threadIdx.x, r);
-        st64<P_F64>(f.rh, g.nblk, blk, threadIdx.x, r);
+        ld64<PV>(f.r, g.nblk, blk, threadIdx.x, r);
+        st64<PV>(f.rh, g.nblk, blk, threadIdx.x, r);
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[0].re += r[k].re * r[k].re + r[k].im * r[k].im;
     }
     wg_reduce_store<1>(acc, 1, partials);
 }
 
+template <int PV>
 __global__ __launch_bounds__(TPB) void k_bi_norm2(Geom g, const void* v, double2* partials) {
     cpx<double> acc[1] = {{0.0, 0.0}};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> r[12];
-        ld64<P_F64>(v, g.nblk, blk, threadIdx.x, r);
+        ld64<PV>(v, g.nblk, blk, threadIdx.x, r);
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[0].re += r[k].re * r[k].re + r[k].im * r[k].im;
     }
     wg_reduce_store<1>(acc, 1, partials);
+}
+
+// dst (F32) = scale * src (F64)
+__global__ __launch_bounds__(TPB) void k_bi_demote(Geom g, const void* src, void* dst, double scale) {
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> v[12];
+        ld64<P_F64>(src, g.nblk, blk, threadIdx.x, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = scale * v[k];
+        st64<P_F32>(dst, g.nblk, blk, threadIdx.x, v);
+    }
+}
+
+// x (F64) += scale * e (F32)
+__global__ __launch_bounds__(TPB) void k_bi_promote_add(Geom g, void* x, const void* e, double scale) {
+    for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
+        cpx<double> xv[12], ev[12];
+        ld64<P_F64>(x, g.nblk, blk, threadIdx.x, xv);
+        ld64<P_F32>(e, g.nblk, blk, threadIdx.x, ev);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) xv[k] = xv[k] + scale * ev[k];
+        st64<P_F64>(x, g.nblk, blk, threadIdx.x, xv);
+    }
 }
 
 __global__ __launch_bounds__(FIN_TPB) void k_bi_finalize(const double2* partials, int nwg, BiScalars* sc,
@@ -668,69 +703,134 @@ hipError_t blas_gcr_solution_update(const BlasCtx& c, int pz, const void* Z, siz
 
 // ------------------------------------------------------------- BiCGStab
 
-#define CS_DISPATCH_NAT(P, CALL)                                 \
-    switch (P) {                                                 \
-    case P_F64: { constexpr int PP = P_F64; CALL; } break;       \
-    case P_F32: { constexpr int PP = P_F32; CALL; } break;       \
-    default: return hipErrorInvalidValue;                        \
-    }
-
 static hipError_t bi_fin(const BlasCtx& c, BiScalars* sc, BiTail* tail, int step, hipStream_t s) {
     hipLaunchKernelGGL(k_bi_finalize, dim3(1), dim3(FIN_TPB), 0, s, c.partials, nwg_for(c.g), sc, tail, step);
     return hipGetLastError();
 }
 
-hipError_t bicg_update_p(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pi, hipStream_t s) {
-    ProfScope ps("blas", s);
-    CS_DISPATCH_P(pi, hipLaunchKernelGGL((k_bi_p<PP>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f));
-    return hipGetLastError();
+// Calls f(integral_constant<PV>, integral_constant<PI>) for the supported
+// vector precisions (F64, F32) and inner precisions.
+template <class F>
+static hipError_t with_pv_pi(int pv, int pi, F f) {
+    auto inner = [&](auto pvt) -> hipError_t {
+        switch (pi) {
+        case P_F64: return f(pvt, std::integral_constant<int, P_F64>{});
+        case P_F32: return f(pvt, std::integral_constant<int, P_F32>{});
+        case P_F16: return f(pvt, std::integral_constant<int, P_F16>{});
+        case P_BF16: return f(pvt, std::integral_constant<int, P_BF16>{});
+        default: return hipErrorInvalidValue;
+        }
+    };
+    switch (pv) {
+    case P_F64: return inner(std::integral_constant<int, P_F64>{});
+    case P_F32: return inner(std::integral_constant<int, P_F32>{});
+    default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t bicg_alpha(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pw, hipStream_t s) {
+template <class F>
+static hipError_t with_pv(int pv, F f) {
+    switch (pv) {
+    case P_F64: return f(std::integral_constant<int, P_F64>{});
+    case P_F32: return f(std::integral_constant<int, P_F32>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t bicg_update_p(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pv, int pi, hipStream_t s) {
     ProfScope ps("blas", s);
-    CS_DISPATCH_NAT(pw, hipLaunchKernelGGL((k_bi_take<PP, false>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f.w, f.v, f.rh, nullptr, c.partials));
-    hipError_t e = hipGetLastError();
+    return with_pv_pi(pv, pi, [&](auto a, auto b) {
+        hipLaunchKernelGGL((k_bi_p<decltype(a)::value, decltype(b)::value>), dim3(nwg_for(c.g)), dim3(TPB), 0, s,
+                           c.g, sc, f);
+        return hipGetLastError();
+    });
+}
+
+hipError_t bicg_alpha(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pv, int pw, hipStream_t s) {
+    ProfScope ps("blas", s);
+    hipError_t e = with_pv_pi(pv, pw, [&](auto a, auto b) {
+        constexpr int PV = decltype(a)::value, PW = decltype(b)::value;
+        if constexpr (PW != P_F64 && PW != P_F32) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_bi_take<PW, false, PV>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f.w, f.v,
+                               f.rh, nullptr, c.partials);
+            return hipGetLastError();
+        }
+    });
     if (e != hipSuccess) return e;
     return bi_fin(c, sc, nullptr, BI_ALPHA, s);
 }
 
-hipError_t bicg_update_s(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pi, hipStream_t s) {
+hipError_t bicg_update_s(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pv, int pi, hipStream_t s) {
     ProfScope ps("blas", s);
-    CS_DISPATCH_P(pi, hipLaunchKernelGGL((k_bi_s<PP>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f));
-    return hipGetLastError();
+    return with_pv_pi(pv, pi, [&](auto a, auto b) {
+        hipLaunchKernelGGL((k_bi_s<decltype(a)::value, decltype(b)::value>), dim3(nwg_for(c.g)), dim3(TPB), 0, s,
+                           c.g, sc, f);
+        return hipGetLastError();
+    });
 }
 
-hipError_t bicg_omega(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pw, hipStream_t s) {
+hipError_t bicg_omega(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pv, int pw, hipStream_t s) {
     ProfScope ps("blas", s);
-    CS_DISPATCH_NAT(pw, hipLaunchKernelGGL((k_bi_take<PP, true>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f.w, f.t, nullptr, f.s, c.partials));
-    hipError_t e = hipGetLastError();
+    hipError_t e = with_pv_pi(pv, pw, [&](auto a, auto b) {
+        constexpr int PV = decltype(a)::value, PW = decltype(b)::value;
+        if constexpr (PW != P_F64 && PW != P_F32) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_bi_take<PW, true, PV>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f.w, f.t,
+                               nullptr, f.s, c.partials);
+            return hipGetLastError();
+        }
+    });
     if (e != hipSuccess) return e;
     return bi_fin(c, sc, nullptr, BI_OMEGA, s);
 }
 
-hipError_t bicg_update_xr(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, int pi,
+hipError_t bicg_update_xr(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, int pv, int pi,
                           hipStream_t s) {
     ProfScope ps("blas", s);
-    CS_DISPATCH_P(pi, hipLaunchKernelGGL((k_bi_xr<PP>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, sc, f, c.partials));
-    hipError_t e = hipGetLastError();
+    hipError_t e = with_pv_pi(pv, pi, [&](auto a, auto b) {
+        hipLaunchKernelGGL((k_bi_xr<decltype(a)::value, decltype(b)::value>), dim3(nwg_for(c.g)), dim3(TPB), 0, s,
+                           c.g, sc, f, c.partials);
+        return hipGetLastError();
+    });
     if (e != hipSuccess) return e;
     return bi_fin(c, sc, tail, BI_RHO, s);
 }
 
-hipError_t bicg_restart(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, hipStream_t s) {
+hipError_t bicg_restart(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, int pv, hipStream_t s) {
     ProfScope ps("blas", s);
-    hipLaunchKernelGGL(k_bi_restart, dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, f, c.partials);
-    hipError_t e = hipGetLastError();
+    hipError_t e = with_pv(pv, [&](auto a) {
+        hipLaunchKernelGGL((k_bi_restart<decltype(a)::value>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, f,
+                           c.partials);
+        return hipGetLastError();
+    });
     if (e != hipSuccess) return e;
     return bi_fin(c, sc, tail, BI_RESTART, s);
 }
 
-hipError_t bicg_norm2(const BlasCtx& c, BiScalars* sc, BiTail* tail, const void* v, hipStream_t s) {
+hipError_t bicg_norm2(const BlasCtx& c, BiScalars* sc, BiTail* tail, const void* v, int pv, hipStream_t s) {
     ProfScope ps("blas", s);
-    hipLaunchKernelGGL(k_bi_norm2, dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, v, c.partials);
-    hipError_t e = hipGetLastError();
+    hipError_t e = with_pv(pv, [&](auto a) {
+        hipLaunchKernelGGL((k_bi_norm2<decltype(a)::value>), dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, v,
+                           c.partials);
+        return hipGetLastError();
+    });
     if (e != hipSuccess) return e;
     return bi_fin(c, sc, tail, BI_NORM, s);
+}
+
+hipError_t bicg_demote(const BlasCtx& c, const void* src64, void* dst32, double scale, hipStream_t s) {
+    ProfScope ps("blas", s);
+    hipLaunchKernelGGL(k_bi_demote, dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, src64, dst32, scale);
+    return hipGetLastError();
+}
+
+hipError_t bicg_promote_add(const BlasCtx& c, void* x64, const void* e32, double scale, hipStream_t s) {
+    ProfScope ps("blas", s);
+    hipLaunchKernelGGL(k_bi_promote_add, dim3(nwg_for(c.g)), dim3(TPB), 0, s, c.g, x64, e32, scale);
+    return hipGetLastError();
 }
 
 }  // namespace cs

@@ -94,30 +94,34 @@ struct BiTail {
     int flag, pad;
 };
 
-// Fields of one BiCGStab solve: FP64 x, r, rh (shadow), p, v, s, t; inner
-// precision plo / slo (smoother inputs) and zp / zs (smoother outputs); w
-// (the operator's output, precision pw).
+// Fields of one BiCGStab solve: x, r, rh (shadow), p, v, s, t in the vector
+// precision pv (F64, or F32 for the single-precision inner solve); plo / slo
+// (smoother inputs) and zp / zs (smoother outputs) in the inner precision pi;
+// w (the operator's output) in pw (F64 or F32).
 struct BiFields {
     void *x, *r, *rh, *p, *v, *s, *t;
     void *plo, *slo, *zp, *zs, *w;
 };
 
 // p = r + beta (p - omega v), plo = p in precision pi
-hipError_t bicg_update_p(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pi, hipStream_t s);
+hipError_t bicg_update_p(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pv, int pi, hipStream_t s);
 // v = w; alpha = rho / <rh, v> (flag 1 and alpha = 0 when <rh, v> = 0)
-hipError_t bicg_alpha(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pw, hipStream_t s);
+hipError_t bicg_alpha(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pv, int pw, hipStream_t s);
 // s = r - alpha v, slo = s in precision pi (nothing under flag 1)
-hipError_t bicg_update_s(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pi, hipStream_t s);
+hipError_t bicg_update_s(const BlasCtx& c, const BiScalars* sc, const BiFields& f, int pv, int pi, hipStream_t s);
 // t = w; omega = <t, s> / <t, t> (0 and flag 2 when t = 0)
-hipError_t bicg_omega(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pw, hipStream_t s);
+hipError_t bicg_omega(const BlasCtx& c, BiScalars* sc, const BiFields& f, int pv, int pw, hipStream_t s);
 // x += alpha zp + omega zs, r = s - omega t; rho' = <rh, r>,
 // beta = (rho' / rho)(alpha / omega), rho = rho', rr = |r|^2 -> tail
 // (nothing under flag 1)
-hipError_t bicg_update_xr(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, int pi,
+hipError_t bicg_update_xr(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, int pv, int pi,
                           hipStream_t s);
 // restart: rh = r, rho = rr = |r|^2, alpha = omega = 1, beta = 0, flag = 0 -> tail
-hipError_t bicg_restart(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, hipStream_t s);
-// |v|^2 -> tail.rr (v FP64)
-hipError_t bicg_norm2(const BlasCtx& c, BiScalars* sc, BiTail* tail, const void* v, hipStream_t s);
+hipError_t bicg_restart(const BlasCtx& c, BiScalars* sc, BiTail* tail, const BiFields& f, int pv, hipStream_t s);
+// |v|^2 -> tail.rr (v in precision pv)
+hipError_t bicg_norm2(const BlasCtx& c, BiScalars* sc, BiTail* tail, const void* v, int pv, hipStream_t s);
+// dst32 = scale * src64;  x64 += scale * e32
+hipError_t bicg_demote(const BlasCtx& c, const void* src64, void* dst32, double scale, hipStream_t s);
+hipError_t bicg_promote_add(const BlasCtx& c, void* x64, const void* e32, double scale, hipStream_t s);
 
 }  // namespace cs

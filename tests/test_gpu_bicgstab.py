@@ -22,8 +22,8 @@ def cfg1():
     return Case((8, 8, 8, 8), 0.3, 0.13, 1.0, 1001)
 
 
-def _solve(c, b, inner, **kw):
-    p = cs.SolverParams(inner_prec=inner, basis_prec=cs.F64 if inner == cs.F64 else cs.F32, **kw)
+def _solve(c, b, inner, vec=cs.F64, **kw):
+    p = cs.SolverParams(inner_prec=inner, basis_prec=vec, **kw)
     bd = c.to_dev(b, cs.F64)
     xd = c.lat.new_field(cs.F64).zero_()
     st, stats = c.op.bicgstab_solve(xd, bd, p, allow_fail=True)
@@ -60,7 +60,7 @@ def test_mixed_bicgstab_reaches_fp64_residual(cfg1, inner):
 
 def test_bicgstab_zero_rhs_warm_start_and_cap(cfg1):
     c = cfg1
-    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, tol=1e-10)
+    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F64, tol=1e-10)
     # zero right-hand side: x = 0 without iterations, whatever x held
     xd = c.to_dev(synth.source(c.dims, 5), cs.F64)
     st, stats = c.op.bicgstab_solve(xd, c.lat.new_field(cs.F64).zero_(), p)
@@ -69,7 +69,7 @@ def test_bicgstab_zero_rhs_warm_start_and_cap(cfg1):
     b = synth.source(c.dims, 6)
     bd = c.to_dev(b, cs.F64)
     x1 = c.lat.new_field(cs.F64).zero_()
-    st, s1 = c.op.bicgstab_solve(x1, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, tol=1e-4))
+    st, s1 = c.op.bicgstab_solve(x1, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F64, tol=1e-4))
     x2 = x1.clone()
     st, s2 = c.op.bicgstab_solve(x2, bd, p)
     x3 = c.lat.new_field(cs.F64).zero_()
@@ -79,7 +79,7 @@ def test_bicgstab_zero_rhs_warm_start_and_cap(cfg1):
     assert rel <= 1e-10 * (1 + 1e-6)
     # iteration cap
     x4 = c.lat.new_field(cs.F64).zero_()
-    st, s4 = c.op.bicgstab_solve(x4, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, max_iter=2),
+    st, s4 = c.op.bicgstab_solve(x4, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F64, max_iter=2),
                                  allow_fail=True)
     assert st == 1 and s4["iters"] == 2 and s4["true_relres"] > 1e-10
 
@@ -88,9 +88,31 @@ def test_bicgstab_graph_replay_equals_eager(cfg1):
     c = cfg1
     b = c.to_dev(synth.source(c.dims, 7), cs.F64)
     outs = []
-    for use_graph in (False, True, True):
-        x = c.lat.new_field(cs.F64).zero_()
-        c.op.bicgstab_solve(x, b, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, use_graph=use_graph))
-        torch.cuda.synchronize()
-        outs.append(x)
-    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    for vec in (cs.F64, cs.F32):
+        outs = []
+        for use_graph in (False, True, True):
+            x = c.lat.new_field(cs.F64).zero_()
+            c.op.bicgstab_solve(x, b, cs.SolverParams(inner_prec=cs.F32, basis_prec=vec, use_graph=use_graph))
+            torch.cuda.synchronize()
+            outs.append(x)
+        assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("inner", [cs.F32, cs.F16, cs.BF16])
+def test_single_precision_richardson_form(cfg1, inner):
+    """FP32 BiCGStab vectors inside an FP64 Richardson iteration (the QWS
+    scheme, paper Section 2): the true residual still reaches 1e-10, in about
+    as many Richardson steps as the oracle's FP64 version of the scheme."""
+    for c, seed in ((cfg1, 2001), (Case((16, 16, 16, 32), 0.3, 0.1355, 1.0, 1002, oracle_T=False), 2002)):
+        b = synth.source(c.dims, seed)
+        st, stats, x = _solve(c, b, inner, vec=cs.F32, tol=1e-10, reliable_delta=1e-5)
+        rel = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, b, x) / np.linalg.norm(b)
+        print(f"{c.dims} inner={inner} iters={stats['iters']} richardson steps={stats['restarts'] + 1} "
+              f"oracle relres={rel:.3e}")
+        assert st == 0
+        assert rel <= 1e-10 * (1 + 1e-6)
+        if c is cfg1:
+            _, st_r, it_r, outer_r, _ = oracle.richardson_bicgstab(c.dims, BDIM, c.U, c.T, c.kappa, b,
+                                                                   inner_tol=1e-5)
+            print(f"  oracle: iters={it_r} richardson steps={outer_r}")
+            assert st_r == 0 and abs(stats["restarts"] + 1 - outer_r) <= 1

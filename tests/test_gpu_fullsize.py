@@ -165,14 +165,16 @@ def test_batched_24_rhs_full_size():
         assert r <= 1e-10 * (1 + 1e-6)
 
 
-def test_bicgstab_full_size_oracle_residual(big):
+@pytest.mark.parametrize("vec", [cs.F64, cs.F32])
+def test_bicgstab_full_size_oracle_residual(big, vec):
     c = big
     bd = c.to_dev(c.b, cs.F64)
     xd = c.lat.new_field(cs.F64).zero_()
-    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10)
+    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=vec, n_cy=2, n_mr=4, tol=1e-10)
     st, stats = c.op.bicgstab_solve(xd, bd, p)
     x = c.to_host(xd, cs.F64)
     r = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, c.b, x) / np.linalg.norm(c.b)
-    print(f"32^3x64 BiCGStab iters={stats['iters']} restarts={stats['restarts']} oracle relres={r:.3e}")
+    print(f"32^3x64 BiCGStab vectors={vec} iters={stats['iters']} restarts={stats['restarts']} "
+          f"oracle relres={r:.3e}")
     assert st == 0
     assert r <= 1e-10 * (1 + 1e-6)

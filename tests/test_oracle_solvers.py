@@ -241,3 +241,17 @@ def test_fbicgstab_reliable_restarts_zero_rhs_and_covariance(system):
     sg, _, itg, _, _, _ = oracle.fbicgstab(DIMS, BDIM, Ug, Tg, KAPPA, gauge_transform_spinor(Om, b), n_cy=2)
     assert its == itg
     assert np.abs(sg - gauge_transform_spinor(Om, s)).max() < 1e-9
+
+
+def test_richardson_bicgstab_matches_dense_lu(system, cond2):
+    """The QWS scheme (Section 2): FP64 Richardson around inner BiCGStab
+    solves reaches the dense solution; with an inner tolerance at the outer
+    one a single Richardson step suffices."""
+    U, T, M = system
+    b = synth.source(DIMS, 45)
+    x_lu = np.linalg.solve(M, b.reshape(-1))
+    x, st, it, outer, rel = oracle.richardson_bicgstab(DIMS, BDIM, U, T, KAPPA, b, inner_tol=1e-4)
+    assert st == 0 and rel <= 1e-10 and outer >= 2
+    assert np.linalg.norm(x.reshape(-1) - x_lu) <= cond2 * 1e-10 * np.linalg.norm(x_lu)
+    x1, st1, it1, outer1, rel1 = oracle.richardson_bicgstab(DIMS, BDIM, U, T, KAPPA, b, inner_tol=1e-12)
+    assert st1 == 0 and outer1 == 1 and rel1 <= 1e-10
