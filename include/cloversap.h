@@ -116,11 +116,16 @@ int cs_gauge_destroy(cs_gauge g);
  *   T(x) = i kappa c_sw sum_{mu<nu} sigma_{mu nu} F_{mu nu}(x),
  *   sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu],  F = (Q - Q^dag)/8,
  *   Q_{mu nu}(x) = the four counter-clockwise plaquettes at x in the plane.
- * Stored in double and float.  Synchronises the stream before returning. */
+ * Stored in double and float, together with the inverse C^-1 = (1 + T)^-1
+ * (each 6x6 chirality block inverted in double precision; used by the
+ * Jacobi form of the smoother).  Synchronises the stream before returning. */
 int cs_clover_create(cs_gauge g, double kappa, double csw, void* stream, cs_clover* out);
 int cs_clover_destroy(cs_clover c);
 /* Write T (not 1 + T) in the canonical complex128 [V][12][12] layout. */
 int cs_clover_export(cs_clover c, void* dst_canonical, void* stream);
+/* Write (1 + T)^-1 (double precision) in the canonical complex128
+ * [V][12][12] layout. */
+int cs_clover_inverse_export(cs_clover c, void* dst_canonical, void* stream);
 
 /* ---------------------------------------------------------------- operator */
 
@@ -189,6 +194,21 @@ int cs_sap_smooth_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void
 int cs_apply_D_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void* in,
                    int nrhs, const cs_launch_config* cfg, void* stream);
 
+/* The smoother in the form of the paper's QWS library (Section 2): the same
+ * multiplicative red/black SAP, for the clover-preconditioned operator
+ * A = C^-1 D = 1 + kappa C^-1 H, with every block system A_BB delta = rho
+ * solved by n_jac Jacobi steps (A_BB has the identity on its diagonal, so
+ * no inner products and no workgroup reductions are needed):
+ *   rho = C^-1 (b - D x)_B,  delta = 0,  n_jac times: delta += rho - A_BB delta,
+ *   x_B += delta.
+ * For a right-hand side b of D x = b, A x = C^-1 b is the same system, so the
+ * result smooths D x = b directly.  The Jacobi steps converge when the
+ * spectral radius of kappa (C^-1 H)_BB is below one.  Arguments as
+ * cs_sap_smooth_cfg (cfg may be NULL), n_jac >= 0. */
+int cs_sap_smooth_jacobi(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b,
+                         int n_cy, int n_jac, int x0_is_zero, int nrhs,
+                         const cs_launch_config* cfg, void* stream);
+
 /* ------------------------------------------------------------------ solver */
 
 typedef struct {
@@ -203,6 +223,9 @@ typedef struct {
                              operator launches (0: autotuned, see cs_autotune)    */
     int use_graph;        /* 1: capture each iteration's kernels as a HIP graph
                              once and replay it (ignored while profiling)         */
+    int block_solver;     /* SAP block solves: 0 = n_mr MR steps on D_BB; 1 =
+                             n_mr Jacobi steps on (C^-1 D)_BB (the form of the
+                             paper's QWS smoother, see cs_sap_smooth_jacobi)     */
 } cs_solver_params;
 
 typedef struct {

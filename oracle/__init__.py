@@ -71,6 +71,8 @@ def _declare(L):
     L.or_apply_D_block.argtypes = [_I4, _I4, C.c_long, _P, _P, C.c_double, _P, _P]
     L.or_mr_block.argtypes = [_I4, _I4, C.c_long, _P, _P, C.c_double, C.c_int, _P, _P]
     L.or_sap.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, _P, _P]
+    L.or_clover_inverse_field.argtypes = [_I4, _P, _P]
+    L.or_sap_jacobi.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, _P, _P]
     L.or_fgcr.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int,
                           C.c_double, C.c_int, _P, _P, C.POINTER(C.c_int),
                           C.POINTER(C.c_double), _P]
@@ -218,6 +220,23 @@ def sap(dims, bdim, U, T, kappa, n_cy, n_mr, b, x0=None) -> np.ndarray:
     x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
     lib().or_sap(_dims(dims), _dims(bdim), _ptr(U), _ptr(T), float(kappa), int(n_cy),
                  int(n_mr), _ptr(b), _ptr(x))
+    return x
+
+
+def clover_inverse_field(dims, T) -> np.ndarray:
+    """(1 + T(x))^-1 for every site, [V][12][12]."""
+    T = None if T is None else _c128(T)
+    out = np.zeros((volume(dims), 12, 12), np.complex128)
+    lib().or_clover_inverse_field(_dims(dims), _ptr(T), _ptr(out))
+    return out
+
+
+def sap_jacobi(dims, bdim, U, T, kappa, n_cy, n_jac, b, x0=None) -> np.ndarray:
+    U, b = _c128(U), _c128(b)
+    T = None if T is None else _c128(T)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    lib().or_sap_jacobi(_dims(dims), _dims(bdim), _ptr(U), _ptr(T), float(kappa), int(n_cy), int(n_jac),
+                        _ptr(b), _ptr(x))
     return x
 
 

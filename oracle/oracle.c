@@ -575,6 +575,101 @@ void or_sap(const int d[4], const int b[4], const ocplx* U, const ocplx* T, doub
         }
 }
 
+/* ------------------------------------------- SAP with Jacobi block solves */
+
+/* Inverse of C = 1 + T(x) (12 x 12) by Gauss-Jordan elimination with
+ * partial pivoting. */
+void or_clover_inverse_site(const ocplx* Tx, ocplx* Cinv) {
+    ocplx a[12][24];
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) {
+            a[i][j] = (Tx ? Tx[i * 12 + j] : 0) + (i == j ? 1.0 : 0.0);
+            a[i][12 + j] = i == j ? 1.0 : 0.0;
+        }
+    for (int c = 0; c < 12; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < 12; ++i)
+            if (cabs(a[i][c]) > cabs(a[piv][c])) piv = i;
+        if (piv != c)
+            for (int j = 0; j < 24; ++j) {
+                ocplx t = a[c][j];
+                a[c][j] = a[piv][j];
+                a[piv][j] = t;
+            }
+        ocplx inv = 1.0 / a[c][c];
+        for (int j = 0; j < 24; ++j) a[c][j] *= inv;
+        for (int i = 0; i < 12; ++i) {
+            if (i == c) continue;
+            ocplx f = a[i][c];
+            if (f == 0) continue;
+            for (int j = 0; j < 24; ++j) a[i][j] -= f * a[c][j];
+        }
+    }
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) Cinv[i * 12 + j] = a[i][12 + j];
+}
+
+void or_clover_inverse_field(const int d[4], const ocplx* T, ocplx* Cinv) {
+    long V = vol4(d);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (long x = 0; x < V; ++x) or_clover_inverse_site(T ? T + x * 144 : NULL, Cinv + x * 144);
+}
+
+static void m12_apply(const ocplx* M, const ocplx* v, ocplx* out) {
+    for (int i = 0; i < 12; ++i) {
+        ocplx t = 0;
+        for (int j = 0; j < 12; ++j) t += M[i * 12 + j] * v[j];
+        out[i] = t;
+    }
+}
+
+/* The smoother of QWS (paper Section 2): multiplicative SAP for the
+ * clover-preconditioned operator A = C^-1 D, each block system A_BB delta =
+ * rho solved by n_jac Jacobi steps (A_BB has the identity on its diagonal):
+ * delta = 0, then n_jac times delta += rho - A_BB delta.  For a right-hand
+ * side b of D x = b the block residual is rho = C^-1 (b - D x)_B (C is site
+ * diagonal, so A x = C^-1 b is D x = b).  Same colouring and order as
+ * or_sap. */
+void or_sap_jacobi(const int d[4], const int b[4], const ocplx* U, const ocplx* T, double kappa,
+                   int n_cy, int n_jac, const ocplx* bsrc, ocplx* x) {
+    long nblk = or_num_blocks(d, b), bv = vol4(b);
+    ocplx G[4][16];
+    load_gammas(G);
+    for (int cy = 0; cy < n_cy; ++cy)
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic)
+            for (long blk = 0; blk < nblk; ++blk) {
+                if (or_block_colour(d, b, blk) != colour) continue;
+                ocplx* rho = malloc(sizeof(ocplx) * 12 * bv);
+                ocplx* dl = calloc(12 * bv, sizeof(ocplx));
+                ocplx* q = malloc(sizeof(ocplx) * 12 * bv);
+                ocplx* ci = malloc(sizeof(ocplx) * 144 * bv);
+                for (long l = 0; l < bv; ++l) {
+                    long s = block_site(d, b, blk, l);
+                    ocplx hop[12], dx[12];
+                    hop_site(d, U, (const ocplx(*)[16])G, x, s, NULL, NULL, hop);
+                    d_site(T ? T + s * 144 : NULL, kappa, x + s * 12, hop, dx);
+                    for (int i = 0; i < 12; ++i) dx[i] = bsrc[s * 12 + i] - dx[i];
+                    or_clover_inverse_site(T ? T + s * 144 : NULL, ci + l * 144);
+                    m12_apply(ci + l * 144, dx, rho + l * 12);
+                }
+                for (int it = 0; it < n_jac; ++it) {
+                    dbb_local(d, b, blk, U, T, kappa, (const ocplx(*)[16])G, dl, q);  /* D_BB delta */
+                    for (long l = 0; l < bv; ++l) {
+                        ocplx aq[12];
+                        m12_apply(ci + l * 144, q + l * 12, aq);                    /* A_BB delta */
+                        for (int i = 0; i < 12; ++i) dl[l * 12 + i] += rho[l * 12 + i] - aq[i];
+                    }
+                }
+                for (long l = 0; l < bv; ++l) {
+                    long s = block_site(d, b, blk, l);
+                    for (int i = 0; i < 12; ++i) x[s * 12 + i] += dl[l * 12 + i];
+                }
+                free(rho); free(dl); free(q); free(ci);
+            }
+        }
+}
+
 /* -------------------------------------------------------------------- FGCR */
 
 int or_fgcr(const int d[4], const int b[4], const ocplx* U, const ocplx* T, double kappa,

@@ -88,6 +88,13 @@ void or_sap(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T
  * hist (length max_iter + 1, may be NULL) receives the recursive relative
  * residual after each iteration (hist[0] = initial true residual).
  * Returns 0 on convergence, 1 if max_iter was reached, 2 on breakdown. */
+/* C^-1 = (1 + T)^-1 per site (Gauss-Jordan); T NULL means T = 0. */
+void or_clover_inverse_site(const ocplx* T, ocplx* Cinv);
+void or_clover_inverse_field(const int dims[4], const ocplx* T, ocplx* Cinv);
+/* SAP on A = C^-1 D with n_jac Jacobi steps per block; see oracle.c. */
+void or_sap_jacobi(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T,
+                   double kappa, int n_cy, int n_jac, const ocplx* b, ocplx* x);
+
 int or_fgcr(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T,
             double kappa, int n_cy, int n_mr, int restart, double tol, int max_iter,
             const ocplx* b, ocplx* x, int* iters, double* true_relres, double* hist);

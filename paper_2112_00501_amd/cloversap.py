@@ -32,7 +32,8 @@ class CloverSapError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iter", C.c_int), ("n_cy", C.c_int), ("n_mr", C.c_int),
                 ("tol", C.c_double), ("inner_prec", C.c_int), ("basis_prec", C.c_int),
-                ("reliable_delta", C.c_double), ("rhs_tile", C.c_int), ("use_graph", C.c_int)]
+                ("reliable_delta", C.c_double), ("rhs_tile", C.c_int), ("use_graph", C.c_int),
+                ("block_solver", C.c_int)]
 
 
 class LaunchConfig(C.Structure):
@@ -54,9 +55,10 @@ _lib = None
 EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_destroy",
             "cs_lattice_volume", "cs_field_bytes", "cs_field_import", "cs_field_export",
             "cs_gauge_create", "cs_gauge_destroy", "cs_clover_create", "cs_clover_destroy",
-            "cs_clover_export", "cs_apply_D", "cs_apply_Ddag", "cs_apply_D_cfg", "cs_sap_smooth",
-            "cs_sap_smooth_cfg", "cs_autotune", "cs_solver_params_default", "cs_gcr_solve",
-            "cs_gcr_solve_dag", "cs_bicgstab_solve", "cs_force", "cs_profile_enable", "cs_profile_query",
+            "cs_clover_export", "cs_clover_inverse_export", "cs_apply_D", "cs_apply_Ddag",
+            "cs_apply_D_cfg", "cs_sap_smooth", "cs_sap_smooth_cfg", "cs_sap_smooth_jacobi",
+            "cs_autotune", "cs_solver_params_default", "cs_gcr_solve", "cs_gcr_solve_dag",
+            "cs_bicgstab_solve", "cs_force", "cs_profile_enable", "cs_profile_query",
             "cs_profile_reset"]
 
 
@@ -87,10 +89,12 @@ def load_library(path: str = LIB_PATH):
     L.cs_clover_create.argtypes = [P, D, D, P, C.POINTER(P)]
     L.cs_clover_destroy.argtypes = [P]
     L.cs_clover_export.argtypes = [P, P, P]
+    L.cs_clover_inverse_export.argtypes = [P, P, P]
     L.cs_apply_D.argtypes = [P, P, I, P, P, I, P]
     L.cs_apply_Ddag.argtypes = [P, P, I, P, P, I, P]
     L.cs_sap_smooth.argtypes = [P, P, I, P, P, I, I, I, I, P]
     L.cs_sap_smooth_cfg.argtypes = [P, P, I, P, P, I, I, I, I, C.POINTER(LaunchConfig), P]
+    L.cs_sap_smooth_jacobi.argtypes = [P, P, I, P, P, I, I, I, I, C.POINTER(LaunchConfig), P]
     L.cs_apply_D_cfg.argtypes = [P, P, I, P, P, I, C.POINTER(LaunchConfig), P]
     L.cs_autotune.argtypes = [P, P, I, I, C.POINTER(LaunchConfig), C.POINTER(LaunchConfig), P]
     L.cs_solver_params_default.argtypes = [C.POINTER(_Params)]
@@ -210,6 +214,14 @@ class Clover:
         _check(_lib.cs_clover_export(self.handle, _ptr(out), _stream(stream)), "cs_clover_export")
         return out
 
+    def export_inverse(self, stream=None) -> torch.Tensor:
+        """(1 + T)^-1 as complex128 [V][12][12] on the GPU."""
+        lat = self.gauge.lat
+        out = torch.empty((lat.volume, 12, 12), dtype=torch.complex128, device="cuda")
+        _check(_lib.cs_clover_inverse_export(self.handle, _ptr(out), _stream(stream)),
+               "cs_clover_inverse_export")
+        return out
+
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.cs_clover_destroy(self.handle)
@@ -239,6 +251,15 @@ class Operator:
         _check(_lib.cs_sap_smooth_cfg(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
                                       int(n_cy), int(n_mr), int(bool(x0_is_zero)), nrhs,
                                       C.byref(cfg), _stream(stream)), "cs_sap_smooth_cfg")
+        return x
+
+    def sap_smooth_jacobi(self, x, b, prec, n_cy=2, n_jac=4, x0_is_zero=True, nrhs=1, cfg=None,
+                          stream=None):
+        """SAP on C^-1 D with n_jac Jacobi steps per block (the QWS smoother form)."""
+        _check(_lib.cs_sap_smooth_jacobi(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
+                                         int(n_cy), int(n_jac), int(bool(x0_is_zero)), nrhs,
+                                         None if cfg is None else C.byref(cfg), _stream(stream)),
+               "cs_sap_smooth_jacobi")
         return x
 
     def autotune(self, prec, nrhs, stream=None):
@@ -313,11 +334,12 @@ class SolverParams:
     reliable_delta: float = 1e-5
     rhs_tile: int = 0
     use_graph: bool = True
+    block_solver: int = 0     # 0: n_mr MR steps on D_BB; 1: n_mr Jacobi steps on (C^-1 D)_BB
 
     def to_c(self) -> _Params:
         return _Params(self.restart, self.max_iter, self.n_cy, self.n_mr, self.tol,
                        self.inner_prec, self.basis_prec, self.reliable_delta, self.rhs_tile,
-                       int(bool(self.use_graph)))
+                       int(bool(self.use_graph)), int(self.block_solver))
 
 
 def profile_enable(on: bool = True):

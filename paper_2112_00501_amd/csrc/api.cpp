@@ -32,6 +32,8 @@ struct cs_clover_s {
     double kappa = 0, csw = 0;
     void* c64 = nullptr;
     void* c32 = nullptr;
+    void* ci64 = nullptr;   // (1 + T)^-1
+    void* ci32 = nullptr;
     std::unique_ptr<cs::GcrWork> work;
     std::unique_ptr<cs::BicgWork> bicg;
     void* force_H = nullptr;   // insertion matrices of the force, 864 B/site
@@ -74,6 +76,8 @@ cs::OpData make_op(const cs_gauge_s* g, const cs_clover_s* c) {
     for (int i = 0; i < 4; ++i) op.links[i] = g->links[i];
     op.clover64 = c->c64;
     op.clover32 = c->c32;
+    op.cinv64 = c->ci64;
+    op.cinv32 = c->ci32;
     op.kappa = c->kappa;
     return op;
 }
@@ -263,12 +267,15 @@ int cs_clover_create(cs_gauge g, double kappa, double csw, void* stream, cs_clov
     c->kappa = kappa;
     c->csw = csw;
     if (hipMalloc(&c->c64, cs::clover_bytes_per_site(cs::P_F64) * g->g.V) != hipSuccess ||
-        hipMalloc(&c->c32, cs::clover_bytes_per_site(cs::P_F32) * g->g.V) != hipSuccess) {
+        hipMalloc(&c->c32, cs::clover_bytes_per_site(cs::P_F32) * g->g.V) != hipSuccess ||
+        hipMalloc(&c->ci64, cs::clover_bytes_per_site(cs::P_F64) * g->g.V) != hipSuccess ||
+        hipMalloc(&c->ci32, cs::clover_bytes_per_site(cs::P_F32) * g->g.V) != hipSuccess) {
         cs_clover_destroy(c);
         return fail(CS_ERR_ALLOC, "could not allocate the clover term");
     }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = cs::launch_clover_build(g->g, g->links[cs::P_F64], kappa, csw, c->c64, c->c32, s);
+    if (e == hipSuccess) e = cs::launch_clover_invert(g->g, c->c64, c->ci64, c->ci32, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         cs_clover_destroy(c);
@@ -285,13 +292,21 @@ int cs_clover_destroy(cs_clover c) {
     if (c->dag_tmp) hipFree(c->dag_tmp);
     if (c->c64) hipFree(c->c64);
     if (c->c32) hipFree(c->c32);
+    if (c->ci64) hipFree(c->ci64);
+    if (c->ci32) hipFree(c->ci32);
     delete c;
     return ok();
 }
 
 int cs_clover_export(cs_clover c, void* dst, void* stream) {
     if (!c || !dst) return fail(CS_ERR_NULL, "clover and dst must be non-NULL");
-    CS_HIP(cs::launch_clover_export(c->gauge->g, c->c64, dst, (hipStream_t)stream));
+    CS_HIP(cs::launch_clover_export(c->gauge->g, c->c64, dst, false, (hipStream_t)stream));
+    return ok();
+}
+
+int cs_clover_inverse_export(cs_clover c, void* dst, void* stream) {
+    if (!c || !dst) return fail(CS_ERR_NULL, "clover and dst must be non-NULL");
+    CS_HIP(cs::launch_clover_export(c->gauge->g, c->ci64, dst, true, (hipStream_t)stream));
     return ok();
 }
 
@@ -341,8 +356,8 @@ int cs_apply_D_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* out, const void*
     return apply(g, c, prec, out, in, nrhs, cfg, stream, false);
 }
 
-int cs_sap_smooth_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
-                      int x0_is_zero, int nrhs, const cs_launch_config* cfg, void* stream) {
+static int sap_common(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
+                      int x0_is_zero, int nrhs, const cs_launch_config* cfg, void* stream, int solver) {
     int st = check_op(g, c);
     if (st) return st;
     if (!x || !b) return fail(CS_ERR_NULL, "x and b must be non-NULL");
@@ -363,9 +378,19 @@ int cs_sap_smooth_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void
     for (int cy = 0; cy < n_cy; ++cy)
         for (int col = 0; col < 2; ++col) {
             const int mode = (x0_is_zero && cy == 0) ? (col == 0 ? 1 : 2) : 0;
-            CS_HIP(cs::launch_sap_halfsweep(op, prec, col, n_mr, mode, x, b, nrhs, lc, s));
+            CS_HIP(cs::launch_sap_halfsweep(op, prec, col, n_mr, mode, x, b, nrhs, lc, s, solver));
         }
     return ok();
+}
+
+int cs_sap_smooth_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
+                      int x0_is_zero, int nrhs, const cs_launch_config* cfg, void* stream) {
+    return sap_common(g, c, prec, x, b, n_cy, n_mr, x0_is_zero, nrhs, cfg, stream, cs::BLOCK_MR);
+}
+
+int cs_sap_smooth_jacobi(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_jac,
+                         int x0_is_zero, int nrhs, const cs_launch_config* cfg, void* stream) {
+    return sap_common(g, c, prec, x, b, n_cy, n_jac, x0_is_zero, nrhs, cfg, stream, cs::BLOCK_JACOBI);
 }
 
 int cs_sap_smooth(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
@@ -480,6 +505,7 @@ void cs_solver_params_default(cs_solver_params* p) {
     p->reliable_delta = 1e-5;
     p->rhs_tile = 0;
     p->use_graph = 1;
+    p->block_solver = 0;
 }
 
 static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
@@ -492,6 +518,7 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
     if (p->max_iter < 0 || p->n_cy < 0 || (p->n_cy > 0 && p->n_mr < 1))
         return fail(CS_ERR_INVALID, "max_iter and n_cy must be >= 0 and n_mr >= 1 when n_cy > 0");
     if (!(p->tol >= 0.0)) return fail(CS_ERR_INVALID, "tol must be >= 0");
+    if (p->block_solver != 0 && p->block_solver != 1) return fail(CS_ERR_INVALID, "block_solver must be 0 or 1");
     if (!valid_prec(p->inner_prec)) return fail(CS_ERR_PRECISION, "unknown inner precision");
     if (p->basis_prec != CS_F64 && p->basis_prec != CS_F32)
         return fail(CS_ERR_PRECISION, "basis precision must be CS_F64 or CS_F32");
@@ -535,7 +562,7 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         prof = g_prof_on;
     }
     const cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
-                           p->reliable_delta, sap_cfg, d_cfg, p->use_graph != 0 && !prof};
+                           p->reliable_delta, sap_cfg, d_cfg, p->use_graph != 0 && !prof, p->block_solver};
     std::vector<cs::GcrResult> res(nrhs);
     e = cs::gcr_solve(make_op(g, c), gp, *c->work, x, b, nrhs, dagger, c->dag_tmp, res.data(), s);
     if (e != hipSuccess) {
@@ -564,6 +591,7 @@ int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
     if (p->max_iter < 0 || p->n_cy < 0 || (p->n_cy > 0 && p->n_mr < 1))
         return fail(CS_ERR_INVALID, "max_iter and n_cy must be >= 0 and n_mr >= 1 when n_cy > 0");
     if (!(p->tol >= 0.0)) return fail(CS_ERR_INVALID, "tol must be >= 0");
+    if (p->block_solver != 0 && p->block_solver != 1) return fail(CS_ERR_INVALID, "block_solver must be 0 or 1");
     if (!valid_prec(p->inner_prec)) return fail(CS_ERR_PRECISION, "unknown inner precision");
     if (p->n_cy > 0 && !sap_geometry_ok(g->g))
         return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
@@ -587,7 +615,8 @@ int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         prof = g_prof_on;
     }
     const cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
-                           p->reliable_delta, cs::LaunchCfg{}, cs::LaunchCfg{}, p->use_graph != 0 && !prof};
+                           p->reliable_delta, cs::LaunchCfg{}, cs::LaunchCfg{}, p->use_graph != 0 && !prof,
+                           p->block_solver};
     cs::GcrResult res{};
     e = cs::bicgstab_solve(make_op(g, c), gp, *c->bicg, x, b, &res, (hipStream_t)stream);
     if (e != hipSuccess) {

@@ -133,7 +133,8 @@ struct Bicg {
         for (int cy = 0; cy < p.n_cy; ++cy)
             for (int col = 0; col < 2; ++col) {
                 const int mode = cy == 0 ? (col == 0 ? 1 : 2) : 0;
-                BI_CHK(launch_sap_halfsweep(op, p.inner, col, p.n_mr, mode, z, lo, 1, p.sap_cfg, s));
+                BI_CHK(launch_sap_halfsweep(op, p.inner, col, p.n_mr, mode, z, lo, 1, p.sap_cfg, s,
+                                            p.block_solver));
             }
         const int nout = natural_out(p.inner);
         return launch_dslash(op, p.inner, nout, nout, false, w.w, z, nullptr, 1, s);
@@ -151,7 +152,7 @@ struct Bicg {
 
     std::vector<char> key(const void* x) const {
         std::vector<char> k(256, 0);
-        const int vals[] = {p.n_cy, p.n_mr, p.inner, pv, p.sap_cfg.rhs_tile, p.sap_cfg.persistent_wgs,
+        const int vals[] = {p.n_cy, p.n_mr, p.block_solver, p.inner, pv, p.sap_cfg.rhs_tile, p.sap_cfg.persistent_wgs,
                             p.sap_cfg.lanes_per_site};
         std::memcpy(k.data(), vals, sizeof vals);
         const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32, x};

@@ -283,7 +283,10 @@ hipError_t launch_import_links(const Geom& g, const void* U_canonical, void* l64
                                void* l16, void* lbf16, hipStream_t s);
 hipError_t launch_clover_build(const Geom& g, const void* links64, double kappa, double csw,
                                void* c64, void* c32, hipStream_t s);
-hipError_t launch_clover_export(const Geom& g, const void* c64, void* dst, hipStream_t s);
+// canonical [V][12][12]: T (inverse false) or the packed matrix itself (true)
+hipError_t launch_clover_export(const Geom& g, const void* c64, void* dst, bool inverse, hipStream_t s);
+// (1 + T)^-1 per site, packed like the clover term, FP64 and FP32
+hipError_t launch_clover_invert(const Geom& g, const void* c64, void* ci64, void* ci32, hipStream_t s);
 hipError_t launch_field_import(const Geom& g, int prec, void* dst, const void* src, int nrhs,
                                hipStream_t s);
 hipError_t launch_field_export(const Geom& g, int prec, void* dst, const void* src, int nrhs,
@@ -299,6 +302,8 @@ struct OpData {
     const void* links[4];   // indexed by Prec
     const void* clover64;
     const void* clover32;
+    const void* cinv64;     // (1 + T)^-1, same packing
+    const void* cinv32;
     double kappa;
 };
 hipError_t launch_dslash(const OpData& op, int in_prec, int out_prec, int link_prec, bool dagger,
@@ -321,11 +326,15 @@ hipError_t launch_dslash_tiled(const OpData& op, int prec, bool dagger, void* ou
 
 // sap.hip: one half-sweep over the blocks of one colour.  mode 0: general;
 // 1: x is zero everywhere (r = b); 2: x is zero on the blocks of this colour.
-hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode,
-                                void* x, const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s);
+// Block solver: BLOCK_MR, n_block MR steps on D_BB; BLOCK_JACOBI, n_block
+// Jacobi steps on A_BB = (C^-1 D)_BB.
+enum { BLOCK_MR = 0, BLOCK_JACOBI = 1 };
+hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_block, int mode,
+                                void* x, const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s,
+                                int block_solver = BLOCK_MR);
 // sap_pair.hip: the same half-sweep with two lanes per site (FP32, FP16, BF16).
-hipError_t launch_sap_pair(const OpData& op, int prec, int colour, int n_mr, int mode, void* x, const void* b,
-                           int nrhs, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_sap_pair(const OpData& op, int prec, int colour, int n_block, int mode, void* x,
+                           const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s, int block_solver);
 
 // force.hip: g_{mu,a}(x) = dL/dw of L with dL = -Re(y^dag dD x); either output
 // may be null.  Hbuf holds 864 bytes per site (insertion matrices).

@@ -163,7 +163,8 @@ struct Solver {
             for (int cy = 0; cy < p.n_cy; ++cy)
                 for (int col = 0; col < 2; ++col) {
                     const int mode = cy == 0 ? (col == 0 ? 1 : 2) : 0;
-                    GCR_CHK(launch_sap_halfsweep(op, p.inner, col, p.n_mr, mode, zk, w.rlo, n, p.sap_cfg, s));
+                    GCR_CHK(launch_sap_halfsweep(op, p.inner, col, p.n_mr, mode, zk, w.rlo, n, p.sap_cfg, s,
+                                                 p.block_solver));
                 }
         } else {
             GCR_CHK(blas_convert(bc, p.inner, zk, P_F64, w.r, true, s));
@@ -177,7 +178,7 @@ struct Solver {
 
     std::vector<char> key() const {
         std::vector<char> kbuf(256, 0);
-        const int vals[] = {p.restart, p.n_cy, p.n_mr, p.inner, p.basis, p.sap_cfg.rhs_tile,
+        const int vals[] = {p.restart, p.n_cy, p.n_mr, p.block_solver, p.inner, p.basis, p.sap_cfg.rhs_tile,
                             p.sap_cfg.persistent_wgs, p.sap_cfg.lanes_per_site, p.dslash_cfg.rhs_tile,
                             p.dslash_cfg.persistent_wgs, n};
         std::memcpy(kbuf.data(), vals, sizeof vals);

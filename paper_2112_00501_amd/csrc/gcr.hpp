@@ -17,6 +17,7 @@ struct GcrParams {
     double reliable_delta;
     LaunchCfg sap_cfg, dslash_cfg;  // multi-right-hand-side launch shapes
     bool use_graph;                 // replay each iteration as a captured HIP graph
+    int block_solver;               // BLOCK_MR or BLOCK_JACOBI (n_mr steps either way)
 };
 
 struct GcrResult {

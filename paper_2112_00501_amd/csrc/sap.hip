@@ -119,6 +119,52 @@ __device__ __forceinline__ void face_pair(const Geom& g, const BlockPos& p, int 
     face_apply<MB>(l, kb, pb, ub, sm, acc);
 }
 
+// out = M in for a packed clover-format matrix M read from global memory one
+// chirality block at a time (36 reals live instead of 72).
+template <typename R>
+__device__ __forceinline__ void clover_apply_by_chirality(const void* m, int blk, int l, const cpx<R>* in,
+                                                          cpx<R>* out) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        R d[36];
+        if constexpr (std::is_same<R, double>::value) {
+            const double2* p = (const double2*)m + ((size_t)blk * 36 + 18 * h) * BLOCK_SITES + l;
+#pragma unroll
+            for (int k = 0; k < 18; ++k) {
+                const double2 v = p[k * BLOCK_SITES];
+                d[2 * k] = v.x;
+                d[2 * k + 1] = v.y;
+            }
+        } else {
+            const float4* p = (const float4*)m + ((size_t)blk * 18 + 9 * h) * BLOCK_SITES + l;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float4 v = p[k * BLOCK_SITES];
+                d[4 * k] = v.x;
+                d[4 * k + 1] = v.y;
+                d[4 * k + 2] = v.z;
+                d[4 * k + 3] = v.w;
+            }
+        }
+        const R* up = d + 6;
+        const cpx<R>* v = in + 6 * h;
+        cpx<R> o[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) o[i] = d[i] * v[i];
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j, ++k) {
+                const cpx<R> a = {up[2 * k], up[2 * k + 1]};
+                cmac(o[i], a, v[j]);
+                cmac_conj(o[j], a, v[i]);
+            }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) out[6 * h + i] = o[i];
+    }
+}
+
 // Sum of three values over the 256 lanes; every lane receives the same total.
 template <typename R>
 __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
@@ -146,7 +192,15 @@ __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
 // clover are read from HBM once per tile instead of once per right-hand side.
 // With gridDim.x < nitems the launch is persistent: workgroups stride over
 // the work items.
-template <int P, int PLINK>
+//
+// BS = BLOCK_JACOBI: the block system of A = C^-1 D is solved instead, by
+// Jacobi steps (A_BB has the identity on its diagonal); `clover` is then
+// (1 + T)^-1 and the visit is
+//   rho = C^-1 (b + kappa hop(x)) - x_B      (= C^-1 (b - D x)_B)
+//   delta = rho;  n_mr - 1 times: delta = rho + kappa C^-1 hop_BB(delta)
+//   x_B += delta
+// (hop = the hopping sum, D = C - kappa hop), with no reductions.
+template <int P, int PLINK, int BS>
 __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ links,
                                               const void* __restrict__ clover, double kappa_d,
                                               int colour, int n_mr, int mode, void* __restrict__ x,
@@ -155,6 +209,10 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
     using R = typename Arith<P>::R;
     constexpr bool F32PATH = std::is_same<R, float>::value;
     __shared__ cpx<R> s_rho[12][BLOCK_SITES];
+    // FP64 Jacobi keeps the block residual in LDS instead of registers (the
+    // FP64 kernel runs one workgroup per compute unit either way)
+    constexpr bool RHO_LDS = BS == BLOCK_JACOBI && !F32PATH;
+    __shared__ cpx<R> s_rho0[RHO_LDS ? 12 : 1][RHO_LDS ? BLOCK_SITES : 1];
     __shared__ LinkSmem<F32PATH> s_lk;
     __shared__ R s_red[3][4];
 
@@ -189,7 +247,8 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
             char* xr = (char*)x + (size_t)r * stride;
             const char* br = (const char*)b + (size_t)r * stride;
 
-            // ---- block residual r_B = b_B - (D x)_B, stored as rho in LDS
+            // ---- block residual r_B = b_B - (D x)_B (Jacobi: C^-1 r_B), stored as rho in LDS
+            cpx<R> rho0[12];
             if constexpr (F32PATH && CS_SAP_LDS_RESIDUAL) {
                 // own x staged in LDS: the hops inside the block read it (and
                 // the links) from LDS; the face hops read HBM two directions
@@ -213,23 +272,35 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                     face_pair<2, 3, P, R>(g, p, l, xr, links, s_lk, acc);
                 }
                 cpx<R> cx[12];
+                cpx<R> self[12];
                 if (mode == 0) {
-                    cpx<R> self[12];
                     ls.load_nb(0, l, true, self);
-                    clover_apply(cl, self, cx);
+                    if constexpr (BS == BLOCK_MR) clover_apply(cl, self, cx);
                 } else {
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) cx[k] = {(R)0, (R)0};
+                    for (int k = 0; k < 12; ++k) cx[k] = self[k] = {(R)0, (R)0};
                 }
                 using RS = typename SpinorIO<P>::R;
                 cpx<RS> t[12];
                 SpinorIO<P>::load(br, g.nblk, blk, l, t);
+                if constexpr (BS == BLOCK_MR) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        rho0[k] = {(R)t[k].re - (cx[k].re - kappa * acc[k].re),
+                                   (R)t[k].im - (cx[k].im - kappa * acc[k].im)};
+                } else {
+                    cpx<R> u[12];
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        u[k] = {(R)t[k].re + kappa * acc[k].re, (R)t[k].im + kappa * acc[k].im};
+                    clover_apply(cl, u, rho0);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) rho0[k] = rho0[k] - self[k];
+                }
                 __syncthreads();  // every lane has read x from rho
 #pragma unroll
-                for (int k = 0; k < 12; ++k)
-                    s_rho[k][l] = {(R)t[k].re - (cx[k].re - kappa * acc[k].re),
-                                   (R)t[k].im - (cx[k].im - kappa * acc[k].im)};
-            } else {
+                for (int k = 0; k < 12; ++k) s_rho[k][l] = rho0[k];
+            } else if constexpr (BS == BLOCK_MR) {
                 cpx<R> acc[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
@@ -259,16 +330,85 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 using RS = typename SpinorIO<P>::R;
                 cpx<RS> t[12];
                 SpinorIO<P>::load(br, g.nblk, blk, l, t);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) rho0[k] = {(R)t[k].re - acc[k].re, (R)t[k].im - acc[k].im};
                 __syncthreads();  // the previous right-hand side's readers of rho are done
 #pragma unroll
-                for (int k = 0; k < 12; ++k) s_rho[k][l] = {(R)t[k].re - acc[k].re, (R)t[k].im - acc[k].im};
+                for (int k = 0; k < 12; ++k) s_rho[k][l] = rho0[k];
+            } else {
+                // Jacobi: rho = C^-1 (b + kappa hop) - x
+                cpx<R> acc[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+                if (mode != 1) {
+                    GlobalLinks<PLINK> glk{links};
+                    if (mode == 0) {
+                        GlobalSpinor<P, false> gs{xr, g.nblk};
+                        hopping_sum_rolled<R>(g, p, l, gs, glk, acc);
+                    } else {
+                        OutsideSpinor<P> os{xr, g.nblk};
+                        hopping_sum_rolled<R>(g, p, l, os, glk, acc);
+                    }
+                }
+                using RS = typename SpinorIO<P>::R;
+                cpx<RS> t[12];
+                SpinorIO<P>::load(br, g.nblk, blk, l, t);
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    acc[k] = {(R)t[k].re + kappa * acc[k].re, (R)t[k].im + kappa * acc[k].im};
+                if constexpr (F32PATH) clover_apply(cl, acc, rho0);
+                else clover_apply_by_chirality<R>(clover, blk, l, acc, rho0);
+                if (mode == 0) {
+                    using RS = typename SpinorIO<P>::R;
+                    cpx<RS> xs[12];
+                    SpinorIO<P>::load(xr, g.nblk, blk, l, xs);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) rho0[k] = {rho0[k].re - (R)xs[k].re, rho0[k].im - (R)xs[k].im};
+                }
+                __syncthreads();  // the previous right-hand side's readers of rho are done
+#pragma unroll
+                for (int k = 0; k < 12; ++k) s_rho[k][l] = rho0[k];
             }
 
-            // ---- MR on the Dirichlet block operator; rho lives in LDS only
             cpx<R> delta[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) delta[k] = {(R)0, (R)0};
-            for (int it = 0; it < n_mr; ++it) {
+            if constexpr (BS == BLOCK_JACOBI) {
+                // ---- Jacobi steps on A_BB; the current delta lives in LDS
+                if (n_mr > 0) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) delta[k] = rho0[k];
+                }
+                if constexpr (RHO_LDS) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) s_rho0[k][l] = rho0[k];
+                }
+                for (int it = 1; it < n_mr; ++it) {
+                    __syncthreads();  // delta of every site is in LDS
+                    cpx<R> acc[12];
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+                    if constexpr (F32PATH) {
+                        LdsLinks lk{&s_lk};
+                        hopping_sum<R>(g, p, l, ls, lk, acc);
+                        clover_apply(cl, acc, delta);
+                    } else {
+                        GlobalLinks<PLINK, false> lk{links};
+                        hopping_sum_rolled<R>(g, p, l, ls, lk, acc);
+                        clover_apply_by_chirality<R>(clover, blk, l, acc, delta);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        const cpx<R> r0 = RHO_LDS ? s_rho0[k][l] : rho0[k];
+                        delta[k] = {r0.re + kappa * delta[k].re, r0.im + kappa * delta[k].im};
+                    }
+                    __syncthreads();  // every lane has read the previous delta
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) s_rho[k][l] = delta[k];
+                }
+            }
+            // ---- MR on the Dirichlet block operator; rho lives in LDS only
+            for (int it = 0; BS == BLOCK_MR && it < n_mr; ++it) {
                 __syncthreads();
                 cpx<R> q[12];
                 {
@@ -342,14 +482,20 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
 
 template <int P, int PLINK>
 hipError_t launch_p(const OpData& op, int colour, int n_mr, int mode, void* x, const void* b,
-                    int nrhs, const LaunchCfg& cfg, hipStream_t s) {
+                    int nrhs, const LaunchCfg& cfg, hipStream_t s, int bs) {
     const int tile = cfg.rhs_tile < 1 ? 1 : (cfg.rhs_tile > nrhs ? nrhs : cfg.rhs_tile);
     const int nitems = (op.g.nblk / 2) * ((nrhs + tile - 1) / tile);
     const int grid = cfg.persistent_wgs > 0 && cfg.persistent_wgs < nitems ? cfg.persistent_wgs : nitems;
     const size_t stride = spinor_bytes_per_site(P) * op.g.V;
-    const void* cl = P == P_F64 ? op.clover64 : op.clover32;
-    hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
-                       op.links[PLINK], cl, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
+    if (bs == BLOCK_JACOBI) {
+        const void* cl = P == P_F64 ? op.cinv64 : op.cinv32;
+        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_JACOBI>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
+                           op.links[PLINK], cl, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
+    } else {
+        const void* cl = P == P_F64 ? op.clover64 : op.clover32;
+        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_MR>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
+                           op.links[PLINK], cl, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
+    }
     return hipGetLastError();
 }
 
@@ -364,15 +510,16 @@ hipError_t launch_p(const OpData& op, int colour, int n_mr, int mode, void* x, c
 static int default_lanes_per_site(const Geom& g) { return g.nblk / 2 <= 256 ? 2 : 1; }
 
 hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode, void* x,
-                                const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s) {
+                                const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s, int bs) {
     ProfScope ps("sap_halfsweep", s);
+    if (bs != BLOCK_MR && bs != BLOCK_JACOBI) return hipErrorInvalidValue;
     const int lanes = cfg.lanes_per_site > 0 ? cfg.lanes_per_site : default_lanes_per_site(op.g);
-    if (lanes == 2 && prec != P_F64) return launch_sap_pair(op, prec, colour, n_mr, mode, x, b, nrhs, cfg, s);
+    if (lanes == 2 && prec != P_F64) return launch_sap_pair(op, prec, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
     switch (prec) {
-    case P_F64: return launch_p<P_F64, P_F64>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
-    case P_F32: return launch_p<P_F32, P_F32>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
-    case P_F16: return launch_p<P_F16, P_F16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
-    case P_BF16: return launch_p<P_BF16, P_BF16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
+    case P_F64: return launch_p<P_F64, P_F64>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
+    case P_F32: return launch_p<P_F32, P_F32>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
+    case P_F16: return launch_p<P_F16, P_F16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
+    case P_BF16: return launch_p<P_BF16, P_BF16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
     default: return hipErrorInvalidValue;
     }
 }

@@ -285,7 +285,9 @@ __device__ __forceinline__ void pair_sum3(float& a, float& b, float& c, float (*
     c = ((red[2][0] + red[2][1]) + (red[2][2] + red[2][3])) + ((red[2][4] + red[2][5]) + (red[2][6] + red[2][7]));
 }
 
-template <int P, int PLINK>
+// BS = BLOCK_JACOBI: the Jacobi form for A = C^-1 D (see k_sap_halfsweep);
+// `clover` is then (1 + T)^-1.
+template <int P, int PLINK, int BS>
 __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __restrict__ links,
                                                        const void* __restrict__ clover, double kappa_d, int colour,
                                                        int n_mr, int mode, void* __restrict__ x,
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                         pair_hop_lds<1>(g, p, q, sm, acc);
                         pair_hop_lds<2>(g, p, q, sm, acc);
                         pair_hop_lds<3>(g, p, q, sm, acc);
-                        clover_apply_half(cl, xh, cx);
+                        if constexpr (BS == BLOCK_MR) clover_apply_half(cl, xh, cx);
                     }
                     pair_faces<0, 1, P, PLINK>(g, p, q, xr, links, acc);
                     pair_faces<2, 3, P, PLINK>(g, p, q, xr, links, acc);
@@ -351,19 +353,56 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                 }
                 cpx<float> bh[6];
                 load_half<P>(br, g.nblk, blk, q, bh);
+                if constexpr (BS == BLOCK_MR) {
+#pragma unroll
+                    for (int i = 0; i < 6; ++i)
+                        rho[i] = {bh[i].re - (cx[i].re - kappa * hop[i].re), bh[i].im - (cx[i].im - kappa * hop[i].im)};
+                } else {
+                    // rho = C^-1 (b + kappa hop) - x; own x is still staged in LDS
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) bh[i] = {bh[i].re + kappa * hop[i].re, bh[i].im + kappa * hop[i].im};
+                    clover_apply_half(cl, bh, rho);
+                    if (mode == 0) {
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) rho[i] = rho[i] - sm.rho[6 * q.h + i][q.l];
+                    }
+                }
                 __syncthreads();  // every lane has read x (or the previous rho) from LDS
 #pragma unroll
-                for (int i = 0; i < 6; ++i) {
-                    rho[i] = {bh[i].re - (cx[i].re - kappa * hop[i].re), bh[i].im - (cx[i].im - kappa * hop[i].im)};
-                    sm.rho[6 * q.h + i][q.l] = rho[i];
-                }
+                for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l] = rho[i];
             }
 
-            // ---- MR on the Dirichlet block operator
             cpx<float> delta[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) delta[i] = {0.f, 0.f};
-            for (int it = 0; it < n_mr; ++it) {
+            if constexpr (BS == BLOCK_JACOBI) {
+                // ---- Jacobi steps on A_BB = (C^-1 D)_BB
+                if (n_mr > 0) {
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) delta[i] = rho[i];
+                }
+                for (int it = 1; it < n_mr; ++it) {
+                    __syncthreads();  // delta of the whole block is in LDS
+                    cpx<float> acc[12];
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
+                    pair_hop_lds<0>(g, p, q, sm, acc);
+                    pair_hop_lds<1>(g, p, q, sm, acc);
+                    pair_hop_lds<2>(g, p, q, sm, acc);
+                    pair_hop_lds<3>(g, p, q, sm, acc);
+                    cpx<float> hop[6];
+                    pair_combine(acc, q.h, hop);
+                    clover_apply_half(cl, hop, delta);
+#pragma unroll
+                    for (int i = 0; i < 6; ++i)
+                        delta[i] = {rho[i].re + kappa * delta[i].re, rho[i].im + kappa * delta[i].im};
+                    __syncthreads();  // every lane has read the previous delta
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l] = delta[i];
+                }
+            }
+            // ---- MR on the Dirichlet block operator
+            for (int it = 0; BS == BLOCK_MR && it < n_mr; ++it) {
                 __syncthreads();  // rho of the whole block is in LDS
                 cpx<float> qv[6];
                 {
@@ -417,24 +456,29 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
 
 template <int P, int PLINK>
 hipError_t launch_pair(const OpData& op, int colour, int n_mr, int mode, void* x, const void* b, int nrhs,
-                       const LaunchCfg& cfg, hipStream_t s) {
+                       const LaunchCfg& cfg, hipStream_t s, int bs) {
     const int tile = cfg.rhs_tile < 1 ? 1 : (cfg.rhs_tile > nrhs ? nrhs : cfg.rhs_tile);
     const int nitems = (op.g.nblk / 2) * ((nrhs + tile - 1) / tile);
     const int grid = cfg.persistent_wgs > 0 && cfg.persistent_wgs < nitems ? cfg.persistent_wgs : nitems;
     const size_t stride = spinor_bytes_per_site(P) * op.g.V;
-    hipLaunchKernelGGL((k_sap_pair<P, PLINK>), dim3(grid), dim3(PAIR_TPB), 0, s, op.g, op.links[PLINK],
-                       op.clover32, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
+    if (bs == BLOCK_JACOBI)
+        hipLaunchKernelGGL((k_sap_pair<P, PLINK, BLOCK_JACOBI>), dim3(grid), dim3(PAIR_TPB), 0, s, op.g,
+                           op.links[PLINK], op.cinv32, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
+    else
+        hipLaunchKernelGGL((k_sap_pair<P, PLINK, BLOCK_MR>), dim3(grid), dim3(PAIR_TPB), 0, s, op.g,
+                           op.links[PLINK], op.clover32, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile,
+                           nitems);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_sap_pair(const OpData& op, int prec, int colour, int n_mr, int mode, void* x, const void* b,
-                           int nrhs, const LaunchCfg& cfg, hipStream_t s) {
+                           int nrhs, const LaunchCfg& cfg, hipStream_t s, int bs) {
     switch (prec) {
-    case P_F32: return launch_pair<P_F32, P_F32>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
-    case P_F16: return launch_pair<P_F16, P_F16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
-    case P_BF16: return launch_pair<P_BF16, P_BF16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s);
+    case P_F32: return launch_pair<P_F32, P_F32>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
+    case P_F16: return launch_pair<P_F16, P_F16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
+    case P_BF16: return launch_pair<P_BF16, P_BF16>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
     default: return hipErrorInvalidValue;
     }
 }

@@ -165,8 +165,10 @@ __global__ __launch_bounds__(TPB) void k_clover_build(Geom g, const void* __rest
                                            (float)m[4 * k + 3]);
 }
 
+// Canonical [V][12][12] matrix of a packed field: T = (1 + T) - 1 for the
+// clover term (minus_one), or the packed matrix itself (its inverse).
 __global__ __launch_bounds__(TPB) void k_clover_export(Geom g, const double2* __restrict__ c64,
-                                                       double2* __restrict__ out) {
+                                                       double2* __restrict__ out, double minus_one) {
     const int blk = blockIdx.x, l = threadIdx.x;
     const long long s = canonical_site(g, blk, l);
     double m[72];
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(TPB) void k_clover_export(Geom g, const double2* __
         const double* d = m + 36 * h;
         const double* up = d + 6;
         const int o = 6 * h;
-        for (int i = 0; i < 6; ++i) T[(o + i) * 12 + o + i] = make_double2(d[i] - 1.0, 0.0);
+        for (int i = 0; i < 6; ++i) T[(o + i) * 12 + o + i] = make_double2(d[i] - minus_one, 0.0);
         for (int i = 0; i < 6; ++i)
             for (int j = i + 1; j < 6; ++j) {
                 const int k = up_slot(i, j);
@@ -185,6 +187,59 @@ __global__ __launch_bounds__(TPB) void k_clover_export(Geom g, const double2* __
                 T[(o + j) * 12 + o + i] = make_double2(up[2 * k], -up[2 * k + 1]);
             }
     }
+}
+
+// (1 + T)^-1 per site and chirality (grid.y): each 6x6 block of 1 + T is
+// Hermitian positive definite (the clover term is small against the unit
+// matrix: its norm is below 6 kappa c_SW times the norm of F), so in-place
+// Gauss-Jordan elimination without pivoting inverts it; the result is
+// symmetrised and packed like the clover term, in FP64 and FP32.
+__global__ __launch_bounds__(TPB) void k_clover_invert(Geom g, const double2* __restrict__ c64,
+                                                       double2* __restrict__ ci64, float4* __restrict__ ci32) {
+    const int blk = blockIdx.x, h = blockIdx.y, l = threadIdx.x;
+    const double2* p = c64 + ((size_t)blk * 36 + 18 * h) * BLOCK_SITES + l;
+    double m[36];
+    for (int k = 0; k < 18; ++k) {
+        const double2 v = p[k * BLOCK_SITES];
+        m[2 * k] = v.x;
+        m[2 * k + 1] = v.y;
+    }
+    cpx<double> a[6][6];
+    for (int i = 0; i < 6; ++i) {
+        a[i][i] = {m[i], 0.0};
+        for (int j = i + 1; j < 6; ++j) {
+            const int k = up_slot(i, j);
+            a[i][j] = {m[6 + 2 * k], m[7 + 2 * k]};
+            a[j][i] = {m[6 + 2 * k], -m[7 + 2 * k]};
+        }
+    }
+    for (int k = 0; k < 6; ++k) {
+        const cpx<double> piv = a[k][k];
+        const double n2 = piv.re * piv.re + piv.im * piv.im;
+        const cpx<double> ip = {piv.re / n2, -piv.im / n2};
+        a[k][k] = {1.0, 0.0};
+        for (int j = 0; j < 6; ++j) a[k][j] = a[k][j] * ip;
+        for (int i = 0; i < 6; ++i) {
+            if (i == k) continue;
+            const cpx<double> f = a[i][k];
+            a[i][k] = {0.0, 0.0};
+            for (int j = 0; j < 6; ++j) a[i][j] = a[i][j] - f * a[k][j];
+        }
+    }
+    for (int i = 0; i < 6; ++i) {
+        m[i] = a[i][i].re;
+        for (int j = i + 1; j < 6; ++j) {
+            const int k = up_slot(i, j);
+            m[6 + 2 * k] = 0.5 * (a[i][j].re + a[j][i].re);
+            m[7 + 2 * k] = 0.5 * (a[i][j].im - a[j][i].im);
+        }
+    }
+    double2* q64 = ci64 + ((size_t)blk * 36 + 18 * h) * BLOCK_SITES + l;
+    for (int k = 0; k < 18; ++k) q64[k * BLOCK_SITES] = make_double2(m[2 * k], m[2 * k + 1]);
+    float4* q32 = ci32 + ((size_t)blk * 18 + 9 * h) * BLOCK_SITES + l;
+    for (int k = 0; k < 9; ++k)
+        q32[k * BLOCK_SITES] = make_float4((float)m[4 * k], (float)m[4 * k + 1], (float)m[4 * k + 2],
+                                           (float)m[4 * k + 3]);
 }
 
 template <int P>
@@ -231,9 +286,16 @@ hipError_t launch_clover_build(const Geom& g, const void* links64, double kappa,
     return hipGetLastError();
 }
 
-hipError_t launch_clover_export(const Geom& g, const void* c64, void* dst, hipStream_t s) {
+hipError_t launch_clover_export(const Geom& g, const void* c64, void* dst, bool inverse, hipStream_t s) {
     hipLaunchKernelGGL(k_clover_export, dim3(g.nblk), dim3(TPB), 0, s, g, (const double2*)c64,
-                       (double2*)dst);
+                       (double2*)dst, inverse ? 0.0 : 1.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_clover_invert(const Geom& g, const void* c64, void* ci64, void* ci32, hipStream_t s) {
+    ProfScope ps("clover_build", s);
+    hipLaunchKernelGGL(k_clover_invert, dim3(g.nblk, 2), dim3(TPB), 0, s, g, (const double2*)c64,
+                       (double2*)ci64, (float4*)ci32);
     return hipGetLastError();
 }
 

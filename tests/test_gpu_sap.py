@@ -3,6 +3,7 @@ Schwarz, fixed-count block solves; Section 3: post-smoother with a start
 vector) against the FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from paper_2112_00501_amd import cloversap as cs
@@ -98,3 +99,30 @@ def test_sap_rejects_odd_block_count():
     with pytest.raises(cs.CloverSapError) as e:
         c.op.sap_smooth(xd, bd, cs.F64)
     assert e.value.status == -2
+
+
+# ---- the QWS smoother form: SAP on A = C^-1 D with Jacobi block solves
+
+def test_clover_inverse_matches_oracle(cfg1):
+    c = cfg1
+    Ci = c.op.clover.export_inverse()
+    torch.cuda.synchronize()
+    ref = oracle.clover_inverse_field(c.dims, c.T)
+    err = rel(Ci.cpu().numpy(), ref)
+    print(f"(1 + T)^-1 rel.err={err:.3e}")
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("prec,lanes", PREC_LANES)
+def test_jacobi_sap_matches_oracle(cfg1, noncubic, prec, lanes):
+    for c in (cfg1, noncubic):
+        b = synth.source(c.dims, 2011)
+        x0 = 0.3 * synth.source(c.dims, 2012)
+        for zero, n_cy, n_jac in ((True, 2, 4), (False, 1, 3)):
+            ref = oracle.sap_jacobi(c.dims, BDIM, c.U, c.T, c.kappa, n_cy, n_jac, b, x0=None if zero else x0)
+            xd = c.lat.new_field(prec) if zero else c.to_dev(x0, prec)
+            c.op.sap_smooth_jacobi(xd, c.to_dev(b, prec), prec, n_cy=n_cy, n_jac=n_jac, x0_is_zero=zero,
+                                   cfg=cs.LaunchConfig(1, 0, lanes))
+            err = rel(c.to_host(xd, prec), ref)
+            print(f"dims={c.dims} prec={prec} lanes={lanes} from_zero={zero} jacobi sap rel.err={err:.3e}")
+            assert err <= TOL_SAP[prec]

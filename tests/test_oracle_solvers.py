@@ -255,3 +255,62 @@ def test_richardson_bicgstab_matches_dense_lu(system, cond2):
     assert np.linalg.norm(x.reshape(-1) - x_lu) <= cond2 * 1e-10 * np.linalg.norm(x_lu)
     x1, st1, it1, outer1, rel1 = oracle.richardson_bicgstab(DIMS, BDIM, U, T, KAPPA, b, inner_tol=1e-12)
     assert st1 == 0 and outer1 == 1 and rel1 <= 1e-10
+
+
+# ---- QWS smoother form: SAP on A = C^-1 D with Jacobi block solves (Section 2)
+
+def test_clover_inverse_is_the_inverse(system):
+    U, T, M = system
+    Ci = oracle.clover_inverse_field(DIMS, T)
+    eye = np.eye(12)
+    err = max(np.abs(Ci[s] @ (eye + T[s]) - eye).max() for s in range(0, T.shape[0], 5))
+    assert err < 1e-13
+    # the inverse of a Hermitian matrix is Hermitian
+    assert max(np.abs(Ci[s] - Ci[s].conj().T).max() for s in range(0, T.shape[0], 5)) < 1e-13
+
+
+def test_jacobi_sap_exact_block_limit_equals_mr_sap_limit():
+    """With converged block solves, SAP on A = C^-1 D equals SAP on D: C is
+    site diagonal, so (A_BB)^-1 C^-1 = (D_BB)^-1 and both are red/black block
+    Gauss-Seidel of D.  kappa is small enough for the block Jacobi iteration
+    to converge."""
+    kappa = 0.06
+    U = synth.gauge_field(DIMS, 0.3, 24)
+    T = oracle.clover_field(DIMS, U, kappa, CSW)
+    b = synth.source(DIMS, 46)
+    x0 = synth.source(DIMS, 47)
+    xj = oracle.sap_jacobi(DIMS, BDIM, U, T, kappa, 2, 200, b, x0=x0)
+    xm = oracle.sap(DIMS, BDIM, U, T, kappa, 2, 200, b, x0=x0)
+    assert np.linalg.norm(xj - xm) < 1e-11 * np.linalg.norm(xm)
+
+
+def test_jacobi_sap_one_step_closed_form_and_kappa_zero(system):
+    U, T, M = system
+    Ci = oracle.clover_inverse_field(DIMS, T)
+    b = synth.source(DIMS, 48)
+    # one Jacobi step per block, one cycle from x = 0: colour-0 blocks get
+    # C^-1 b, colour-1 blocks C^-1 (b - D x0) with x0 the colour-0 result
+    x = oracle.sap_jacobi(DIMS, BDIM, U, T, KAPPA, 1, 1, b)
+    col = np.array([oracle.block_colour(DIMS, BDIM, oracle.block_of_site(DIMS, BDIM, s))
+                    for s in range(b.shape[0])])
+    x0 = np.einsum("sij,sj->si", Ci, b.reshape(-1, 12)) * (col == 0)[:, None]
+    r = b.reshape(-1) - M @ x0.reshape(-1)
+    x1 = np.einsum("sij,sj->si", Ci, r.reshape(-1, 12))
+    ref = np.where((col == 0)[:, None], x0, x1)
+    assert np.abs(x.reshape(-1, 12) - ref).max() < 1e-13 * np.abs(ref).max()
+    # kappa = 0: D = C, so any number of cycles gives x = C^-1 b
+    T0 = oracle.clover_field(DIMS, U, 0.0, CSW)
+    x = oracle.sap_jacobi(DIMS, BDIM, U, T0, 0.0, 2, 3, b)
+    C0 = oracle.clover_inverse_field(DIMS, T0)
+    assert np.abs(x.reshape(-1, 12) - np.einsum("sij,sj->si", C0, b.reshape(-1, 12))).max() < 1e-14
+
+
+def test_jacobi_sap_gauge_covariant(system):
+    U, T, M = system
+    Om = synth.gauge_transform(DIMS, 4005)
+    Ug = gauge_transform_links(DIMS, U, Om)
+    Tg = oracle.clover_field(DIMS, Ug, KAPPA, CSW)
+    b = synth.source(DIMS, 49)
+    x = oracle.sap_jacobi(DIMS, BDIM, U, T, KAPPA, 2, 3, b)
+    xg = oracle.sap_jacobi(DIMS, BDIM, Ug, Tg, KAPPA, 2, 3, gauge_transform_spinor(Om, b))
+    assert np.abs(xg - gauge_transform_spinor(Om, x)).max() < 1e-12
