@@ -72,6 +72,7 @@ def _declare(L):
     L.or_mr_block.argtypes = [_I4, _I4, C.c_long, _P, _P, C.c_double, C.c_int, _P, _P]
     L.or_sap.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, _P, _P]
     L.or_clover_inverse_field.argtypes = [_I4, _P, _P]
+    L.or_jacobi_block.argtypes = [_I4, _I4, C.c_long, _P, _P, C.c_double, C.c_int, _P, _P]
     L.or_sap_jacobi.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, _P, _P]
     L.or_fgcr.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int,
                           C.c_double, C.c_int, _P, _P, C.POINTER(C.c_int),
@@ -229,6 +230,16 @@ def clover_inverse_field(dims, T) -> np.ndarray:
     out = np.zeros((volume(dims), 12, 12), np.complex128)
     lib().or_clover_inverse_field(_dims(dims), _ptr(T), _ptr(out))
     return out
+
+
+def jacobi_block(dims, bdim, blk, U, T, kappa, n_jac, r) -> np.ndarray:
+    """Jacobi block solve of (C^-1 D)_BB delta = C^-1 r_B for one block."""
+    U, r = _c128(U), _c128(r)
+    T = None if T is None else _c128(T)
+    delta = np.zeros_like(r)
+    lib().or_jacobi_block(_dims(dims), _dims(bdim), int(blk), _ptr(U), _ptr(T), float(kappa), int(n_jac),
+                          _ptr(r), _ptr(delta))
+    return delta
 
 
 def sap_jacobi(dims, bdim, U, T, kappa, n_cy, n_jac, b, x0=None) -> np.ndarray:

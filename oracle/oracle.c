@@ -623,6 +623,49 @@ static void m12_apply(const ocplx* M, const ocplx* v, ocplx* out) {
     }
 }
 
+/* Jacobi on the block system A_BB delta = rho of A = C^-1 D (local arrays):
+ * delta = 0, then n_jac times delta += rho - C^-1 D_BB delta.  ci holds
+ * C^-1 of the block's sites. */
+static void jacobi_local(const int d[4], const int b[4], long blk, const ocplx* U, const ocplx* T,
+                         double kappa, const ocplx G[4][16], int n_jac, const ocplx* ci,
+                         const ocplx* rho, ocplx* dl) {
+    long bv = vol4(b);
+    ocplx* q = malloc(sizeof(ocplx) * 12 * bv);
+    memset(dl, 0, sizeof(ocplx) * 12 * bv);
+    for (int it = 0; it < n_jac; ++it) {
+        dbb_local(d, b, blk, U, T, kappa, G, dl, q);  /* D_BB delta */
+        for (long l = 0; l < bv; ++l) {
+            ocplx aq[12];
+            m12_apply(ci + l * 144, q + l * 12, aq);   /* A_BB delta */
+            for (int i = 0; i < 12; ++i) dl[l * 12 + i] += rho[l * 12 + i] - aq[i];
+        }
+    }
+    free(q);
+}
+
+/* The block solve of the Jacobi smoother for one block: delta_B for the
+ * block residual r_B of D (rho = C^-1 r_B), full-lattice arrays r, delta. */
+void or_jacobi_block(const int d[4], const int b[4], long blk, const ocplx* U, const ocplx* T,
+                     double kappa, int n_jac, const ocplx* r, ocplx* delta) {
+    long bv = vol4(b);
+    ocplx G[4][16];
+    load_gammas(G);
+    ocplx* ci = malloc(sizeof(ocplx) * 144 * bv);
+    ocplx* rho = malloc(sizeof(ocplx) * 12 * bv);
+    ocplx* dl = malloc(sizeof(ocplx) * 12 * bv);
+    for (long l = 0; l < bv; ++l) {
+        long s = block_site(d, b, blk, l);
+        or_clover_inverse_site(T ? T + s * 144 : NULL, ci + l * 144);
+        m12_apply(ci + l * 144, r + s * 12, rho + l * 12);
+    }
+    jacobi_local(d, b, blk, U, T, kappa, (const ocplx(*)[16])G, n_jac, ci, rho, dl);
+    for (long l = 0; l < bv; ++l)
+        memcpy(delta + block_site(d, b, blk, l) * 12, dl + l * 12, 12 * sizeof(ocplx));
+    free(ci);
+    free(rho);
+    free(dl);
+}
+
 /* The smoother of QWS (paper Section 2): multiplicative SAP for the
  * clover-preconditioned operator A = C^-1 D, each block system A_BB delta =
  * rho solved by n_jac Jacobi steps (A_BB has the identity on its diagonal):
@@ -641,8 +684,7 @@ void or_sap_jacobi(const int d[4], const int b[4], const ocplx* U, const ocplx* 
             for (long blk = 0; blk < nblk; ++blk) {
                 if (or_block_colour(d, b, blk) != colour) continue;
                 ocplx* rho = malloc(sizeof(ocplx) * 12 * bv);
-                ocplx* dl = calloc(12 * bv, sizeof(ocplx));
-                ocplx* q = malloc(sizeof(ocplx) * 12 * bv);
+                ocplx* dl = malloc(sizeof(ocplx) * 12 * bv);
                 ocplx* ci = malloc(sizeof(ocplx) * 144 * bv);
                 for (long l = 0; l < bv; ++l) {
                     long s = block_site(d, b, blk, l);
@@ -653,19 +695,12 @@ void or_sap_jacobi(const int d[4], const int b[4], const ocplx* U, const ocplx* 
                     or_clover_inverse_site(T ? T + s * 144 : NULL, ci + l * 144);
                     m12_apply(ci + l * 144, dx, rho + l * 12);
                 }
-                for (int it = 0; it < n_jac; ++it) {
-                    dbb_local(d, b, blk, U, T, kappa, (const ocplx(*)[16])G, dl, q);  /* D_BB delta */
-                    for (long l = 0; l < bv; ++l) {
-                        ocplx aq[12];
-                        m12_apply(ci + l * 144, q + l * 12, aq);                    /* A_BB delta */
-                        for (int i = 0; i < 12; ++i) dl[l * 12 + i] += rho[l * 12 + i] - aq[i];
-                    }
-                }
+                jacobi_local(d, b, blk, U, T, kappa, (const ocplx(*)[16])G, n_jac, ci, rho, dl);
                 for (long l = 0; l < bv; ++l) {
                     long s = block_site(d, b, blk, l);
                     for (int i = 0; i < 12; ++i) x[s * 12 + i] += dl[l * 12 + i];
                 }
-                free(rho); free(dl); free(q); free(ci);
+                free(rho); free(dl); free(ci);
             }
         }
 }

@@ -91,6 +91,9 @@ void or_sap(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T
 /* C^-1 = (1 + T)^-1 per site (Gauss-Jordan); T NULL means T = 0. */
 void or_clover_inverse_site(const ocplx* T, ocplx* Cinv);
 void or_clover_inverse_field(const int dims[4], const ocplx* T, ocplx* Cinv);
+/* Jacobi block solve of one block (rho = C^-1 r_B); see oracle.c. */
+void or_jacobi_block(const int dims[4], const int bdim[4], long blk, const ocplx* U, const ocplx* T,
+                     double kappa, int n_jac, const ocplx* r, ocplx* delta);
 /* SAP on A = C^-1 D with n_jac Jacobi steps per block; see oracle.c. */
 void or_sap_jacobi(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T,
                    double kappa, int n_cy, int n_jac, const ocplx* b, ocplx* x);

@@ -58,12 +58,18 @@ def test_dslash_full_size_sampled(big):
         assert err <= TOL_D[prec]
 
 
-def test_sap_full_size_sampled_blocks(big):
-    c = big
+def _check_sap_cycle_on_sampled_blocks(c, prec, jacobi, tol, nblocks=6):
+    """One SAP cycle from zero on the GPU, then the oracle's block solve of
+    sampled blocks of both colours: a colour-0 block solves its block system
+    with r = b, a colour-1 block with r = b - D x0, x0 the GPU's colour-0
+    result.  MR: n_mr = 4 steps on D_BB; Jacobi: 4 steps on (C^-1 D)_BB."""
     dims, V = c.dims, int(np.prod(c.dims))
-    xd = c.lat.new_field(cs.F32)
-    c.op.sap_smooth(xd, c.to_dev(c.b, cs.F32), cs.F32, n_cy=1, n_mr=4, x0_is_zero=True)
-    x = c.to_host(xd, cs.F32)
+    xd = c.lat.new_field(prec)
+    if jacobi:
+        c.op.sap_smooth_jacobi(xd, c.to_dev(c.b, prec), prec, n_cy=1, n_jac=4, x0_is_zero=True)
+    else:
+        c.op.sap_smooth(xd, c.to_dev(c.b, prec), prec, n_cy=1, n_mr=4, x0_is_zero=True)
+    x = c.to_host(xd, prec)
     colour_of_site = (coords(dims, V) // 4).sum(axis=1) % 2
     x0 = x * (colour_of_site == 0)[:, None, None]  # state after the colour-0 half-sweep
 
@@ -72,7 +78,7 @@ def test_sap_full_size_sampled_blocks(big):
     picks = {0: [], 1: []}
     for blk in rng.permutation(nblk):
         col = oracle.block_colour(dims, BDIM, int(blk))
-        if len(picks[col]) < 6:
+        if len(picks[col]) < nblocks:
             picks[col].append(int(blk))
     for blk in (0, 1, nblk - 2, nblk - 1):  # blocks whose faces wrap around the lattice
         picks[oracle.block_colour(dims, BDIM, blk)].append(blk)
@@ -88,10 +94,30 @@ def test_sap_full_size_sampled_blocks(big):
                 r[sites] = c.b[sites]
             else:
                 r[sites] = c.b[sites] - oracle.apply_D_sites(dims, c.U, c.kappa, c.csw, x0, sites)
-            ref = oracle.mr_block(dims, BDIM, blk, c.U, T, c.kappa, 4, r)[sites]
+            if jacobi:
+                ref = oracle.jacobi_block(dims, BDIM, blk, c.U, T, c.kappa, 4, r)[sites]
+            else:
+                ref = oracle.mr_block(dims, BDIM, blk, c.U, T, c.kappa, 4, r)[sites]
             err = rel(x[sites], ref)
-            print(f"block {blk} colour {col} rel.err={err:.3e}")
-            assert err <= TOL_SAP_F32
+            print(f"{dims} block {blk} colour {col} rel.err={err:.3e}")
+            assert err <= tol
+
+
+def test_sap_full_size_sampled_blocks(big):
+    _check_sap_cycle_on_sampled_blocks(big, cs.F32, jacobi=False, tol=TOL_SAP_F32)
+
+
+def test_jacobi_sap_full_size_sampled_blocks(big):
+    _check_sap_cycle_on_sampled_blocks(big, cs.F32, jacobi=True, tol=TOL_SAP_F32, nblocks=3)
+
+
+def test_sap_benchmark_lattice_sampled_blocks():
+    """16^3 x 32, the benchmark's lattice, where the library's default is the
+    lane-pair kernel."""
+    cfg = synth.CONFIGS["mixed_16x16x16x32"]
+    c = Case(cfg["dims"], cfg["eps"], cfg["kappa"], cfg["csw"], cfg["gauge_seed"], oracle_T=False)
+    c.b = synth.source(c.dims, cfg["src_seed"])
+    _check_sap_cycle_on_sampled_blocks(c, cs.F32, jacobi=False, tol=TOL_SAP_F32)
 
 
 @pytest.mark.parametrize("inner", [cs.F32, cs.F16, cs.BF16])
