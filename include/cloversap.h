@@ -295,6 +295,84 @@ int cs_gcr_solve_dag(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x
 int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
                       const void* b, cs_solver_stats* stats, void* stream);
 
+/* --------------------------------------------------------------- multigrid */
+
+/* Two-level multigrid preconditioner of the paper's Section 3 (adaptive
+ * aggregation with SAP smoothing).  The aggregates are the 4^4 SAP blocks;
+ * every aggregate carries nc = 2 nv coarse degrees of freedom, index
+ * c = chi * nv + i with chi the chirality (spins 0, 1 / spins 2, 3), so that
+ * the prolongator commutes with gamma5.  Everything runs in FP32 (coarse
+ * reductions in FP64).
+ *   setup       v_i = n_cy_setup SAP cycles on D v = eta_i from v = 0
+ *               (i < nv); P = the columns p_{a,chi,i} obtained by modified
+ *               Gram-Schmidt of v_0 .. v_{nv-1} restricted to aggregate a
+ *               and chirality chi; D_c = P^dag D P.  Each of n_adapt passes
+ *               then replaces every v_i by M_MG v_i and rebuilds P and D_c.
+ *   M_MG r      r_c = P^dag r; e_c = BiCGStab on D_c e_c = r_c from zero,
+ *               at most n_coarse iterations, stopping once the recursive
+ *               residual is below tol_coarse |r_c| or on a breakdown;
+ *               z = P e_c; then n_cy_post SAP cycles (MR block solves, n_mr
+ *               steps) on D z = r started from z.
+ * Storage: P as nv CS_F32 internal fields (field i holds p_{a,chi,i} for
+ * every a and chi); coarse vectors float2[nblk][nc] with nblk the number of
+ * 4^4 blocks in the lattice's block order (bx fastest); D_c as the 9-point
+ * stencil float2[nblk][9][nc][nc], index [a][d][column][row] with d = 0 the
+ * aggregate itself, d = 1 + 2 mu its +mu neighbour and d = 2 + 2 mu its -mu
+ * neighbour (periodic), so that (D_c e)_a,row = sum_d sum_col
+ * D_c[a][d][col][row] e_{n(a,d),col}. */
+typedef struct cs_mg_s* cs_mg;
+
+typedef struct {
+    int nv;             /* null vectors (1..32)                                  */
+    int n_cy_setup;     /* SAP cycles turning eta_i into v_i (>= 1)               */
+    int n_mr;           /* MR steps per block solve in every SAP use (>= 1)       */
+    int n_adapt;        /* adaptive passes (>= 0)                                 */
+    int n_coarse;       /* coarse BiCGStab iteration cap per application (>= 1)   */
+    int n_cy_post;      /* SAP post-smoothing cycles per application (>= 0)       */
+    double tol_coarse;  /* relative coarse residual that ends the coarse solve    */
+} cs_mg_params;
+
+/* Defaults: nv 8, n_cy_setup 4, n_mr 4, n_adapt 1, n_coarse 50, n_cy_post 2,
+ * tol_coarse 0.05. */
+void cs_mg_params_default(cs_mg_params* p);
+
+/* Build the hierarchy for operator (g, c).  etas: nv consecutive CS_F32
+ * internal fields (device, caller-owned, read only; random vectors), so the
+ * caller controls the random numbers.  Allocates 2 nv + 1 CS_F32 fields,
+ * D_c (nblk * 9 * nc^2 float2, 288 nv^2 bytes per aggregate) and eight
+ * coarse vectors; the handle refers to c, which must outlive it.  Asynchronous on
+ * the stream.  Errors: CS_ERR_NULL, CS_ERR_INVALID (parameters out of
+ * range), CS_ERR_GEOMETRY (an odd number of blocks in some direction),
+ * CS_ERR_ALLOC, CS_ERR_HIP. */
+int cs_mg_create(cs_gauge g, cs_clover c, const cs_mg_params* p, const void* etas, void* stream,
+                 cs_mg* out);
+int cs_mg_destroy(cs_mg m);
+
+/* Copies of P (nv CS_F32 internal fields) and D_c (layout above) into
+ * caller-owned device buffers; either may be NULL.  Asynchronous. */
+int cs_mg_export(cs_mg m, void* P, void* Dc, void* stream);
+
+/* The pieces of M_MG on caller-owned device buffers (asynchronous):
+ *   restrict      rc = P^dag r      (r a CS_F32 field, rc a coarse vector)
+ *   prolong       z = P ec          (ec a coarse vector, z a CS_F32 field)
+ *   coarse_apply  y = D_c x         (coarse vectors, x != y)
+ *   coarse_solve  ec = the coarse BiCGStab above from zero, with at most
+ *                 n_iter iterations and relative tolerance tol
+ *   apply         z = M_MG r        (CS_F32 fields, z != r) */
+int cs_mg_restrict(cs_mg m, const void* r, void* rc, void* stream);
+int cs_mg_prolong(cs_mg m, const void* ec, void* z, void* stream);
+int cs_mg_coarse_apply(cs_mg m, const void* x, void* y, void* stream);
+int cs_mg_coarse_solve(cs_mg m, const void* rc, void* ec, int n_iter, double tol, void* stream);
+int cs_mg_apply(cs_mg m, void* z, const void* r, void* stream);
+
+/* cs_gcr_solve with M_MG as the preconditioner (one right-hand side):
+ * z_k = M_MG(r / |r_prev|) in FP32.  p->inner_prec must be CS_F32 (the
+ * precision of w = D z); n_cy, n_mr and block_solver are not used (the
+ * smoothing is the hierarchy's).  m must have been built for (g, c).  Same
+ * stats, status codes and stream behaviour as cs_gcr_solve. */
+int cs_gcr_solve_mg(cs_gauge g, cs_clover c, cs_mg m, const cs_solver_params* p, void* x,
+                    const void* b, cs_solver_stats* stats, void* stream);
+
 /* ---------------------------------------------------------------- gradient */
 
 /* Gradient with respect to the links of a real function L of x = D^{-1} b.

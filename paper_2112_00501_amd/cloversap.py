@@ -45,6 +45,11 @@ class LaunchConfig(C.Structure):
                 f"lanes_per_site={self.lanes_per_site})")
 
 
+class _MgParams(C.Structure):
+    _fields_ = [("nv", C.c_int), ("n_cy_setup", C.c_int), ("n_mr", C.c_int), ("n_adapt", C.c_int),
+                ("n_coarse", C.c_int), ("n_cy_post", C.c_int), ("tol_coarse", C.c_double)]
+
+
 class _Stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("true_relres", C.c_double),
                 ("seconds", C.c_double)]
@@ -58,8 +63,10 @@ EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_des
             "cs_clover_export", "cs_clover_inverse_export", "cs_apply_D", "cs_apply_Ddag",
             "cs_apply_D_cfg", "cs_sap_smooth", "cs_sap_smooth_cfg", "cs_sap_smooth_jacobi",
             "cs_autotune", "cs_solver_params_default", "cs_gcr_solve", "cs_gcr_solve_dag",
-            "cs_bicgstab_solve", "cs_force", "cs_profile_enable", "cs_profile_query",
-            "cs_profile_reset"]
+            "cs_bicgstab_solve", "cs_mg_params_default", "cs_mg_create", "cs_mg_destroy",
+            "cs_mg_export", "cs_mg_restrict", "cs_mg_prolong", "cs_mg_coarse_apply",
+            "cs_mg_coarse_solve", "cs_mg_apply", "cs_gcr_solve_mg", "cs_force", "cs_profile_enable",
+            "cs_profile_query", "cs_profile_reset"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -102,6 +109,17 @@ def load_library(path: str = LIB_PATH):
     L.cs_gcr_solve.argtypes = [P, P, C.POINTER(_Params), P, P, I, C.POINTER(_Stats), P]
     L.cs_gcr_solve_dag.argtypes = [P, P, C.POINTER(_Params), P, P, I, C.POINTER(_Stats), P]
     L.cs_bicgstab_solve.argtypes = [P, P, C.POINTER(_Params), P, P, C.POINTER(_Stats), P]
+    L.cs_mg_params_default.argtypes = [C.POINTER(_MgParams)]
+    L.cs_mg_params_default.restype = None
+    L.cs_mg_create.argtypes = [P, P, C.POINTER(_MgParams), P, P, C.POINTER(P)]
+    L.cs_mg_destroy.argtypes = [P]
+    L.cs_mg_export.argtypes = [P, P, P, P]
+    L.cs_mg_restrict.argtypes = [P, P, P, P]
+    L.cs_mg_prolong.argtypes = [P, P, P, P]
+    L.cs_mg_coarse_apply.argtypes = [P, P, P, P]
+    L.cs_mg_coarse_solve.argtypes = [P, P, P, I, D, P]
+    L.cs_mg_apply.argtypes = [P, P, P, P]
+    L.cs_gcr_solve_mg.argtypes = [P, P, P, C.POINTER(_Params), P, P, C.POINTER(_Stats), P]
     L.cs_force.argtypes = [P, P, P, P, P, P, P]
     L.cs_profile_enable.argtypes = [I]
     L.cs_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
@@ -320,6 +338,93 @@ class Operator:
                              None if g is None else _ptr(g), None if G is None else _ptr(G),
                              _stream(stream)), "cs_force")
         return g, G
+
+
+@dataclass
+class MgParams:
+    nv: int = 8             # null vectors; nc = 2 nv coarse values per aggregate
+    n_cy_setup: int = 4     # SAP cycles turning each random vector into a null-vector candidate
+    n_mr: int = 4           # MR steps per block solve in every SAP use
+    n_adapt: int = 1        # adaptive passes v <- M_MG v
+    n_coarse: int = 50      # coarse BiCGStab iteration cap per application
+    n_cy_post: int = 2      # SAP post-smoothing cycles per application
+    tol_coarse: float = 0.05
+
+    def to_c(self) -> _MgParams:
+        return _MgParams(self.nv, self.n_cy_setup, self.n_mr, self.n_adapt, self.n_coarse,
+                         self.n_cy_post, self.tol_coarse)
+
+
+class Multigrid:
+    """Two-level multigrid hierarchy of one operator (cs_mg).  etas: nv
+    consecutive F32 internal fields of random vectors."""
+
+    def __init__(self, op: "Operator", etas: torch.Tensor, params: MgParams | None = None, stream=None):
+        self.op = op
+        self.params = params or MgParams()
+        p = self.params.to_c()
+        h = C.c_void_p()
+        _check(_lib.cs_mg_create(op.gauge.handle, op.clover.handle, C.byref(p), _ptr(etas),
+                                 _stream(stream), C.byref(h)), "cs_mg_create")
+        self.handle = h
+        self.nv = self.params.nv
+        self.nc = 2 * self.nv
+        self.nblk = op.lat.volume // 256
+
+    def new_coarse(self) -> torch.Tensor:
+        """A coarse vector: complex64 [nblk][nc] (float2 per entry)."""
+        return torch.zeros((self.nblk, self.nc), dtype=torch.complex64, device="cuda")
+
+    def export(self, stream=None):
+        """(P as nv F32 internal fields, D_c complex64 [nblk][9][nc (column)][nc (row)])."""
+        P = self.op.lat.new_field(F32, self.nv)
+        Dc = torch.empty((self.nblk, 9, self.nc, self.nc), dtype=torch.complex64, device="cuda")
+        _check(_lib.cs_mg_export(self.handle, _ptr(P), _ptr(Dc), _stream(stream)), "cs_mg_export")
+        return P, Dc
+
+    def restrict(self, r, rc=None, stream=None):
+        rc = self.new_coarse() if rc is None else rc
+        _check(_lib.cs_mg_restrict(self.handle, _ptr(r), _ptr(rc), _stream(stream)), "cs_mg_restrict")
+        return rc
+
+    def prolong(self, ec, z=None, stream=None):
+        z = self.op.lat.new_field(F32) if z is None else z
+        _check(_lib.cs_mg_prolong(self.handle, _ptr(ec), _ptr(z), _stream(stream)), "cs_mg_prolong")
+        return z
+
+    def coarse_apply(self, x, y=None, stream=None):
+        y = self.new_coarse() if y is None else y
+        _check(_lib.cs_mg_coarse_apply(self.handle, _ptr(x), _ptr(y), _stream(stream)), "cs_mg_coarse_apply")
+        return y
+
+    def coarse_solve(self, rc, n_iter, tol=0.0, ec=None, stream=None):
+        ec = self.new_coarse() if ec is None else ec
+        _check(_lib.cs_mg_coarse_solve(self.handle, _ptr(rc), _ptr(ec), int(n_iter), float(tol),
+                                       _stream(stream)), "cs_mg_coarse_solve")
+        return ec
+
+    def apply(self, r, z=None, stream=None):
+        """z = M_MG r (F32 internal fields)."""
+        z = self.op.lat.new_field(F32) if z is None else z
+        _check(_lib.cs_mg_apply(self.handle, _ptr(z), _ptr(r), _stream(stream)), "cs_mg_apply")
+        return z
+
+    def gcr_solve(self, x, b, params: "SolverParams", stream=None, allow_fail=False):
+        """Flexible GCR on D x = b (CS_F64 internal fields) preconditioned by
+        M_MG.  Returns (status, stats)."""
+        p = params.to_c()
+        st_ = _Stats()
+        st = _lib.cs_gcr_solve_mg(self.op.gauge.handle, self.op.clover.handle, self.handle, C.byref(p),
+                                  _ptr(x), _ptr(b), C.byref(st_), _stream(stream))
+        if not allow_fail:
+            _check(st, "cs_gcr_solve_mg")
+        return st, dict(iters=st_.iters, restarts=st_.restarts, true_relres=st_.true_relres,
+                        seconds=st_.seconds)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cs_mg_destroy(self.handle)
+            self.handle = None
 
 
 @dataclass

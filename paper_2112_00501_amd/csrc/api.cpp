@@ -17,6 +17,7 @@
 #include "blas.hpp"
 #include "bicgstab.hpp"
 #include "gcr.hpp"
+#include "mg.hpp"
 
 struct cs_lattice_s {
     cs::Geom g;
@@ -25,6 +26,12 @@ struct cs_lattice_s {
 struct cs_gauge_s {
     cs::Geom g;
     void* links[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+struct cs_mg_s {
+    cs_gauge_s* gauge = nullptr;
+    struct cs_clover_s* clover = nullptr;
+    cs::MgData data;
 };
 
 struct cs_clover_s {
@@ -509,7 +516,7 @@ void cs_solver_params_default(cs_solver_params* p) {
 }
 
 static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
-                      cs_solver_stats* stats, void* stream, bool dagger) {
+                      cs_solver_stats* stats, void* stream, bool dagger, const cs::MgData* mg = nullptr) {
     int st = check_op(g, c);
     if (st) return st;
     if (!p || !x || !b) return fail(CS_ERR_NULL, "params, x and b must be non-NULL");
@@ -526,8 +533,10 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         return fail(CS_ERR_PRECISION, "an FP64 inner solve needs an FP64 basis");
     if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
     if (p->rhs_tile < 0) return fail(CS_ERR_INVALID, "rhs_tile must be >= 0");
-    if (p->n_cy > 0 && !sap_geometry_ok(g->g))
+    if ((p->n_cy > 0 || mg) && !sap_geometry_ok(g->g))
         return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
+    if (mg && (nrhs != 1 || p->inner_prec != CS_F32))
+        return fail(CS_ERR_INVALID, "the multigrid preconditioner takes one right-hand side and inner_prec CS_F32");
     const size_t f64 = cs::spinor_bytes_per_site(cs::P_F64) * (size_t)g->g.V;
     if (overlap(b, x, f64 * nrhs)) return fail(CS_ERR_INVALID, "x and b overlap");
     hipStream_t s = (hipStream_t)stream;
@@ -561,8 +570,9 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         std::lock_guard<std::mutex> lk(g_pm);
         prof = g_prof_on;
     }
-    const cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
-                           p->reliable_delta, sap_cfg, d_cfg, p->use_graph != 0 && !prof, p->block_solver};
+    cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
+                     p->reliable_delta, sap_cfg, d_cfg, p->use_graph != 0 && !prof, p->block_solver};
+    gp.mg = mg;
     std::vector<cs::GcrResult> res(nrhs);
     e = cs::gcr_solve(make_op(g, c), gp, *c->work, x, b, nrhs, dagger, c->dag_tmp, res.data(), s);
     if (e != hipSuccess) {
@@ -641,6 +651,101 @@ int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, co
 int cs_gcr_solve_dag(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
                      cs_solver_stats* stats, void* stream) {
     return gcr_common(g, c, p, x, b, nrhs, stats, stream, true);
+}
+
+void cs_mg_params_default(cs_mg_params* p) {
+    if (!p) return;
+    p->nv = 8;
+    p->n_cy_setup = 4;
+    p->n_mr = 4;
+    p->n_adapt = 1;
+    p->n_coarse = 50;
+    p->n_cy_post = 2;
+    p->tol_coarse = 0.05;
+}
+
+int cs_mg_create(cs_gauge g, cs_clover c, const cs_mg_params* p, const void* etas, void* stream, cs_mg* out) {
+    int st = check_op(g, c);
+    if (st) return st;
+    if (!p || !etas || !out) return fail(CS_ERR_NULL, "params, etas and out must be non-NULL");
+    *out = nullptr;
+    if (p->nv < 1 || p->nv > cs::MG_MAX_NV) return fail(CS_ERR_INVALID, "nv must be in 1..%d", cs::MG_MAX_NV);
+    if (p->n_cy_setup < 1 || p->n_mr < 1 || p->n_adapt < 0 || p->n_coarse < 1 || p->n_cy_post < 0)
+        return fail(CS_ERR_INVALID, "need n_cy_setup, n_mr, n_coarse >= 1 and n_adapt, n_cy_post >= 0");
+    if (!(p->tol_coarse >= 0.0)) return fail(CS_ERR_INVALID, "tol_coarse must be >= 0");
+    if (!sap_geometry_ok(g->g))
+        return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
+    std::unique_ptr<cs_mg_s> m(new cs_mg_s);
+    m->gauge = g;
+    m->clover = c;
+    const cs::MgParams mp{p->nv, p->n_cy_setup, p->n_mr, p->n_adapt, p->n_coarse, p->n_cy_post, p->tol_coarse};
+    hipError_t e = m->data.alloc(g->g, mp);
+    if (e != hipSuccess) return fail(CS_ERR_ALLOC, "multigrid workspace: %s", hipGetErrorString(e));
+    if (overlap(etas, m->data.V, m->data.field_bytes() * p->nv))
+        return fail(CS_ERR_INVALID, "etas overlap the hierarchy");
+    CS_HIP(cs::mg_setup(make_op(g, c), m->data, etas, (hipStream_t)stream));
+    *out = m.release();
+    return ok();
+}
+
+int cs_mg_destroy(cs_mg m) {
+    if (!m) return fail(CS_ERR_NULL, "multigrid handle is NULL");
+    hipDeviceSynchronize();
+    delete m;
+    return ok();
+}
+
+int cs_mg_export(cs_mg m, void* P, void* Dc, void* stream) {
+    if (!m) return fail(CS_ERR_NULL, "multigrid handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (P) CS_HIP(hipMemcpyAsync(P, m->data.P, m->data.field_bytes() * m->data.p.nv, hipMemcpyDeviceToDevice, s));
+    if (Dc) CS_HIP(hipMemcpyAsync(Dc, m->data.Dc, m->data.dc_bytes(), hipMemcpyDeviceToDevice, s));
+    return ok();
+}
+
+int cs_mg_restrict(cs_mg m, const void* r, void* rc, void* stream) {
+    if (!m || !r || !rc) return fail(CS_ERR_NULL, "handle, r and rc must be non-NULL");
+    CS_HIP(cs::mg_restrict(m->data.g, m->data.P, m->data.p.nv, r, (float2*)rc, (hipStream_t)stream));
+    return ok();
+}
+
+int cs_mg_prolong(cs_mg m, const void* ec, void* z, void* stream) {
+    if (!m || !ec || !z) return fail(CS_ERR_NULL, "handle, ec and z must be non-NULL");
+    CS_HIP(cs::mg_prolong(m->data.g, m->data.P, m->data.p.nv, (const float2*)ec, z, (hipStream_t)stream));
+    return ok();
+}
+
+int cs_mg_coarse_apply(cs_mg m, const void* x, void* y, void* stream) {
+    if (!m || !x || !y) return fail(CS_ERR_NULL, "handle, x and y must be non-NULL");
+    if (overlap(x, y, m->data.coarse_bytes())) return fail(CS_ERR_INVALID, "x and y overlap");
+    CS_HIP(cs::mg_coarse_apply(m->data.g, m->data.Dc, m->data.nc(), (const float2*)x, (float2*)y, nullptr,
+                               (hipStream_t)stream));
+    return ok();
+}
+
+int cs_mg_coarse_solve(cs_mg m, const void* rc, void* ec, int n_iter, double tol, void* stream) {
+    if (!m || !rc || !ec) return fail(CS_ERR_NULL, "handle, rc and ec must be non-NULL");
+    if (n_iter < 0 || !(tol >= 0.0)) return fail(CS_ERR_INVALID, "need n_iter >= 0 and tol >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const cs::MgData& d = m->data;
+    CS_HIP(cs::mg_coarse_bicgstab(d.g, d.Dc, d.nc(), (const float2*)rc, d.cv, d.sc, d.partials, n_iter, tol, s));
+    CS_HIP(hipMemcpyAsync(ec, d.cv.x, d.coarse_bytes(), hipMemcpyDeviceToDevice, s));
+    return ok();
+}
+
+int cs_mg_apply(cs_mg m, void* z, const void* r, void* stream) {
+    if (!m || !z || !r) return fail(CS_ERR_NULL, "handle, z and r must be non-NULL");
+    if (overlap(z, r, m->data.field_bytes())) return fail(CS_ERR_INVALID, "z and r overlap");
+    CS_HIP(cs::mg_apply(make_op(m->gauge, m->clover), m->data, z, r, (hipStream_t)stream));
+    return ok();
+}
+
+int cs_gcr_solve_mg(cs_gauge g, cs_clover c, cs_mg m, const cs_solver_params* p, void* x, const void* b,
+                    cs_solver_stats* stats, void* stream) {
+    if (!m) return fail(CS_ERR_NULL, "multigrid handle is NULL");
+    if (m->gauge != g || m->clover != c)
+        return fail(CS_ERR_INVALID, "the multigrid handle was built for a different operator");
+    return gcr_common(g, c, p, x, b, 1, stats, stream, false, &m->data);
 }
 
 int cs_force(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_lie, void* grad_U, void* stream) {

@@ -1,4 +1,5 @@
-// Flexible GCR(m) outer solver with a SAP preconditioner (host driver).
+// Flexible GCR(m) outer solver with a SAP or two-level multigrid preconditioner
+// (host driver).
 //
 // Outer arithmetic, reductions and the residual recomputation are FP64; the
 // preconditioner and w = D z run in the inner precision.  This is the
@@ -10,7 +11,8 @@
 //
 // One iteration k (all on the device; solver scalars stay in device memory):
 //   z_k = SAP(r / |r_prev|)            inner precision (r_prev: the residual
-//                                      before the update that produced r)
+//                                      before the update that produced r);
+//                                      or z_k = M_MG(r / |r_prev|), FP32
 //   w_k = D z_k                        inner precision arithmetic
 //   beta_jk = <w_j_hat, w_k>, j < k    classical Gram-Schmidt, FP64
 //   w_k -= sum_j beta_jk w_j_hat; nu_k = |w_k|; c_k = <w_k_hat, r>
@@ -130,7 +132,7 @@ struct Solver {
 
     size_t f64() const { return spinor_bytes_per_site(P_F64) * op.g.V; }
     // precision of the residual copy the smoother reads (none without smoother)
-    int lo_prec() const { return p.n_cy > 0 ? p.inner : -1; }
+    int lo_prec() const { return (p.n_cy > 0 || p.mg) ? p.inner : -1; }
 
     hipError_t upload_mask(const std::vector<char>& m) {
         for (int r = 0; r < n; ++r) w.host_active[r] = m[r] ? 1 : 0;
@@ -157,7 +159,9 @@ struct Solver {
     hipError_t iteration(int k) {
         char* zk = (char*)w.Z + (size_t)k * n * w.zstride;
         char* wk = (char*)w.W + (size_t)k * n * w.wstride;
-        if (p.n_cy > 0) {
+        if (p.mg) {
+            GCR_CHK(mg_apply(op, *p.mg, zk, w.rlo, s));
+        } else if (p.n_cy > 0) {
             // w.rlo holds the residual in the inner precision, written by the
             // kernel that last updated w.r
             for (int cy = 0; cy < p.n_cy; ++cy)
@@ -182,9 +186,17 @@ struct Solver {
                             p.sap_cfg.persistent_wgs, p.sap_cfg.lanes_per_site, p.dslash_cfg.rhs_tile,
                             p.dslash_cfg.persistent_wgs, n};
         std::memcpy(kbuf.data(), vals, sizeof vals);
-        const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32};
+        const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32,
+                              p.mg, p.mg ? p.mg->P : nullptr, p.mg ? p.mg->Dc : nullptr};
         std::memcpy(kbuf.data() + sizeof vals, ptrs, sizeof ptrs);
         std::memcpy(kbuf.data() + sizeof vals + sizeof ptrs, &op.kappa, sizeof op.kappa);
+        if (p.mg) {  // the shape of a multigrid application
+            const MgParams& q = p.mg->p;
+            const int mv[] = {q.nv, q.n_mr, q.n_coarse, q.n_cy_post};
+            char* at = kbuf.data() + sizeof vals + sizeof ptrs + sizeof op.kappa;
+            std::memcpy(at, mv, sizeof mv);
+            std::memcpy(at + sizeof mv, &q.tol_coarse, sizeof q.tol_coarse);
+        }
         return kbuf;
     }
 

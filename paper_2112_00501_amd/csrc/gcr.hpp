@@ -5,6 +5,7 @@
 
 #include "blas.hpp"
 #include "cs_internal.hpp"
+#include "mg.hpp"
 
 namespace cs {
 
@@ -18,6 +19,7 @@ struct GcrParams {
     LaunchCfg sap_cfg, dslash_cfg;  // multi-right-hand-side launch shapes
     bool use_graph;                 // replay each iteration as a captured HIP graph
     int block_solver;               // BLOCK_MR or BLOCK_JACOBI (n_mr steps either way)
+    const MgData* mg = nullptr;     // multigrid preconditioner in place of SAP (one right-hand side, FP32)
 };
 
 struct GcrResult {

@@ -1,0 +1,99 @@
+// Two-level multigrid preconditioner (paper Section 3), host drivers.
+//
+// Setup: v_i = M_SAP eta_i (n_cy_setup SAP cycles from zero, all nv vectors
+// in one batched launch per half-sweep); P = the local orthonormalisation of
+// v_0 .. v_{nv-1} per aggregate and chirality; D_c = P^dag D P.  Each of the
+// n_adapt adaptive passes replaces every v_i by M_MG v_i with the current P
+// and D_c, then rebuilds P and D_c.
+//
+// Application z = M_MG r: r_c = P^dag r; e_c = coarse BiCGStab on D_c r_c
+// (FP32 vectors, FP64 reductions, at most n_coarse iterations, stopping at a
+// relative residual of tol_coarse, decided on the device); z = P e_c; then
+// n_cy_post SAP cycles on D z = r started from z.  Every launch has a fixed
+// shape, so an application can be captured into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include "mg.hpp"
+
+namespace cs {
+
+namespace {
+
+#define MG_CHK(x)                            \
+    do {                                     \
+        hipError_t e_ = (x);                 \
+        if (e_ != hipSuccess) return e_;     \
+    } while (0)
+
+constexpr int CB_PARTIAL_SLOTS = 2 * 1024;  // two complex sums per workgroup, at most 1024 workgroups
+
+// n_cy SAP cycles on D x = b for nrhs FP32 fields; x0_zero: x starts at zero
+hipError_t sap_cycles(const OpData& op, const LaunchCfg& cfg, int n_cy, int n_mr, bool x0_zero, void* x,
+                      const void* b, int nrhs, hipStream_t s) {
+    for (int cy = 0; cy < n_cy; ++cy)
+        for (int col = 0; col < 2; ++col) {
+            const int mode = (x0_zero && cy == 0) ? (col == 0 ? 1 : 2) : 0;
+            MG_CHK(launch_sap_halfsweep(op, P_F32, col, n_mr, mode, x, b, nrhs, cfg, s, BLOCK_MR));
+        }
+    return hipSuccess;
+}
+
+hipError_t rebuild(const OpData& op, MgData& m, hipStream_t s) {
+    MG_CHK(hipMemcpyAsync(m.P, m.V, m.field_bytes() * m.p.nv, hipMemcpyDeviceToDevice, s));
+    MG_CHK(mg_orthonormalize(m.g, m.P, m.p.nv, s));
+    return mg_assemble(op, m.P, m.p.nv, m.Dc, s);
+}
+
+}  // namespace
+
+size_t MgData::field_bytes() const { return spinor_bytes_per_site(P_F32) * g.V; }
+
+void MgData::release() {
+    for (void** q : {&P, &V, &tmp, (void**)&Dc, (void**)&rc, (void**)&cv.x, (void**)&sc, (void**)&partials}) {
+        if (*q) hipFree(*q);
+        *q = nullptr;
+    }
+    cv = CbVecs{};
+}
+
+hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
+    release();
+    g = g_;
+    p = p_;
+    MG_CHK(hipMalloc(&P, field_bytes() * p.nv));
+    MG_CHK(hipMalloc(&V, field_bytes() * p.nv));
+    MG_CHK(hipMalloc(&tmp, field_bytes()));
+    MG_CHK(hipMalloc((void**)&Dc, dc_bytes()));
+    MG_CHK(hipMalloc((void**)&rc, coarse_bytes()));
+    // the seven coarse vectors in one allocation (cv.x owns it)
+    float2* base = nullptr;
+    MG_CHK(hipMalloc((void**)&base, coarse_bytes() * 7));
+    const size_t n = (size_t)g.nblk * nc();
+    cv = CbVecs{base, base + n, base + 2 * n, base + 3 * n, base + 4 * n, base + 5 * n, base + 6 * n};
+    MG_CHK(hipMalloc((void**)&sc, sizeof(CbScalars)));
+    MG_CHK(hipMalloc((void**)&partials, sizeof(double2) * CB_PARTIAL_SLOTS));
+    return hipSuccess;
+}
+
+hipError_t mg_setup(const OpData& op, MgData& m, const void* etas, hipStream_t s) {
+    MG_CHK(sap_cycles(op, m.sap_cfg, m.p.n_cy_setup, m.p.n_mr, true, m.V, etas, m.p.nv, s));
+    MG_CHK(rebuild(op, m, s));
+    for (int pass = 0; pass < m.p.n_adapt; ++pass) {
+        for (int i = 0; i < m.p.nv; ++i) {
+            char* vi = (char*)m.V + (size_t)i * m.field_bytes();
+            MG_CHK(mg_apply(op, m, m.tmp, vi, s));
+            MG_CHK(hipMemcpyAsync(vi, m.tmp, m.field_bytes(), hipMemcpyDeviceToDevice, s));
+        }
+        MG_CHK(rebuild(op, m, s));
+    }
+    return hipSuccess;
+}
+
+hipError_t mg_apply(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s) {
+    MG_CHK(mg_restrict(m.g, m.P, m.p.nv, r, m.rc, s));
+    MG_CHK(mg_coarse_bicgstab(m.g, m.Dc, m.nc(), m.rc, m.cv, m.sc, m.partials, m.p.n_coarse, m.p.tol_coarse, s));
+    MG_CHK(mg_prolong(m.g, m.P, m.p.nv, m.cv.x, z, s));
+    return sap_cycles(op, m.sap_cfg, m.p.n_cy_post, m.p.n_mr, false, z, r, 1, s);
+}
+
+}  // namespace cs

@@ -1,0 +1,73 @@
+// Two-level multigrid preconditioner (paper Section 3): kernels in mg.hip,
+// setup and application drivers in mg.cpp.
+#pragma once
+
+#include "cs_internal.hpp"
+
+namespace cs {
+
+constexpr int MG_MAX_NV = 32;  // nc = 2 nv coarse values per aggregate fit one wave
+
+// Scalars of the coarse BiCGStab, kept on the device.  Once `stopped` is set
+// every later kernel of the iteration returns at once, so a fixed number of
+// iterations can be launched (or captured) without host round trips.
+struct CbScalars {
+    double2 rho, alpha, omega, beta;
+    double rr, stop2;  // |r|^2 and the stopping threshold tol^2 |r_0|^2
+    int stopped, pad;
+};
+
+struct CbVecs {
+    float2 *x, *r, *rh, *p, *v, *s, *t;
+};
+
+struct MgParams {
+    int nv, n_cy_setup, n_mr, n_adapt, n_coarse, n_cy_post;
+    double tol_coarse;
+};
+
+// Device state of one hierarchy.  P: nv FP32 fields (field i holds
+// p_{a,chi,i}); V: the nv null vectors before orthonormalisation; Dc:
+// float2[nblk][9][nc][nc]; coarse vectors float2[nblk][nc].
+struct MgData {
+    Geom g{};
+    MgParams p{};
+    void* P = nullptr;
+    void* V = nullptr;
+    void* tmp = nullptr;  // one FP32 field
+    float2* Dc = nullptr;
+    float2* rc = nullptr;
+    CbVecs cv{};
+    CbScalars* sc = nullptr;
+    double2* partials = nullptr;
+    LaunchCfg sap_cfg{};
+
+    int nc() const { return 2 * p.nv; }
+    size_t field_bytes() const;
+    size_t coarse_bytes() const { return (size_t)g.nblk * nc() * sizeof(float2); }
+    size_t dc_bytes() const { return (size_t)g.nblk * 9 * nc() * nc() * sizeof(float2); }
+    hipError_t alloc(const Geom& g, const MgParams& p);
+    void release();
+    ~MgData() { release(); }
+};
+
+// mg.hip
+hipError_t mg_orthonormalize(const Geom& g, void* P, int nv, hipStream_t s);
+hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipStream_t s);
+hipError_t mg_restrict(const Geom& g, const void* P, int nv, const void* r, float2* rc, hipStream_t s);
+hipError_t mg_prolong(const Geom& g, const void* P, int nv, const float2* ec, void* z, hipStream_t s);
+// y = D_c x (sc may be null; when set and stopped the launch does nothing)
+hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2* x, float2* y,
+                           const CbScalars* sc, hipStream_t s);
+// cv.x = BiCGStab(D_c, rc) from zero: at most max_iter iterations, fewer once
+// |r| <= tol |rc| or on a breakdown (all decided on the device)
+hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const float2* rc, const CbVecs& cv,
+                              CbScalars* sc, double2* partials, int max_iter, double tol, hipStream_t s);
+
+// mg.cpp
+// Null vectors from the nv FP32 fields etas, P and D_c, n_adapt adaptive passes.
+hipError_t mg_setup(const OpData& op, MgData& m, const void* etas, hipStream_t s);
+// z = M_MG r (FP32 fields, z != r): coarse correction, then n_cy_post SAP cycles.
+hipError_t mg_apply(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s);
+
+}  // namespace cs
