@@ -718,7 +718,7 @@ int cs_mg_prolong(cs_mg m, const void* ec, void* z, void* stream) {
 int cs_mg_coarse_apply(cs_mg m, const void* x, void* y, void* stream) {
     if (!m || !x || !y) return fail(CS_ERR_NULL, "handle, x and y must be non-NULL");
     if (overlap(x, y, m->data.coarse_bytes())) return fail(CS_ERR_INVALID, "x and y overlap");
-    CS_HIP(cs::mg_coarse_apply(m->data.g, m->data.Dc, m->data.nc(), (const float2*)x, (float2*)y, nullptr,
+    CS_HIP(cs::mg_coarse_apply(m->data.g, m->data.Dc, m->data.nc(), (const float2*)x, (float2*)y,
                                (hipStream_t)stream));
     return ok();
 }
@@ -728,7 +728,7 @@ int cs_mg_coarse_solve(cs_mg m, const void* rc, void* ec, int n_iter, double tol
     if (n_iter < 0 || !(tol >= 0.0)) return fail(CS_ERR_INVALID, "need n_iter >= 0 and tol >= 0");
     hipStream_t s = (hipStream_t)stream;
     const cs::MgData& d = m->data;
-    CS_HIP(cs::mg_coarse_bicgstab(d.g, d.Dc, d.nc(), (const float2*)rc, d.cv, d.sc, d.partials, n_iter, tol, s));
+    CS_HIP(cs::mg_coarse_bicgstab(d.g, d.Dc, d.nc(), (const float2*)rc, d.cv, d.sc, d.pa, n_iter, tol, s));
     CS_HIP(hipMemcpyAsync(ec, d.cv.x, d.coarse_bytes(), hipMemcpyDeviceToDevice, s));
     return ok();
 }

@@ -25,8 +25,6 @@ namespace {
         if (e_ != hipSuccess) return e_;     \
     } while (0)
 
-constexpr int CB_PARTIAL_SLOTS = 2 * 1024;  // two complex sums per workgroup, at most 1024 workgroups
-
 // n_cy SAP cycles on D x = b for nrhs FP32 fields; x0_zero: x starts at zero
 hipError_t sap_cycles(const OpData& op, const LaunchCfg& cfg, int n_cy, int n_mr, bool x0_zero, void* x,
                       const void* b, int nrhs, hipStream_t s) {
@@ -49,11 +47,12 @@ hipError_t rebuild(const OpData& op, MgData& m, hipStream_t s) {
 size_t MgData::field_bytes() const { return spinor_bytes_per_site(P_F32) * g.V; }
 
 void MgData::release() {
-    for (void** q : {&P, &V, &tmp, (void**)&Dc, (void**)&rc, (void**)&cv.x, (void**)&sc, (void**)&partials}) {
+    for (void** q : {&P, &V, &tmp, (void**)&Dc, (void**)&rc, (void**)&cv.x, (void**)&sc, (void**)&pa.A}) {
         if (*q) hipFree(*q);
         *q = nullptr;
     }
     cv = CbVecs{};
+    pa = CbPartials{};
 }
 
 hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
@@ -65,13 +64,25 @@ hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
     MG_CHK(hipMalloc(&tmp, field_bytes()));
     MG_CHK(hipMalloc((void**)&Dc, dc_bytes()));
     MG_CHK(hipMalloc((void**)&rc, coarse_bytes()));
-    // the seven coarse vectors in one allocation (cv.x owns it)
+    // the nine coarse vectors in one allocation (cv.x owns it)
     float2* base = nullptr;
-    MG_CHK(hipMalloc((void**)&base, coarse_bytes() * 7));
+    MG_CHK(hipMalloc((void**)&base, coarse_bytes() * 9));
     const size_t n = (size_t)g.nblk * nc();
-    cv = CbVecs{base, base + n, base + 2 * n, base + 3 * n, base + 4 * n, base + 5 * n, base + 6 * n};
+    cv.x = base;
+    cv.r = base + n;
+    cv.rh = base + 2 * n;
+    cv.p[0] = base + 3 * n;
+    cv.p[1] = base + 4 * n;
+    cv.v[0] = base + 5 * n;
+    cv.v[1] = base + 6 * n;
+    cv.s = base + 7 * n;
+    cv.t = base + 8 * n;
     MG_CHK(hipMalloc((void**)&sc, sizeof(CbScalars)));
-    MG_CHK(hipMalloc((void**)&partials, sizeof(double2) * CB_PARTIAL_SLOTS));
+    // partial sums, two complex values per workgroup (pa.A owns the allocation)
+    const size_t na = 2 * (size_t)MG_ELEM_WG, nb = 2 * (size_t)g.nblk;
+    double2* pb = nullptr;
+    MG_CHK(hipMalloc((void**)&pb, sizeof(double2) * (na + 2 * nb)));
+    pa = CbPartials{pb, pb + na, pb + na + nb};
     return hipSuccess;
 }
 
@@ -91,7 +102,7 @@ hipError_t mg_setup(const OpData& op, MgData& m, const void* etas, hipStream_t s
 
 hipError_t mg_apply(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s) {
     MG_CHK(mg_restrict(m.g, m.P, m.p.nv, r, m.rc, s));
-    MG_CHK(mg_coarse_bicgstab(m.g, m.Dc, m.nc(), m.rc, m.cv, m.sc, m.partials, m.p.n_coarse, m.p.tol_coarse, s));
+    MG_CHK(mg_coarse_bicgstab(m.g, m.Dc, m.nc(), m.rc, m.cv, m.sc, m.pa, m.p.n_coarse, m.p.tol_coarse, s));
     MG_CHK(mg_prolong(m.g, m.P, m.p.nv, m.cv.x, z, s));
     return sap_cycles(op, m.sap_cfg, m.p.n_cy_post, m.p.n_mr, false, z, r, 1, s);
 }

@@ -20,20 +20,44 @@ namespace {
 
 constexpr int TPB = BLOCK_SITES;
 
+// Sum over the 64 lanes of a wave, the same value in every lane: DPP steps
+// within each row of 16 lanes (swap neighbours, swap pairs, mirror halves of
+// 8, mirror the row), then the four row totals read from lanes 0, 16, 32, 48
+// and added in a fixed order.
+__device__ __forceinline__ float dpp_add(float v, int ctrl_sel) {
+    int x = __float_as_int(v), y;
+    switch (ctrl_sel) {
+    case 0: y = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
+    case 1: y = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
+    case 2: y = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+    default: y = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false); break; // row_mirror
+    }
+    return v + __int_as_float(y);
+}
+
 __device__ __forceinline__ float wsum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v = dpp_add(v, 0);
+    v = dpp_add(v, 1);
+    v = dpp_add(v, 2);
+    v = dpp_add(v, 3);
+    const int x = __float_as_int(v);
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(x, 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(x, 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(x, 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(x, 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 // Sum N values over the workgroup; afterwards out[k] (LDS) holds total k.
 template <int N>
 __device__ __forceinline__ void block_sum(const float* v, float (*red)[N], float* out) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float t[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float s = wsum(v[k]);
-        if (lane == 0) red[wave][k] = s;
+    for (int k = 0; k < N; ++k) t[k] = wsum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) red[wave][k] = t[k];
     }
     __syncthreads();
     if ((int)threadIdx.x < N) {
@@ -117,91 +141,146 @@ struct LdsColumn {  // in-block neighbours for the self term
     }
 };
 
-// Hop term of direction MU, sign S (forward -1 / backward +1), for the lanes
-// whose neighbour lies in the adjacent aggregate: acc += that hop of column col
-// of P on the neighbouring aggregate.
-template <int MU, int S>
-__device__ __forceinline__ void face_term(const Geom& g, const BlockPos& p, int l, const void* links,
-                                          const char* P, size_t fs, int nv, int col, cpx<float>* acc) {
-    int nl;
-    bool in;
-    const int nb = neighbour(g, p, l, MU, S < 0 ? +1 : -1, &nl, &in);
-    if (in) return;
-    cpx<float> psi[12], u[9];
-    column_site(P, fs, nv, col, g.nblk, nb, nl, psi);
-    if (S < 0) load_link<P_F32, float, false>(links, p.blk, l, MU, u);  // U_mu(x)
-    else load_link<P_F32, float, false>(links, nb, nl, MU, u);          // U_mu(x - mu)
-    hop_term<MU, S>(u, psi, acc);
+// Row chunk of the assembly: RC fields of P held in registers.
+constexpr int ASM_RC = 4;
+
+// Block sum of N values (one per lane) into out[0..N): wave shuffles, then
+// the four wave totals added in a fixed order.  red holds 4 x N floats.
+template <int N>
+__device__ __forceinline__ void block_sum_to(const float* v, float* red, float* out) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float t[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) t[k] = wsum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) red[wave * N + k] = t[k];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < N) {
+        const int k = threadIdx.x;
+        out[k] = (red[k] + red[N + k]) + (red[2 * N + k] + red[3 * N + k]);
+    }
+    __syncthreads();
+}
+
+// dots[4 r + 2 chi + (re, im)] = sum over the spins of chirality chi of
+// conj(q_r) y, for the RC rows of the chunk
+__device__ __forceinline__ void row_dots(const cpx<float> (*q)[12], const cpx<float>* y, float* dots) {
+#pragma unroll
+    for (int r = 0; r < ASM_RC; ++r) {
+        float a[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const int o = k < 6 ? 0 : 2;
+            a[o] += q[r][k].re * y[k].re + q[r][k].im * y[k].im;
+            a[o + 1] += q[r][k].re * y[k].im - q[r][k].im * y[k].re;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dots[4 * r + k] = a[k];
+    }
+}
+
+// Store the 16 reduced dots of direction d and column col (lanes 0..15).
+__device__ __forceinline__ void store_dots(float2* Dc, int blk, int d, int col, int nc, int nv, int rc0,
+                                           const float* tot) {
+    const int t = threadIdx.x;
+    if (t < 4 * ASM_RC && (t & 1) == 0) {
+        const int r = t >> 2, chi = (t >> 1) & 1;
+        if (rc0 + r < nv) {
+            const int row = chi * nv + rc0 + r;
+            Dc[(((size_t)blk * 9 + d) * nc + col) * nc + row] = make_float2(tot[t], tot[t + 1]);
+        }
+    }
+}
+
+// Face term of direction MU for one column: y = -kappa (hop across the face)
+// on the lanes of the +MU face (forward hop, direction d = 1 + 2 MU) or of
+// the -MU face (backward hop, d = 2 + 2 MU); the dots of both faces are then
+// reduced.
+template <int MU>
+__device__ __forceinline__ void face_dots(const Geom& g, const BlockPos& p, int l, const void* links,
+                                          const char* P, size_t fs, int nv, int col, float kappa,
+                                          const cpx<float> (*q)[12], float2* Dc, int nc, int rc0, float* red,
+                                          float* tot) {
+    const int lc = (l >> (2 * MU)) & 3;
+    float dp[4 * ASM_RC], dm[4 * ASM_RC];
+#pragma unroll
+    for (int k = 0; k < 4 * ASM_RC; ++k) dp[k] = dm[k] = 0.f;
+    if (lc == 3 || lc == 0) {
+        int nl;
+        bool in;
+        const int nb = neighbour(g, p, l, MU, lc == 3 ? +1 : -1, &nl, &in);
+        cpx<float> psi[12], u[9], acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
+        column_site(P, fs, nv, col, g.nblk, nb, nl, psi);
+        if (lc == 3) {
+            load_link<P_F32, float, false>(links, p.blk, l, MU, u);  // U_mu(x)
+            hop_term<MU, -1>(u, psi, acc);
+        } else {
+            load_link<P_F32, float, false>(links, nb, nl, MU, u);    // U_mu(x - mu)
+            hop_term<MU, +1>(u, psi, acc);
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {-kappa * acc[k].re, -kappa * acc[k].im};
+        row_dots(q, acc, lc == 3 ? dp : dm);
+    }
+    block_sum_to<4 * ASM_RC>(dp, red, tot);
+    store_dots(Dc, p.blk, 1 + 2 * MU, col, nc, nv, rc0, tot);
+    block_sum_to<4 * ASM_RC>(dm, red, tot);
+    store_dots(Dc, p.blk, 2 + 2 * MU, col, nc, nv, rc0, tot);
 }
 
 // D_c[a][d][col][row] = <p_{a,row}, D p_{n(a,d),col}> restricted to the
-// terms of D that couple aggregate a to its neighbour in direction d.
+// terms of D that couple aggregate a to its neighbour in direction d.  One
+// workgroup per aggregate (lane = site); ASM_RC rows of P stay in registers
+// while every column is applied once per row chunk: the self term (clover and
+// the in-aggregate hops, the column staged in LDS) and the four face terms
+// of the site.
 __global__ __launch_bounds__(TPB) void k_mg_assemble(Geom g, const void* links, const void* clover, float kappa,
                                                      const char* P, size_t fs, int nv, float2* Dc) {
-    const int blk = blockIdx.x, d = blockIdx.y, l = threadIdx.x, nc = 2 * nv;
+    const int blk = blockIdx.x, l = threadIdx.x, nc = 2 * nv;
     const BlockPos p = block_pos(g, blk);
     __shared__ cpx<float> s[12][BLOCK_SITES];
-    __shared__ float red[4][8];
-    __shared__ float tot[8];
+    __shared__ float red[4 * 4 * ASM_RC];
+    __shared__ float tot[4 * ASM_RC];
     float cl[72];
-    if (d == 0) CloverIO<float>::template load<false>(clover, blk, l, cl);
-    for (int col = 0; col < nc; ++col) {
-        cpx<float> w[12], acc[12];
+    CloverIO<float>::template load<false>(clover, blk, l, cl);
+    for (int rc0 = 0; rc0 < nv; rc0 += ASM_RC) {
+        cpx<float> q[ASM_RC][12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
-        if (d == 0) {
-            cpx<float> c[12];
+        for (int r = 0; r < ASM_RC; ++r) {
+            if (rc0 + r < nv) {
+                load_f32(P, fs, rc0 + r, g.nblk, blk, l, q[r]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) q[r][k] = {0.f, 0.f};
+            }
+        }
+        for (int col = 0; col < nc; ++col) {
+            cpx<float> c[12], w[12], acc[12];
             column_site(P, fs, nv, col, g.nblk, blk, l, c);
             __syncthreads();  // the previous column's readers are done
 #pragma unroll
             for (int k = 0; k < 12; ++k) s[k][l] = c[k];
             __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
             LdsColumn ls{s};
             GlobalLinks<P_F32, false> lk{links};
             hopping_sum<float>(g, p, l, ls, lk, acc);
             clover_apply(cl, c, w);
 #pragma unroll
             for (int k = 0; k < 12; ++k) w[k] = {w[k].re - kappa * acc[k].re, w[k].im - kappa * acc[k].im};
-        } else {
-            switch (d) {
-            case 1: face_term<0, -1>(g, p, l, links, P, fs, nv, col, acc); break;
-            case 2: face_term<0, +1>(g, p, l, links, P, fs, nv, col, acc); break;
-            case 3: face_term<1, -1>(g, p, l, links, P, fs, nv, col, acc); break;
-            case 4: face_term<1, +1>(g, p, l, links, P, fs, nv, col, acc); break;
-            case 5: face_term<2, -1>(g, p, l, links, P, fs, nv, col, acc); break;
-            case 6: face_term<2, +1>(g, p, l, links, P, fs, nv, col, acc); break;
-            case 7: face_term<3, -1>(g, p, l, links, P, fs, nv, col, acc); break;
-            default: face_term<3, +1>(g, p, l, links, P, fs, nv, col, acc); break;
-            }
-#pragma unroll
-            for (int k = 0; k < 12; ++k) w[k] = {-kappa * acc[k].re, -kappa * acc[k].im};
-        }
-        // project onto the columns of this aggregate, two fields at a time
-        for (int i0 = 0; i0 < nv; i0 += 2) {
-            float dd[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (i0 + u < nv) {
-                    cpx<float> q[12];
-                    load_f32(P, fs, i0 + u, g.nblk, blk, l, q);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        const int o = 4 * u + (k < 6 ? 0 : 2);
-                        dd[o] += q[k].re * w[k].re + q[k].im * w[k].im;
-                        dd[o + 1] += q[k].re * w[k].im - q[k].im * w[k].re;
-                    }
-                }
-            }
-            block_sum<8>(dd, red, tot);
-            if (l < 4) {
-                const int u = l >> 1, chi = l & 1;
-                const int i = i0 + u;
-                if (i < nv) {
-                    const int row = chi * nv + i;
-                    Dc[(((size_t)blk * 9 + d) * nc + col) * nc + row] = make_float2(tot[4 * u + 2 * chi],
-                                                                                    tot[4 * u + 2 * chi + 1]);
-                }
-            }
+            float d0[4 * ASM_RC];
+            row_dots(q, w, d0);
+            block_sum_to<4 * ASM_RC>(d0, red, tot);
+            store_dots(Dc, blk, 0, col, nc, nv, rc0, tot);
+            face_dots<0>(g, p, l, links, P, fs, nv, col, kappa, q, Dc, nc, rc0, red, tot);
+            face_dots<1>(g, p, l, links, P, fs, nv, col, kappa, q, Dc, nc, rc0, red, tot);
+            face_dots<2>(g, p, l, links, P, fs, nv, col, kappa, q, Dc, nc, rc0, red, tot);
+            face_dots<3>(g, p, l, links, P, fs, nv, col, kappa, q, Dc, nc, rc0, red, tot);
         }
     }
 }
@@ -259,28 +338,85 @@ __global__ __launch_bounds__(TPB) void k_mg_prolong(Geom g, const char* P, size_
 }
 
 // ---------------------------------------------------------- coarse solver
+//
+// Matrix-vector products with D_c: one workgroup of 256 lanes per coarse
+// site a.  The 9 nc x nc blocks of the site are one K x nc matrix
+// M[k][row] (k = d nc + col, row fastest), applied to the gathered vector
+// xg[k] = x_{n(a,d), col} staged in LDS.  Lane t owns row t % nc and the
+// column chunk t / nc (every (256 / nc)-th k), so a wave reads whole
+// consecutive rows of M (coalesced) and each lane keeps several independent
+// loads in flight; the chunks are then added in a fixed order.
 
-// y = D_c x: one workgroup of 64 lanes per coarse site, lane = row.
-__global__ __launch_bounds__(64) void k_mg_coarse_apply(Geom g, const float2* Dc, int nc, const float2* x,
-                                                        float2* y, const CbScalars* sc) {
-    if (sc && sc->stopped) return;
-    const int a = blockIdx.x, row = threadIdx.x;
-    if (row >= nc) return;
-    const BlockPos p = block_pos(g, a);
-    float re = 0.f, im = 0.f;
-    for (int d = 0; d < 9; ++d) {
-        const int nb = d == 0 ? a : block_step(g, p, (d - 1) >> 1, (d & 1) ? +1 : -1);
-        const float2* m = Dc + ((size_t)a * 9 + d) * nc * nc + row;
-        const float2* xv = x + (size_t)nb * nc;
-        for (int c = 0; c < nc; ++c) {
-            const float2 mm = m[(size_t)c * nc], xx = xv[c];
-            re = fmaf(mm.x, xx.x, re);
-            re = fmaf(-mm.y, xx.y, re);
-            im = fmaf(mm.x, xx.y, im);
-            im = fmaf(mm.y, xx.x, im);
+constexpr int CMV_TPB = 256;
+constexpr int CMV_KMAX = 9 * 2 * MG_MAX_NV;
+
+__device__ __forceinline__ int coarse_nb(const Geom& g, const BlockPos& p, int d) {
+    return d == 0 ? p.blk : block_step(g, p, (d - 1) >> 1, (d & 1) ? +1 : -1);
+}
+
+// y_row = sum_k M[k][row] xs[k]; valid in lanes t < nc (others return 0)
+__device__ __forceinline__ float2 cmv_rows(const float2* __restrict__ M, int nc, const float2* xs, float2* red) {
+    const int t = threadIdx.x, kch = CMV_TPB / nc, row = t % nc, kc = t / nc, K = 9 * nc;
+    float re = 0.f, im = 0.f, re2 = 0.f, im2 = 0.f;
+    if (kc < kch) {
+        int k = kc;
+        for (; k + kch < K; k += 2 * kch) {
+            const float2 m0 = M[(size_t)k * nc + row], m1 = M[(size_t)(k + kch) * nc + row];
+            const float2 x0 = xs[k], x1 = xs[k + kch];
+            re = fmaf(m0.x, x0.x, re); re = fmaf(-m0.y, x0.y, re);
+            im = fmaf(m0.x, x0.y, im); im = fmaf(m0.y, x0.x, im);
+            re2 = fmaf(m1.x, x1.x, re2); re2 = fmaf(-m1.y, x1.y, re2);
+            im2 = fmaf(m1.x, x1.y, im2); im2 = fmaf(m1.y, x1.x, im2);
+        }
+        if (k < K) {
+            const float2 m0 = M[(size_t)k * nc + row], x0 = xs[k];
+            re = fmaf(m0.x, x0.x, re); re = fmaf(-m0.y, x0.y, re);
+            im = fmaf(m0.x, x0.y, im); im = fmaf(m0.y, x0.x, im);
         }
     }
-    y[(size_t)a * nc + row] = make_float2(re, im);
+    red[t] = make_float2(re + re2, im + im2);
+    __syncthreads();
+    float2 y = make_float2(0.f, 0.f);
+    if (t < nc)
+        for (int c = 0; c < kch; ++c) {
+            const float2 v = red[c * nc + t];
+            y.x += v.x;
+            y.y += v.y;
+        }
+    return y;
+}
+
+// Workgroup sums of a and b (FP64) from lanes of wave 0 into partials[2 wg], [2 wg + 1]
+__device__ __forceinline__ void wave0_partials(double2 a, double2 b, double2* partials) {
+    if (threadIdx.x >= 64) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a.x += __shfl_xor(a.x, off);
+        a.y += __shfl_xor(a.y, off);
+        b.x += __shfl_xor(b.x, off);
+        b.y += __shfl_xor(b.y, off);
+    }
+    if (threadIdx.x == 0) {
+        partials[(size_t)blockIdx.x * 2] = a;
+        partials[(size_t)blockIdx.x * 2 + 1] = b;
+    }
+}
+
+__device__ __forceinline__ double2 cdot_d(float2 a, float2 b) {  // conj(a) b
+    return make_double2((double)a.x * b.x + (double)a.y * b.y, (double)a.x * b.y - (double)a.y * b.x);
+}
+
+// y = D_c x
+__global__ __launch_bounds__(CMV_TPB) void k_mg_coarse_apply(Geom g, const float2* __restrict__ Dc, int nc,
+                                                             const float2* __restrict__ x, float2* __restrict__ y) {
+    __shared__ float2 xs[CMV_KMAX];
+    __shared__ float2 red[CMV_TPB];
+    const int a = blockIdx.x, K = 9 * nc;
+    const BlockPos p = block_pos(g, a);
+    for (int k = threadIdx.x; k < K; k += CMV_TPB) xs[k] = x[(size_t)coarse_nb(g, p, k / nc) * nc + k % nc];
+    __syncthreads();
+    const float2 v = cmv_rows(Dc + (size_t)a * K * nc, nc, xs, red);
+    if ((int)threadIdx.x < nc) y[(size_t)a * nc + threadIdx.x] = v;
 }
 
 __device__ __forceinline__ double2 cdiv2(double2 a, double2 b) {
@@ -291,141 +427,221 @@ __device__ __forceinline__ double2 cmul_d(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// FP64 wave/workgroup reduction of two complex values into partials slots
-__device__ __forceinline__ void cb_partials(double a_re, double a_im, double b_re, double b_im, double2* partials) {
-    __shared__ double red[4][4];
-    double v[4] = {a_re, a_im, b_re, b_im};
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double s = v[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) red[wave][k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        const int k = threadIdx.x;
-        partials[(size_t)blockIdx.x * 2 + k] = make_double2((red[0][2 * k] + red[1][2 * k]) + (red[2][2 * k] + red[3][2 * k]),
-                                                            (red[0][2 * k + 1] + red[1][2 * k + 1]) +
-                                                                (red[2][2 * k + 1] + red[3][2 * k + 1]));
-    }
-}
+// Coarse BiCGStab, one iteration (it, parity q = it & 1) as six launches:
+//   F1  rho_new = <rh, r>, |r|^2 from the partials A; stop before the
+//       iteration (rho_new = 0; after it > 0 also omega = 0 or |r| <= tol |r_0|);
+//       beta = (rho_new / rho_old) (alpha / omega)
+//   M1  p = r + beta (p_prev - omega v_prev) formed while gathering, v = D_c p,
+//       partials B = <rh, v>
+//   F2  alpha = rho_new / <rh, v> (a zero denominator ends the solve)
+//   M2  s = r - alpha v formed while gathering, t = D_c s, partials C =
+//       <t, s>, |t|^2
+//   F3  omega = <t, s> / |t|^2 (0 when t = 0)
+//   U   x += alpha p + omega s, r = s - omega t, partials A
+// p and v alternate between two buffers by parity, so the gathers of M1 read
+// the previous iteration's values while its own entries are written.  A
+// kernel reads only scalars written by earlier kernels (slots by parity
+// where a kernel would otherwise read what it writes), and every later
+// kernel returns at once after a stop, so a fixed number of iterations can be
+// launched or captured.
 
-enum CbStep { CB_START = 0, CB_ALPHA = 1, CB_OMEGA = 2, CB_RHO = 3 };
-
-// fixed-order sum of the partials (two complex slots per workgroup) and one step
-__global__ __launch_bounds__(256) void k_cb_finalize(const double2* partials, int nwg, CbScalars* sc, int step,
-                                                     double tol2) {
-    if (step != CB_START && sc->stopped) return;
-    __shared__ double2 red[2][256];
+// Fixed-order sum of the first three reals (re, im of slot 0; re of slot 1)
+// of nwg two-slot partials by one workgroup of 1024 lanes; valid in lane 0.
+__device__ __forceinline__ void sum3_partials(const double2* partials, int nwg, double* out) {
+    __shared__ double red[3][1024];
     const int t = threadIdx.x;
-    double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
-    for (int i = t; i < nwg; i += 256) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int i = t; i < nwg; i += 1024) {
         const double2 a = partials[(size_t)i * 2], b = partials[(size_t)i * 2 + 1];
-        s0.x += a.x; s0.y += a.y; s1.x += b.x; s1.y += b.y;
+        s0 += a.x;
+        s1 += a.y;
+        s2 += b.x;
     }
     red[0][t] = s0;
     red[1][t] = s1;
+    red[2][t] = s2;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if (t < w) {
-            red[0][t].x += red[0][t + w].x; red[0][t].y += red[0][t + w].y;
-            red[1][t].x += red[1][t + w].x; red[1][t].y += red[1][t + w].y;
+            red[0][t] += red[0][t + w];
+            red[1][t] += red[1][t + w];
+            red[2][t] += red[2][t + w];
         }
         __syncthreads();
     }
-    if (t != 0) return;
-    const double2 d0 = red[0][0], d1 = red[1][0];
-    if (step == CB_START) {  // d0.x = |r|^2
-        sc->rho = make_double2(d0.x, 0.0);
-        sc->rr = d0.x;
-        sc->stop2 = tol2 * d0.x;
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+    out[2] = red[2][0];
+}
+
+__global__ __launch_bounds__(1024) void k_cb_f1(const double2* partials, int nwg, CbScalars* sc, int it,
+                                                double tol2) {
+    const int q = it & 1;
+    double tot[3];
+    sum3_partials(partials, nwg, tot);
+    if (threadIdx.x != 0) return;
+    const double2 rho = make_double2(tot[0], tot[1]);
+    const double rr = tot[2];
+    int stop;
+    if (it == 0) {
+        sc->stop2 = tol2 * rr;
         sc->alpha = sc->omega = make_double2(1.0, 0.0);
-        sc->beta = make_double2(0.0, 0.0);
-        sc->stopped = d0.x > 0.0 ? 0 : 1;
-    } else if (step == CB_ALPHA) {  // d0 = <rh, v>
-        if (d0.x == 0.0 && d0.y == 0.0) sc->stopped = 1;  // before any update
-        else sc->alpha = cdiv2(sc->rho, d0);
-    } else if (step == CB_OMEGA) {  // d0 = <t, s>, d1.x = |t|^2
-        sc->omega = d1.x > 0.0 ? make_double2(d0.x / d1.x, d0.y / d1.x) : make_double2(0.0, 0.0);
-    } else {  // d0 = <rh, r>, d1.x = |r|^2 of the updated residual
+        sc->beta[q] = make_double2(0.0, 0.0);
+        stop = 0;
+    } else {
         const bool w0 = sc->omega.x == 0.0 && sc->omega.y == 0.0;
-        sc->beta = w0 ? make_double2(0.0, 0.0) : cmul_d(cdiv2(d0, sc->rho), cdiv2(sc->alpha, sc->omega));
-        sc->rho = d0;
-        sc->rr = d1.x;
-        if (w0 || d1.x <= sc->stop2 || (d0.x == 0.0 && d0.y == 0.0)) sc->stopped = 1;
+        stop = sc->stopped[q ^ 1] || sc->brk[q ^ 1] || w0 || rr <= sc->stop2;
+        sc->beta[q] = stop ? make_double2(0.0, 0.0) : cmul_d(cdiv2(rho, sc->rho[q ^ 1]), cdiv2(sc->alpha, sc->omega));
+    }
+    if (rho.x == 0.0 && rho.y == 0.0) stop = 1;
+    sc->rho[q] = rho;
+    sc->rr = rr;
+    sc->stopped[q] = stop;
+}
+
+__global__ __launch_bounds__(CMV_TPB) void k_cb_m1(Geom g, const float2* __restrict__ Dc, int nc, CbVecs cv,
+                                                   const CbScalars* sc, int q, double2* partials) {
+    if (sc->stopped[q]) return;
+    __shared__ float2 xs[CMV_KMAX];
+    __shared__ float2 red[CMV_TPB];
+    const int a = blockIdx.x, K = 9 * nc;
+    const BlockPos p = block_pos(g, a);
+    const float br = (float)sc->beta[q].x, bi = (float)sc->beta[q].y;
+    const float wr = (float)sc->omega.x, wi = (float)sc->omega.y;
+    const float2 *pp = cv.p[q ^ 1], *vp = cv.v[q ^ 1];
+    float2* pn = cv.p[q];
+    for (int k = threadIdx.x; k < K; k += CMV_TPB) {
+        const int d = k / nc, col = k % nc;
+        const size_t i = (size_t)coarse_nb(g, p, d) * nc + col;
+        const float2 r = cv.r[i], po = pp[i], vo = vp[i];
+        const float tr = po.x - (wr * vo.x - wi * vo.y), ti = po.y - (wr * vo.y + wi * vo.x);
+        const float2 pv = make_float2(r.x + (br * tr - bi * ti), r.y + (br * ti + bi * tr));
+        xs[k] = pv;
+        if (d == 0) pn[i] = pv;
+    }
+    __syncthreads();
+    const float2 v = cmv_rows(Dc + (size_t)a * K * nc, nc, xs, red);
+    double2 d0 = make_double2(0.0, 0.0);
+    if ((int)threadIdx.x < nc) {
+        const size_t i = (size_t)a * nc + threadIdx.x;
+        cv.v[q][i] = v;
+        d0 = cdot_d(cv.rh[i], v);
+    }
+    wave0_partials(d0, make_double2(0.0, 0.0), partials);
+}
+
+__global__ __launch_bounds__(1024) void k_cb_f2(const double2* partials, int nwg, CbScalars* sc, int q) {
+    if (sc->stopped[q]) return;
+    double tot[3];
+    sum3_partials(partials, nwg, tot);
+    if (threadIdx.x != 0) return;
+    const double2 rv = make_double2(tot[0], tot[1]);
+    const bool brk = rv.x == 0.0 && rv.y == 0.0;
+    sc->brk[q] = brk;
+    if (!brk) sc->alpha = cdiv2(sc->rho[q], rv);
+}
+
+__global__ __launch_bounds__(CMV_TPB) void k_cb_m2(Geom g, const float2* __restrict__ Dc, int nc, CbVecs cv,
+                                                   const CbScalars* sc, int q, double2* partials) {
+    if (sc->stopped[q] || sc->brk[q]) return;
+    __shared__ float2 xs[CMV_KMAX];
+    __shared__ float2 red[CMV_TPB];
+    const int a = blockIdx.x, K = 9 * nc;
+    const BlockPos p = block_pos(g, a);
+    const float ar = (float)sc->alpha.x, ai = (float)sc->alpha.y;
+    const float2* vq = cv.v[q];
+    for (int k = threadIdx.x; k < K; k += CMV_TPB) {
+        const int d = k / nc, col = k % nc;
+        const size_t i = (size_t)coarse_nb(g, p, d) * nc + col;
+        const float2 r = cv.r[i], v = vq[i];
+        const float2 sv = make_float2(r.x - (ar * v.x - ai * v.y), r.y - (ar * v.y + ai * v.x));
+        xs[k] = sv;
+        if (d == 0) cv.s[i] = sv;
+    }
+    __syncthreads();
+    const float2 tv = cmv_rows(Dc + (size_t)a * K * nc, nc, xs, red);
+    double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
+    if ((int)threadIdx.x < nc) {
+        const size_t i = (size_t)a * nc + threadIdx.x;
+        cv.t[i] = tv;
+        ts = cdot_d(tv, xs[threadIdx.x]);  // own entries of s sit at d = 0
+        tt.x = (double)tv.x * tv.x + (double)tv.y * tv.y;
+    }
+    wave0_partials(ts, tt, partials);
+}
+
+__global__ __launch_bounds__(1024) void k_cb_f3(const double2* partials, int nwg, CbScalars* sc, int q) {
+    if (sc->stopped[q] || sc->brk[q]) return;
+    double tot[3];
+    sum3_partials(partials, nwg, tot);
+    if (threadIdx.x != 0) return;
+    const double tt = tot[2];
+    sc->omega = tt > 0.0 ? make_double2(tot[0] / tt, tot[1] / tt) : make_double2(0.0, 0.0);
+}
+
+// partials A of <rh, r>, |r|^2 over 256-entry chunks
+__device__ __forceinline__ void chunk_partials(double2 a, double b, double2* partials) {
+    __shared__ double red[3][4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a.x += __shfl_xor(a.x, off);
+        a.y += __shfl_xor(a.y, off);
+        b += __shfl_xor(b, off);
+    }
+    if (lane == 0) {
+        red[0][wave] = a.x;
+        red[1][wave] = a.y;
+        red[2][wave] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[(size_t)blockIdx.x * 2] = make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
+                                                        (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+        partials[(size_t)blockIdx.x * 2 + 1] =
+            make_double2((red[2][0] + red[2][1]) + (red[2][2] + red[2][3]), 0.0);
     }
 }
 
-// x = 0, r = rh = rc, p = v = 0, partial |r|^2
+// x = 0, r = rh = rc, p_prev = v_prev = 0 (slot 1), partials A
 __global__ __launch_bounds__(256) void k_cb_init(int n, const float2* rc, CbVecs cv, double2* partials) {
-    double s = 0.0;
+    double2 a = make_double2(0.0, 0.0);
+    double b = 0.0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const float2 r = rc[i];
-        cv.x[i] = cv.p[i] = cv.v[i] = make_float2(0.f, 0.f);
+        cv.x[i] = cv.p[1][i] = cv.v[1][i] = make_float2(0.f, 0.f);
         cv.r[i] = cv.rh[i] = r;
-        s += (double)r.x * r.x + (double)r.y * r.y;
+        const double rr = (double)r.x * r.x + (double)r.y * r.y;
+        a.x += rr;
+        b += rr;
     }
-    cb_partials(s, 0.0, 0.0, 0.0, partials);
+    chunk_partials(a, b, partials);
 }
 
-__global__ __launch_bounds__(256) void k_cb_p(int n, const CbScalars* sc, CbVecs cv) {
-    if (sc->stopped) return;
-    const float br = (float)sc->beta.x, bi = (float)sc->beta.y, wr = (float)sc->omega.x, wi = (float)sc->omega.y;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const float2 r = cv.r[i], p = cv.p[i], v = cv.v[i];
-        // p = r + beta (p - omega v)
-        const float tr = p.x - (wr * v.x - wi * v.y), ti = p.y - (wr * v.y + wi * v.x);
-        cv.p[i] = make_float2(r.x + br * tr - bi * ti, r.y + br * ti + bi * tr);
-    }
-}
-
-// partial <a, b> (slot 0) and, with TWO, |a|^2 (slot 1)
-template <bool TWO>
-__global__ __launch_bounds__(256) void k_cb_dot(int n, const CbScalars* sc, const float2* a, const float2* b,
-                                                double2* partials) {
-    if (sc->stopped) return;
-    double re = 0.0, im = 0.0, aa = 0.0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const float2 x = a[i], y = b[i];
-        re += (double)x.x * y.x + (double)x.y * y.y;
-        im += (double)x.x * y.y - (double)x.y * y.x;
-        if (TWO) aa += (double)x.x * x.x + (double)x.y * x.y;
-    }
-    cb_partials(re, im, aa, 0.0, partials);
-}
-
-__global__ __launch_bounds__(256) void k_cb_s(int n, const CbScalars* sc, CbVecs cv) {
-    if (sc->stopped) return;
-    const float ar = (float)sc->alpha.x, ai = (float)sc->alpha.y;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const float2 r = cv.r[i], v = cv.v[i];
-        cv.s[i] = make_float2(r.x - (ar * v.x - ai * v.y), r.y - (ar * v.y + ai * v.x));
-    }
-}
-
-// x += alpha p + omega s, r = s - omega t; partials <rh, r>, |r|^2
-__global__ __launch_bounds__(256) void k_cb_xr(int n, const CbScalars* sc, CbVecs cv, double2* partials) {
-    if (sc->stopped) return;
+__global__ __launch_bounds__(256) void k_cb_update(int n, const CbScalars* sc, int q, CbVecs cv,
+                                                   double2* partials) {
+    if (sc->stopped[q] || sc->brk[q]) return;
     const float ar = (float)sc->alpha.x, ai = (float)sc->alpha.y, wr = (float)sc->omega.x, wi = (float)sc->omega.y;
-    double re = 0.0, im = 0.0, rr = 0.0;
+    const float2* pq = cv.p[q];
+    double2 a = make_double2(0.0, 0.0);
+    double b = 0.0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const float2 x = cv.x[i], p = cv.p[i], s = cv.s[i], t = cv.t[i], h = cv.rh[i];
+        const float2 x = cv.x[i], p = pq[i], s = cv.s[i], t = cv.t[i], h = cv.rh[i];
         cv.x[i] = make_float2(x.x + (ar * p.x - ai * p.y) + (wr * s.x - wi * s.y),
                               x.y + (ar * p.y + ai * p.x) + (wr * s.y + wi * s.x));
         const float2 r = make_float2(s.x - (wr * t.x - wi * t.y), s.y - (wr * t.y + wi * t.x));
         cv.r[i] = r;
-        re += (double)h.x * r.x + (double)h.y * r.y;
-        im += (double)h.x * r.y - (double)h.y * r.x;
-        rr += (double)r.x * r.x + (double)r.y * r.y;
+        const double2 hr = cdot_d(h, r);
+        a.x += hr.x;
+        a.y += hr.y;
+        b += (double)r.x * r.x + (double)r.y * r.y;
     }
-    cb_partials(re, im, rr, 0.0, partials);
+    chunk_partials(a, b, partials);
 }
 
 int cb_grid(int n) {
     const int b = (n + 255) / 256;
-    return b < 1024 ? b : 1024;
+    return b < MG_ELEM_WG ? b : MG_ELEM_WG;
 }
 
 }  // namespace
@@ -439,7 +655,7 @@ hipError_t mg_orthonormalize(const Geom& g, void* P, int nv, hipStream_t s) {
 
 hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipStream_t s) {
     ProfScope ps("mg", s);
-    hipLaunchKernelGGL(k_mg_assemble, dim3(op.g.nblk, 9), dim3(TPB), 0, s, op.g, op.links[P_F32], op.clover32,
+    hipLaunchKernelGGL(k_mg_assemble, dim3(op.g.nblk), dim3(TPB), 0, s, op.g, op.links[P_F32], op.clover32,
                        (float)op.kappa, (const char*)P, spinor_bytes_per_site(P_F32) * op.g.V, nv, Dc);
     return hipGetLastError();
 }
@@ -458,15 +674,14 @@ hipError_t mg_prolong(const Geom& g, const void* P, int nv, const float2* ec, vo
     return hipGetLastError();
 }
 
-hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2* x, float2* y,
-                           const CbScalars* sc, hipStream_t s) {
+hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2* x, float2* y, hipStream_t s) {
     ProfScope ps("mg", s);
-    hipLaunchKernelGGL(k_mg_coarse_apply, dim3(g.nblk), dim3(64), 0, s, g, Dc, nc, x, y, sc);
+    hipLaunchKernelGGL(k_mg_coarse_apply, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, Dc, nc, x, y);
     return hipGetLastError();
 }
 
 hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const float2* rc, const CbVecs& cv,
-                              CbScalars* sc, double2* partials, int max_iter, double tol, hipStream_t s) {
+                              CbScalars* sc, const CbPartials& pa, int max_iter, double tol, hipStream_t s) {
     ProfScope ps("mg", s);
     const int n = g.nblk * nc, grid = cb_grid(n);
 #define CB_LAUNCH(...)                           \
@@ -475,19 +690,15 @@ hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const flo
         hipError_t e_ = hipGetLastError();       \
         if (e_ != hipSuccess) return e_;         \
     } while (0)
-    CB_LAUNCH(k_cb_init, dim3(grid), dim3(256), 0, s, n, rc, cv, partials);
-    CB_LAUNCH(k_cb_finalize, dim3(1), dim3(256), 0, s, partials, grid, sc, (int)CB_START, tol * tol);
+    CB_LAUNCH(k_cb_init, dim3(grid), dim3(256), 0, s, n, rc, cv, pa.A);
     for (int it = 0; it < max_iter; ++it) {
-        CB_LAUNCH(k_cb_p, dim3(grid), dim3(256), 0, s, n, sc, cv);
-        CB_LAUNCH(k_mg_coarse_apply, dim3(g.nblk), dim3(64), 0, s, g, Dc, nc, cv.p, cv.v, sc);
-        CB_LAUNCH((k_cb_dot<false>), dim3(grid), dim3(256), 0, s, n, sc, cv.rh, cv.v, partials);
-        CB_LAUNCH(k_cb_finalize, dim3(1), dim3(256), 0, s, partials, grid, sc, (int)CB_ALPHA, 0.0);
-        CB_LAUNCH(k_cb_s, dim3(grid), dim3(256), 0, s, n, sc, cv);
-        CB_LAUNCH(k_mg_coarse_apply, dim3(g.nblk), dim3(64), 0, s, g, Dc, nc, cv.s, cv.t, sc);
-        CB_LAUNCH((k_cb_dot<true>), dim3(grid), dim3(256), 0, s, n, sc, cv.t, cv.s, partials);
-        CB_LAUNCH(k_cb_finalize, dim3(1), dim3(256), 0, s, partials, grid, sc, (int)CB_OMEGA, 0.0);
-        CB_LAUNCH(k_cb_xr, dim3(grid), dim3(256), 0, s, n, sc, cv, partials);
-        CB_LAUNCH(k_cb_finalize, dim3(1), dim3(256), 0, s, partials, grid, sc, (int)CB_RHO, 0.0);
+        const int q = it & 1;
+        CB_LAUNCH(k_cb_f1, dim3(1), dim3(1024), 0, s, pa.A, grid, sc, it, tol * tol);
+        CB_LAUNCH(k_cb_m1, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, Dc, nc, cv, sc, q, pa.B);
+        CB_LAUNCH(k_cb_f2, dim3(1), dim3(1024), 0, s, pa.B, g.nblk, sc, q);
+        CB_LAUNCH(k_cb_m2, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, Dc, nc, cv, sc, q, pa.C);
+        CB_LAUNCH(k_cb_f3, dim3(1), dim3(1024), 0, s, pa.C, g.nblk, sc, q);
+        CB_LAUNCH(k_cb_update, dim3(grid), dim3(256), 0, s, n, sc, q, cv, pa.A);
     }
 #undef CB_LAUNCH
     return hipSuccess;

@@ -8,17 +8,26 @@ namespace cs {
 
 constexpr int MG_MAX_NV = 32;  // nc = 2 nv coarse values per aggregate fit one wave
 
-// Scalars of the coarse BiCGStab, kept on the device.  Once `stopped` is set
-// every later kernel of the iteration returns at once, so a fixed number of
-// iterations can be launched (or captured) without host round trips.
+constexpr int MG_ELEM_WG = 1024;  // workgroups of the elementwise coarse kernels (at most)
+
+// Scalars of the coarse BiCGStab, kept on the device.  Once a stop flag is
+// set every later kernel of the solve returns at once, so a fixed number of
+// iterations can be launched (or captured) without host round trips.  Slots
+// [2] are indexed by iteration parity.
 struct CbScalars {
-    double2 rho, alpha, omega, beta;
+    double2 rho[2], beta[2], alpha, omega;
     double rr, stop2;  // |r|^2 and the stopping threshold tol^2 |r_0|^2
-    int stopped, pad;
+    int stopped[2], brk[2];
 };
 
 struct CbVecs {
-    float2 *x, *r, *rh, *p, *v, *s, *t;
+    float2 *x, *r, *rh, *p[2], *v[2], *s, *t;
+};
+
+// Workgroup partial sums: A from the elementwise kernels (at most
+// MG_ELEM_WG workgroups), B and C from the two products (one per coarse site).
+struct CbPartials {
+    double2 *A, *B, *C;
 };
 
 struct MgParams {
@@ -39,7 +48,7 @@ struct MgData {
     float2* rc = nullptr;
     CbVecs cv{};
     CbScalars* sc = nullptr;
-    double2* partials = nullptr;
+    CbPartials pa{};
     LaunchCfg sap_cfg{};
 
     int nc() const { return 2 * p.nv; }
@@ -56,13 +65,12 @@ hipError_t mg_orthonormalize(const Geom& g, void* P, int nv, hipStream_t s);
 hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipStream_t s);
 hipError_t mg_restrict(const Geom& g, const void* P, int nv, const void* r, float2* rc, hipStream_t s);
 hipError_t mg_prolong(const Geom& g, const void* P, int nv, const float2* ec, void* z, hipStream_t s);
-// y = D_c x (sc may be null; when set and stopped the launch does nothing)
-hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2* x, float2* y,
-                           const CbScalars* sc, hipStream_t s);
+// y = D_c x
+hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2* x, float2* y, hipStream_t s);
 // cv.x = BiCGStab(D_c, rc) from zero: at most max_iter iterations, fewer once
 // |r| <= tol |rc| or on a breakdown (all decided on the device)
 hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const float2* rc, const CbVecs& cv,
-                              CbScalars* sc, double2* partials, int max_iter, double tol, hipStream_t s);
+                              CbScalars* sc, const CbPartials& pa, int max_iter, double tol, hipStream_t s);
 
 // mg.cpp
 // Null vectors from the nv FP32 fields etas, P and D_c, n_adapt adaptive passes.
