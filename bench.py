@@ -183,7 +183,73 @@ def hbm_resident_measurement(cs, synth, torch, reps_d=20, reps_sap=10):
     res["sp_bicgstab_richardson_f32_time_to_1e-10_s"] = round(t, 4)
     res["sp_bicgstab_richardson_f32_iterations"] = it
     res["sp_bicgstab_richardson_f32_status"] = st
+    # SAP-FGCR again right before the multigrid runs (median of 3), then MG
+    t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32), 3)
+    log("[bench] 32^3x64 two-level multigrid")
+    res["multigrid"] = multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, t, it)
     return res
+
+
+# Two-level multigrid of the paper's Section 3: N_vec = 16 null vectors from
+# SAP-smoothed random vectors and 4 adaptive passes, coarse BiCGStab to 5%
+# (at most 50 iterations), 2 SAP post-smoothing cycles of 4 MR steps.
+MG_PARAMS = dict(nv=16, n_cy_setup=4, n_mr=4, n_adapt=4, n_coarse=50, n_cy_post=2, tol_coarse=0.05)
+
+
+def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap_it, reps=3):
+    """MG-preconditioned FGCR to 1e-10 on the same system as SAP-FGCR:
+    setup time, solve time (median of reps), iterations, per-family kernel
+    time of one solve, and the paper's comparison of one and of twelve
+    equations with the setup included."""
+    import numpy as np
+
+    import oracle
+    dims = c["dims"]
+    prm = cs.MgParams(**MG_PARAMS)
+    fb = lat.field_bytes(cs.F32)
+    etas = lat.new_field(cs.F32, prm.nv)
+    for i in range(prm.nv):
+        eta = torch.from_numpy(synth.source(dims, c["mg_eta_seed"] + i)).cuda()
+        lat.import_field(eta, cs.F32, out=etas[i * fb:(i + 1) * fb])
+        del eta
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    m = cs.Multigrid(op, etas, prm)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, tol=1e-10)
+    times = []
+    for i in range(reps + 1):
+        xd.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats = m.gcr_solve(xd, bd, p, allow_fail=True)
+        torch.cuda.synchronize()
+        if i:
+            times.append(time.perf_counter() - t)
+    solve_s = float(sorted(times)[len(times) // 2])
+    x = lat.export_field(xd, cs.F64).cpu().numpy()
+    rel = oracle.residual_norm(dims, U, c["kappa"], c["csw"], b, x) / np.linalg.norm(b)
+    cs.profile_reset()
+    cs.profile_enable(True)
+    xd.zero_()
+    m.gcr_solve(xd, bd, p, allow_fail=True)
+    torch.cuda.synchronize()
+    cs.profile_enable(False)
+    fam = {k: cs.profile_query(k) for k in ("mg", "sap_halfsweep", "dslash", "blas")}
+    del m, etas
+    torch.cuda.empty_cache()
+    return dict(params=MG_PARAMS, setup_s=round(setup_s, 4), solve_s=round(solve_s, 4),
+                iterations=stats["iters"], status=st, oracle_checked_relres=float(f"{rel:.3e}"),
+                sap_fgcr_solve_s=round(sap_s, 4), sap_fgcr_iterations=sap_it,
+                solve_speedup_vs_sap_fgcr=round(sap_s / solve_s, 3),
+                one_equation_incl_setup_s=round(setup_s + solve_s, 4),
+                twelve_equations_incl_setup_s=round(setup_s + 12 * solve_s, 4),
+                twelve_equations_sap_fgcr_s=round(12 * sap_s, 4),
+                kernels_ms_one_solve={k: round(v[1], 3) for k, v in fam.items()},
+                note=("FP32 multigrid preconditioner (P, D_c and coarse vectors FP32, coarse reductions "
+                      "FP64) inside FP64 flexible GCR(16); aggregates are the 4^4 SAP blocks; the "
+                      "kernel times come from an eager pass with HIP events around every launch"))
 
 
 def time_gcr(cs, torch, op, xd, bd, p, reps):
@@ -491,6 +557,10 @@ def main():
     jq_s, jq_it, jq_st = time_bicgstab(cs, torch, op, xd, bd, cs.SolverParams(
         inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10, block_solver=1), 5)
 
+    log("[bench] two-level multigrid on the same system")
+    mg16 = multigrid_measurement(cs, synth, torch, op, lat, cfg, U, b, bd, xd, ms_per_step / 1e3,
+                                 int(np.median(iters)), reps=5)
+
     import oracle
     rel_or = oracle.residual_norm(dims, U, kappa, csw, b, x_gpu) / np.linalg.norm(b)
     rel_bi = oracle.residual_norm(dims, U, kappa, csw, b, x_bi) / np.linalg.norm(b)
@@ -522,6 +592,7 @@ def main():
                                            oracle_checked_relres=float(f"{rel_sp:.3e}"),
                                            note="FP32-vector BiCGStab inner solves to 1e-5 inside an FP64 "
                                                 "Richardson iteration, same FP32 smoother, median of 5"),
+               multigrid=mg16,
                kernels={k: dict(launches=v[0], total_ms=round(v[1], 3),
                                 avg_us=round(v[1] / max(v[0], 1) * 1e3, 2))
                         for k, v in fam.items()},

@@ -160,7 +160,8 @@ struct Solver {
         char* zk = (char*)w.Z + (size_t)k * n * w.zstride;
         char* wk = (char*)w.W + (size_t)k * n * w.wstride;
         if (p.mg) {
-            GCR_CHK(mg_apply(op, *p.mg, zk, w.rlo, s));
+            // the coarse phase (restriction and coarse solve) has run already
+            GCR_CHK(mg_finish(op, *p.mg, zk, w.rlo, s));
         } else if (p.n_cy > 0) {
             // w.rlo holds the residual in the inner precision, written by the
             // kernel that last updated w.r
@@ -201,6 +202,8 @@ struct Solver {
     }
 
     hipError_t run_iteration(int k) {
+        // the multigrid coarse phase runs first, in chunks with host checks
+        if (p.mg) GCR_CHK(mg_coarse_phase(*p.mg, w.rlo, s, p.use_graph));
         if (!p.use_graph) return iteration(k);
         const std::vector<char> kk = key();
         if (w.graph_key != kk) {

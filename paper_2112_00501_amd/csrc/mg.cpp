@@ -9,8 +9,9 @@
 // Application z = M_MG r: r_c = P^dag r; e_c = coarse BiCGStab on D_c r_c
 // (FP32 vectors, FP64 reductions, at most n_coarse iterations, stopping at a
 // relative residual of tol_coarse, decided on the device); z = P e_c; then
-// n_cy_post SAP cycles on D z = r started from z.  Every launch has a fixed
-// shape, so an application can be captured into a HIP graph.
+// n_cy_post SAP cycles on D z = r started from z.  The coarse iterations run
+// in chunks of MG_CHUNK; after each chunk the host reads the device's stop
+// flag, so iterations after convergence are not launched.
 #include <hip/hip_runtime.h>
 
 #include "mg.hpp"
@@ -46,11 +47,21 @@ hipError_t rebuild(const OpData& op, MgData& m, hipStream_t s) {
 
 size_t MgData::field_bytes() const { return spinor_bytes_per_site(P_F32) * g.V; }
 
+void MgData::drop_graphs() const {
+    if (gr.first) hipGraphExecDestroy(gr.first);
+    for (hipGraphExec_t e : gr.chunk)
+        if (e) hipGraphExecDestroy(e);
+    gr = Graphs{};
+}
+
 void MgData::release() {
+    drop_graphs();
     for (void** q : {&P, &V, &tmp, (void**)&Dc, (void**)&rc, (void**)&cv.x, (void**)&sc, (void**)&pa.A}) {
         if (*q) hipFree(*q);
         *q = nullptr;
     }
+    if (host_flag) hipHostFree(host_flag);
+    host_flag = nullptr;
     cv = CbVecs{};
     pa = CbPartials{};
 }
@@ -83,6 +94,7 @@ hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
     double2* pb = nullptr;
     MG_CHK(hipMalloc((void**)&pb, sizeof(double2) * (na + 2 * nb)));
     pa = CbPartials{pb, pb + na, pb + na + nb};
+    MG_CHK(hipHostMalloc((void**)&host_flag, sizeof(int), hipHostMallocDefault));
     return hipSuccess;
 }
 
@@ -100,11 +112,63 @@ hipError_t mg_setup(const OpData& op, MgData& m, const void* etas, hipStream_t s
     return hipSuccess;
 }
 
-hipError_t mg_apply(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s) {
-    MG_CHK(mg_restrict(m.g, m.P, m.p.nv, r, m.rc, s));
-    MG_CHK(mg_coarse_bicgstab(m.g, m.Dc, m.nc(), m.rc, m.cv, m.sc, m.pa, m.p.n_coarse, m.p.tol_coarse, s));
+namespace {
+
+// Run launch() directly, or as a graph captured into *exec on first use.
+template <typename F>
+hipError_t run_piece(hipGraphExec_t* exec, bool use_graph, hipStream_t s, F launch) {
+    if (!use_graph) return launch();
+    if (!*exec) {
+        hipGraph_t graph;
+        MG_CHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch();
+        hipError_t e2 = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess) return e;
+        if (e2 != hipSuccess) return e2;
+        e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+    }
+    return hipGraphLaunch(*exec, s);
+}
+
+}  // namespace
+
+hipError_t mg_coarse_phase(const MgData& m, const void* r, hipStream_t s, bool use_graph) {
+    if (use_graph && m.gr.r != r) {
+        m.drop_graphs();
+        m.gr.r = r;
+    }
+    const int cap = m.p.n_coarse;
+    int done = cap < MG_CHUNK ? cap : MG_CHUNK;
+    MG_CHK(run_piece(&m.gr.first, use_graph, s, [&]() -> hipError_t {
+        MG_CHK(mg_restrict(m.g, m.P, m.p.nv, r, m.rc, s));
+        MG_CHK(mg_coarse_begin(m.g, m.nc(), m.rc, m.cv, m.sc, m.pa, m.p.tol_coarse, s));
+        return mg_coarse_iters(m.g, m.Dc, m.nc(), m.cv, m.sc, m.pa, 0, done, s);
+    }));
+    for (int j = 0; done < cap; ++j) {
+        // stopped[done & 1] was set by the stop test of iteration `done`
+        MG_CHK(hipMemcpyAsync(m.host_flag, &m.sc->stopped[done & 1], sizeof(int), hipMemcpyDeviceToHost, s));
+        MG_CHK(hipStreamSynchronize(s));
+        if (*m.host_flag) break;
+        const int to = done + MG_CHUNK < cap ? done + MG_CHUNK : cap;
+        if ((int)m.gr.chunk.size() <= j) m.gr.chunk.resize(j + 1, nullptr);
+        MG_CHK(run_piece(&m.gr.chunk[j], use_graph, s, [&]() -> hipError_t {
+            return mg_coarse_iters(m.g, m.Dc, m.nc(), m.cv, m.sc, m.pa, done, to, s);
+        }));
+        done = to;
+    }
+    return hipSuccess;
+}
+
+hipError_t mg_finish(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s) {
     MG_CHK(mg_prolong(m.g, m.P, m.p.nv, m.cv.x, z, s));
     return sap_cycles(op, m.sap_cfg, m.p.n_cy_post, m.p.n_mr, false, z, r, 1, s);
+}
+
+hipError_t mg_apply(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s) {
+    MG_CHK(mg_coarse_phase(m, r, s, false));
+    return mg_finish(op, m, z, r, s);
 }
 
 }  // namespace cs

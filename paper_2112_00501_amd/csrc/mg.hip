@@ -427,10 +427,9 @@ __device__ __forceinline__ double2 cmul_d(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Coarse BiCGStab, one iteration (it, parity q = it & 1) as six launches:
-//   F1  rho_new = <rh, r>, |r|^2 from the partials A; stop before the
-//       iteration (rho_new = 0; after it > 0 also omega = 0 or |r| <= tol |r_0|);
-//       beta = (rho_new / rho_old) (alpha / omega)
+// Coarse BiCGStab.  The start (x = 0, r = rh = r_c) is followed by the stop
+// test F1 of iteration 0; iteration it (parity q = it & 1) is then six
+// launches, the last of which is the stop test of iteration it + 1:
 //   M1  p = r + beta (p_prev - omega v_prev) formed while gathering, v = D_c p,
 //       partials B = <rh, v>
 //   F2  alpha = rho_new / <rh, v> (a zero denominator ends the solve)
@@ -438,12 +437,15 @@ __device__ __forceinline__ double2 cmul_d(double2 a, double2 b) {
 //       <t, s>, |t|^2
 //   F3  omega = <t, s> / |t|^2 (0 when t = 0)
 //   U   x += alpha p + omega s, r = s - omega t, partials A
+//   F1  rho_new = <rh, r>, |r|^2 from the partials A; stop before the next
+//       iteration when rho_new = 0, omega = 0, |r| <= tol |r_0| or an earlier
+//       stop; beta = (rho_new / rho_old) (alpha / omega)
 // p and v alternate between two buffers by parity, so the gathers of M1 read
 // the previous iteration's values while its own entries are written.  A
 // kernel reads only scalars written by earlier kernels (slots by parity
 // where a kernel would otherwise read what it writes), and every later
 // kernel returns at once after a stop, so a fixed number of iterations can be
-// launched or captured.
+// launched or captured; stopped[it & 1] tells whether iteration it runs.
 
 // Fixed-order sum of the first three reals (re, im of slot 0; re of slot 1)
 // of nwg two-slot partials by one workgroup of 1024 lanes; valid in lane 0.
@@ -680,28 +682,45 @@ hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2
     return hipGetLastError();
 }
 
-hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const float2* rc, const CbVecs& cv,
-                              CbScalars* sc, const CbPartials& pa, int max_iter, double tol, hipStream_t s) {
-    ProfScope ps("mg", s);
-    const int n = g.nblk * nc, grid = cb_grid(n);
 #define CB_LAUNCH(...)                           \
     do {                                         \
         hipLaunchKernelGGL(__VA_ARGS__);         \
         hipError_t e_ = hipGetLastError();       \
         if (e_ != hipSuccess) return e_;         \
     } while (0)
+
+hipError_t mg_coarse_begin(const Geom& g, int nc, const float2* rc, const CbVecs& cv, CbScalars* sc,
+                           const CbPartials& pa, double tol, hipStream_t s) {
+    ProfScope ps("mg", s);
+    const int n = g.nblk * nc, grid = cb_grid(n);
     CB_LAUNCH(k_cb_init, dim3(grid), dim3(256), 0, s, n, rc, cv, pa.A);
-    for (int it = 0; it < max_iter; ++it) {
+    CB_LAUNCH(k_cb_f1, dim3(1), dim3(1024), 0, s, pa.A, grid, sc, 0, tol * tol);
+    return hipSuccess;
+}
+
+hipError_t mg_coarse_iters(const Geom& g, const float2* Dc, int nc, const CbVecs& cv, CbScalars* sc,
+                           const CbPartials& pa, int it0, int it1, hipStream_t s) {
+    ProfScope ps("mg", s);
+    const int n = g.nblk * nc, grid = cb_grid(n);
+    for (int it = it0; it < it1; ++it) {
         const int q = it & 1;
-        CB_LAUNCH(k_cb_f1, dim3(1), dim3(1024), 0, s, pa.A, grid, sc, it, tol * tol);
         CB_LAUNCH(k_cb_m1, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, Dc, nc, cv, sc, q, pa.B);
         CB_LAUNCH(k_cb_f2, dim3(1), dim3(1024), 0, s, pa.B, g.nblk, sc, q);
         CB_LAUNCH(k_cb_m2, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, Dc, nc, cv, sc, q, pa.C);
         CB_LAUNCH(k_cb_f3, dim3(1), dim3(1024), 0, s, pa.C, g.nblk, sc, q);
         CB_LAUNCH(k_cb_update, dim3(grid), dim3(256), 0, s, n, sc, q, cv, pa.A);
+        CB_LAUNCH(k_cb_f1, dim3(1), dim3(1024), 0, s, pa.A, grid, sc, it + 1, 0.0);
     }
-#undef CB_LAUNCH
     return hipSuccess;
+}
+
+#undef CB_LAUNCH
+
+hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const float2* rc, const CbVecs& cv,
+                              CbScalars* sc, const CbPartials& pa, int max_iter, double tol, hipStream_t s) {
+    hipError_t e = mg_coarse_begin(g, nc, rc, cv, sc, pa, tol, s);
+    if (e != hipSuccess) return e;
+    return mg_coarse_iters(g, Dc, nc, cv, sc, pa, 0, max_iter, s);
 }
 
 }  // namespace cs

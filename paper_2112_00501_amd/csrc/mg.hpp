@@ -2,6 +2,8 @@
 // setup and application drivers in mg.cpp.
 #pragma once
 
+#include <vector>
+
 #include "cs_internal.hpp"
 
 namespace cs {
@@ -9,6 +11,7 @@ namespace cs {
 constexpr int MG_MAX_NV = 32;  // nc = 2 nv coarse values per aggregate fit one wave
 
 constexpr int MG_ELEM_WG = 1024;  // workgroups of the elementwise coarse kernels (at most)
+constexpr int MG_CHUNK = 8;       // coarse iterations between two host reads of the stop flag
 
 // Scalars of the coarse BiCGStab, kept on the device.  Once a stop flag is
 // set every later kernel of the solve returns at once, so a fixed number of
@@ -50,6 +53,16 @@ struct MgData {
     CbScalars* sc = nullptr;
     CbPartials pa{};
     LaunchCfg sap_cfg{};
+    int* host_flag = nullptr;  // pinned copy of a stop flag
+    // captured graphs of the coarse phase: restriction of `r`, start and the
+    // first chunk; then chunk j covers iterations [(j + 1) MG_CHUNK, ...)
+    struct Graphs {
+        const void* r = nullptr;
+        hipGraphExec_t first = nullptr;
+        std::vector<hipGraphExec_t> chunk;
+    };
+    mutable Graphs gr;
+    void drop_graphs() const;
 
     int nc() const { return 2 * p.nv; }
     size_t field_bytes() const;
@@ -71,11 +84,24 @@ hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2
 // |r| <= tol |rc| or on a breakdown (all decided on the device)
 hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const float2* rc, const CbVecs& cv,
                               CbScalars* sc, const CbPartials& pa, int max_iter, double tol, hipStream_t s);
+// The same solve in pieces: the start with the stop test of iteration 0, then
+// iterations [it0, it1), each ending with the stop test of the next one.
+hipError_t mg_coarse_begin(const Geom& g, int nc, const float2* rc, const CbVecs& cv, CbScalars* sc,
+                           const CbPartials& pa, double tol, hipStream_t s);
+hipError_t mg_coarse_iters(const Geom& g, const float2* Dc, int nc, const CbVecs& cv, CbScalars* sc,
+                           const CbPartials& pa, int it0, int it1, hipStream_t s);
 
 // mg.cpp
 // Null vectors from the nv FP32 fields etas, P and D_c, n_adapt adaptive passes.
 hipError_t mg_setup(const OpData& op, MgData& m, const void* etas, hipStream_t s);
 // z = M_MG r (FP32 fields, z != r): coarse correction, then n_cy_post SAP cycles.
 hipError_t mg_apply(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s);
+// The first part of M_MG r: r_c = P^dag r and the coarse solve into m.cv.x,
+// run in chunks of MG_CHUNK iterations with a host read of the stop flag
+// after each (synchronises s); with use_graph the pieces are captured once
+// (s must then be a non-null stream) and replayed.
+hipError_t mg_coarse_phase(const MgData& m, const void* r, hipStream_t s, bool use_graph);
+// The second part: z = P m.cv.x, then n_cy_post SAP cycles on D z = r.
+hipError_t mg_finish(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s);
 
 }  // namespace cs

@@ -150,9 +150,9 @@ CONFIGS = {
     "plain_fp64_8x8x8x8": dict(dims=(8, 8, 8, 8), eps=0.3, kappa=0.13, csw=1.0,
                                gauge_seed=1001, src_seed=2001),
     "mixed_16x16x16x32": dict(dims=(16, 16, 16, 32), eps=0.3, kappa=0.1355, csw=1.0,
-                              gauge_seed=1002, src_seed=2002),
+                              gauge_seed=1002, src_seed=2002, mg_eta_seed=4002),
     "lowprec_32x32x32x64": dict(dims=(32, 32, 32, 64), eps=0.25, kappa=0.1370, csw=1.1,
-                                gauge_seed=1003, src_seed=2003),
+                                gauge_seed=1003, src_seed=2003, mg_eta_seed=4003),
     "lowprec_sub_16x16x16x16": dict(dims=(16, 16, 16, 16), eps=0.25, kappa=0.1370, csw=1.1,
                                     gauge_seed=1013, src_seed=2013),
     "multirhs_24x24x24x48": dict(dims=(24, 24, 24, 48), eps=0.3, kappa=0.1355, csw=1.0,
