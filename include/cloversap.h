@@ -330,10 +330,13 @@ typedef struct {
     int n_coarse;       /* coarse BiCGStab iteration cap per application (>= 1)   */
     int n_cy_post;      /* SAP post-smoothing cycles per application (>= 0)       */
     double tol_coarse;  /* relative coarse residual that ends the coarse solve    */
+    cs_prec coarse_prec;/* storage of D_c read by the coarse solve and by
+                           cs_mg_coarse_apply: CS_F32, or CS_F16 (an FP16 copy
+                           made after every assembly; arithmetic stays FP32)  */
 } cs_mg_params;
 
 /* Defaults: nv 8, n_cy_setup 4, n_mr 4, n_adapt 1, n_coarse 50, n_cy_post 2,
- * tol_coarse 0.05. */
+ * tol_coarse 0.05, coarse_prec CS_F32. */
 void cs_mg_params_default(cs_mg_params* p);
 
 /* Build the hierarchy for operator (g, c).  etas: nv consecutive CS_F32

@@ -662,6 +662,7 @@ void cs_mg_params_default(cs_mg_params* p) {
     p->n_coarse = 50;
     p->n_cy_post = 2;
     p->tol_coarse = 0.05;
+    p->coarse_prec = CS_F32;
 }
 
 int cs_mg_create(cs_gauge g, cs_clover c, const cs_mg_params* p, const void* etas, void* stream, cs_mg* out) {
@@ -678,7 +679,10 @@ int cs_mg_create(cs_gauge g, cs_clover c, const cs_mg_params* p, const void* eta
     std::unique_ptr<cs_mg_s> m(new cs_mg_s);
     m->gauge = g;
     m->clover = c;
-    const cs::MgParams mp{p->nv, p->n_cy_setup, p->n_mr, p->n_adapt, p->n_coarse, p->n_cy_post, p->tol_coarse};
+    if (p->coarse_prec != CS_F32 && p->coarse_prec != CS_F16)
+        return fail(CS_ERR_PRECISION, "coarse_prec must be CS_F32 or CS_F16");
+    const cs::MgParams mp{p->nv,         p->n_cy_setup, p->n_mr,       p->n_adapt,
+                          p->n_coarse,   p->n_cy_post,  p->tol_coarse, p->coarse_prec == CS_F16 ? 1 : 0};
     hipError_t e = m->data.alloc(g->g, mp);
     if (e != hipSuccess) return fail(CS_ERR_ALLOC, "multigrid workspace: %s", hipGetErrorString(e));
     if (overlap(etas, m->data.V, m->data.field_bytes() * p->nv))
@@ -718,7 +722,7 @@ int cs_mg_prolong(cs_mg m, const void* ec, void* z, void* stream) {
 int cs_mg_coarse_apply(cs_mg m, const void* x, void* y, void* stream) {
     if (!m || !x || !y) return fail(CS_ERR_NULL, "handle, x and y must be non-NULL");
     if (overlap(x, y, m->data.coarse_bytes())) return fail(CS_ERR_INVALID, "x and y overlap");
-    CS_HIP(cs::mg_coarse_apply(m->data.g, m->data.Dc, m->data.nc(), (const float2*)x, (float2*)y,
+    CS_HIP(cs::mg_coarse_apply(m->data.g, m->data.coarse(), m->data.nc(), (const float2*)x, (float2*)y,
                                (hipStream_t)stream));
     return ok();
 }
@@ -728,7 +732,7 @@ int cs_mg_coarse_solve(cs_mg m, const void* rc, void* ec, int n_iter, double tol
     if (n_iter < 0 || !(tol >= 0.0)) return fail(CS_ERR_INVALID, "need n_iter >= 0 and tol >= 0");
     hipStream_t s = (hipStream_t)stream;
     const cs::MgData& d = m->data;
-    CS_HIP(cs::mg_coarse_bicgstab(d.g, d.Dc, d.nc(), (const float2*)rc, d.cv, d.sc, d.pa, n_iter, tol, s));
+    CS_HIP(cs::mg_coarse_bicgstab(d.g, d.coarse(), d.nc(), (const float2*)rc, d.cv, d.sc, d.pa, n_iter, tol, s));
     CS_HIP(hipMemcpyAsync(ec, d.cv.x, d.coarse_bytes(), hipMemcpyDeviceToDevice, s));
     return ok();
 }

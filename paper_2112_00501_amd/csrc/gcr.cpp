@@ -191,12 +191,13 @@ struct Solver {
                               p.mg, p.mg ? p.mg->P : nullptr, p.mg ? p.mg->Dc : nullptr};
         std::memcpy(kbuf.data() + sizeof vals, ptrs, sizeof ptrs);
         std::memcpy(kbuf.data() + sizeof vals + sizeof ptrs, &op.kappa, sizeof op.kappa);
-        if (p.mg) {  // the shape of a multigrid application
+        if (p.mg) {  // the hierarchy (a fresh id for every allocation) and its shape
             const MgParams& q = p.mg->p;
-            const int mv[] = {q.nv, q.n_mr, q.n_coarse, q.n_cy_post};
+            const int mv[] = {q.nv, q.n_mr, q.n_coarse, q.n_cy_post, q.coarse_half};
             char* at = kbuf.data() + sizeof vals + sizeof ptrs + sizeof op.kappa;
             std::memcpy(at, mv, sizeof mv);
             std::memcpy(at + sizeof mv, &q.tol_coarse, sizeof q.tol_coarse);
+            std::memcpy(at + sizeof mv + sizeof q.tol_coarse, &p.mg->id, sizeof p.mg->id);
         }
         return kbuf;
     }

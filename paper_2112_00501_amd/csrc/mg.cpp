@@ -14,6 +14,8 @@
 // flag, so iterations after convergence are not launched.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "mg.hpp"
 
 namespace cs {
@@ -40,7 +42,9 @@ hipError_t sap_cycles(const OpData& op, const LaunchCfg& cfg, int n_cy, int n_mr
 hipError_t rebuild(const OpData& op, MgData& m, hipStream_t s) {
     MG_CHK(hipMemcpyAsync(m.P, m.V, m.field_bytes() * m.p.nv, hipMemcpyDeviceToDevice, s));
     MG_CHK(mg_orthonormalize(m.g, m.P, m.p.nv, s));
-    return mg_assemble(op, m.P, m.p.nv, m.Dc, s);
+    MG_CHK(mg_assemble(op, m.P, m.p.nv, m.Dc, s));
+    if (m.p.coarse_half) MG_CHK(mg_coarse_half(m.Dc, m.Dc16, m.dc_bytes() / sizeof(float2), s));
+    return hipSuccess;
 }
 
 }  // namespace
@@ -56,7 +60,7 @@ void MgData::drop_graphs() const {
 
 void MgData::release() {
     drop_graphs();
-    for (void** q : {&P, &V, &tmp, (void**)&Dc, (void**)&rc, (void**)&cv.x, (void**)&sc, (void**)&pa.A}) {
+    for (void** q : {&P, &V, &tmp, (void**)&Dc, &Dc16, (void**)&rc, (void**)&cv.x, (void**)&sc, (void**)&pa.A}) {
         if (*q) hipFree(*q);
         *q = nullptr;
     }
@@ -67,13 +71,16 @@ void MgData::release() {
 }
 
 hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
+    static std::atomic<unsigned long long> next_id{1};
     release();
     g = g_;
     p = p_;
+    id = next_id++;
     MG_CHK(hipMalloc(&P, field_bytes() * p.nv));
     MG_CHK(hipMalloc(&V, field_bytes() * p.nv));
     MG_CHK(hipMalloc(&tmp, field_bytes()));
     MG_CHK(hipMalloc((void**)&Dc, dc_bytes()));
+    if (p.coarse_half) MG_CHK(hipMalloc(&Dc16, dc_bytes() / 2));
     MG_CHK(hipMalloc((void**)&rc, coarse_bytes()));
     // the nine coarse vectors in one allocation (cv.x owns it)
     float2* base = nullptr;
@@ -144,7 +151,7 @@ hipError_t mg_coarse_phase(const MgData& m, const void* r, hipStream_t s, bool u
     MG_CHK(run_piece(&m.gr.first, use_graph, s, [&]() -> hipError_t {
         MG_CHK(mg_restrict(m.g, m.P, m.p.nv, r, m.rc, s));
         MG_CHK(mg_coarse_begin(m.g, m.nc(), m.rc, m.cv, m.sc, m.pa, m.p.tol_coarse, s));
-        return mg_coarse_iters(m.g, m.Dc, m.nc(), m.cv, m.sc, m.pa, 0, done, s);
+        return mg_coarse_iters(m.g, m.coarse(), m.nc(), m.cv, m.sc, m.pa, 0, done, s);
     }));
     for (int j = 0; done < cap; ++j) {
         // stopped[done & 1] was set by the stop test of iteration `done`
@@ -154,7 +161,7 @@ hipError_t mg_coarse_phase(const MgData& m, const void* r, hipStream_t s, bool u
         const int to = done + MG_CHUNK < cap ? done + MG_CHUNK : cap;
         if ((int)m.gr.chunk.size() <= j) m.gr.chunk.resize(j + 1, nullptr);
         MG_CHK(run_piece(&m.gr.chunk[j], use_graph, s, [&]() -> hipError_t {
-            return mg_coarse_iters(m.g, m.Dc, m.nc(), m.cv, m.sc, m.pa, done, to, s);
+            return mg_coarse_iters(m.g, m.coarse(), m.nc(), m.cv, m.sc, m.pa, done, to, s);
         }));
         done = to;
     }

@@ -354,14 +354,30 @@ __device__ __forceinline__ int coarse_nb(const Geom& g, const BlockPos& p, int d
     return d == 0 ? p.blk : block_step(g, p, (d - 1) >> 1, (d & 1) ? +1 : -1);
 }
 
-// y_row = sum_k M[k][row] xs[k]; valid in lanes t < nc (others return 0)
-__device__ __forceinline__ float2 cmv_rows(const float2* __restrict__ M, int nc, const float2* xs, float2* red) {
+// Entry (k, row) of a site's coarse matrix, FP32 or FP16 storage.
+template <bool HALF>
+__device__ __forceinline__ float2 cm_load(const void* M, size_t i) {
+    if (HALF) {
+        float a, b;
+        unpack2<P_F16>(((const unsigned int*)M)[i], a, b);
+        return make_float2(a, b);
+    }
+    return ((const float2*)M)[i];
+}
+
+// y_row = sum_k M[k][row] xs[k] for the coarse matrix M of site a; valid in
+// lanes t < nc (others return 0)
+template <bool HALF>
+__device__ __forceinline__ float2 cmv_rows(const void* __restrict__ Dc, int a, int nc, const float2* xs,
+                                           float2* red) {
     const int t = threadIdx.x, kch = CMV_TPB / nc, row = t % nc, kc = t / nc, K = 9 * nc;
+    const size_t base = (size_t)a * K * nc + row;
     float re = 0.f, im = 0.f, re2 = 0.f, im2 = 0.f;
     if (kc < kch) {
         int k = kc;
         for (; k + kch < K; k += 2 * kch) {
-            const float2 m0 = M[(size_t)k * nc + row], m1 = M[(size_t)(k + kch) * nc + row];
+            const float2 m0 = cm_load<HALF>(Dc, base + (size_t)k * nc);
+            const float2 m1 = cm_load<HALF>(Dc, base + (size_t)(k + kch) * nc);
             const float2 x0 = xs[k], x1 = xs[k + kch];
             re = fmaf(m0.x, x0.x, re); re = fmaf(-m0.y, x0.y, re);
             im = fmaf(m0.x, x0.y, im); im = fmaf(m0.y, x0.x, im);
@@ -369,7 +385,7 @@ __device__ __forceinline__ float2 cmv_rows(const float2* __restrict__ M, int nc,
             im2 = fmaf(m1.x, x1.y, im2); im2 = fmaf(m1.y, x1.x, im2);
         }
         if (k < K) {
-            const float2 m0 = M[(size_t)k * nc + row], x0 = xs[k];
+            const float2 m0 = cm_load<HALF>(Dc, base + (size_t)k * nc), x0 = xs[k];
             re = fmaf(m0.x, x0.x, re); re = fmaf(-m0.y, x0.y, re);
             im = fmaf(m0.x, x0.y, im); im = fmaf(m0.y, x0.x, im);
         }
@@ -407,7 +423,8 @@ __device__ __forceinline__ double2 cdot_d(float2 a, float2 b) {  // conj(a) b
 }
 
 // y = D_c x
-__global__ __launch_bounds__(CMV_TPB) void k_mg_coarse_apply(Geom g, const float2* __restrict__ Dc, int nc,
+template <bool HALF>
+__global__ __launch_bounds__(CMV_TPB) void k_mg_coarse_apply(Geom g, const void* __restrict__ Dc, int nc,
                                                              const float2* __restrict__ x, float2* __restrict__ y) {
     __shared__ float2 xs[CMV_KMAX];
     __shared__ float2 red[CMV_TPB];
@@ -415,7 +432,7 @@ __global__ __launch_bounds__(CMV_TPB) void k_mg_coarse_apply(Geom g, const float
     const BlockPos p = block_pos(g, a);
     for (int k = threadIdx.x; k < K; k += CMV_TPB) xs[k] = x[(size_t)coarse_nb(g, p, k / nc) * nc + k % nc];
     __syncthreads();
-    const float2 v = cmv_rows(Dc + (size_t)a * K * nc, nc, xs, red);
+    const float2 v = cmv_rows<HALF>(Dc, a, nc, xs, red);
     if ((int)threadIdx.x < nc) y[(size_t)a * nc + threadIdx.x] = v;
 }
 
@@ -501,7 +518,8 @@ __global__ __launch_bounds__(1024) void k_cb_f1(const double2* partials, int nwg
     sc->stopped[q] = stop;
 }
 
-__global__ __launch_bounds__(CMV_TPB) void k_cb_m1(Geom g, const float2* __restrict__ Dc, int nc, CbVecs cv,
+template <bool HALF>
+__global__ __launch_bounds__(CMV_TPB) void k_cb_m1(Geom g, const void* __restrict__ Dc, int nc, CbVecs cv,
                                                    const CbScalars* sc, int q, double2* partials) {
     if (sc->stopped[q]) return;
     __shared__ float2 xs[CMV_KMAX];
@@ -522,7 +540,7 @@ __global__ __launch_bounds__(CMV_TPB) void k_cb_m1(Geom g, const float2* __restr
         if (d == 0) pn[i] = pv;
     }
     __syncthreads();
-    const float2 v = cmv_rows(Dc + (size_t)a * K * nc, nc, xs, red);
+    const float2 v = cmv_rows<HALF>(Dc, a, nc, xs, red);
     double2 d0 = make_double2(0.0, 0.0);
     if ((int)threadIdx.x < nc) {
         const size_t i = (size_t)a * nc + threadIdx.x;
@@ -543,7 +561,8 @@ __global__ __launch_bounds__(1024) void k_cb_f2(const double2* partials, int nwg
     if (!brk) sc->alpha = cdiv2(sc->rho[q], rv);
 }
 
-__global__ __launch_bounds__(CMV_TPB) void k_cb_m2(Geom g, const float2* __restrict__ Dc, int nc, CbVecs cv,
+template <bool HALF>
+__global__ __launch_bounds__(CMV_TPB) void k_cb_m2(Geom g, const void* __restrict__ Dc, int nc, CbVecs cv,
                                                    const CbScalars* sc, int q, double2* partials) {
     if (sc->stopped[q] || sc->brk[q]) return;
     __shared__ float2 xs[CMV_KMAX];
@@ -561,7 +580,7 @@ __global__ __launch_bounds__(CMV_TPB) void k_cb_m2(Geom g, const float2* __restr
         if (d == 0) cv.s[i] = sv;
     }
     __syncthreads();
-    const float2 tv = cmv_rows(Dc + (size_t)a * K * nc, nc, xs, red);
+    const float2 tv = cmv_rows<HALF>(Dc, a, nc, xs, red);
     double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
     if ((int)threadIdx.x < nc) {
         const size_t i = (size_t)a * nc + threadIdx.x;
@@ -641,6 +660,15 @@ __global__ __launch_bounds__(256) void k_cb_update(int n, const CbScalars* sc, i
     chunk_partials(a, b, partials);
 }
 
+// FP16 copy of the FP32 coarse matrices
+__global__ __launch_bounds__(256) void k_mg_dc_half(const float2* __restrict__ src, unsigned int* __restrict__ dst,
+                                                    size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float2 v = src[i];
+        dst[i] = pack2<P_F16>(v.x, v.y);
+    }
+}
+
 int cb_grid(int n) {
     const int b = (n + 255) / 256;
     return b < MG_ELEM_WG ? b : MG_ELEM_WG;
@@ -676,9 +704,18 @@ hipError_t mg_prolong(const Geom& g, const void* P, int nv, const float2* ec, vo
     return hipGetLastError();
 }
 
-hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2* x, float2* y, hipStream_t s) {
+hipError_t mg_coarse_half(const float2* Dc, void* Dc16, size_t n, hipStream_t s) {
     ProfScope ps("mg", s);
-    hipLaunchKernelGGL(k_mg_coarse_apply, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, Dc, nc, x, y);
+    const size_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_mg_dc_half, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, Dc, (unsigned int*)Dc16,
+                       n);
+    return hipGetLastError();
+}
+
+hipError_t mg_coarse_apply(const Geom& g, CoarseMat M, int nc, const float2* x, float2* y, hipStream_t s) {
+    ProfScope ps("mg", s);
+    if (M.half) hipLaunchKernelGGL(k_mg_coarse_apply<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, x, y);
+    else hipLaunchKernelGGL(k_mg_coarse_apply<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, x, y);
     return hipGetLastError();
 }
 
@@ -698,15 +735,17 @@ hipError_t mg_coarse_begin(const Geom& g, int nc, const float2* rc, const CbVecs
     return hipSuccess;
 }
 
-hipError_t mg_coarse_iters(const Geom& g, const float2* Dc, int nc, const CbVecs& cv, CbScalars* sc,
+hipError_t mg_coarse_iters(const Geom& g, CoarseMat M, int nc, const CbVecs& cv, CbScalars* sc,
                            const CbPartials& pa, int it0, int it1, hipStream_t s) {
     ProfScope ps("mg", s);
     const int n = g.nblk * nc, grid = cb_grid(n);
     for (int it = it0; it < it1; ++it) {
         const int q = it & 1;
-        CB_LAUNCH(k_cb_m1, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, Dc, nc, cv, sc, q, pa.B);
+        if (M.half) CB_LAUNCH(k_cb_m1<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q, pa.B);
+        else CB_LAUNCH(k_cb_m1<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q, pa.B);
         CB_LAUNCH(k_cb_f2, dim3(1), dim3(1024), 0, s, pa.B, g.nblk, sc, q);
-        CB_LAUNCH(k_cb_m2, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, Dc, nc, cv, sc, q, pa.C);
+        if (M.half) CB_LAUNCH(k_cb_m2<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q, pa.C);
+        else CB_LAUNCH(k_cb_m2<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q, pa.C);
         CB_LAUNCH(k_cb_f3, dim3(1), dim3(1024), 0, s, pa.C, g.nblk, sc, q);
         CB_LAUNCH(k_cb_update, dim3(grid), dim3(256), 0, s, n, sc, q, cv, pa.A);
         CB_LAUNCH(k_cb_f1, dim3(1), dim3(1024), 0, s, pa.A, grid, sc, it + 1, 0.0);
@@ -716,11 +755,11 @@ hipError_t mg_coarse_iters(const Geom& g, const float2* Dc, int nc, const CbVecs
 
 #undef CB_LAUNCH
 
-hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const float2* rc, const CbVecs& cv,
+hipError_t mg_coarse_bicgstab(const Geom& g, CoarseMat M, int nc, const float2* rc, const CbVecs& cv,
                               CbScalars* sc, const CbPartials& pa, int max_iter, double tol, hipStream_t s) {
     hipError_t e = mg_coarse_begin(g, nc, rc, cv, sc, pa, tol, s);
     if (e != hipSuccess) return e;
-    return mg_coarse_iters(g, Dc, nc, cv, sc, pa, 0, max_iter, s);
+    return mg_coarse_iters(g, M, nc, cv, sc, pa, 0, max_iter, s);
 }
 
 }  // namespace cs

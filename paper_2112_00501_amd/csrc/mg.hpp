@@ -36,6 +36,13 @@ struct CbPartials {
 struct MgParams {
     int nv, n_cy_setup, n_mr, n_adapt, n_coarse, n_cy_post;
     double tol_coarse;
+    int coarse_half;  // the coarse solve reads an FP16 copy of D_c
+};
+
+// The coarse matrices as the coarse solver reads them.
+struct CoarseMat {
+    const void* m;
+    bool half;
 };
 
 // Device state of one hierarchy.  P: nv FP32 fields (field i holds
@@ -48,12 +55,14 @@ struct MgData {
     void* V = nullptr;
     void* tmp = nullptr;  // one FP32 field
     float2* Dc = nullptr;
+    void* Dc16 = nullptr;  // FP16 copy (coarse_half)
     float2* rc = nullptr;
     CbVecs cv{};
     CbScalars* sc = nullptr;
     CbPartials pa{};
     LaunchCfg sap_cfg{};
     int* host_flag = nullptr;  // pinned copy of a stop flag
+    unsigned long long id = 0; // distinct for every allocation (keys of captured graphs)
     // captured graphs of the coarse phase: restriction of `r`, start and the
     // first chunk; then chunk j covers iterations [(j + 1) MG_CHUNK, ...)
     struct Graphs {
@@ -68,6 +77,7 @@ struct MgData {
     size_t field_bytes() const;
     size_t coarse_bytes() const { return (size_t)g.nblk * nc() * sizeof(float2); }
     size_t dc_bytes() const { return (size_t)g.nblk * 9 * nc() * nc() * sizeof(float2); }
+    CoarseMat coarse() const { return p.coarse_half ? CoarseMat{Dc16, true} : CoarseMat{Dc, false}; }
     hipError_t alloc(const Geom& g, const MgParams& p);
     void release();
     ~MgData() { release(); }
@@ -78,17 +88,19 @@ hipError_t mg_orthonormalize(const Geom& g, void* P, int nv, hipStream_t s);
 hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipStream_t s);
 hipError_t mg_restrict(const Geom& g, const void* P, int nv, const void* r, float2* rc, hipStream_t s);
 hipError_t mg_prolong(const Geom& g, const void* P, int nv, const float2* ec, void* z, hipStream_t s);
+// Dc16 = FP16 copy of the n complex entries of Dc
+hipError_t mg_coarse_half(const float2* Dc, void* Dc16, size_t n, hipStream_t s);
 // y = D_c x
-hipError_t mg_coarse_apply(const Geom& g, const float2* Dc, int nc, const float2* x, float2* y, hipStream_t s);
+hipError_t mg_coarse_apply(const Geom& g, CoarseMat M, int nc, const float2* x, float2* y, hipStream_t s);
 // cv.x = BiCGStab(D_c, rc) from zero: at most max_iter iterations, fewer once
 // |r| <= tol |rc| or on a breakdown (all decided on the device)
-hipError_t mg_coarse_bicgstab(const Geom& g, const float2* Dc, int nc, const float2* rc, const CbVecs& cv,
+hipError_t mg_coarse_bicgstab(const Geom& g, CoarseMat M, int nc, const float2* rc, const CbVecs& cv,
                               CbScalars* sc, const CbPartials& pa, int max_iter, double tol, hipStream_t s);
 // The same solve in pieces: the start with the stop test of iteration 0, then
 // iterations [it0, it1), each ending with the stop test of the next one.
 hipError_t mg_coarse_begin(const Geom& g, int nc, const float2* rc, const CbVecs& cv, CbScalars* sc,
                            const CbPartials& pa, double tol, hipStream_t s);
-hipError_t mg_coarse_iters(const Geom& g, const float2* Dc, int nc, const CbVecs& cv, CbScalars* sc,
+hipError_t mg_coarse_iters(const Geom& g, CoarseMat M, int nc, const CbVecs& cv, CbScalars* sc,
                            const CbPartials& pa, int it0, int it1, hipStream_t s);
 
 // mg.cpp

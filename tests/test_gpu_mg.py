@@ -226,3 +226,56 @@ def test_mg_argument_errors(sys8, plain):
     st = cs._lib.cs_gcr_solve_mg(other.op.gauge.handle, other.op.clover.handle, m.handle, ctypes.byref(prm),
                                  cs._ptr(x), cs._ptr(b), None, cs._stream(None))
     assert st != 0  # the hierarchy was built for another operator
+
+
+def test_fp16_coarse_matrices(sys8, plain):
+    """FP16 storage of D_c for the coarse solve: the coarse product agrees
+    with the oracle's FP64 D_c to the FP16 rounding of the entries (unit
+    roundoff 4.9e-4), and MG-FGCR still reaches 1e-10 in about as many
+    iterations as with FP32 storage."""
+    c, etas, etas_d = sys8
+    _, m32, P_or, Dc_or, aggs = plain
+    m = cs.Multigrid(c.op, etas_d, cs.MgParams(**{**_params(0).__dict__, "coarse_prec": cs.F16}))
+    rng = np.random.default_rng(6700)
+    ec = rng.standard_normal((len(aggs), 2 * NV)) + 1j * rng.standard_normal((len(aggs), 2 * NV))
+    y = m.coarse_apply(_coarse(ec)).cpu().numpy().reshape(-1)
+    err = rel(y, Dc_or @ ec.reshape(-1))
+    print(f"FP16 coarse product: rel diff {err:.2e}")
+    assert err <= 1e-3
+    b = c.to_dev(synth.source(DIMS, 6800), cs.F64)
+    its = []
+    for mm in (m32, m):
+        x = c.lat.new_field(cs.F64).zero_()
+        st, stats = mm.gcr_solve(x, b, cs.SolverParams(inner_prec=cs.F32, tol=1e-10))
+        relres = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, synth.source(DIMS, 6800),
+                                      c.to_host(x, cs.F64)) / np.linalg.norm(synth.source(DIMS, 6800))
+        assert st == 0 and relres <= 1e-10 * (1 + 1e-6)
+        its.append(stats["iters"])
+    print(f"MG-FGCR iterations FP32 / FP16 coarse matrices: {its}")
+    assert its[1] <= its[0] + 2
+
+
+def test_graphs_follow_a_recreated_hierarchy(sys8):
+    """A hierarchy destroyed and another created (possibly at the same
+    addresses) must not replay graphs captured for the first: graph-replayed
+    and eager solves with the second agree bit for bit."""
+    import gc
+    c, etas, etas_d = sys8
+    b = c.to_dev(synth.source(DIMS, 6900), cs.F64)
+    m1 = cs.Multigrid(c.op, etas_d, _params(0))
+    x = c.lat.new_field(cs.F64).zero_()
+    m1.gcr_solve(x, b, cs.SolverParams(inner_prec=cs.F32, tol=1e-10))
+    torch.cuda.synchronize()
+    del m1
+    gc.collect()
+    etas2 = c.lat.import_field(torch.from_numpy(np.stack([synth.source(DIMS, 7100 + i) for i in range(NV)])).cuda(),
+                               cs.F32)
+    m2 = cs.Multigrid(c.op, etas2, cs.MgParams(**{**_params(1).__dict__, "coarse_prec": cs.F16}))
+    outs = []
+    for use_graph in (True, False):
+        x = c.lat.new_field(cs.F64).zero_()
+        st, stats = m2.gcr_solve(x, b, cs.SolverParams(inner_prec=cs.F32, tol=1e-10, use_graph=use_graph))
+        torch.cuda.synchronize()
+        outs.append((x, stats["iters"]))
+    print(f"iterations graph / eager: {outs[0][1]} / {outs[1][1]}")
+    assert outs[0][1] == outs[1][1] and torch.equal(outs[0][0], outs[1][0])
