@@ -11,7 +11,12 @@ benchmark uses, on outputs the FP64 oracle can evaluate one by one:
   precision);
 * the link force on sampled links (32^3 x 64) against central differences of
   -Re(y^dag D(U) x) under U -> exp(i h T^a) U, which hold at any size; the
-  oracle evaluates D only on the rows the perturbed link enters."""
+  oracle evaluates D only on the rows the perturbed link enters;
+* the two-level multigrid at 32^3 x 64 in the benchmark's configuration
+  (16 null vectors, 4 adaptive passes, FP32 and FP16 coarse matrices):
+  properties that hold at any size (P^dag P = 1, so restriction undoes
+  prolongation; D_c e = P^dag D P e, with D the GPU operator in FP32), and
+  the MG-FGCR solution checked by the oracle's own residual."""
 import itertools
 
 import numpy as np
@@ -204,3 +209,40 @@ def test_bicgstab_full_size_oracle_residual(big, vec):
           f"oracle relres={r:.3e}")
     assert st == 0
     assert r <= 1e-10 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("coarse_prec", [cs.F32, cs.F16])
+def test_multigrid_full_size(big, coarse_prec):
+    c = big
+    import bench
+    prm = cs.MgParams(**bench.MG_PARAMS)
+    prm.coarse_prec = coarse_prec
+    cfg = synth.CONFIGS["lowprec_32x32x32x64"]
+    fb = c.lat.field_bytes(cs.F32)
+    etas = c.lat.new_field(cs.F32, prm.nv)
+    for i in range(prm.nv):
+        c.lat.import_field(torch.from_numpy(synth.source(c.dims, cfg["mg_eta_seed"] + i)).cuda(), cs.F32,
+                           out=etas[i * fb:(i + 1) * fb])
+    m = cs.Multigrid(c.op, etas, prm)
+    rng = np.random.default_rng(8)
+    ec = rng.standard_normal((m.nblk, m.nc)) + 1j * rng.standard_normal((m.nblk, m.nc))
+    ecd = torch.from_numpy(ec.astype(np.complex64)).cuda()
+    z = m.prolong(ecd)
+    back = m.restrict(z).cpu().numpy()
+    e_orth = rel(back, ec)
+    dz = c.lat.new_field(cs.F32)
+    c.op.apply_D(dz, z, cs.F32)
+    galerkin = m.restrict(dz).cpu().numpy()
+    direct = m.coarse_apply(ecd).cpu().numpy()
+    e_gal = rel(direct, galerkin)
+    b = c.to_dev(c.b, cs.F64)
+    x = c.lat.new_field(cs.F64).zero_()
+    st, stats = m.gcr_solve(x, b, cs.SolverParams(inner_prec=cs.F32, tol=1e-10))
+    relres = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, c.b, c.to_host(x, cs.F64)) / np.linalg.norm(c.b)
+    print(f"32^3x64 MG coarse_prec={coarse_prec}: |R P e - e|/|e| {e_orth:.2e}, "
+          f"|D_c e - R D P e|/|.| {e_gal:.2e}, iters {stats['iters']}, oracle relres {relres:.2e}")
+    assert e_orth <= 1e-5
+    assert e_gal <= (1e-5 if coarse_prec == cs.F32 else 1e-3)
+    assert st == 0 and relres <= 1e-10 * (1 + 1e-6)
+    del m, etas
+    torch.cuda.empty_cache()
