@@ -16,7 +16,9 @@ Definitions (aggregates are the 4^4 SAP blocks; every coarse site carries
 * coarse solver: BiCGStab on D_c from zero, at most n_coarse iterations,
   stopping once the recursive residual is below tol_coarse times |r_c|;
 * the multigrid preconditioner: z = P (coarse solve of P^dag r), then
-  n_cy_post SAP cycles on D z = r started from z (post-smoothing).
+  n_cy_post SAP cycles on D z = r started from z (post-smoothing);
+* outer solvers with a callable preconditioner: flexible GCR and the
+  paper's flexible BiCGStab.
 P is kept as Nv full-lattice fields: field i holds p_{a,chi,i} on every
 aggregate a and chirality chi (aggregates and chiralities occupy disjoint
 components)."""
@@ -177,3 +179,59 @@ def fgcr(matvec, precond, b, restart=16, tol=1e-10, max_iter=500):
         gam = np.linalg.solve(np.triu(R[:kk, :kk]), np.array(c))
         for k in range(kk):
             x = x + gam[k] * Z[k]
+
+
+def fbicgstab(matvec, precond, b, tol=1e-10, max_iter=500, delta=0.0):
+    """Flexible BiCGStab with a callable right preconditioner (the paper's
+    outer solver around the multigrid preconditioner, Section 3), FP64.  The
+    true residual b - D x is recomputed, and the iteration restarted from x
+    with rh = r, whenever the recursive residual meets tol, falls below
+    delta times the last true residual, or the iteration breaks down
+    (<rh, v> = 0 or omega = 0); a restart without a smaller true residual is
+    a breakdown (status 2).  Returns (x, status, iterations, restarts,
+    true relative residual)."""
+    bn = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    if bn == 0:
+        return x, 0, 0, 0, 0.0
+    it = restarts = 0
+    last_true = 0.0
+    while True:
+        r = b - matvec(x)
+        rt = np.linalg.norm(r)
+        rel = rt / bn
+        if rel <= tol:
+            return x, 0, it, restarts, rel
+        if it >= max_iter:
+            return x, 1, it, restarts, rel
+        if it > 0 and not rt < last_true:
+            return x, 2, it, restarts, rel
+        if it > 0:
+            restarts += 1
+        last_true = rt
+        rh = r.copy()
+        p = np.zeros_like(r)
+        v = np.zeros_like(r)
+        rho = alpha = omega = 1.0 + 0j
+        while it < max_iter:
+            rho_new = np.vdot(rh, r)
+            beta = (rho_new / rho) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+            ph = precond(p)
+            v = matvec(ph)
+            rv = np.vdot(rh, v)
+            if rv == 0:
+                break
+            alpha = rho_new / rv
+            s = r - alpha * v
+            sh = precond(s)
+            t = matvec(sh)
+            tt = np.vdot(t, t).real
+            omega = np.vdot(t, s) / tt if tt > 0 else 0.0
+            x = x + alpha * ph + omega * sh
+            r = s - omega * t
+            rho = rho_new
+            it += 1
+            rr = np.linalg.norm(r)
+            if rr <= tol * bn or omega == 0 or (delta > 0 and rr < delta * last_true):
+                break

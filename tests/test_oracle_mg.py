@@ -106,3 +106,25 @@ def test_adaptive_pass_improves_the_coarse_space(system):
     _, it1, _ = mg.fgcr(mv, lambda r: mg.mg_apply(DIMS, BDIM, U, T, KAPPA, P, aggs, Dc, r, 50, 2, 4), b)
     print(f"FGCR iterations: initial setup {it0}, one adaptive pass {it1}")
     assert it1 < it0
+
+
+def test_flexible_bicgstab_with_a_callable_preconditioner(system):
+    """The numpy flexible BiCGStab taking any preconditioner equals the plain-C
+    oracle's SAP-preconditioned one when handed the same SAP (an independent
+    implementation of the same recurrences), reaches the dense solution, and
+    with M_MG needs fewer iterations than with SAP."""
+    U, T, M, P, Dc, aggs, vecs = system
+    b = synth.source(DIMS, 57)
+    mv = lambda v: oracle.apply_D(DIMS, U, T, KAPPA, v)  # noqa: E731
+    sap = lambda r: oracle.sap(DIMS, BDIM, U, T, KAPPA, 2, 4, r)  # noqa: E731
+    x, st, it, rs, rel = mg.fbicgstab(mv, sap, b, tol=1e-10, delta=1e-5)
+    xc, stc, itc, rsc, relc, _ = oracle.fbicgstab(DIMS, BDIM, U, T, KAPPA, b, n_cy=2, n_mr=4, tol=1e-10,
+                                                 delta=1e-5)
+    assert st == 0 and stc == 0 and it == itc and rs == rsc
+    assert np.linalg.norm(x - xc) <= 1e-12 * np.linalg.norm(xc)
+    xd = np.linalg.solve(M, b.reshape(-1)).reshape(b.shape)
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+    mgp = lambda r: mg.mg_apply(DIMS, BDIM, U, T, KAPPA, P, aggs, Dc, r, 50, 2, 4)  # noqa: E731
+    x2, st2, it2, _, rel2 = mg.fbicgstab(mv, mgp, b, tol=1e-10, delta=1e-5)
+    assert st2 == 0 and rel2 <= 1e-10 and it2 < it
+    assert np.linalg.norm(x2 - xd) <= 1e-8 * np.linalg.norm(xd)
