@@ -376,6 +376,17 @@ int cs_mg_apply(cs_mg m, void* z, const void* r, void* stream);
 int cs_gcr_solve_mg(cs_gauge g, cs_clover c, cs_mg m, const cs_solver_params* p, void* x,
                     const void* b, cs_solver_stats* stats, void* stream);
 
+/* cs_bicgstab_solve with M_MG on the right in both preconditioner
+ * applications of every iteration: the paper's method (Section 3), flexible
+ * BiCGStab around the two-level multigrid preconditioner, in either vector
+ * precision (p->basis_prec CS_F64: flexible BiCGStab with reliable restarts;
+ * CS_F32: FP32 BiCGStab inner solves inside the FP64 Richardson iteration).
+ * p->inner_prec must be CS_F32; n_cy, n_mr and block_solver are not used.  m
+ * must have been built for (g, c).  Same stats, status codes and stream
+ * behaviour as cs_bicgstab_solve. */
+int cs_bicgstab_solve_mg(cs_gauge g, cs_clover c, cs_mg m, const cs_solver_params* p, void* x,
+                         const void* b, cs_solver_stats* stats, void* stream);
+
 /* ---------------------------------------------------------------- gradient */
 
 /* Gradient with respect to the links of a real function L of x = D^{-1} b.

@@ -66,7 +66,8 @@ EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_des
             "cs_autotune", "cs_solver_params_default", "cs_gcr_solve", "cs_gcr_solve_dag",
             "cs_bicgstab_solve", "cs_mg_params_default", "cs_mg_create", "cs_mg_destroy",
             "cs_mg_export", "cs_mg_restrict", "cs_mg_prolong", "cs_mg_coarse_apply",
-            "cs_mg_coarse_solve", "cs_mg_apply", "cs_gcr_solve_mg", "cs_force", "cs_profile_enable",
+            "cs_mg_coarse_solve", "cs_mg_apply", "cs_gcr_solve_mg", "cs_bicgstab_solve_mg", "cs_force",
+            "cs_profile_enable",
             "cs_profile_query", "cs_profile_reset"]
 
 
@@ -121,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     L.cs_mg_coarse_solve.argtypes = [P, P, P, I, D, P]
     L.cs_mg_apply.argtypes = [P, P, P, P]
     L.cs_gcr_solve_mg.argtypes = [P, P, P, C.POINTER(_Params), P, P, C.POINTER(_Stats), P]
+    L.cs_bicgstab_solve_mg.argtypes = [P, P, P, C.POINTER(_Params), P, P, C.POINTER(_Stats), P]
     L.cs_force.argtypes = [P, P, P, P, P, P, P]
     L.cs_profile_enable.argtypes = [I]
     L.cs_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
@@ -420,6 +422,19 @@ class Multigrid:
                                   _ptr(x), _ptr(b), C.byref(st_), _stream(stream))
         if not allow_fail:
             _check(st, "cs_gcr_solve_mg")
+        return st, dict(iters=st_.iters, restarts=st_.restarts, true_relres=st_.true_relres,
+                        seconds=st_.seconds)
+
+    def bicgstab_solve(self, x, b, params: "SolverParams", stream=None, allow_fail=False):
+        """Flexible BiCGStab on D x = b (CS_F64 internal fields) with M_MG on
+        the right (params.basis_prec F64), or FP32 BiCGStab with M_MG inside
+        the FP64 Richardson iteration (F32).  Returns (status, stats)."""
+        p = params.to_c()
+        st_ = _Stats()
+        st = _lib.cs_bicgstab_solve_mg(self.op.gauge.handle, self.op.clover.handle, self.handle, C.byref(p),
+                                       _ptr(x), _ptr(b), C.byref(st_), _stream(stream))
+        if not allow_fail:
+            _check(st, "cs_bicgstab_solve_mg")
         return st, dict(iters=st_.iters, restarts=st_.restarts, true_relres=st_.true_relres,
                         seconds=st_.seconds)
 

@@ -593,8 +593,8 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
     return ok();
 }
 
-int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b,
-                      cs_solver_stats* stats, void* stream) {
+static int bicgstab_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b,
+                           cs_solver_stats* stats, void* stream, const cs::MgData* mg) {
     int st = check_op(g, c);
     if (st) return st;
     if (!p || !x || !b) return fail(CS_ERR_NULL, "params, x and b must be non-NULL");
@@ -613,6 +613,10 @@ int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         return fail(CS_ERR_PRECISION, "an FP64 inner solve needs FP64 vectors");
     if (p->basis_prec == CS_F32 && !(p->reliable_delta > 0.0 && p->reliable_delta < 1.0))
         return fail(CS_ERR_INVALID, "the single-precision form needs 0 < reliable_delta < 1");
+    if (mg && p->inner_prec != CS_F32)
+        return fail(CS_ERR_INVALID, "the multigrid preconditioner needs inner_prec CS_F32");
+    if (mg && !sap_geometry_ok(g->g))
+        return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
     if (!c->bicg) c->bicg.reset(new cs::BicgWork);
     hipError_t e = c->bicg->ensure(g->g, p->inner_prec, p->basis_prec);
     if (e != hipSuccess) {
@@ -624,9 +628,10 @@ int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         std::lock_guard<std::mutex> lk(g_pm);
         prof = g_prof_on;
     }
-    const cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
-                           p->reliable_delta, cs::LaunchCfg{}, cs::LaunchCfg{}, p->use_graph != 0 && !prof,
-                           p->block_solver};
+    cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
+                     p->reliable_delta, cs::LaunchCfg{}, cs::LaunchCfg{}, p->use_graph != 0 && !prof,
+                     p->block_solver};
+    gp.mg = mg;
     cs::GcrResult res{};
     e = cs::bicgstab_solve(make_op(g, c), gp, *c->bicg, x, b, &res, (hipStream_t)stream);
     if (e != hipSuccess) {
@@ -641,6 +646,11 @@ int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
     }
     if (res.status != cs::GCR_OK) return fail(res.status, "%s", cs_strerror(res.status));
     return ok();
+}
+
+int cs_bicgstab_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b,
+                      cs_solver_stats* stats, void* stream) {
+    return bicgstab_common(g, c, p, x, b, stats, stream, nullptr);
 }
 
 int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
@@ -750,6 +760,14 @@ int cs_gcr_solve_mg(cs_gauge g, cs_clover c, cs_mg m, const cs_solver_params* p,
     if (m->gauge != g || m->clover != c)
         return fail(CS_ERR_INVALID, "the multigrid handle was built for a different operator");
     return gcr_common(g, c, p, x, b, 1, stats, stream, false, &m->data);
+}
+
+int cs_bicgstab_solve_mg(cs_gauge g, cs_clover c, cs_mg m, const cs_solver_params* p, void* x, const void* b,
+                         cs_solver_stats* stats, void* stream) {
+    if (!m) return fail(CS_ERR_NULL, "multigrid handle is NULL");
+    if (m->gauge != g || m->clover != c)
+        return fail(CS_ERR_INVALID, "the multigrid handle was built for a different operator");
+    return bicgstab_common(g, c, p, x, b, stats, stream, &m->data);
 }
 
 int cs_force(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_lie, void* grad_U, void* stream) {

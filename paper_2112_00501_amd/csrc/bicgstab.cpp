@@ -1,5 +1,5 @@
-// Flexible BiCGStab with the SAP preconditioner on the right (host driver):
-// the outer solver of the paper's multigrid code (Section 3), in the
+// Flexible BiCGStab with the SAP or the multigrid preconditioner on the right
+// (host driver): the outer solver of the paper's multigrid code (Section 3), in the
 // mixed-precision form of Section 2 (low-precision smoother and w = D z,
 // FP64 everything else).  One iteration, all on the device:
 //   p = r + beta (p - omega v)               FP64, plus p in the inner precision
@@ -16,7 +16,9 @@
 // tolerance the iteration restarts from x with rh = r.  A restart whose true
 // residual has not decreased since the previous restart is a breakdown.
 // The kernels of one iteration are the same every time, so they are captured
-// once as a HIP graph and replayed.
+// once as a HIP graph and replayed.  With the multigrid preconditioner the
+// iteration is three captured pieces around the two coarse phases, which run
+// in chunks with host reads of their stop flags.
 //
 // Single-precision form (the scheme of the paper's Section 2 for QWS): the
 // iteration vectors are FP32 and BiCGStab solves D e = r / |r| to the
@@ -47,6 +49,10 @@ int natural_out(int inner) { return inner == P_F64 ? P_F64 : P_F32; }
 void BicgWork::drop_graph() {
     if (graph) hipGraphExecDestroy(graph);
     graph = nullptr;
+    for (hipGraphExec_t& g : mg_graph) {
+        if (g) hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     graph_key.clear();
 }
 
@@ -118,8 +124,8 @@ struct Bicg {
         bc = BlasCtx{op.g, 1, nullptr, w.partials, nullptr, nullptr};
         // without smoothing the preconditioner is the identity: z is the
         // inner-precision copy itself
-        void* zp = p.n_cy > 0 ? w.zp : w.plo;
-        void* zs = p.n_cy > 0 ? w.zs : w.slo;
+        void* zp = p.n_cy > 0 || p.mg ? w.zp : w.plo;
+        void* zs = p.n_cy > 0 || p.mg ? w.zs : w.slo;
         f = BiFields{x, w.r, w.rh, w.p, w.v, w.s, w.t, w.plo, w.slo, zp, zs, w.w};
     }
 
@@ -150,18 +156,73 @@ struct Bicg {
         return bicg_update_xr(bc, w.sc, w.tail, f, pv, p.inner, s);
     }
 
+    // the pieces of an iteration with the multigrid preconditioner: before
+    // the coarse phase of p, between the two coarse phases, after that of s
+    hipError_t mg_piece(int piece) {
+        const int nout = natural_out(p.inner);
+        if (piece == 0) return bicg_update_p(bc, w.sc, f, pv, p.inner, s);
+        if (piece == 1) {
+            BI_CHK(mg_finish(op, *p.mg, f.zp, f.plo, s));
+            BI_CHK(launch_dslash(op, p.inner, nout, nout, false, w.w, f.zp, nullptr, 1, s));
+            BI_CHK(bicg_alpha(bc, w.sc, f, pv, nout, s));
+            return bicg_update_s(bc, w.sc, f, pv, p.inner, s);
+        }
+        BI_CHK(mg_finish(op, *p.mg, f.zs, f.slo, s));
+        BI_CHK(launch_dslash(op, p.inner, nout, nout, false, w.w, f.zs, nullptr, 1, s));
+        BI_CHK(bicg_omega(bc, w.sc, f, pv, nout, s));
+        return bicg_update_xr(bc, w.sc, w.tail, f, pv, p.inner, s);
+    }
+
     std::vector<char> key(const void* x) const {
         std::vector<char> k(256, 0);
         const int vals[] = {p.n_cy, p.n_mr, p.block_solver, p.inner, pv, p.sap_cfg.rhs_tile, p.sap_cfg.persistent_wgs,
                             p.sap_cfg.lanes_per_site};
         std::memcpy(k.data(), vals, sizeof vals);
-        const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32, x};
+        const void* ptrs[] = {op.links[0], op.links[1], op.links[2], op.links[3], op.clover64, op.clover32, x, p.mg};
         std::memcpy(k.data() + sizeof vals, ptrs, sizeof ptrs);
         std::memcpy(k.data() + sizeof vals + sizeof ptrs, &op.kappa, sizeof op.kappa);
+        if (p.mg) {  // the hierarchy (a fresh id for every allocation) and its shape
+            const MgParams& q = p.mg->p;
+            const int mv[] = {q.nv, q.n_mr, q.n_coarse, q.n_cy_post, q.coarse_half};
+            char* at = k.data() + sizeof vals + sizeof ptrs + sizeof op.kappa;
+            std::memcpy(at, mv, sizeof mv);
+            std::memcpy(at + sizeof mv, &q.tol_coarse, sizeof q.tol_coarse);
+            std::memcpy(at + sizeof mv + sizeof q.tol_coarse, &p.mg->id, sizeof p.mg->id);
+        }
         return k;
     }
 
+    hipError_t capture(hipGraphExec_t* exec, int piece) {
+        hipGraph_t graph;
+        BI_CHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = piece < 0 ? iteration() : mg_piece(piece);
+        hipError_t e2 = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess) return e;
+        if (e2 != hipSuccess) return e2;
+        e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) *exec = nullptr;
+        return e;
+    }
+
     hipError_t run_iteration(const void* x) {
+        if (p.mg) {
+            const bool g = p.use_graph;
+            if (g) {
+                const std::vector<char> kk = key(x);
+                if (w.graph_key != kk) {
+                    w.drop_graph();
+                    w.graph_key = kk;
+                }
+                for (int i = 0; i < 3; ++i)
+                    if (!w.mg_graph[i]) BI_CHK(capture(&w.mg_graph[i], i));
+            }
+            BI_CHK(g ? hipGraphLaunch(w.mg_graph[0], s) : mg_piece(0));
+            BI_CHK(mg_coarse_phase(*p.mg, f.plo, s, g));
+            BI_CHK(g ? hipGraphLaunch(w.mg_graph[1], s) : mg_piece(1));
+            BI_CHK(mg_coarse_phase(*p.mg, f.slo, s, g));
+            return g ? hipGraphLaunch(w.mg_graph[2], s) : mg_piece(2);
+        }
         if (!p.use_graph) return iteration();
         const std::vector<char> kk = key(x);
         if (w.graph_key != kk) {

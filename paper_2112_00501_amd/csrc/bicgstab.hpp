@@ -24,6 +24,7 @@ struct BicgWork {
     BiTail* host_tail = nullptr;    // pinned
     hipStream_t stream = nullptr;   // private stream (graph capture needs a non-null stream)
     hipGraphExec_t graph = nullptr;
+    hipGraphExec_t mg_graph[3] = {nullptr, nullptr, nullptr};  // the pieces around two coarse phases
     std::vector<char> graph_key;
     hipError_t ensure(const Geom& g, int inner, int pv);
     void drop_graph();
@@ -36,7 +37,7 @@ struct BicgWork {
 // with FP64 vectors and reliable restarts; p.basis = F32: FP32 BiCGStab
 // inner solves to p.reliable_delta inside an FP64 Richardson iteration.
 // Uses p.tol, max_iter, n_cy, n_mr, inner, basis, reliable_delta, use_graph,
-// sap_cfg.
+// sap_cfg.  With p.mg the preconditioner is the multigrid M_MG (p.inner F32).
 hipError_t bicgstab_solve(const OpData& op, const GcrParams& p, BicgWork& w, void* x, const void* b,
                           GcrResult* res, hipStream_t user_stream);
 

@@ -52,10 +52,12 @@ hipError_t rebuild(const OpData& op, MgData& m, hipStream_t s) {
 size_t MgData::field_bytes() const { return spinor_bytes_per_site(P_F32) * g.V; }
 
 void MgData::drop_graphs() const {
-    if (gr.first) hipGraphExecDestroy(gr.first);
-    for (hipGraphExec_t e : gr.chunk)
-        if (e) hipGraphExecDestroy(e);
-    gr = Graphs{};
+    for (Graphs& g : gr) {
+        if (g.first) hipGraphExecDestroy(g.first);
+        for (hipGraphExec_t e : g.chunk)
+            if (e) hipGraphExecDestroy(e);
+    }
+    gr.clear();
 }
 
 void MgData::release() {
@@ -142,13 +144,22 @@ hipError_t run_piece(hipGraphExec_t* exec, bool use_graph, hipStream_t s, F laun
 }  // namespace
 
 hipError_t mg_coarse_phase(const MgData& m, const void* r, hipStream_t s, bool use_graph) {
-    if (use_graph && m.gr.r != r) {
-        m.drop_graphs();
-        m.gr.r = r;
+    MgData::Graphs* gs = nullptr;
+    if (use_graph) {
+        for (MgData::Graphs& g : m.gr)
+            if (g.r == r) gs = &g;
+        if (!gs) {
+            if (m.gr.size() >= 4) m.drop_graphs();  // a few input fields at a time
+            m.gr.push_back(MgData::Graphs{});
+            gs = &m.gr.back();
+            gs->r = r;
+        }
     }
+    MgData::Graphs none;
+    MgData::Graphs& G = gs ? *gs : none;
     const int cap = m.p.n_coarse;
     int done = cap < MG_CHUNK ? cap : MG_CHUNK;
-    MG_CHK(run_piece(&m.gr.first, use_graph, s, [&]() -> hipError_t {
+    MG_CHK(run_piece(&G.first, use_graph, s, [&]() -> hipError_t {
         MG_CHK(mg_restrict(m.g, m.P, m.p.nv, r, m.rc, s));
         MG_CHK(mg_coarse_begin(m.g, m.nc(), m.rc, m.cv, m.sc, m.pa, m.p.tol_coarse, s));
         return mg_coarse_iters(m.g, m.coarse(), m.nc(), m.cv, m.sc, m.pa, 0, done, s);
@@ -159,8 +170,8 @@ hipError_t mg_coarse_phase(const MgData& m, const void* r, hipStream_t s, bool u
         MG_CHK(hipStreamSynchronize(s));
         if (*m.host_flag) break;
         const int to = done + MG_CHUNK < cap ? done + MG_CHUNK : cap;
-        if ((int)m.gr.chunk.size() <= j) m.gr.chunk.resize(j + 1, nullptr);
-        MG_CHK(run_piece(&m.gr.chunk[j], use_graph, s, [&]() -> hipError_t {
+        if ((int)G.chunk.size() <= j) G.chunk.resize(j + 1, nullptr);
+        MG_CHK(run_piece(&G.chunk[j], use_graph, s, [&]() -> hipError_t {
             return mg_coarse_iters(m.g, m.coarse(), m.nc(), m.cv, m.sc, m.pa, done, to, s);
         }));
         done = to;

@@ -63,14 +63,15 @@ struct MgData {
     LaunchCfg sap_cfg{};
     int* host_flag = nullptr;  // pinned copy of a stop flag
     unsigned long long id = 0; // distinct for every allocation (keys of captured graphs)
-    // captured graphs of the coarse phase: restriction of `r`, start and the
-    // first chunk; then chunk j covers iterations [(j + 1) MG_CHUNK, ...)
+    // captured graphs of the coarse phase, one set per input field `r`:
+    // restriction of r, start and the first chunk; then chunk j covers
+    // iterations [(j + 1) MG_CHUNK, ...)
     struct Graphs {
         const void* r = nullptr;
         hipGraphExec_t first = nullptr;
         std::vector<hipGraphExec_t> chunk;
     };
-    mutable Graphs gr;
+    mutable std::vector<Graphs> gr;
     void drop_graphs() const;
 
     int nc() const { return 2 * p.nv; }

@@ -279,3 +279,37 @@ def test_graphs_follow_a_recreated_hierarchy(sys8):
         outs.append((x, stats["iters"]))
     print(f"iterations graph / eager: {outs[0][1]} / {outs[1][1]}")
     assert outs[0][1] == outs[1][1] and torch.equal(outs[0][0], outs[1][0])
+
+
+@pytest.mark.parametrize("vec", [cs.F64, cs.F32])
+def test_mg_bicgstab_reaches_fp64_residual(sys8, vec):
+    """The paper's method: flexible BiCGStab around M_MG (FP64 vectors), and
+    FP32 BiCGStab with M_MG inside the FP64 Richardson iteration; both reach
+    1e-10 by the oracle's residual, the first in about as many iterations as
+    the oracle's flexible BiCGStab around its own M_MG; graph replay equals
+    the eager path bit for bit."""
+    c, etas, etas_d = sys8
+    prm = cs.MgParams(nv=NV, n_cy_setup=4, n_mr=4, n_adapt=1, n_coarse=50, n_cy_post=2, tol_coarse=0.05)
+    m = cs.Multigrid(c.op, etas_d, prm)
+    b = synth.source(DIMS, 7200)
+    bd = c.to_dev(b, cs.F64)
+    outs = []
+    for use_graph in (True, False):
+        xd = c.lat.new_field(cs.F64).zero_()
+        st, stats = m.bicgstab_solve(xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=vec, tol=1e-10,
+                                                             reliable_delta=1e-5, use_graph=use_graph))
+        torch.cuda.synchronize()
+        outs.append((xd, stats))
+    assert torch.equal(outs[0][0], outs[1][0]) and outs[0][1]["iters"] == outs[1][1]["iters"]
+    xd, stats = outs[0]
+    relres = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, b, c.to_host(xd, cs.F64)) / np.linalg.norm(b)
+    msg = f"MG-BiCGStab vec={vec}: gpu iters {stats['iters']} restarts {stats['restarts']} relres {relres:.2e}"
+    if vec == cs.F64:
+        P, Dc, aggs, _ = mg.setup(DIMS, BDIM, c.U, c.T, KAPPA, etas, n_cy_setup=4, n_mr=4, n_adapt=1)
+        mv = lambda v: oracle.apply_D(DIMS, c.U, c.T, KAPPA, v)  # noqa: E731
+        pre = lambda r: mg.mg_apply(DIMS, BDIM, c.U, c.T, KAPPA, P, aggs, Dc, r, 50, 2, 4)  # noqa: E731
+        _, st_or, it_or, _, _ = mg.fbicgstab(mv, pre, b, tol=1e-10, delta=1e-5)
+        msg += f"; oracle iters {it_or}"
+        assert st_or == 0 and abs(stats["iters"] - it_or) <= max(2, it_or // 10)
+    print(msg)
+    assert relres <= 1e-10 * (1 + 1e-6)
