@@ -187,9 +187,9 @@ def hbm_resident_measurement(cs, synth, torch, reps_d=20, reps_sap=10):
     t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32), 3)
     log("[bench] 32^3x64 two-level multigrid")
     res["multigrid"] = multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, t, it)
-    log("[bench] 32^3x64 two-level multigrid, FP16 coarse matrices")
-    res["multigrid_f16_coarse"] = multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, t, it,
-                                                        coarse_prec=cs.F16)
+    log("[bench] 32^3x64 two-level multigrid, FP16 coarse matrices and prolongator")
+    res["multigrid_f16_storage"] = multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, t, it,
+                                                         half=True)
     return res
 
 
@@ -199,7 +199,7 @@ def hbm_resident_measurement(cs, synth, torch, reps_d=20, reps_sap=10):
 MG_PARAMS = dict(nv=16, n_cy_setup=4, n_mr=4, n_adapt=4, n_coarse=50, n_cy_post=2, tol_coarse=0.05)
 
 
-def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap_it, reps=3, coarse_prec=None):
+def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap_it, reps=3, half=False):
     """MG-preconditioned FGCR to 1e-10 on the same system as SAP-FGCR:
     setup time, solve time (median of reps), iterations, per-family kernel
     time of one solve, and the paper's comparison of one and of twelve
@@ -209,8 +209,8 @@ def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap
     import oracle
     dims = c["dims"]
     prm = cs.MgParams(**MG_PARAMS)
-    if coarse_prec is not None:
-        prm.coarse_prec = coarse_prec
+    if half:  # FP16 copies of D_c and P for the bandwidth-bound coarse products and transfers
+        prm.coarse_prec = prm.transfer_prec = cs.F16
     fb = lat.field_bytes(cs.F32)
     etas = lat.new_field(cs.F32, prm.nv)
     for i in range(prm.nv):
@@ -258,7 +258,7 @@ def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap
     fam = {k: cs.profile_query(k) for k in ("mg", "sap_halfsweep", "dslash", "blas")}
     del m, etas
     torch.cuda.empty_cache()
-    return dict(params=dict(MG_PARAMS, coarse_prec="f16" if prm.coarse_prec == cs.F16 else "f32"),
+    return dict(params=dict(MG_PARAMS, coarse_prec="f16" if half else "f32", transfer_prec="f16" if half else "f32"),
                 setup_s=round(setup_s, 4), solve_s=round(solve_s, 4),
                 iterations=stats["iters"], status=st, oracle_checked_relres=float(f"{rel:.3e}"),
                 sap_fgcr_solve_s=round(sap_s, 4), sap_fgcr_iterations=sap_it,

@@ -333,10 +333,14 @@ typedef struct {
     cs_prec coarse_prec;/* storage of D_c read by the coarse solve and by
                            cs_mg_coarse_apply: CS_F32, or CS_F16 (an FP16 copy
                            made after every assembly; arithmetic stays FP32)  */
+    cs_prec transfer_prec; /* storage of P read by restriction and
+                           prolongation: CS_F32, or CS_F16 (an FP16 copy with
+                           one FP32 scale per site, made after every rebuild;
+                           D_c is still assembled from the FP32 P)            */
 } cs_mg_params;
 
 /* Defaults: nv 8, n_cy_setup 4, n_mr 4, n_adapt 1, n_coarse 50, n_cy_post 2,
- * tol_coarse 0.05, coarse_prec CS_F32. */
+ * tol_coarse 0.05, coarse_prec CS_F32, transfer_prec CS_F32. */
 void cs_mg_params_default(cs_mg_params* p);
 
 /* Build the hierarchy for operator (g, c).  etas: nv consecutive CS_F32
@@ -356,7 +360,8 @@ int cs_mg_destroy(cs_mg m);
 int cs_mg_export(cs_mg m, void* P, void* Dc, void* stream);
 
 /* The pieces of M_MG on caller-owned device buffers (asynchronous):
- *   restrict      rc = P^dag r      (r a CS_F32 field, rc a coarse vector)
+ *   restrict      rc = P^dag r      (r a CS_F32 field, rc a coarse vector;
+ *                                    P in transfer_prec)
  *   prolong       z = P ec          (ec a coarse vector, z a CS_F32 field)
  *   coarse_apply  y = D_c x         (coarse vectors, x != y)
  *   coarse_solve  ec = the coarse BiCGStab above from zero, with at most

@@ -48,7 +48,7 @@ class LaunchConfig(C.Structure):
 class _MgParams(C.Structure):
     _fields_ = [("nv", C.c_int), ("n_cy_setup", C.c_int), ("n_mr", C.c_int), ("n_adapt", C.c_int),
                 ("n_coarse", C.c_int), ("n_cy_post", C.c_int), ("tol_coarse", C.c_double),
-                ("coarse_prec", C.c_int)]
+                ("coarse_prec", C.c_int), ("transfer_prec", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -353,10 +353,11 @@ class MgParams:
     n_cy_post: int = 2      # SAP post-smoothing cycles per application
     tol_coarse: float = 0.05
     coarse_prec: int = F32   # D_c storage read by the coarse solve: F32 or F16
+    transfer_prec: int = F32  # P storage read by restriction and prolongation: F32 or F16
 
     def to_c(self) -> _MgParams:
         return _MgParams(self.nv, self.n_cy_setup, self.n_mr, self.n_adapt, self.n_coarse,
-                         self.n_cy_post, self.tol_coarse, self.coarse_prec)
+                         self.n_cy_post, self.tol_coarse, self.coarse_prec, self.transfer_prec)
 
 
 class Multigrid:

@@ -673,6 +673,7 @@ void cs_mg_params_default(cs_mg_params* p) {
     p->n_cy_post = 2;
     p->tol_coarse = 0.05;
     p->coarse_prec = CS_F32;
+    p->transfer_prec = CS_F32;
 }
 
 int cs_mg_create(cs_gauge g, cs_clover c, const cs_mg_params* p, const void* etas, void* stream, cs_mg* out) {
@@ -691,8 +692,11 @@ int cs_mg_create(cs_gauge g, cs_clover c, const cs_mg_params* p, const void* eta
     m->clover = c;
     if (p->coarse_prec != CS_F32 && p->coarse_prec != CS_F16)
         return fail(CS_ERR_PRECISION, "coarse_prec must be CS_F32 or CS_F16");
-    const cs::MgParams mp{p->nv,         p->n_cy_setup, p->n_mr,       p->n_adapt,
-                          p->n_coarse,   p->n_cy_post,  p->tol_coarse, p->coarse_prec == CS_F16 ? 1 : 0};
+    if (p->transfer_prec != CS_F32 && p->transfer_prec != CS_F16)
+        return fail(CS_ERR_PRECISION, "transfer_prec must be CS_F32 or CS_F16");
+    const cs::MgParams mp{p->nv,       p->n_cy_setup, p->n_mr,       p->n_adapt,
+                          p->n_coarse, p->n_cy_post,  p->tol_coarse, p->coarse_prec == CS_F16 ? 1 : 0,
+                          p->transfer_prec == CS_F16 ? 1 : 0};
     hipError_t e = m->data.alloc(g->g, mp);
     if (e != hipSuccess) return fail(CS_ERR_ALLOC, "multigrid workspace: %s", hipGetErrorString(e));
     if (overlap(etas, m->data.V, m->data.field_bytes() * p->nv))
@@ -719,13 +723,13 @@ int cs_mg_export(cs_mg m, void* P, void* Dc, void* stream) {
 
 int cs_mg_restrict(cs_mg m, const void* r, void* rc, void* stream) {
     if (!m || !r || !rc) return fail(CS_ERR_NULL, "handle, r and rc must be non-NULL");
-    CS_HIP(cs::mg_restrict(m->data.g, m->data.P, m->data.p.nv, r, (float2*)rc, (hipStream_t)stream));
+    CS_HIP(cs::mg_restrict(m->data.g, m->data.transfer(), m->data.p.nv, r, (float2*)rc, (hipStream_t)stream));
     return ok();
 }
 
 int cs_mg_prolong(cs_mg m, const void* ec, void* z, void* stream) {
     if (!m || !ec || !z) return fail(CS_ERR_NULL, "handle, ec and z must be non-NULL");
-    CS_HIP(cs::mg_prolong(m->data.g, m->data.P, m->data.p.nv, (const float2*)ec, z, (hipStream_t)stream));
+    CS_HIP(cs::mg_prolong(m->data.g, m->data.transfer(), m->data.p.nv, (const float2*)ec, z, (hipStream_t)stream));
     return ok();
 }
 

@@ -183,7 +183,7 @@ struct Bicg {
         std::memcpy(k.data() + sizeof vals + sizeof ptrs, &op.kappa, sizeof op.kappa);
         if (p.mg) {  // the hierarchy (a fresh id for every allocation) and its shape
             const MgParams& q = p.mg->p;
-            const int mv[] = {q.nv, q.n_mr, q.n_coarse, q.n_cy_post, q.coarse_half};
+            const int mv[] = {q.nv, q.n_mr, q.n_coarse, q.n_cy_post, q.coarse_half, q.transfer_half};
             char* at = k.data() + sizeof vals + sizeof ptrs + sizeof op.kappa;
             std::memcpy(at, mv, sizeof mv);
             std::memcpy(at + sizeof mv, &q.tol_coarse, sizeof q.tol_coarse);

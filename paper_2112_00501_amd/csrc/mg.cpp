@@ -16,6 +16,7 @@
 
 #include <atomic>
 
+#include "blas.hpp"
 #include "mg.hpp"
 
 namespace cs {
@@ -43,6 +44,10 @@ hipError_t rebuild(const OpData& op, MgData& m, hipStream_t s) {
     MG_CHK(hipMemcpyAsync(m.P, m.V, m.field_bytes() * m.p.nv, hipMemcpyDeviceToDevice, s));
     MG_CHK(mg_orthonormalize(m.g, m.P, m.p.nv, s));
     MG_CHK(mg_assemble(op, m.P, m.p.nv, m.Dc, s));
+    if (m.p.transfer_half) {
+        const BlasCtx bc{m.g, m.p.nv, nullptr, nullptr, nullptr, nullptr};
+        MG_CHK(blas_convert(bc, P_F16, m.P16, P_F32, m.P, false, s));
+    }
     if (m.p.coarse_half) MG_CHK(mg_coarse_half(m.Dc, m.Dc16, m.dc_bytes() / sizeof(float2), s));
     return hipSuccess;
 }
@@ -62,7 +67,7 @@ void MgData::drop_graphs() const {
 
 void MgData::release() {
     drop_graphs();
-    for (void** q : {&P, &V, &tmp, (void**)&Dc, &Dc16, (void**)&rc, (void**)&cv.x, (void**)&sc, (void**)&pa.A}) {
+    for (void** q : {&P, &P16, &V, &tmp, (void**)&Dc, &Dc16, (void**)&rc, (void**)&cv.x, (void**)&sc, (void**)&pa.A}) {
         if (*q) hipFree(*q);
         *q = nullptr;
     }
@@ -79,6 +84,7 @@ hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
     p = p_;
     id = next_id++;
     MG_CHK(hipMalloc(&P, field_bytes() * p.nv));
+    if (p.transfer_half) MG_CHK(hipMalloc(&P16, spinor_bytes_per_site(P_F16) * g.V * p.nv));
     MG_CHK(hipMalloc(&V, field_bytes() * p.nv));
     MG_CHK(hipMalloc(&tmp, field_bytes()));
     MG_CHK(hipMalloc((void**)&Dc, dc_bytes()));
@@ -160,7 +166,7 @@ hipError_t mg_coarse_phase(const MgData& m, const void* r, hipStream_t s, bool u
     const int cap = m.p.n_coarse;
     int done = cap < MG_CHUNK ? cap : MG_CHUNK;
     MG_CHK(run_piece(&G.first, use_graph, s, [&]() -> hipError_t {
-        MG_CHK(mg_restrict(m.g, m.P, m.p.nv, r, m.rc, s));
+        MG_CHK(mg_restrict(m.g, m.transfer(), m.p.nv, r, m.rc, s));
         MG_CHK(mg_coarse_begin(m.g, m.nc(), m.rc, m.cv, m.sc, m.pa, m.p.tol_coarse, s));
         return mg_coarse_iters(m.g, m.coarse(), m.nc(), m.cv, m.sc, m.pa, 0, done, s);
     }));
@@ -180,7 +186,7 @@ hipError_t mg_coarse_phase(const MgData& m, const void* r, hipStream_t s, bool u
 }
 
 hipError_t mg_finish(const OpData& op, const MgData& m, void* z, const void* r, hipStream_t s) {
-    MG_CHK(mg_prolong(m.g, m.P, m.p.nv, m.cv.x, z, s));
+    MG_CHK(mg_prolong(m.g, m.transfer(), m.p.nv, m.cv.x, z, s));
     return sap_cycles(op, m.sap_cfg, m.p.n_cy_post, m.p.n_mr, false, z, r, 1, s);
 }
 

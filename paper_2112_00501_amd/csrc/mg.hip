@@ -288,6 +288,7 @@ __global__ __launch_bounds__(TPB) void k_mg_assemble(Geom g, const void* links, 
 // --------------------------------------------------------------- transfer
 
 // rc[a][chi * nv + i] = <p_{a,chi,i}, r> (r an FP32 field)
+template <int PP>
 __global__ __launch_bounds__(TPB) void k_mg_restrict(Geom g, const char* P, size_t fs, int nv, const void* r,
                                                      float2* rc) {
     const int blk = blockIdx.x, l = threadIdx.x;
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(TPB) void k_mg_restrict(Geom g, const char* P, size
         for (int u = 0; u < 2; ++u) {
             if (i0 + u < nv) {
                 cpx<float> q[12];
-                load_f32(P, fs, i0 + u, g.nblk, blk, l, q);
+                SpinorIO<PP>::load(P + (size_t)(i0 + u) * fs, g.nblk, blk, l, q);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
                     const int o = 4 * u + (k < 6 ? 0 : 2);
@@ -319,6 +320,7 @@ __global__ __launch_bounds__(TPB) void k_mg_restrict(Geom g, const char* P, size
 }
 
 // z = P ec (an FP32 field)
+template <int PP>
 __global__ __launch_bounds__(TPB) void k_mg_prolong(Geom g, const char* P, size_t fs, int nv, const float2* ec,
                                                     void* z) {
     const int blk = blockIdx.x, l = threadIdx.x;
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(TPB) void k_mg_prolong(Geom g, const char* P, size_
     const float2* e = ec + (size_t)blk * 2 * nv;
     for (int i = 0; i < nv; ++i) {
         cpx<float> q[12];
-        load_f32(P, fs, i, g.nblk, blk, l, q);
+        SpinorIO<PP>::load(P + (size_t)i * fs, g.nblk, blk, l, q);
         const float2 e0 = e[i], e1 = e[nv + i];
         const cpx<float> c0 = {e0.x, e0.y}, c1 = {e1.x, e1.y};
 #pragma unroll
@@ -690,17 +692,23 @@ hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipS
     return hipGetLastError();
 }
 
-hipError_t mg_restrict(const Geom& g, const void* P, int nv, const void* r, float2* rc, hipStream_t s) {
+hipError_t mg_restrict(const Geom& g, Transfer T, int nv, const void* r, float2* rc, hipStream_t s) {
     ProfScope ps("mg", s);
-    hipLaunchKernelGGL(k_mg_restrict, dim3(g.nblk), dim3(TPB), 0, s, g, (const char*)P,
-                       spinor_bytes_per_site(P_F32) * g.V, nv, r, rc);
+    const size_t fs = spinor_bytes_per_site(T.prec) * g.V;
+    if (T.prec == P_F16)
+        hipLaunchKernelGGL(k_mg_restrict<P_F16>, dim3(g.nblk), dim3(TPB), 0, s, g, (const char*)T.P, fs, nv, r, rc);
+    else
+        hipLaunchKernelGGL(k_mg_restrict<P_F32>, dim3(g.nblk), dim3(TPB), 0, s, g, (const char*)T.P, fs, nv, r, rc);
     return hipGetLastError();
 }
 
-hipError_t mg_prolong(const Geom& g, const void* P, int nv, const float2* ec, void* z, hipStream_t s) {
+hipError_t mg_prolong(const Geom& g, Transfer T, int nv, const float2* ec, void* z, hipStream_t s) {
     ProfScope ps("mg", s);
-    hipLaunchKernelGGL(k_mg_prolong, dim3(g.nblk), dim3(TPB), 0, s, g, (const char*)P,
-                       spinor_bytes_per_site(P_F32) * g.V, nv, ec, z);
+    const size_t fs = spinor_bytes_per_site(T.prec) * g.V;
+    if (T.prec == P_F16)
+        hipLaunchKernelGGL(k_mg_prolong<P_F16>, dim3(g.nblk), dim3(TPB), 0, s, g, (const char*)T.P, fs, nv, ec, z);
+    else
+        hipLaunchKernelGGL(k_mg_prolong<P_F32>, dim3(g.nblk), dim3(TPB), 0, s, g, (const char*)T.P, fs, nv, ec, z);
     return hipGetLastError();
 }
 

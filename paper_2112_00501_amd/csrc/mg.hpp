@@ -36,7 +36,14 @@ struct CbPartials {
 struct MgParams {
     int nv, n_cy_setup, n_mr, n_adapt, n_coarse, n_cy_post;
     double tol_coarse;
-    int coarse_half;  // the coarse solve reads an FP16 copy of D_c
+    int coarse_half;    // the coarse solve reads an FP16 copy of D_c
+    int transfer_half;  // restriction and prolongation read an FP16 copy of P
+};
+
+// The prolongator as restriction and prolongation read it.
+struct Transfer {
+    const void* P;
+    int prec;  // P_F32 or P_F16
 };
 
 // The coarse matrices as the coarse solver reads them.
@@ -52,6 +59,7 @@ struct MgData {
     Geom g{};
     MgParams p{};
     void* P = nullptr;
+    void* P16 = nullptr;  // FP16 copy (transfer_half)
     void* V = nullptr;
     void* tmp = nullptr;  // one FP32 field
     float2* Dc = nullptr;
@@ -79,6 +87,7 @@ struct MgData {
     size_t coarse_bytes() const { return (size_t)g.nblk * nc() * sizeof(float2); }
     size_t dc_bytes() const { return (size_t)g.nblk * 9 * nc() * nc() * sizeof(float2); }
     CoarseMat coarse() const { return p.coarse_half ? CoarseMat{Dc16, true} : CoarseMat{Dc, false}; }
+    Transfer transfer() const { return p.transfer_half ? Transfer{P16, P_F16} : Transfer{P, P_F32}; }
     hipError_t alloc(const Geom& g, const MgParams& p);
     void release();
     ~MgData() { release(); }
@@ -87,8 +96,8 @@ struct MgData {
 // mg.hip
 hipError_t mg_orthonormalize(const Geom& g, void* P, int nv, hipStream_t s);
 hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipStream_t s);
-hipError_t mg_restrict(const Geom& g, const void* P, int nv, const void* r, float2* rc, hipStream_t s);
-hipError_t mg_prolong(const Geom& g, const void* P, int nv, const float2* ec, void* z, hipStream_t s);
+hipError_t mg_restrict(const Geom& g, Transfer T, int nv, const void* r, float2* rc, hipStream_t s);
+hipError_t mg_prolong(const Geom& g, Transfer T, int nv, const float2* ec, void* z, hipStream_t s);
 // Dc16 = FP16 copy of the n complex entries of Dc
 hipError_t mg_coarse_half(const float2* Dc, void* Dc16, size_t n, hipStream_t s);
 // y = D_c x

@@ -13,7 +13,7 @@ benchmark uses, on outputs the FP64 oracle can evaluate one by one:
   -Re(y^dag D(U) x) under U -> exp(i h T^a) U, which hold at any size; the
   oracle evaluates D only on the rows the perturbed link enters;
 * the two-level multigrid at 32^3 x 64 in the benchmark's configuration
-  (16 null vectors, 4 adaptive passes, FP32 and FP16 coarse matrices):
+  (16 null vectors, 4 adaptive passes; FP32, and FP16 copies of D_c and P):
   properties that hold at any size (P^dag P = 1, so restriction undoes
   prolongation; D_c e = P^dag D P e, with D the GPU operator in FP32), and
   the MG-FGCR solution checked by the oracle's own residual."""
@@ -211,12 +211,13 @@ def test_bicgstab_full_size_oracle_residual(big, vec):
     assert r <= 1e-10 * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("coarse_prec", [cs.F32, cs.F16])
-def test_multigrid_full_size(big, coarse_prec):
+@pytest.mark.parametrize("half", [False, True])
+def test_multigrid_full_size(big, half):
     c = big
     import bench
     prm = cs.MgParams(**bench.MG_PARAMS)
-    prm.coarse_prec = coarse_prec
+    if half:
+        prm.coarse_prec = prm.transfer_prec = cs.F16
     cfg = synth.CONFIGS["lowprec_32x32x32x64"]
     fb = c.lat.field_bytes(cs.F32)
     etas = c.lat.new_field(cs.F32, prm.nv)
@@ -239,10 +240,10 @@ def test_multigrid_full_size(big, coarse_prec):
     x = c.lat.new_field(cs.F64).zero_()
     st, stats = m.gcr_solve(x, b, cs.SolverParams(inner_prec=cs.F32, tol=1e-10))
     relres = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, c.b, c.to_host(x, cs.F64)) / np.linalg.norm(c.b)
-    print(f"32^3x64 MG coarse_prec={coarse_prec}: |R P e - e|/|e| {e_orth:.2e}, "
+    print(f"32^3x64 MG fp16 storage={half}: |R P e - e|/|e| {e_orth:.2e}, "
           f"|D_c e - R D P e|/|.| {e_gal:.2e}, iters {stats['iters']}, oracle relres {relres:.2e}")
-    assert e_orth <= 1e-5
-    assert e_gal <= (1e-5 if coarse_prec == cs.F32 else 1e-3)
+    assert e_orth <= (1e-5 if not half else 2e-3)
+    assert e_gal <= (1e-5 if not half else 2e-3)
     assert st == 0 and relres <= 1e-10 * (1 + 1e-6)
     del m, etas
     torch.cuda.empty_cache()

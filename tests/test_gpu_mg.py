@@ -313,3 +313,32 @@ def test_mg_bicgstab_reaches_fp64_residual(sys8, vec):
         assert st_or == 0 and abs(stats["iters"] - it_or) <= max(2, it_or // 10)
     print(msg)
     assert relres <= 1e-10 * (1 + 1e-6)
+
+
+def test_fp16_prolongator_transfers(sys8, plain):
+    """FP16 storage of P for restriction and prolongation (one FP32 scale per
+    site): both agree with the oracle's FP64 transfers to the FP16 rounding of
+    P (unit roundoff 4.9e-4), and MG-FGCR with FP16 transfers and FP16 coarse
+    matrices reaches 1e-10 in about as many iterations as the FP32 hierarchy."""
+    c, etas, etas_d = sys8
+    _, m32, P_or, Dc_or, aggs = plain
+    m = cs.Multigrid(c.op, etas_d, cs.MgParams(**{**_params(0).__dict__, "transfer_prec": cs.F16,
+                                                 "coarse_prec": cs.F16}))
+    r = synth.source(DIMS, 7300)
+    rc = m.restrict(c.to_dev(r, cs.F32)).cpu().numpy()
+    rng = np.random.default_rng(7301)
+    ec = rng.standard_normal(rc.shape) + 1j * rng.standard_normal(rc.shape)
+    z = c.to_host(m.prolong(_coarse(ec)), cs.F32)
+    e = (rel(rc, mg.restrict(P_or, aggs, r)), rel(z, mg.prolong(P_or, aggs, ec)))
+    print("FP16 transfers: restrict / prolong rel diff %.2e %.2e" % e)
+    assert max(e) <= 1e-3
+    b = synth.source(DIMS, 7302)
+    its = []
+    for mm in (m32, m):
+        x = c.lat.new_field(cs.F64).zero_()
+        st, stats = mm.gcr_solve(x, c.to_dev(b, cs.F64), cs.SolverParams(inner_prec=cs.F32, tol=1e-10))
+        relres = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, b, c.to_host(x, cs.F64)) / np.linalg.norm(b)
+        assert st == 0 and relres <= 1e-10 * (1 + 1e-6)
+        its.append(stats["iters"])
+    print(f"MG-FGCR iterations FP32 / FP16 storage: {its}")
+    assert its[1] <= its[0] + 2
