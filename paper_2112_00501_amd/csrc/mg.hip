@@ -141,127 +141,65 @@ struct LdsColumn {  // in-block neighbours for the self term
     }
 };
 
-// Row chunk of the assembly: RC fields of P held in registers.
-constexpr int ASM_RC = 4;
+// Assembly of D_c[a][d][col][row] = <p_{a,row}, D p_{n(a,d),col}> restricted
+// to the terms of D that couple aggregate a to its neighbour in direction d.
+// One workgroup per aggregate (lane = site).  Each column is applied once:
+// the self term (clover and the in-aggregate hops of the column, staged in
+// LDS) and the four -mu face terms (hops from the neighbouring aggregates)
+// stay in registers while every row of P streams past; per row each lane
+// forms 20 partial dot products (self term and four faces, two row
+// chiralities, re and im), which are summed over the lanes through a
+// lane-major LDS array in a fixed order.  The +mu blocks follow afterwards
+// from gamma5-hermiticity (k_mg_assemble_fwd).
+constexpr int ASM_R = 4;                 // rows per reduction round
+constexpr int ASM_VALS = 20 * ASM_R;     // partial sums per lane and round
+constexpr int ASM_LD = ASM_VALS + 1;     // padded row of the lane-major array
 
-// Block sum of N values (one per lane) into out[0..N): wave shuffles, then
-// the four wave totals added in a fixed order.  red holds 4 x N floats.
-template <int N>
-__device__ __forceinline__ void block_sum_to(const float* v, float* red, float* out) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float t[N];
+// y += conj(q) . x over the spins of each chirality: out[2 chi + (re, im)]
+__device__ __forceinline__ void chi_dots(const cpx<float>* q, const cpx<float>* x, float* out) {
+    float a[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k = 0; k < N; ++k) t[k] = wsum(v[k]);
-    if (lane == 0) {
+    for (int k = 0; k < 12; ++k) {
+        const int o = k < 6 ? 0 : 2;
+        a[o] += q[k].re * x[k].re + q[k].im * x[k].im;
+        a[o + 1] += q[k].re * x[k].im - q[k].im * x[k].re;
+    }
 #pragma unroll
-        for (int k = 0; k < N; ++k) red[wave * N + k] = t[k];
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < N) {
-        const int k = threadIdx.x;
-        out[k] = (red[k] + red[N + k]) + (red[2 * N + k] + red[3 * N + k]);
-    }
-    __syncthreads();
+    for (int k = 0; k < 4; ++k) out[k] = a[k];
 }
 
-// dots[4 r + 2 chi + (re, im)] = sum over the spins of chirality chi of
-// conj(q_r) y, for the RC rows of the chunk
-__device__ __forceinline__ void row_dots(const cpx<float> (*q)[12], const cpx<float>* y, float* dots) {
-#pragma unroll
-    for (int r = 0; r < ASM_RC; ++r) {
-        float a[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const int o = k < 6 ? 0 : 2;
-            a[o] += q[r][k].re * y[k].re + q[r][k].im * y[k].im;
-            a[o + 1] += q[r][k].re * y[k].im - q[r][k].im * y[k].re;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) dots[4 * r + k] = a[k];
-    }
-}
-
-// Store the 16 reduced dots of direction d and column col (lanes 0..15).
-__device__ __forceinline__ void store_dots(float2* Dc, int blk, int d, int col, int nc, int nv, int rc0,
-                                           const float* tot) {
-    const int t = threadIdx.x;
-    if (t < 4 * ASM_RC && (t & 1) == 0) {
-        const int r = t >> 2, chi = (t >> 1) & 1;
-        if (rc0 + r < nv) {
-            const int row = chi * nv + rc0 + r;
-            Dc[(((size_t)blk * 9 + d) * nc + col) * nc + row] = make_float2(tot[t], tot[t + 1]);
-        }
-    }
-}
-
-// Face term of direction MU for one column: y = -kappa (hop across the face)
-// on the lanes of the +MU face (forward hop, direction d = 1 + 2 MU) or of
-// the -MU face (backward hop, d = 2 + 2 MU); the dots of both faces are then
-// reduced.
+// -kappa times the backward hop across the -MU face into lane l (zero on
+// lanes not on that face)
 template <int MU>
-__device__ __forceinline__ void face_dots(const Geom& g, const BlockPos& p, int l, const void* links,
-                                          const char* P, size_t fs, int nv, int col, float kappa,
-                                          const cpx<float> (*q)[12], float2* Dc, int nc, int rc0, float* red,
-                                          float* tot) {
-    const int lc = (l >> (2 * MU)) & 3;
-    float dp[4 * ASM_RC], dm[4 * ASM_RC];
+__device__ __forceinline__ void back_face(const Geom& g, const BlockPos& p, int l, const void* links,
+                                          const char* P, size_t fs, int nv, int col, float kappa, cpx<float>* y) {
 #pragma unroll
-    for (int k = 0; k < 4 * ASM_RC; ++k) dp[k] = dm[k] = 0.f;
-    if (lc == 3 || lc == 0) {
-        int nl;
-        bool in;
-        const int nb = neighbour(g, p, l, MU, lc == 3 ? +1 : -1, &nl, &in);
-        cpx<float> psi[12], u[9], acc[12];
+    for (int k = 0; k < 12; ++k) y[k] = {0.f, 0.f};
+    if (((l >> (2 * MU)) & 3) != 0) return;
+    int nl;
+    bool in;
+    const int nb = neighbour(g, p, l, MU, -1, &nl, &in);
+    cpx<float> psi[12], u[9];
+    column_site(P, fs, nv, col, g.nblk, nb, nl, psi);
+    load_link<P_F32, float, false>(links, nb, nl, MU, u);  // U_mu(x - mu)
+    hop_term<MU, +1>(u, psi, y);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
-        column_site(P, fs, nv, col, g.nblk, nb, nl, psi);
-        if (lc == 3) {
-            load_link<P_F32, float, false>(links, p.blk, l, MU, u);  // U_mu(x)
-            hop_term<MU, -1>(u, psi, acc);
-        } else {
-            load_link<P_F32, float, false>(links, nb, nl, MU, u);    // U_mu(x - mu)
-            hop_term<MU, +1>(u, psi, acc);
-        }
-#pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = {-kappa * acc[k].re, -kappa * acc[k].im};
-        row_dots(q, acc, lc == 3 ? dp : dm);
-    }
-    block_sum_to<4 * ASM_RC>(dp, red, tot);
-    store_dots(Dc, p.blk, 1 + 2 * MU, col, nc, nv, rc0, tot);
-    block_sum_to<4 * ASM_RC>(dm, red, tot);
-    store_dots(Dc, p.blk, 2 + 2 * MU, col, nc, nv, rc0, tot);
+    for (int k = 0; k < 12; ++k) y[k] = {-kappa * y[k].re, -kappa * y[k].im};
 }
 
-// D_c[a][d][col][row] = <p_{a,row}, D p_{n(a,d),col}> restricted to the
-// terms of D that couple aggregate a to its neighbour in direction d.  One
-// workgroup per aggregate (lane = site); ASM_RC rows of P stay in registers
-// while every column is applied once per row chunk: the self term (clover and
-// the in-aggregate hops, the column staged in LDS) and the four face terms
-// of the site.
 __global__ __launch_bounds__(TPB) void k_mg_assemble(Geom g, const void* links, const void* clover, float kappa,
                                                      const char* P, size_t fs, int nv, float2* Dc) {
     const int blk = blockIdx.x, l = threadIdx.x, nc = 2 * nv;
     const BlockPos p = block_pos(g, blk);
     __shared__ cpx<float> s[12][BLOCK_SITES];
-    __shared__ float red[4 * 4 * ASM_RC];
-    __shared__ float tot[4 * ASM_RC];
-    float cl[72];
-    CloverIO<float>::template load<false>(clover, blk, l, cl);
-    for (int rc0 = 0; rc0 < nv; rc0 += ASM_RC) {
-        cpx<float> q[ASM_RC][12];
-#pragma unroll
-        for (int r = 0; r < ASM_RC; ++r) {
-            if (rc0 + r < nv) {
-                load_f32(P, fs, rc0 + r, g.nblk, blk, l, q[r]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) q[r][k] = {0.f, 0.f};
-            }
-        }
-        for (int col = 0; col < nc; ++col) {
-            cpx<float> c[12], w[12], acc[12];
+    __shared__ float red[BLOCK_SITES * ASM_LD];
+    __shared__ float part[ASM_VALS][4];
+    for (int col = 0; col < nc; ++col) {
+        cpx<float> y0[12], yf[4][12];
+        {
+            cpx<float> c[12], acc[12];
             column_site(P, fs, nv, col, g.nblk, blk, l, c);
-            __syncthreads();  // the previous column's readers are done
+            __syncthreads();  // the previous column's readers of s are done
 #pragma unroll
             for (int k = 0; k < 12; ++k) s[k][l] = c[k];
             __syncthreads();
@@ -270,18 +208,72 @@ __global__ __launch_bounds__(TPB) void k_mg_assemble(Geom g, const void* links, 
             LdsColumn ls{s};
             GlobalLinks<P_F32, false> lk{links};
             hopping_sum<float>(g, p, l, ls, lk, acc);
-            clover_apply(cl, c, w);
+            float cl[72];
+            CloverIO<float>::template load<false>(clover, blk, l, cl);
+            clover_apply(cl, c, y0);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) w[k] = {w[k].re - kappa * acc[k].re, w[k].im - kappa * acc[k].im};
-            float d0[4 * ASM_RC];
-            row_dots(q, w, d0);
-            block_sum_to<4 * ASM_RC>(d0, red, tot);
-            store_dots(Dc, blk, 0, col, nc, nv, rc0, tot);
-            face_dots<0>(g, p, l, links, P, fs, nv, col, kappa, q, Dc, nc, rc0, red, tot);
-            face_dots<1>(g, p, l, links, P, fs, nv, col, kappa, q, Dc, nc, rc0, red, tot);
-            face_dots<2>(g, p, l, links, P, fs, nv, col, kappa, q, Dc, nc, rc0, red, tot);
-            face_dots<3>(g, p, l, links, P, fs, nv, col, kappa, q, Dc, nc, rc0, red, tot);
+            for (int k = 0; k < 12; ++k) y0[k] = {y0[k].re - kappa * acc[k].re, y0[k].im - kappa * acc[k].im};
         }
+        back_face<0>(g, p, l, links, P, fs, nv, col, kappa, yf[0]);
+        back_face<1>(g, p, l, links, P, fs, nv, col, kappa, yf[1]);
+        back_face<2>(g, p, l, links, P, fs, nv, col, kappa, yf[2]);
+        back_face<3>(g, p, l, links, P, fs, nv, col, kappa, yf[3]);
+        for (int i0 = 0; i0 < nv; i0 += ASM_R) {
+            // partial sums of this lane: value 20 r + 4 e + 2 chi + (re, im),
+            // e = 0 the self term, e = 1 + mu the -mu face
+#pragma unroll
+            for (int r = 0; r < ASM_R; ++r) {
+                float v[20];
+                if (i0 + r < nv) {
+                    cpx<float> q[12];
+                    load_f32(P, fs, i0 + r, g.nblk, blk, l, q);
+                    chi_dots(q, y0, v);
+#pragma unroll
+                    for (int mu = 0; mu < 4; ++mu) chi_dots(q, yf[mu], v + 4 + 4 * mu);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 20; ++k) v[k] = 0.f;
+                }
+#pragma unroll
+                for (int k = 0; k < 20; ++k) red[l * ASM_LD + 20 * r + k] = v[k];
+            }
+            __syncthreads();
+            // four partial sums of 64 lanes per value, then their fixed-order total
+            for (int w = l; w < 4 * ASM_VALS; w += TPB) {
+                const int val = w >> 2, seg = w & 3;
+                float sum = 0.f;
+                for (int j = 0; j < 64; ++j) sum += red[(seg * 64 + j) * ASM_LD + val];
+                part[val][seg] = sum;
+            }
+            __syncthreads();
+            for (int val = l; val < ASM_VALS; val += TPB) {
+                const int r = val / 20, rem = val % 20, e = rem >> 2, chi = (rem >> 1) & 1;
+                if ((rem & 1) == 0 && i0 + r < nv) {
+                    const float re = (part[val][0] + part[val][1]) + (part[val][2] + part[val][3]);
+                    const float im = (part[val + 1][0] + part[val + 1][1]) + (part[val + 1][2] + part[val + 1][3]);
+                    const int row = chi * nv + i0 + r, d = e == 0 ? 0 : 2 * e;  // e = 1 + mu -> d = 2 + 2 mu
+                    Dc[(((size_t)blk * 9 + d) * nc + col) * nc + row] = make_float2(re, im);
+                }
+            }
+            __syncthreads();  // red and part are reused by the next round
+        }
+    }
+}
+
+// D_c[a][1 + 2 mu] from gamma5-hermiticity of D (P keeps chirality):
+// D_c[a][+mu][col][row] = g5(col) g5(row) conj(D_c[b][-mu][row][col]) with
+// b the +mu neighbour of a and g5 = +1 on chirality 0, -1 on chirality 1.
+__global__ __launch_bounds__(TPB) void k_mg_assemble_fwd(Geom g, int nv, float2* Dc) {
+    const int a = blockIdx.x, mu = blockIdx.y, nc = 2 * nv;
+    const BlockPos p = block_pos(g, a);
+    const int b = block_step(g, p, mu, +1);
+    const float2* src = Dc + ((size_t)b * 9 + 2 + 2 * mu) * nc * nc;
+    float2* dst = Dc + ((size_t)a * 9 + 1 + 2 * mu) * nc * nc;
+    for (int idx = threadIdx.x; idx < nc * nc; idx += TPB) {
+        const int col = idx / nc, row = idx % nc;
+        const float sg = ((col < nv) == (row < nv)) ? 1.f : -1.f;
+        const float2 v = src[(size_t)row * nc + col];
+        dst[idx] = make_float2(sg * v.x, -sg * v.y);
     }
 }
 
@@ -689,6 +681,9 @@ hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipS
     ProfScope ps("mg", s);
     hipLaunchKernelGGL(k_mg_assemble, dim3(op.g.nblk), dim3(TPB), 0, s, op.g, op.links[P_F32], op.clover32,
                        (float)op.kappa, (const char*)P, spinor_bytes_per_site(P_F32) * op.g.V, nv, Dc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mg_assemble_fwd, dim3(op.g.nblk, 4), dim3(TPB), 0, s, op.g, nv, Dc);
     return hipGetLastError();
 }
 
