@@ -74,6 +74,8 @@ def _declare(L):
     L.or_clover_inverse_field.argtypes = [_I4, _P, _P]
     L.or_jacobi_block.argtypes = [_I4, _I4, C.c_long, _P, _P, C.c_double, C.c_int, _P, _P]
     L.or_sap_jacobi.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, _P, _P]
+    L.or_mr_eo_block.argtypes = [_I4, _I4, C.c_long, _P, _P, C.c_double, C.c_int, _P, _P]
+    L.or_sap_eo.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, _P, _P]
     L.or_fgcr.argtypes = [_I4, _I4, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int,
                           C.c_double, C.c_int, _P, _P, C.POINTER(C.c_int),
                           C.POINTER(C.c_double), _P]
@@ -248,6 +250,26 @@ def sap_jacobi(dims, bdim, U, T, kappa, n_cy, n_jac, b, x0=None) -> np.ndarray:
     x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
     lib().or_sap_jacobi(_dims(dims), _dims(bdim), _ptr(U), _ptr(T), float(kappa), int(n_cy), int(n_jac),
                         _ptr(b), _ptr(x))
+    return x
+
+
+def mr_eo_block(dims, bdim, blk, U, T, kappa, n_mr, r) -> np.ndarray:
+    """Even-odd preconditioned MR solve of D_BB delta = r_B for one block."""
+    U, r = _c128(U), _c128(r)
+    T = None if T is None else _c128(T)
+    delta = np.zeros_like(r)
+    lib().or_mr_eo_block(_dims(dims), _dims(bdim), int(blk), _ptr(U), _ptr(T), float(kappa), int(n_mr),
+                         _ptr(r), _ptr(delta))
+    return delta
+
+
+def sap_eo(dims, bdim, U, T, kappa, n_cy, n_mr, b, x0=None) -> np.ndarray:
+    """SAP with even-odd preconditioned MR block solves."""
+    U, b = _c128(U), _c128(b)
+    T = None if T is None else _c128(T)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    lib().or_sap_eo(_dims(dims), _dims(bdim), _ptr(U), _ptr(T), float(kappa), int(n_cy), int(n_mr),
+                    _ptr(b), _ptr(x))
     return x
 
 

@@ -705,6 +705,137 @@ void or_sap_jacobi(const int d[4], const int b[4], const ocplx* U, const ocplx* 
         }
 }
 
+/* ------------------------------------------------- even-odd block MR (SAP) */
+
+/* Global parity (x + y + z + t) mod 2 of site s; every hop joins opposite
+ * parities. */
+static int site_parity(const int d[4], long s) {
+    int c[4];
+    site_coords(d, s, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+/* Even-odd preconditioned MR on the Dirichlet block operator (local arrays).
+ * With the block's sites split by parity, D_BB = [[C_e, -k H_eo],
+ * [-k H_oe, C_o]] (C site diagonal); the Schur complement on the even sites
+ * is S = C_e - k^2 H_eo C_o^-1 H_oe.  The block system D_BB delta = r becomes
+ *   S delta_e = r_e + k H_eo C_o^-1 r_o,   delta_o = C_o^-1 (r_o + k H_oe delta_e),
+ * and S delta_e = rhat_e is solved by n_mr MR steps from delta_e = 0 (as
+ * mr_local, on vectors that vanish on the odd sites).  Every product with the
+ * off-diagonal blocks is taken from D_BB itself: for u vanishing on the even
+ * sites (D_BB u)_e = -k H_eo u_o; for v vanishing on the odd sites
+ * (D_BB v)_o = -k H_oe v_e, so S v_e = [D_BB (v_e, -C_o^-1 (D_BB v)_o)]_e.
+ * ci holds C^-1 of the block's sites, par their parities. */
+static void eo_mr_local(const int d[4], const int b[4], long blk, const ocplx* U, const ocplx* T,
+                        double kappa, const ocplx G[4][16], int n_mr, const ocplx* ci, const int* par,
+                        const ocplx* r_l, ocplx* delta_l) {
+    long bv = vol4(b), n = bv * 12;
+    ocplx* rho = malloc(sizeof(ocplx) * n);
+    ocplx* t = malloc(sizeof(ocplx) * n);
+    ocplx* w = malloc(sizeof(ocplx) * n);
+    ocplx* q = malloc(sizeof(ocplx) * n);
+    /* rhat_e = r_e - (D_BB (0, C_o^-1 r_o))_e */
+    for (long l = 0; l < bv; ++l) {
+        if (par[l]) m12_apply(ci + l * 144, r_l + l * 12, t + l * 12);
+        else memset(t + l * 12, 0, 12 * sizeof(ocplx));
+    }
+    dbb_local(d, b, blk, U, T, kappa, G, t, w);
+    for (long l = 0; l < bv; ++l)
+        for (int i = 0; i < 12; ++i) rho[l * 12 + i] = par[l] ? 0 : r_l[l * 12 + i] - w[l * 12 + i];
+    memset(delta_l, 0, sizeof(ocplx) * n);
+    for (int it = 0; it < n_mr; ++it) {
+        /* q = S rho (rho vanishes on the odd sites) */
+        dbb_local(d, b, blk, U, T, kappa, G, rho, w);
+        for (long l = 0; l < bv; ++l) {
+            if (par[l]) {
+                ocplx u[12];
+                m12_apply(ci + l * 144, w + l * 12, u);
+                for (int i = 0; i < 12; ++i) t[l * 12 + i] = -u[i];
+            } else {
+                memcpy(t + l * 12, rho + l * 12, 12 * sizeof(ocplx));
+            }
+        }
+        dbb_local(d, b, blk, U, T, kappa, G, t, q);
+        for (long l = 0; l < bv; ++l)
+            if (par[l]) memset(q + l * 12, 0, 12 * sizeof(ocplx));
+        double qq = vnorm2(n, q);
+        if (qq == 0.0) break;
+        ocplx alpha = vdot(n, q, rho) / qq;
+        for (long i = 0; i < n; ++i) {
+            delta_l[i] += alpha * rho[i];
+            rho[i] -= alpha * q[i];
+        }
+    }
+    /* delta_o = C_o^-1 (r_o - (D_BB (delta_e, 0))_o) */
+    dbb_local(d, b, blk, U, T, kappa, G, delta_l, w);
+    for (long l = 0; l < bv; ++l)
+        if (par[l]) {
+            ocplx u[12];
+            for (int i = 0; i < 12; ++i) u[i] = r_l[l * 12 + i] - w[l * 12 + i];
+            m12_apply(ci + l * 144, u, delta_l + l * 12);
+        }
+    free(rho); free(t); free(w); free(q);
+}
+
+static void eo_block_tables(const int d[4], const int b[4], long blk, const ocplx* T, ocplx* ci, int* par) {
+    for (long l = 0; l < vol4(b); ++l) {
+        long s = block_site(d, b, blk, l);
+        or_clover_inverse_site(T ? T + s * 144 : NULL, ci + l * 144);
+        par[l] = site_parity(d, s);
+    }
+}
+
+/* The even-odd block solve for one block: delta_B for the block residual r_B
+ * (full-lattice arrays r, delta). */
+void or_mr_eo_block(const int d[4], const int b[4], long blk, const ocplx* U, const ocplx* T,
+                    double kappa, int n_mr, const ocplx* r, ocplx* delta) {
+    long bv = vol4(b);
+    ocplx G[4][16];
+    load_gammas(G);
+    ocplx* ci = malloc(sizeof(ocplx) * 144 * bv);
+    int* par = malloc(sizeof(int) * bv);
+    ocplx* rl = malloc(sizeof(ocplx) * 12 * bv);
+    ocplx* dl = malloc(sizeof(ocplx) * 12 * bv);
+    eo_block_tables(d, b, blk, T, ci, par);
+    for (long l = 0; l < bv; ++l) memcpy(rl + l * 12, r + block_site(d, b, blk, l) * 12, 12 * sizeof(ocplx));
+    eo_mr_local(d, b, blk, U, T, kappa, (const ocplx(*)[16])G, n_mr, ci, par, rl, dl);
+    for (long l = 0; l < bv; ++l) memcpy(delta + block_site(d, b, blk, l) * 12, dl + l * 12, 12 * sizeof(ocplx));
+    free(ci); free(par); free(rl); free(dl);
+}
+
+/* SAP as or_sap with the even-odd preconditioned block solve. */
+void or_sap_eo(const int d[4], const int b[4], const ocplx* U, const ocplx* T, double kappa,
+               int n_cy, int n_mr, const ocplx* bsrc, ocplx* x) {
+    long nblk = or_num_blocks(d, b), bv = vol4(b);
+    ocplx G[4][16];
+    load_gammas(G);
+    for (int cy = 0; cy < n_cy; ++cy)
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic)
+            for (long blk = 0; blk < nblk; ++blk) {
+                if (or_block_colour(d, b, blk) != colour) continue;
+                ocplx* rl = malloc(sizeof(ocplx) * 12 * bv);
+                ocplx* dl = malloc(sizeof(ocplx) * 12 * bv);
+                ocplx* ci = malloc(sizeof(ocplx) * 144 * bv);
+                int* par = malloc(sizeof(int) * bv);
+                eo_block_tables(d, b, blk, T, ci, par);
+                for (long l = 0; l < bv; ++l) {
+                    long s = block_site(d, b, blk, l);
+                    ocplx hop[12], dx[12];
+                    hop_site(d, U, (const ocplx(*)[16])G, x, s, NULL, NULL, hop);
+                    d_site(T ? T + s * 144 : NULL, kappa, x + s * 12, hop, dx);
+                    for (int i = 0; i < 12; ++i) rl[l * 12 + i] = bsrc[s * 12 + i] - dx[i];
+                }
+                eo_mr_local(d, b, blk, U, T, kappa, (const ocplx(*)[16])G, n_mr, ci, par, rl, dl);
+                for (long l = 0; l < bv; ++l) {
+                    long s = block_site(d, b, blk, l);
+                    for (int i = 0; i < 12; ++i) x[s * 12 + i] += dl[l * 12 + i];
+                }
+                free(rl); free(dl); free(ci); free(par);
+            }
+        }
+}
+
 /* -------------------------------------------------------------------- FGCR */
 
 int or_fgcr(const int d[4], const int b[4], const ocplx* U, const ocplx* T, double kappa,

@@ -97,6 +97,12 @@ void or_jacobi_block(const int dims[4], const int bdim[4], long blk, const ocplx
 /* SAP on A = C^-1 D with n_jac Jacobi steps per block; see oracle.c. */
 void or_sap_jacobi(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T,
                    double kappa, int n_cy, int n_jac, const ocplx* b, ocplx* x);
+/* Even-odd preconditioned MR block solve (Schur complement on the even sites,
+ * back-substitution on the odd ones) and SAP built on it. */
+void or_mr_eo_block(const int dims[4], const int bdim[4], long blk, const ocplx* U, const ocplx* T,
+                    double kappa, int n_mr, const ocplx* r, ocplx* delta);
+void or_sap_eo(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T, double kappa,
+               int n_cy, int n_mr, const ocplx* b, ocplx* x);
 
 int or_fgcr(const int dims[4], const int bdim[4], const ocplx* U, const ocplx* T,
             double kappa, int n_cy, int n_mr, int restart, double tol, int max_iter,

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2112_00501_amd import synth
-from tests.oracle_helpers import (block_sites, dense_D, dof_indices, gauge_transform_links,
+from tests.oracle_helpers import (block_sites, coords, dense_D, dof_indices, gauge_transform_links,
                                   gauge_transform_spinor)
 
 DIMS, BDIM = (4, 4, 4, 4), (2, 2, 2, 2)
@@ -314,3 +314,66 @@ def test_jacobi_sap_gauge_covariant(system):
     x = oracle.sap_jacobi(DIMS, BDIM, U, T, KAPPA, 2, 3, b)
     xg = oracle.sap_jacobi(DIMS, BDIM, Ug, Tg, KAPPA, 2, 3, gauge_transform_spinor(Om, b))
     assert np.abs(xg - gauge_transform_spinor(Om, x)).max() < 1e-12
+
+
+def _eo_split(blk):
+    sites = block_sites(DIMS, BDIM, blk)
+    par = coords(DIMS, int(np.prod(DIMS)))[sites].sum(axis=1) % 2
+    return dof_indices(sites[par == 0]), dof_indices(sites[par == 1])
+
+
+def test_eo_block_mr_one_step_against_the_dense_schur_complement(system):
+    """One even-odd MR step, built from dense blocks of D: S = D_ee - D_eo
+    D_oo^-1 D_oe, rhat = r_e - D_eo D_oo^-1 r_o, delta_e = alpha rhat with
+    alpha = <S rhat, rhat> / |S rhat|^2, delta_o = D_oo^-1 (r_o - D_oe delta_e)."""
+    U, T, M = system
+    r = synth.source(DIMS, 41)
+    blk = 5
+    ie, io = _eo_split(blk)
+    Dee, Deo = M[np.ix_(ie, ie)], M[np.ix_(ie, io)]
+    Doe, Doo = M[np.ix_(io, ie)], M[np.ix_(io, io)]
+    assert np.abs(Dee - np.diag(np.diag(Dee))).max() > 0  # clover couples spins and colours on a site
+    rf = r.reshape(-1)
+    S = Dee - Deo @ np.linalg.solve(Doo, Doe)
+    rhat = rf[ie] - Deo @ np.linalg.solve(Doo, rf[io])
+    q = S @ rhat
+    de = np.vdot(q, rhat) / np.vdot(q, q) * rhat
+    do = np.linalg.solve(Doo, rf[io] - Doe @ de)
+    got = oracle.mr_eo_block(DIMS, BDIM, blk, U, T, KAPPA, 1, r).reshape(-1)
+    assert np.abs(got[ie] - de).max() < 1e-13 and np.abs(got[io] - do).max() < 1e-13
+    # outside the block nothing is written
+    rest = np.setdiff1d(np.arange(rf.size), np.concatenate([ie, io]))
+    assert np.abs(got[rest]).max() == 0.0
+
+
+def test_eo_block_mr_converges_to_the_block_solve_and_beats_plain_mr(system):
+    U, T, M = system
+    r = synth.source(DIMS, 42)
+    blk = 2
+    ie, io = _eo_split(blk)
+    idx = np.sort(np.concatenate([ie, io]))
+    exact = np.linalg.solve(M[np.ix_(idx, idx)], r.reshape(-1)[idx])
+    got = oracle.mr_eo_block(DIMS, BDIM, blk, U, T, KAPPA, 60, r).reshape(-1)[idx]
+    assert np.linalg.norm(got - exact) < 1e-10 * np.linalg.norm(exact)
+    # at equal step counts the Schur-complement iteration is closer to the block solve
+    for n in (2, 4):
+        e_eo = np.linalg.norm(oracle.mr_eo_block(DIMS, BDIM, blk, U, T, KAPPA, n, r).reshape(-1)[idx] - exact)
+        e_mr = np.linalg.norm(oracle.mr_block(DIMS, BDIM, blk, U, T, KAPPA, n, r).reshape(-1)[idx] - exact)
+        assert e_eo < e_mr
+
+
+def test_eo_sap_exact_block_limit_equals_mr_sap_limit(system):
+    """With enough steps both block solvers are exact, so even-odd SAP and
+    MR-SAP reach the same red/black block Gauss-Seidel result; the even-odd
+    smoother is gauge covariant."""
+    U, T, M = system
+    b = synth.source(DIMS, 43)
+    x_eo = oracle.sap_eo(DIMS, BDIM, U, T, KAPPA, 2, 60, b)
+    x_mr = oracle.sap(DIMS, BDIM, U, T, KAPPA, 2, 200, b)
+    assert np.linalg.norm(x_eo - x_mr) < 1e-9 * np.linalg.norm(x_mr)
+    g = synth.gauge_transform(DIMS, 44)
+    Ug = gauge_transform_links(DIMS, U, g)
+    Tg = oracle.clover_field(DIMS, Ug, KAPPA, CSW)
+    x1 = oracle.sap_eo(DIMS, BDIM, U, T, KAPPA, 2, 4, b)
+    x2 = oracle.sap_eo(DIMS, BDIM, Ug, Tg, KAPPA, 2, 4, gauge_transform_spinor(g, b))
+    assert np.linalg.norm(x2 - gauge_transform_spinor(g, x1)) < 1e-12 * np.linalg.norm(x1)
