@@ -209,6 +209,20 @@ int cs_sap_smooth_jacobi(cs_gauge g, cs_clover c, cs_prec prec, void* x, const v
                          int n_cy, int n_jac, int x0_is_zero, int nrhs,
                          const cs_launch_config* cfg, void* stream);
 
+/* SAP whose block solves are even-odd preconditioned MR (the other block
+ * solver of the paper's smoother family, Section 2): with the sites of a
+ * block split by parity (x + y + z + t even / odd), the block system
+ * D_BB delta = r_B is reduced to its Schur complement on the even sites,
+ *   S = C_e - kappa^2 H_eo C_o^-1 H_oe,   S delta_e = r_e + kappa H_eo C_o^-1 r_o,
+ * solved by n_mr MR steps from delta_e = 0, and the odd sites follow from
+ * delta_o = C_o^-1 (r_o + kappa H_oe delta_e) (H_eo, H_oe the in-block hops,
+ * C^-1 the inverse clover term of cs_clover_inverse_export).  One lane per
+ * site (cfg->lanes_per_site is ignored).  Arguments, modes and errors as
+ * cs_sap_smooth_cfg (cfg may be NULL). */
+int cs_sap_smooth_eo(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b,
+                     int n_cy, int n_mr, int x0_is_zero, int nrhs,
+                     const cs_launch_config* cfg, void* stream);
+
 /* ------------------------------------------------------------------ solver */
 
 typedef struct {
@@ -225,7 +239,9 @@ typedef struct {
                              once and replay it (ignored while profiling)         */
     int block_solver;     /* SAP block solves: 0 = n_mr MR steps on D_BB; 1 =
                              n_mr Jacobi steps on (C^-1 D)_BB (the form of the
-                             paper's QWS smoother, see cs_sap_smooth_jacobi)     */
+                             paper's QWS smoother, see cs_sap_smooth_jacobi); 2 =
+                             n_mr even-odd preconditioned MR steps (see
+                             cs_sap_smooth_eo)                                   */
 } cs_solver_params;
 
 typedef struct {

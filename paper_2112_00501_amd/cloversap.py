@@ -62,7 +62,7 @@ EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_des
             "cs_lattice_volume", "cs_field_bytes", "cs_field_import", "cs_field_export",
             "cs_gauge_create", "cs_gauge_destroy", "cs_clover_create", "cs_clover_destroy",
             "cs_clover_export", "cs_clover_inverse_export", "cs_apply_D", "cs_apply_Ddag",
-            "cs_apply_D_cfg", "cs_sap_smooth", "cs_sap_smooth_cfg", "cs_sap_smooth_jacobi",
+            "cs_apply_D_cfg", "cs_sap_smooth", "cs_sap_smooth_cfg", "cs_sap_smooth_jacobi", "cs_sap_smooth_eo",
             "cs_autotune", "cs_solver_params_default", "cs_gcr_solve", "cs_gcr_solve_dag",
             "cs_bicgstab_solve", "cs_mg_params_default", "cs_mg_create", "cs_mg_destroy",
             "cs_mg_export", "cs_mg_restrict", "cs_mg_prolong", "cs_mg_coarse_apply",
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
     L.cs_sap_smooth.argtypes = [P, P, I, P, P, I, I, I, I, P]
     L.cs_sap_smooth_cfg.argtypes = [P, P, I, P, P, I, I, I, I, C.POINTER(LaunchConfig), P]
     L.cs_sap_smooth_jacobi.argtypes = [P, P, I, P, P, I, I, I, I, C.POINTER(LaunchConfig), P]
+    L.cs_sap_smooth_eo.argtypes = [P, P, I, P, P, I, I, I, I, C.POINTER(LaunchConfig), P]
     L.cs_apply_D_cfg.argtypes = [P, P, I, P, P, I, C.POINTER(LaunchConfig), P]
     L.cs_autotune.argtypes = [P, P, I, I, C.POINTER(LaunchConfig), C.POINTER(LaunchConfig), P]
     L.cs_solver_params_default.argtypes = [C.POINTER(_Params)]
@@ -283,6 +284,13 @@ class Operator:
                "cs_sap_smooth_jacobi")
         return x
 
+    def sap_smooth_eo(self, x, b, prec, n_cy=2, n_mr=4, x0_is_zero=True, nrhs=1, cfg=None, stream=None):
+        """SAP with even-odd preconditioned MR block solves."""
+        _check(_lib.cs_sap_smooth_eo(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
+                                     int(n_cy), int(n_mr), int(bool(x0_is_zero)), nrhs,
+                                     None if cfg is None else C.byref(cfg), _stream(stream)), "cs_sap_smooth_eo")
+        return x
+
     def autotune(self, prec, nrhs, stream=None):
         """Fastest (SAP, operator) launch shapes for nrhs right-hand sides."""
         a, b = LaunchConfig(), LaunchConfig()
@@ -457,7 +465,7 @@ class SolverParams:
     reliable_delta: float = 1e-5
     rhs_tile: int = 0
     use_graph: bool = True
-    block_solver: int = 0     # 0: n_mr MR steps on D_BB; 1: n_mr Jacobi steps on (C^-1 D)_BB
+    block_solver: int = 0     # 0: MR on D_BB; 1: Jacobi on (C^-1 D)_BB; 2: even-odd preconditioned MR (n_mr steps)
 
     def to_c(self) -> _Params:
         return _Params(self.restart, self.max_iter, self.n_cy, self.n_mr, self.tol,

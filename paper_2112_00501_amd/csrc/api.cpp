@@ -395,6 +395,11 @@ int cs_sap_smooth_cfg(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void
     return sap_common(g, c, prec, x, b, n_cy, n_mr, x0_is_zero, nrhs, cfg, stream, cs::BLOCK_MR);
 }
 
+int cs_sap_smooth_eo(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_mr,
+                     int x0_is_zero, int nrhs, const cs_launch_config* cfg, void* stream) {
+    return sap_common(g, c, prec, x, b, n_cy, n_mr, x0_is_zero, nrhs, cfg, stream, cs::BLOCK_EO);
+}
+
 int cs_sap_smooth_jacobi(cs_gauge g, cs_clover c, cs_prec prec, void* x, const void* b, int n_cy, int n_jac,
                          int x0_is_zero, int nrhs, const cs_launch_config* cfg, void* stream) {
     return sap_common(g, c, prec, x, b, n_cy, n_jac, x0_is_zero, nrhs, cfg, stream, cs::BLOCK_JACOBI);
@@ -525,7 +530,7 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
     if (p->max_iter < 0 || p->n_cy < 0 || (p->n_cy > 0 && p->n_mr < 1))
         return fail(CS_ERR_INVALID, "max_iter and n_cy must be >= 0 and n_mr >= 1 when n_cy > 0");
     if (!(p->tol >= 0.0)) return fail(CS_ERR_INVALID, "tol must be >= 0");
-    if (p->block_solver != 0 && p->block_solver != 1) return fail(CS_ERR_INVALID, "block_solver must be 0 or 1");
+    if (p->block_solver < 0 || p->block_solver > 2) return fail(CS_ERR_INVALID, "block_solver must be 0, 1 or 2");
     if (!valid_prec(p->inner_prec)) return fail(CS_ERR_PRECISION, "unknown inner precision");
     if (p->basis_prec != CS_F64 && p->basis_prec != CS_F32)
         return fail(CS_ERR_PRECISION, "basis precision must be CS_F64 or CS_F32");
@@ -601,7 +606,7 @@ static int bicgstab_common(cs_gauge g, cs_clover c, const cs_solver_params* p, v
     if (p->max_iter < 0 || p->n_cy < 0 || (p->n_cy > 0 && p->n_mr < 1))
         return fail(CS_ERR_INVALID, "max_iter and n_cy must be >= 0 and n_mr >= 1 when n_cy > 0");
     if (!(p->tol >= 0.0)) return fail(CS_ERR_INVALID, "tol must be >= 0");
-    if (p->block_solver != 0 && p->block_solver != 1) return fail(CS_ERR_INVALID, "block_solver must be 0 or 1");
+    if (p->block_solver < 0 || p->block_solver > 2) return fail(CS_ERR_INVALID, "block_solver must be 0, 1 or 2");
     if (!valid_prec(p->inner_prec)) return fail(CS_ERR_PRECISION, "unknown inner precision");
     if (p->n_cy > 0 && !sap_geometry_ok(g->g))
         return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");

@@ -327,8 +327,9 @@ hipError_t launch_dslash_tiled(const OpData& op, int prec, bool dagger, void* ou
 // sap.hip: one half-sweep over the blocks of one colour.  mode 0: general;
 // 1: x is zero everywhere (r = b); 2: x is zero on the blocks of this colour.
 // Block solver: BLOCK_MR, n_block MR steps on D_BB; BLOCK_JACOBI, n_block
-// Jacobi steps on A_BB = (C^-1 D)_BB.
-enum { BLOCK_MR = 0, BLOCK_JACOBI = 1 };
+// Jacobi steps on A_BB = (C^-1 D)_BB; BLOCK_EO, n_block MR steps on the
+// even-site Schur complement of D_BB (one lane per site only).
+enum { BLOCK_MR = 0, BLOCK_JACOBI = 1, BLOCK_EO = 2 };
 hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_block, int mode,
                                 void* x, const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s,
                                 int block_solver = BLOCK_MR);
@@ -343,7 +344,5 @@ hipError_t launch_force(const Geom& g, const void* links64, double kappa, double
 
 // blas.hip
 struct BlasWork;  // defined in blas.hip
-hipError_t launch_convert(const Geom& g, int dst_prec, void* dst, int src_prec, const void* src,
-                          const double* scale_dev, int nrhs, hipStream_t s);
 
 }  // namespace cs

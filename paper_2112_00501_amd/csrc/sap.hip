@@ -193,6 +193,13 @@ __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
 // With gridDim.x < nitems the launch is persistent: workgroups stride over
 // the work items.
 //
+// BS = BLOCK_EO: the same block system D_BB delta = r_B, solved by MR on its
+// Schur complement S = C_e - kappa^2 H_eo C_o^-1 H_oe over the even sites of
+// the block (right-hand side r_e + kappa H_eo C_o^-1 r_o), then delta_o =
+// C_o^-1 (r_o + kappa H_oe delta_e); `cinv` is (1 + T)^-1.  Even and odd
+// lanes take turns (hops join opposite parities), and a step costs about two
+// hopping sums.
+//
 // BS = BLOCK_JACOBI: the block system of A = C^-1 D is solved instead, by
 // Jacobi steps (A_BB has the identity on its diagonal); `clover` is then
 // (1 + T)^-1 and the visit is
@@ -202,7 +209,8 @@ __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
 // (hop = the hopping sum, D = C - kappa hop), with no reductions.
 template <int P, int PLINK, int BS>
 __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ links,
-                                              const void* __restrict__ clover, double kappa_d,
+                                              const void* __restrict__ clover,
+                                              const void* __restrict__ cinv, double kappa_d,
                                               int colour, int n_mr, int mode, void* __restrict__ x,
                                               const void* __restrict__ b, size_t stride, int nrhs,
                                               int tile, int nitems) {
@@ -275,7 +283,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 cpx<R> self[12];
                 if (mode == 0) {
                     ls.load_nb(0, l, true, self);
-                    if constexpr (BS == BLOCK_MR) clover_apply(cl, self, cx);
+                    if constexpr (BS != BLOCK_JACOBI) clover_apply(cl, self, cx);
                 } else {
 #pragma unroll
                     for (int k = 0; k < 12; ++k) cx[k] = self[k] = {(R)0, (R)0};
@@ -283,7 +291,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 using RS = typename SpinorIO<P>::R;
                 cpx<RS> t[12];
                 SpinorIO<P>::load(br, g.nblk, blk, l, t);
-                if constexpr (BS == BLOCK_MR) {
+                if constexpr (BS != BLOCK_JACOBI) {
 #pragma unroll
                     for (int k = 0; k < 12; ++k)
                         rho0[k] = {(R)t[k].re - (cx[k].re - kappa * acc[k].re),
@@ -300,7 +308,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 __syncthreads();  // every lane has read x from rho
 #pragma unroll
                 for (int k = 0; k < 12; ++k) s_rho[k][l] = rho0[k];
-            } else if constexpr (BS == BLOCK_MR) {
+            } else if constexpr (BS != BLOCK_JACOBI) {
                 cpx<R> acc[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
@@ -463,6 +471,108 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 }
             }
 
+            if constexpr (BS == BLOCK_EO) {
+                // ---- even-odd preconditioned MR: S = C_e - kappa^2 H_eo C_o^-1 H_oe on
+                // the even sites, then the odd sites by back-substitution.  s_rho
+                // holds r_B; rho0 keeps it in registers for the odd lanes.
+                const bool odd = (((l & 3) + ((l >> 2) & 3) + ((l >> 4) & 3) + (l >> 6)) & 1) != 0;
+                auto hop_lds = [&](cpx<R>* acc) {  // in-block hopping sum from s_rho
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
+                    if constexpr (F32PATH) {
+                        LdsLinks lk{&s_lk};
+                        hopping_sum<R>(g, p, l, ls, lk, acc);
+                    } else {
+                        GlobalLinks<PLINK, false> lk{links};
+                        hopping_sum_rolled<R>(g, p, l, ls, lk, acc);
+                    }
+                };
+                if (odd) {  // C_o^-1 r_o on the odd sites
+                    cpx<R> t[12];
+                    clover_apply_by_chirality<R>(cinv, blk, l, rho0, t);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) s_rho[k][l] = t[k];
+                }
+                __syncthreads();
+                cpx<R> rr[12];
+                if (!odd) {  // rhat_e = r_e + kappa H_eo C_o^-1 r_o
+                    cpx<R> acc[12];
+                    hop_lds(acc);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) rr[k] = {rho0[k].re + kappa * acc[k].re, rho0[k].im + kappa * acc[k].im};
+                }
+                __syncthreads();  // every even lane has read the odd entries
+                if (!odd) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) s_rho[k][l] = rr[k];
+                }
+                for (int it = 0; it < n_mr; ++it) {
+                    __syncthreads();  // the even residual is in LDS
+                    if (odd) {  // t_o = kappa C_o^-1 H_oe r_e
+                        cpx<R> acc[12], t[12];
+                        hop_lds(acc);
+                        clover_apply_by_chirality<R>(cinv, blk, l, acc, t);
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) s_rho[k][l] = {kappa * t[k].re, kappa * t[k].im};
+                    }
+                    __syncthreads();
+                    cpx<R> q[12];
+                    R qq = 0, qr_re = 0, qr_im = 0;
+                    if (!odd) {  // q_e = C_e r_e - kappa H_eo t_o
+                        cpx<R> acc[12];
+                        hop_lds(acc);
+                        ls.load_nb(0, l, true, rr);
+                        if constexpr (F32PATH) {
+                            clover_apply(cl, rr, q);
+                        } else {
+                            R c2[72];
+                            CloverIO<R>::template load<false>(clover, blk, l, c2);
+                            clover_apply(c2, rr, q);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) {
+                            q[k] = {q[k].re - kappa * acc[k].re, q[k].im - kappa * acc[k].im};
+                            qq = fma(q[k].re, q[k].re, qq);
+                            qq = fma(q[k].im, q[k].im, qq);
+                            qr_re = fma(q[k].re, rr[k].re, qr_re);
+                            qr_re = fma(q[k].im, rr[k].im, qr_re);
+                            qr_im = fma(q[k].re, rr[k].im, qr_im);
+                            qr_im = fma(-q[k].im, rr[k].re, qr_im);
+                        }
+                    }
+                    block_sum3(qq, qr_re, qr_im, s_red);
+                    if (qq == (R)0) break;  // the even residual is zero (uniform branch)
+                    const R inv = (R)1 / qq;
+                    const cpx<R> alpha = {qr_re * inv, qr_im * inv};
+                    if (!odd) {
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) {
+                            cmac(delta[k], alpha, rr[k]);
+                            cpx<R> t = rr[k];
+                            t.re = fma(-alpha.re, q[k].re, t.re);
+                            t.re = fma(alpha.im, q[k].im, t.re);
+                            t.im = fma(-alpha.re, q[k].im, t.im);
+                            t.im = fma(-alpha.im, q[k].re, t.im);
+                            s_rho[k][l] = t;
+                        }
+                    }
+                }
+                // delta_o = C_o^-1 (r_o + kappa H_oe delta_e)
+                __syncthreads();
+                if (!odd) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) s_rho[k][l] = delta[k];
+                }
+                __syncthreads();
+                if (odd) {
+                    cpx<R> acc[12], u[12];
+                    hop_lds(acc);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) u[k] = {rho0[k].re + kappa * acc[k].re, rho0[k].im + kappa * acc[k].im};
+                    clover_apply_by_chirality<R>(cinv, blk, l, u, delta);
+                }
+            }
+
             // ---- x_B += delta (after every lane has finished reading x and rho)
             __syncthreads();
             using RS = typename SpinorIO<P>::R;
@@ -487,14 +597,19 @@ hipError_t launch_p(const OpData& op, int colour, int n_mr, int mode, void* x, c
     const int nitems = (op.g.nblk / 2) * ((nrhs + tile - 1) / tile);
     const int grid = cfg.persistent_wgs > 0 && cfg.persistent_wgs < nitems ? cfg.persistent_wgs : nitems;
     const size_t stride = spinor_bytes_per_site(P) * op.g.V;
+    const void* cl = P == P_F64 ? op.clover64 : op.clover32;
+    const void* ci = P == P_F64 ? op.cinv64 : op.cinv32;
     if (bs == BLOCK_JACOBI) {
-        const void* cl = P == P_F64 ? op.cinv64 : op.cinv32;
         hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_JACOBI>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
-                           op.links[PLINK], cl, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
+                           op.links[PLINK], ci, nullptr, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile,
+                           nitems);
+    } else if (bs == BLOCK_EO) {
+        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_EO>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
+                           op.links[PLINK], cl, ci, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
     } else {
-        const void* cl = P == P_F64 ? op.clover64 : op.clover32;
         hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_MR>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
-                           op.links[PLINK], cl, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
+                           op.links[PLINK], cl, nullptr, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile,
+                           nitems);
     }
     return hipGetLastError();
 }
@@ -512,9 +627,11 @@ static int default_lanes_per_site(const Geom& g) { return g.nblk / 2 <= 256 ? 2 
 hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode, void* x,
                                 const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s, int bs) {
     ProfScope ps("sap_halfsweep", s);
-    if (bs != BLOCK_MR && bs != BLOCK_JACOBI) return hipErrorInvalidValue;
+    if (bs != BLOCK_MR && bs != BLOCK_JACOBI && bs != BLOCK_EO) return hipErrorInvalidValue;
     const int lanes = cfg.lanes_per_site > 0 ? cfg.lanes_per_site : default_lanes_per_site(op.g);
-    if (lanes == 2 && prec != P_F64) return launch_sap_pair(op, prec, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
+    // the even-odd block solver has the one-lane form only
+    if (lanes == 2 && prec != P_F64 && bs != BLOCK_EO)
+        return launch_sap_pair(op, prec, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
     switch (prec) {
     case P_F64: return launch_p<P_F64, P_F64>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);
     case P_F32: return launch_p<P_F32, P_F32>(op, colour, n_mr, mode, x, b, nrhs, cfg, s, bs);

@@ -118,13 +118,16 @@ def test_single_precision_richardson_form(cfg1, inner):
             assert st_r == 0 and abs(stats["restarts"] + 1 - outer_r) <= 1
 
 
+@pytest.mark.parametrize("block_solver", [1, 2])
 @pytest.mark.parametrize("solver", ["gcr", "bicgstab_sp"])
-def test_solves_with_the_jacobi_smoother(cfg1, solver):
-    """The QWS smoother form (SAP on C^-1 D, Jacobi block solves) as the
-    preconditioner of the FP64 outer solvers: the true residual reaches 1e-10."""
+def test_solves_with_the_jacobi_smoother(cfg1, solver, block_solver):
+    """The smoother variants — the QWS form (SAP on C^-1 D, Jacobi block
+    solves) and SAP with even-odd preconditioned MR — as the preconditioner
+    of the FP64 outer solvers: the true residual reaches 1e-10."""
     for c, seed in ((cfg1, 2001), (Case((16, 16, 16, 32), 0.3, 0.1355, 1.0, 1002, oracle_T=False), 2002)):
         b = synth.source(c.dims, seed)
-        p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10, block_solver=1)
+        p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10,
+                            block_solver=block_solver)
         bd = c.to_dev(b, cs.F64)
         xd = c.lat.new_field(cs.F64).zero_()
         if solver == "gcr":
@@ -134,6 +137,6 @@ def test_solves_with_the_jacobi_smoother(cfg1, solver):
             st, stats = c.op.bicgstab_solve(xd, bd, p)
         x = c.to_host(xd, cs.F64)
         rel = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, b, x) / np.linalg.norm(b)
-        print(f"{c.dims} {solver} jacobi smoother iters={stats['iters']} oracle relres={rel:.3e}")
+        print(f"{c.dims} {solver} block solver {block_solver} iters={stats['iters']} oracle relres={rel:.3e}")
         assert st == 0
         assert rel <= 1e-10 * (1 + 1e-6)

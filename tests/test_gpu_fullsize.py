@@ -2,7 +2,8 @@
 benchmark uses, on outputs the FP64 oracle can evaluate one by one:
 
 * the operator on sampled sites (32^3 x 64);
-* one SAP cycle from zero on sampled blocks of both colours (32^3 x 64): a
+* one SAP cycle from zero on sampled blocks of both colours (32^3 x 64; MR,
+  Jacobi and even-odd block solvers): a
   colour-0 block is the MR solve of its block system with r = b; a colour-1
   block is the MR solve with r = b - D x0, x0 the GPU's colour-0 result;
 * mixed-precision FGCR solves (FP32, FP16, BF16 smoother) at 32^3 x 64 and the
@@ -63,15 +64,18 @@ def test_dslash_full_size_sampled(big):
         assert err <= TOL_D[prec]
 
 
-def _check_sap_cycle_on_sampled_blocks(c, prec, jacobi, tol, nblocks=6):
+def _check_sap_cycle_on_sampled_blocks(c, prec, solver, tol, nblocks=6):
     """One SAP cycle from zero on the GPU, then the oracle's block solve of
     sampled blocks of both colours: a colour-0 block solves its block system
     with r = b, a colour-1 block with r = b - D x0, x0 the GPU's colour-0
-    result.  MR: n_mr = 4 steps on D_BB; Jacobi: 4 steps on (C^-1 D)_BB."""
+    result.  "mr": n_mr = 4 steps on D_BB; "jacobi": 4 steps on (C^-1 D)_BB;
+    "eo": 4 even-odd preconditioned MR steps."""
     dims, V = c.dims, int(np.prod(c.dims))
     xd = c.lat.new_field(prec)
-    if jacobi:
+    if solver == "jacobi":
         c.op.sap_smooth_jacobi(xd, c.to_dev(c.b, prec), prec, n_cy=1, n_jac=4, x0_is_zero=True)
+    elif solver == "eo":
+        c.op.sap_smooth_eo(xd, c.to_dev(c.b, prec), prec, n_cy=1, n_mr=4, x0_is_zero=True)
     else:
         c.op.sap_smooth(xd, c.to_dev(c.b, prec), prec, n_cy=1, n_mr=4, x0_is_zero=True)
     x = c.to_host(xd, prec)
@@ -99,8 +103,10 @@ def _check_sap_cycle_on_sampled_blocks(c, prec, jacobi, tol, nblocks=6):
                 r[sites] = c.b[sites]
             else:
                 r[sites] = c.b[sites] - oracle.apply_D_sites(dims, c.U, c.kappa, c.csw, x0, sites)
-            if jacobi:
+            if solver == "jacobi":
                 ref = oracle.jacobi_block(dims, BDIM, blk, c.U, T, c.kappa, 4, r)[sites]
+            elif solver == "eo":
+                ref = oracle.mr_eo_block(dims, BDIM, blk, c.U, T, c.kappa, 4, r)[sites]
             else:
                 ref = oracle.mr_block(dims, BDIM, blk, c.U, T, c.kappa, 4, r)[sites]
             err = rel(x[sites], ref)
@@ -109,11 +115,15 @@ def _check_sap_cycle_on_sampled_blocks(c, prec, jacobi, tol, nblocks=6):
 
 
 def test_sap_full_size_sampled_blocks(big):
-    _check_sap_cycle_on_sampled_blocks(big, cs.F32, jacobi=False, tol=TOL_SAP_F32)
+    _check_sap_cycle_on_sampled_blocks(big, cs.F32, "mr", tol=TOL_SAP_F32)
 
 
 def test_jacobi_sap_full_size_sampled_blocks(big):
-    _check_sap_cycle_on_sampled_blocks(big, cs.F32, jacobi=True, tol=TOL_SAP_F32, nblocks=3)
+    _check_sap_cycle_on_sampled_blocks(big, cs.F32, "jacobi", tol=TOL_SAP_F32, nblocks=3)
+
+
+def test_eo_sap_full_size_sampled_blocks(big):
+    _check_sap_cycle_on_sampled_blocks(big, cs.F32, "eo", tol=TOL_SAP_F32, nblocks=3)
 
 
 def test_sap_benchmark_lattice_sampled_blocks():
@@ -122,7 +132,7 @@ def test_sap_benchmark_lattice_sampled_blocks():
     cfg = synth.CONFIGS["mixed_16x16x16x32"]
     c = Case(cfg["dims"], cfg["eps"], cfg["kappa"], cfg["csw"], cfg["gauge_seed"], oracle_T=False)
     c.b = synth.source(c.dims, cfg["src_seed"])
-    _check_sap_cycle_on_sampled_blocks(c, cs.F32, jacobi=False, tol=TOL_SAP_F32)
+    _check_sap_cycle_on_sampled_blocks(c, cs.F32, "mr", tol=TOL_SAP_F32)
 
 
 @pytest.mark.parametrize("inner", [cs.F32, cs.F16, cs.BF16])

@@ -113,6 +113,24 @@ def test_clover_inverse_matches_oracle(cfg1):
     assert err <= 1e-13
 
 
+@pytest.mark.parametrize("prec", [cs.F64, cs.F32, cs.F16, cs.BF16])
+def test_eo_sap_matches_oracle(cfg1, noncubic, prec):
+    """SAP with even-odd preconditioned MR block solves against the oracle's;
+    the one-lane kernel runs whatever lane count is asked for."""
+    for c in (cfg1, noncubic):
+        b = synth.source(c.dims, 2021)
+        x0 = 0.3 * synth.source(c.dims, 2022)
+        for zero, n_cy, n_mr in ((True, 2, 4), (False, 1, 3), (True, 1, 0)):
+            ref = oracle.sap_eo(c.dims, BDIM, c.U, c.T, c.kappa, n_cy, n_mr, b, x0=None if zero else x0)
+            for lanes in (1, 2):
+                xd = c.lat.new_field(prec) if zero else c.to_dev(x0, prec)
+                c.op.sap_smooth_eo(xd, c.to_dev(b, prec), prec, n_cy=n_cy, n_mr=n_mr, x0_is_zero=zero,
+                                   cfg=cs.LaunchConfig(1, 0, lanes))
+                err = rel(c.to_host(xd, prec), ref)
+                print(f"dims={c.dims} prec={prec} lanes={lanes} from_zero={zero} n_mr={n_mr} eo sap rel.err={err:.3e}")
+                assert err <= TOL_SAP[prec]
+
+
 @pytest.mark.parametrize("prec,lanes", PREC_LANES)
 def test_jacobi_sap_matches_oracle(cfg1, noncubic, prec, lanes):
     for c in (cfg1, noncubic):
