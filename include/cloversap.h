@@ -209,8 +209,9 @@ int cs_sap_smooth_jacobi(cs_gauge g, cs_clover c, cs_prec prec, void* x, const v
                          int n_cy, int n_jac, int x0_is_zero, int nrhs,
                          const cs_launch_config* cfg, void* stream);
 
-/* SAP whose block solves are even-odd preconditioned MR (the other block
- * solver of the paper's smoother family, Section 2): with the sites of a
+/* SAP whose block solves are even-odd preconditioned MR (the preconditioning
+ * of DD-alphaAMG's solvers, which the paper's Section 3 compares its method
+ * with, applied to SAP's block systems of Section 2): with the sites of a
  * block split by parity (x + y + z + t even / odd), the block system
  * D_BB delta = r_B is reduced to its Schur complement on the even sites,
  *   S = C_e - kappa^2 H_eo C_o^-1 H_oe,   S delta_e = r_e + kappa H_eo C_o^-1 r_o,
