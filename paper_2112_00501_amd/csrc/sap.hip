@@ -165,6 +165,17 @@ __device__ __forceinline__ void clover_apply_by_chirality(const void* m, int blk
     }
 }
 
+// Site of lane t when the lanes are ordered by parity: lanes 0..127 take the
+// even sites of a 4^4 block, 128..255 the odd ones, each in increasing site
+// order.  Every x-row of four sites (row m = ly + 4 lz + 16 lt) holds two
+// sites of each parity, at lx = q and q + 2 with q = (parity of m) xor the
+// wanted parity.
+__device__ __forceinline__ int eo_site(int t) {
+    const int par = t >> 7, i = t & 127, m = i >> 1, j = i & 1;
+    const int q = (((m & 3) + ((m >> 2) & 3) + (m >> 4)) & 1) ^ par;
+    return 4 * m + q + 2 * j;
+}
+
 // Sum of three values over the 256 lanes; every lane receives the same total.
 template <typename R>
 __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
@@ -224,7 +235,10 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
     __shared__ LinkSmem<F32PATH> s_lk;
     __shared__ R s_red[3][4];
 
-    const int l = threadIdx.x;
+    // lane -> site; the even-odd solver puts the block's 128 even sites on
+    // lanes 0..127 and its odd sites on 128..255, so that its parity phases
+    // run on whole waves
+    const int l = BS == BLOCK_EO ? eo_site(threadIdx.x) : (int)threadIdx.x;
     const int ncb = g.nblk / 2;
     const R kappa = (R)kappa_d;
     LdsSpinor<R> ls{s_rho};
@@ -475,7 +489,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 // ---- even-odd preconditioned MR: S = C_e - kappa^2 H_eo C_o^-1 H_oe on
                 // the even sites, then the odd sites by back-substitution.  s_rho
                 // holds r_B; rho0 keeps it in registers for the odd lanes.
-                const bool odd = (((l & 3) + ((l >> 2) & 3) + ((l >> 4) & 3) + (l >> 6)) & 1) != 0;
+                const bool odd = threadIdx.x >= BLOCK_SITES / 2;  // wave-uniform
                 auto hop_lds = [&](cpx<R>* acc) {  // in-block hopping sum from s_rho
 #pragma unroll
                     for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
