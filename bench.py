@@ -183,6 +183,12 @@ def hbm_resident_measurement(cs, synth, torch, reps_d=20, reps_sap=10):
     res["sp_bicgstab_richardson_f32_time_to_1e-10_s"] = round(t, 4)
     res["sp_bicgstab_richardson_f32_iterations"] = it
     res["sp_bicgstab_richardson_f32_status"] = st
+    # FGCR with the even-odd block solver in the smoother
+    t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32,
+                                                                 block_solver=2), 1)
+    res["eo_smoother_f32_time_to_1e-10_s"] = round(t, 4)
+    res["eo_smoother_f32_iterations"] = it
+    res["eo_smoother_f32_status"] = st
     # SAP-FGCR again right before the multigrid runs (median of 3), then MG
     t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32), 3)
     log("[bench] 32^3x64 two-level multigrid")
