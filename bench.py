@@ -196,6 +196,10 @@ def hbm_resident_measurement(cs, synth, torch, reps_d=20, reps_sap=10):
     log("[bench] 32^3x64 two-level multigrid, FP16 coarse matrices and prolongator")
     res["multigrid_f16_storage"] = multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, t, it,
                                                          half=True)
+    del op, bd, xd
+    torch.cuda.empty_cache()
+    log("[bench] 32^3x64 kappa scan towards the critical mass, SAP-FGCR vs MG-FGCR")
+    res["kappa_scan"] = kappa_scan(cs, synth, torch, lat, c, U, b)
     return res
 
 
@@ -280,6 +284,53 @@ def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap
                 note=("FP32 multigrid preconditioner (P, D_c and coarse vectors FP32, coarse reductions "
                       "FP64) inside FP64 flexible GCR(16); aggregates are the 4^4 SAP blocks; the "
                       "kernel times come from an eager pass with HIP events around every launch"))
+
+
+def kappa_scan(cs, synth, torch, lat, c, U, b, kappas=(0.1375, 0.1380, 0.1385)):
+    """SAP-FGCR against MG-FGCR (FP16 copies of D_c and P) on the same gauge
+    field and source at lighter quark masses (kappa closer to critical):
+    the regime where the paper finds the multigrid solver ahead.  Each
+    solve timed after one warm-up solve; a fresh hierarchy per kappa."""
+    dims = c["dims"]
+    prm = cs.MgParams(**MG_PARAMS)
+    prm.coarse_prec = prm.transfer_prec = cs.F16
+    fb = lat.field_bytes(cs.F32)
+    etas = lat.new_field(cs.F32, prm.nv)
+    for i in range(prm.nv):
+        lat.import_field(torch.from_numpy(synth.source(dims, c["mg_eta_seed"] + i)).cuda(), cs.F32,
+                         out=etas[i * fb:(i + 1) * fb])
+    Ud = torch.from_numpy(U).cuda()
+    bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
+    xd = lat.new_field(cs.F64)
+    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, max_iter=3000)
+    rows = []
+    for kappa in kappas:
+        op = cs.Operator(lat, Ud, kappa, c["csw"])
+
+        def timed(solve):
+            xd.zero_()
+            solve()  # warm-up: workspace and graph capture
+            xd.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, stats = solve()
+            torch.cuda.synchronize()
+            st_ = stats[0] if isinstance(stats, list) else stats
+            return time.perf_counter() - t, st_["iters"], st
+        ts, its, sts = timed(lambda: op.gcr_solve(xd, bd, p, allow_fail=True))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m = cs.Multigrid(op, etas, prm)
+        torch.cuda.synchronize()
+        tset = time.perf_counter() - t
+        tm, itm, stm = timed(lambda: m.gcr_solve(xd, bd, p, allow_fail=True))
+        rows.append(dict(kappa=kappa, sap_fgcr_s=round(ts, 4), sap_fgcr_iterations=its, sap_fgcr_status=sts,
+                         mg_setup_s=round(tset, 4), mg_fgcr_s=round(tm, 4), mg_fgcr_iterations=itm,
+                         mg_fgcr_status=stm, solve_speedup=round(ts / tm, 3),
+                         twelve_equations_speedup=round(12 * ts / (tset + 12 * tm), 3)))
+        del m, op
+        torch.cuda.empty_cache()
+    return rows
 
 
 def time_gcr(cs, torch, op, xd, bd, p, reps):
