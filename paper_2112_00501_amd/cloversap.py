@@ -145,6 +145,15 @@ def _stream(stream=None):
     return C.c_void_p(stream.cuda_stream)
 
 
+def _need(t: torch.Tensor, nbytes: int, what: str):
+    """Refuse a device buffer smaller than the kernels will touch (the C ABI
+    takes raw pointers and cannot check)."""
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{what}: buffer of {have} bytes, {nbytes} needed")
+    return t
+
+
 def _ptr(t: torch.Tensor):
     if not t.is_cuda:
         raise ValueError("tensor must be on the GPU")
@@ -183,12 +192,14 @@ class Lattice:
             raise ValueError("canonical field has the wrong size")
         if out is None:
             out = self.new_field(prec, nrhs, canonical.device)
+        _need(out, self.field_bytes(prec, nrhs), "import_field out")
         _check(_lib.cs_field_import(self.handle, prec, _ptr(out), _ptr(canonical), nrhs,
                                     _stream(stream)), "cs_field_import")
         return out
 
     def export_field(self, internal: torch.Tensor, prec: int, nrhs: int = 1,
                      stream=None) -> torch.Tensor:
+        _need(internal, self.field_bytes(prec, nrhs), "export_field internal")
         shape = (self.volume, 4, 3) if nrhs == 1 else (nrhs, self.volume, 4, 3)
         out = torch.empty(shape, dtype=torch.complex128, device=internal.device)
         _check(_lib.cs_field_export(self.handle, prec, _ptr(out), _ptr(internal), nrhs,
@@ -258,18 +269,25 @@ class Operator:
         self.gauge = Gauge(lat, U, stream)
         self.clover = Clover(self.gauge, kappa, csw, stream)
 
+    def _fields(self, ts, prec, nrhs):
+        for t in ts:
+            _need(t, self.lat.field_bytes(prec, nrhs), "field")
+
     def apply_D(self, out, inp, prec, nrhs=1, stream=None):
+        self._fields((out, inp), prec, nrhs)
         _check(_lib.cs_apply_D(self.gauge.handle, self.clover.handle, prec, _ptr(out), _ptr(inp),
                                nrhs, _stream(stream)), "cs_apply_D")
         return out
 
     def apply_D_cfg(self, out, inp, prec, nrhs, cfg: "LaunchConfig", stream=None):
+        self._fields((out, inp), prec, nrhs)
         _check(_lib.cs_apply_D_cfg(self.gauge.handle, self.clover.handle, prec, _ptr(out), _ptr(inp),
                                    nrhs, C.byref(cfg), _stream(stream)), "cs_apply_D_cfg")
         return out
 
     def sap_smooth_cfg(self, x, b, prec, nrhs, cfg: "LaunchConfig", n_cy=2, n_mr=4,
                        x0_is_zero=True, stream=None):
+        self._fields((x, b), prec, nrhs)
         _check(_lib.cs_sap_smooth_cfg(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
                                       int(n_cy), int(n_mr), int(bool(x0_is_zero)), nrhs,
                                       C.byref(cfg), _stream(stream)), "cs_sap_smooth_cfg")
@@ -278,6 +296,7 @@ class Operator:
     def sap_smooth_jacobi(self, x, b, prec, n_cy=2, n_jac=4, x0_is_zero=True, nrhs=1, cfg=None,
                           stream=None):
         """SAP on C^-1 D with n_jac Jacobi steps per block (the QWS smoother form)."""
+        self._fields((x, b), prec, nrhs)
         _check(_lib.cs_sap_smooth_jacobi(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
                                          int(n_cy), int(n_jac), int(bool(x0_is_zero)), nrhs,
                                          None if cfg is None else C.byref(cfg), _stream(stream)),
@@ -286,6 +305,7 @@ class Operator:
 
     def sap_smooth_eo(self, x, b, prec, n_cy=2, n_mr=4, x0_is_zero=True, nrhs=1, cfg=None, stream=None):
         """SAP with even-odd preconditioned MR block solves."""
+        self._fields((x, b), prec, nrhs)
         _check(_lib.cs_sap_smooth_eo(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
                                      int(n_cy), int(n_mr), int(bool(x0_is_zero)), nrhs,
                                      None if cfg is None else C.byref(cfg), _stream(stream)), "cs_sap_smooth_eo")
@@ -299,11 +319,13 @@ class Operator:
         return a, b
 
     def apply_Ddag(self, out, inp, prec, nrhs=1, stream=None):
+        self._fields((out, inp), prec, nrhs)
         _check(_lib.cs_apply_Ddag(self.gauge.handle, self.clover.handle, prec, _ptr(out),
                                   _ptr(inp), nrhs, _stream(stream)), "cs_apply_Ddag")
         return out
 
     def sap_smooth(self, x, b, prec, n_cy=2, n_mr=4, x0_is_zero=True, nrhs=1, stream=None):
+        self._fields((x, b), prec, nrhs)
         _check(_lib.cs_sap_smooth(self.gauge.handle, self.clover.handle, prec, _ptr(x), _ptr(b),
                                   int(n_cy), int(n_mr), int(bool(x0_is_zero)), nrhs,
                                   _stream(stream)), "cs_sap_smooth")
@@ -313,6 +335,7 @@ class Operator:
                   dagger=False):
         """x, b: CS_F64 internal fields.  Solves D x = b (D^dag x = b with
         dagger).  Returns (status, [stats per rhs])."""
+        self._fields((x, b), F64, nrhs)
         p = params.to_c()
         stats = (_Stats * nrhs)()
         fn = _lib.cs_gcr_solve_dag if dagger else _lib.cs_gcr_solve
@@ -329,6 +352,7 @@ class Operator:
         (SAP on the right): flexible BiCGStab with FP64 vectors when
         params.basis_prec is F64, FP32 inner solves inside an FP64 Richardson
         iteration when it is F32.  Returns (status, stats)."""
+        self._fields((x, b), F64, 1)
         p = params.to_c()
         st_ = _Stats()
         st = _lib.cs_bicgstab_solve(self.gauge.handle, self.clover.handle, C.byref(p), _ptr(x), _ptr(b),
@@ -342,6 +366,7 @@ class Operator:
         """Link gradient of L given x = D^-1 b and y = D^-dag dL/dx (CS_F64
         internal fields).  Returns (g_lie [V][4][8] float64 or None,
         grad_U [V][4][3][3] complex128 or None), on the GPU."""
+        self._fields((x, y), F64, 1)
         V = self.lat.volume
         g = torch.empty((V, 4, 8), dtype=torch.float64, device="cuda") if want_lie else None
         G = torch.empty((V, 4, 3, 3), dtype=torch.complex128, device="cuda") if want_grad else None
@@ -375,6 +400,7 @@ class Multigrid:
     def __init__(self, op: "Operator", etas: torch.Tensor, params: MgParams | None = None, stream=None):
         self.op = op
         self.params = params or MgParams()
+        _need(etas, op.lat.field_bytes(F32, self.params.nv), "etas")
         p = self.params.to_c()
         h = C.c_void_p()
         _check(_lib.cs_mg_create(op.gauge.handle, op.clover.handle, C.byref(p), _ptr(etas),
@@ -395,23 +421,34 @@ class Multigrid:
         _check(_lib.cs_mg_export(self.handle, _ptr(P), _ptr(Dc), _stream(stream)), "cs_mg_export")
         return P, Dc
 
+    def _coarse_bytes(self):
+        return self.nblk * self.nc * 8
+
     def restrict(self, r, rc=None, stream=None):
         rc = self.new_coarse() if rc is None else rc
+        _need(r, self.op.lat.field_bytes(F32), "r")
+        _need(rc, self._coarse_bytes(), "rc")
         _check(_lib.cs_mg_restrict(self.handle, _ptr(r), _ptr(rc), _stream(stream)), "cs_mg_restrict")
         return rc
 
     def prolong(self, ec, z=None, stream=None):
         z = self.op.lat.new_field(F32) if z is None else z
+        _need(ec, self._coarse_bytes(), "ec")
+        _need(z, self.op.lat.field_bytes(F32), "z")
         _check(_lib.cs_mg_prolong(self.handle, _ptr(ec), _ptr(z), _stream(stream)), "cs_mg_prolong")
         return z
 
     def coarse_apply(self, x, y=None, stream=None):
         y = self.new_coarse() if y is None else y
+        _need(x, self._coarse_bytes(), "x")
+        _need(y, self._coarse_bytes(), "y")
         _check(_lib.cs_mg_coarse_apply(self.handle, _ptr(x), _ptr(y), _stream(stream)), "cs_mg_coarse_apply")
         return y
 
     def coarse_solve(self, rc, n_iter, tol=0.0, ec=None, stream=None):
         ec = self.new_coarse() if ec is None else ec
+        _need(rc, self._coarse_bytes(), "rc")
+        _need(ec, self._coarse_bytes(), "ec")
         _check(_lib.cs_mg_coarse_solve(self.handle, _ptr(rc), _ptr(ec), int(n_iter), float(tol),
                                        _stream(stream)), "cs_mg_coarse_solve")
         return ec
@@ -419,6 +456,8 @@ class Multigrid:
     def apply(self, r, z=None, stream=None):
         """z = M_MG r (F32 internal fields)."""
         z = self.op.lat.new_field(F32) if z is None else z
+        _need(z, self.op.lat.field_bytes(F32), "z")
+        _need(r, self.op.lat.field_bytes(F32), "r")
         _check(_lib.cs_mg_apply(self.handle, _ptr(z), _ptr(r), _stream(stream)), "cs_mg_apply")
         return z
 
@@ -427,6 +466,8 @@ class Multigrid:
         M_MG.  Returns (status, stats)."""
         p = params.to_c()
         st_ = _Stats()
+        _need(x, self.op.lat.field_bytes(F64), "x")
+        _need(b, self.op.lat.field_bytes(F64), "b")
         st = _lib.cs_gcr_solve_mg(self.op.gauge.handle, self.op.clover.handle, self.handle, C.byref(p),
                                   _ptr(x), _ptr(b), C.byref(st_), _stream(stream))
         if not allow_fail:
@@ -440,6 +481,8 @@ class Multigrid:
         the FP64 Richardson iteration (F32).  Returns (status, stats)."""
         p = params.to_c()
         st_ = _Stats()
+        _need(x, self.op.lat.field_bytes(F64), "x")
+        _need(b, self.op.lat.field_bytes(F64), "b")
         st = _lib.cs_bicgstab_solve_mg(self.op.gauge.handle, self.op.clover.handle, self.handle, C.byref(p),
                                        _ptr(x), _ptr(b), C.byref(st_), _stream(stream))
         if not allow_fail:

@@ -57,3 +57,18 @@ def test_null_handles_rejected_on_host(lib):
     assert lib.cs_sap_smooth(None, None, 0, None, None, 2, 4, 1, 1, None) == -3
     assert lib.cs_gcr_solve(None, None, None, None, None, 1, None, None) == -3
     assert lib.cs_strerror(1) == b"not converged within max_iter"
+
+
+def test_binding_refuses_undersized_buffers():
+    """The C ABI takes raw device pointers and cannot see buffer sizes; the
+    binding checks every field and coarse-vector buffer against the size the
+    kernels will touch before any launch (no GPU needed to see the refusal)."""
+    import torch
+
+    from paper_2112_00501_amd import cloversap as cs
+    lat = cs.Lattice((8, 8, 8, 8))
+    one = torch.empty(lat.field_bytes(cs.F32, 1), dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        lat.export_field(one, cs.F32, 8)
+    with pytest.raises(ValueError):
+        lat.import_field(torch.zeros((2, lat.volume, 4, 3), dtype=torch.complex128), cs.F32, out=one)

@@ -82,9 +82,9 @@ def plain(sys8):
 
 def _export(c, m):
     P, Dc = m.export()
-    Pc = c.lat.export_field(P, cs.F32, NV)
+    Pc = c.lat.export_field(P, cs.F32, m.nv)
     torch.cuda.synchronize()
-    return Pc.cpu().numpy(), dense_from_stencil(Dc, DIMS)
+    return Pc.cpu().numpy().reshape(m.nv, -1, 4, 3), dense_from_stencil(Dc, DIMS)
 
 
 def test_prolongator_matches_oracle(plain):
@@ -342,3 +342,27 @@ def test_fp16_prolongator_transfers(sys8, plain):
         its.append(stats["iters"])
     print(f"MG-FGCR iterations FP32 / FP16 storage: {its}")
     assert its[1] <= its[0] + 2
+
+
+@pytest.mark.parametrize("nv", [1, 3, 32])
+def test_unusual_null_vector_counts(sys8, nv):
+    """The index arithmetic that depends on nc = 2 nv (lane split of the
+    coarse product, the assembly's row rounds, the transfers): one null
+    vector, an odd count, and the largest count (nc = 64, one full wave of
+    rows) against the oracle."""
+    c, _, _ = sys8
+    etas = [synth.source(DIMS, 7500 + i) for i in range(nv)]
+    etas_d = c.lat.import_field(torch.from_numpy(np.stack(etas)).cuda(), cs.F32)
+    m = cs.Multigrid(c.op, etas_d, cs.MgParams(nv=nv, n_cy_setup=2, n_mr=4, n_adapt=0, n_coarse=10,
+                                               n_cy_post=1, tol_coarse=0.0))
+    P_or, Dc_or, aggs, _ = mg.setup(DIMS, BDIM, c.U, c.T, KAPPA, etas, n_cy_setup=2, n_mr=4, n_adapt=0)
+    P, Dc = _export(c, m)
+    rng = np.random.default_rng(7600 + nv)
+    rc = rng.standard_normal(Dc_or.shape[0]) + 1j * rng.standard_normal(Dc_or.shape[0])
+    ec = m.coarse_solve(_coarse(rc.reshape(len(aggs), -1)), 10, 0.0).cpu().numpy().reshape(-1)
+    r = synth.source(DIMS, 7601)
+    z = c.to_host(m.apply(c.to_dev(r, cs.F32)), cs.F32)
+    z_or = mg.mg_apply(DIMS, BDIM, c.U, c.T, KAPPA, P_or, aggs, Dc_or, r, 10, 1, 4, tol_coarse=0.0)
+    e = (rel(P, P_or), rel(Dc, Dc_or), rel(ec, mg.coarse_bicgstab(Dc_or, rc, 10)), rel(z, z_or))
+    print(f"nv={nv}: P %.2e D_c %.2e coarse solve %.2e M_MG %.2e" % e)
+    assert e[0] <= TOL_P and e[1] <= TOL_P and e[2] <= TOL_SOLVE and e[3] <= TOL_SOLVE
