@@ -510,6 +510,9 @@ def main():
                     help="only the 32^3x64 HBM-resident operator, smoother and solve measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB five times (counter calibration)")
+    ap.add_argument("--sap-probe", action="store_true",
+                    help="only 10 FP32 SAP applications and 10 FP32 operator launches on the 16^3x32 "
+                         "benchmark field (a short run for hardware-counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -531,6 +534,21 @@ def main():
 
     from paper_2112_00501_amd import cloversap as cs
     from paper_2112_00501_amd import synth
+
+    if args.sap_probe:
+        cfg = synth.CONFIGS["mixed_16x16x16x32"]
+        dims = cfg["dims"]
+        lat = cs.Lattice(dims)
+        op = cs.Operator(lat, torch.from_numpy(synth.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])).cuda(),
+                         cfg["kappa"], cfg["csw"])
+        b32 = lat.import_field(torch.from_numpy(synth.source(dims, cfg["src_seed"])).cuda(), cs.F32)
+        x32 = lat.new_field(cs.F32)
+        for _ in range(10):
+            op.sap_smooth(x32, b32, cs.F32, n_cy=2, n_mr=4)
+            op.apply_D(x32, b32, cs.F32)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(sap_applications=10, dslash_launches=10, lattice="16x16x16x32")), flush=True)
+        return
 
     if args.hbm_only:
         log("[bench] 32^3x64 HBM-resident measurement")
