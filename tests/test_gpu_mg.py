@@ -211,12 +211,15 @@ def test_mg_gcr_graph_replay_equals_eager(plain):
 def test_mg_argument_errors(sys8, plain):
     c, etas, etas_d = sys8
     m = plain[1]
+    big = c.lat.new_field(cs.F32, 33).zero_()  # large enough that the library itself must refuse nv = 33
     for bad in (dict(nv=0), dict(nv=33), dict(n_cy_setup=0), dict(n_coarse=0), dict(tol_coarse=-1.0)):
         p = _params(0)
         for k, v in bad.items():
             setattr(p, k, v)
         with pytest.raises(cs.CloverSapError):
-            cs.Multigrid(c.op, etas_d, p)
+            cs.Multigrid(c.op, big, p)
+    with pytest.raises(ValueError):  # the binding refuses too small a buffer of random vectors
+        cs.Multigrid(c.op, c.lat.new_field(cs.F32, 1), _params(0))
     b = c.to_dev(synth.source(DIMS, 1), cs.F64)
     x = c.lat.new_field(cs.F64).zero_()
     with pytest.raises(cs.CloverSapError):  # the hierarchy is FP32
@@ -366,3 +369,27 @@ def test_unusual_null_vector_counts(sys8, nv):
     e = (rel(P, P_or), rel(Dc, Dc_or), rel(ec, mg.coarse_bicgstab(Dc_or, rc, 10)), rel(z, z_or))
     print(f"nv={nv}: P %.2e D_c %.2e coarse solve %.2e M_MG %.2e" % e)
     assert e[0] <= TOL_P and e[1] <= TOL_P and e[2] <= TOL_SOLVE and e[3] <= TOL_SOLVE
+
+
+def test_noncubic_lattice_stencil():
+    """8 x 8 x 16 x 8: four aggregates along z, so the +z and -z neighbours
+    are different aggregates while the other directions wrap onto the same
+    one; D_c, the coarse product and M_MG against the oracle."""
+    dims, nv = (8, 8, 16, 8), 4
+    c = Case(dims, 0.3, KAPPA, CSW, 63)
+    etas = [synth.source(dims, 7700 + i) for i in range(nv)]
+    etas_d = c.lat.import_field(torch.from_numpy(np.stack(etas)).cuda(), cs.F32)
+    m = cs.Multigrid(c.op, etas_d, cs.MgParams(nv=nv, n_cy_setup=2, n_mr=4, n_adapt=0, n_coarse=10, n_cy_post=1,
+                                               tol_coarse=0.0))
+    P_or, Dc_or, aggs, _ = mg.setup(dims, BDIM, c.U, c.T, KAPPA, etas, n_cy_setup=2, n_mr=4, n_adapt=0)
+    _, Dc = m.export()
+    Dc = dense_from_stencil(Dc, dims)
+    rng = np.random.default_rng(7800)
+    ec = rng.standard_normal((len(aggs), 2 * nv)) + 1j * rng.standard_normal((len(aggs), 2 * nv))
+    y = m.coarse_apply(_coarse(ec)).cpu().numpy().reshape(-1)
+    r = synth.source(dims, 7801)
+    z = c.to_host(m.apply(c.to_dev(r, cs.F32)), cs.F32)
+    z_or = mg.mg_apply(dims, BDIM, c.U, c.T, KAPPA, P_or, aggs, Dc_or, r, 10, 1, 4, tol_coarse=0.0)
+    e = (rel(Dc, Dc_or), rel(y, Dc_or @ ec.reshape(-1)), rel(z, z_or))
+    print("8x8x16x8: D_c %.2e coarse product %.2e M_MG %.2e" % e)
+    assert e[0] <= TOL_P and e[1] <= TOL_P and e[2] <= TOL_SOLVE
