@@ -6,6 +6,7 @@
 
 #include "blas.hpp"
 #include "fields.hpp"
+#include "wave.hpp"
 
 namespace cs {
 
@@ -32,12 +33,6 @@ __device__ __forceinline__ void st64(void* base, int nblk, int blk, int l, const
 #pragma unroll
     for (int k = 0; k < 12; ++k) t[k] = {(RS)c[k].re, (RS)c[k].im};
     SpinorIO<P>::store(base, nblk, blk, l, t);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
 }
 
 __device__ __forceinline__ bool skip(const int* active) { return active && !active[blockIdx.y]; }

@@ -227,6 +227,20 @@ struct cpx {
     R re, im;
 };
 
+// A complex value held in LDS, aligned to its full size: a wave's accesses
+// are then single 8- or 16-byte LDS operations over consecutive addresses
+// rather than two 4- or 8-byte halves at twice the stride, which map two
+// lanes onto one bank.
+template <typename R>
+struct alignas(2 * sizeof(R)) lds_cpx {
+    R re, im;
+    __device__ __forceinline__ void set(const cpx<R>& v) {
+        re = v.re;
+        im = v.im;
+    }
+    __device__ __forceinline__ cpx<R> get() const { return {re, im}; }
+};
+
 template <typename R>
 __device__ __forceinline__ cpx<R> cmake(R a, R b) { return cpx<R>{a, b}; }
 template <typename R>

@@ -60,13 +60,13 @@ __global__ CS_DSLASH_BOUNDS void k_dslash(Geom g, const void* __restrict__ links
 // links of neighbours outside the block come from HBM (cache).  With
 // gridDim.x < nitems the workgroups stride over the items (persistent).
 template <bool ON>
-struct DLinkSmem { cpx<float> u[4][6][BLOCK_SITES]; };
+struct DLinkSmem { lds_cpx<float> u[4][6][BLOCK_SITES]; };
 template <>
-struct DLinkSmem<false> { cpx<double> u[4][6][BLOCK_SITES]; };
+struct DLinkSmem<false> { lds_cpx<double> u[4][6][BLOCK_SITES]; };
 
 template <typename RS, int PLINK>
 struct MixedLinks {
-    const cpx<RS> (*sm)[6][BLOCK_SITES];
+    const lds_cpx<RS> (*sm)[6][BLOCK_SITES];
     const void* base;
     template <typename R>
     __device__ __forceinline__ void load(int blk, int l, int mu, bool inside, cpx<R>* u) const {
@@ -88,7 +88,7 @@ __global__ CS_DSLASH_BOUNDS void k_dslash_tiled(Geom g, const void* __restrict__
                                                 int nitems) {
     using R = typename Arith<PIN>::R;
     using RS = typename LinkIO<PLINK>::R;
-    __shared__ cpx<RS> s_lk[4][6][BLOCK_SITES];
+    __shared__ lds_cpx<RS> s_lk[4][6][BLOCK_SITES];
     const int l = threadIdx.x;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int w = xcd_remap(item, nitems);
@@ -101,7 +101,7 @@ __global__ CS_DSLASH_BOUNDS void k_dslash_tiled(Geom g, const void* __restrict__
             cpx<RS> u[6];
             LinkIO<PLINK>::load6(links, blk, l, mu, u);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) s_lk[mu][k][l] = u[k];
+            for (int k = 0; k < 6; ++k) s_lk[mu][k][l].set(u[k]);
         }
         R cl[72];
         CloverIO<R>::load(clover, blk, l, cl);

@@ -12,6 +12,7 @@
 // faces stay separate, so the stencil is exact on any lattice).
 #include "blas.hpp"
 #include "dslash_core.hpp"
+#include "wave.hpp"
 #include "mg.hpp"
 
 namespace cs {
@@ -20,41 +21,13 @@ namespace {
 
 constexpr int TPB = BLOCK_SITES;
 
-// Sum over the 64 lanes of a wave, the same value in every lane: DPP steps
-// within each row of 16 lanes (swap neighbours, swap pairs, mirror halves of
-// 8, mirror the row), then the four row totals read from lanes 0, 16, 32, 48
-// and added in a fixed order.
-__device__ __forceinline__ float dpp_add(float v, int ctrl_sel) {
-    int x = __float_as_int(v), y;
-    switch (ctrl_sel) {
-    case 0: y = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
-    case 1: y = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
-    case 2: y = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
-    default: y = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false); break; // row_mirror
-    }
-    return v + __int_as_float(y);
-}
-
-__device__ __forceinline__ float wsum(float v) {
-    v = dpp_add(v, 0);
-    v = dpp_add(v, 1);
-    v = dpp_add(v, 2);
-    v = dpp_add(v, 3);
-    const int x = __float_as_int(v);
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(x, 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(x, 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(x, 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(x, 48));
-    return (r0 + r1) + (r2 + r3);
-}
-
 // Sum N values over the workgroup; afterwards out[k] (LDS) holds total k.
 template <int N>
 __device__ __forceinline__ void block_sum(const float* v, float (*red)[N], float* out) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float t[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) t[k] = wsum(v[k]);
+    for (int k = 0; k < N; ++k) t[k] = wave_sum(v[k]);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < N; ++k) red[wave][k] = t[k];
@@ -132,12 +105,12 @@ __device__ __forceinline__ void column_site(const char* P, size_t fs, int nv, in
 }
 
 struct LdsColumn {  // in-block neighbours for the self term
-    const cpx<float> (*s)[BLOCK_SITES];
+    const lds_cpx<float> (*s)[BLOCK_SITES];
     __device__ __forceinline__ bool want(bool inside) const { return inside; }
     template <typename R>
     __device__ __forceinline__ void load_nb(int, int l, bool, cpx<R>* c) const {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) c[k] = s[k][l];
+        for (int k = 0; k < 12; ++k) c[k] = s[k][l].get();
     }
 };
 
@@ -191,7 +164,7 @@ __global__ __launch_bounds__(TPB) void k_mg_assemble(Geom g, const void* links, 
                                                      const char* P, size_t fs, int nv, float2* Dc) {
     const int blk = blockIdx.x, l = threadIdx.x, nc = 2 * nv;
     const BlockPos p = block_pos(g, blk);
-    __shared__ cpx<float> s[12][BLOCK_SITES];
+    __shared__ lds_cpx<float> s[12][BLOCK_SITES];
     __shared__ float red[BLOCK_SITES * ASM_LD];
     __shared__ float part[ASM_VALS][4];
     for (int col = 0; col < nc; ++col) {
@@ -201,7 +174,7 @@ __global__ __launch_bounds__(TPB) void k_mg_assemble(Geom g, const void* links, 
             column_site(P, fs, nv, col, g.nblk, blk, l, c);
             __syncthreads();  // the previous column's readers of s are done
 #pragma unroll
-            for (int k = 0; k < 12; ++k) s[k][l] = c[k];
+            for (int k = 0; k < 12; ++k) s[k][l].set(c[k]);
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
@@ -399,13 +372,8 @@ __device__ __forceinline__ float2 cmv_rows(const void* __restrict__ Dc, int a, i
 // Workgroup sums of a and b (FP64) from lanes of wave 0 into partials[2 wg], [2 wg + 1]
 __device__ __forceinline__ void wave0_partials(double2 a, double2 b, double2* partials) {
     if (threadIdx.x >= 64) return;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a.x += __shfl_xor(a.x, off);
-        a.y += __shfl_xor(a.y, off);
-        b.x += __shfl_xor(b.x, off);
-        b.y += __shfl_xor(b.y, off);
-    }
+    a = make_double2(wave_sum(a.x), wave_sum(a.y));
+    b = make_double2(wave_sum(b.x), wave_sum(b.y));
     if (threadIdx.x == 0) {
         partials[(size_t)blockIdx.x * 2] = a;
         partials[(size_t)blockIdx.x * 2 + 1] = b;
@@ -598,12 +566,8 @@ __global__ __launch_bounds__(1024) void k_cb_f3(const double2* partials, int nwg
 __device__ __forceinline__ void chunk_partials(double2 a, double b, double2* partials) {
     __shared__ double red[3][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a.x += __shfl_xor(a.x, off);
-        a.y += __shfl_xor(a.y, off);
-        b += __shfl_xor(b, off);
-    }
+    a = make_double2(wave_sum(a.x), wave_sum(a.y));
+    b = wave_sum(b);
     if (lane == 0) {
         red[0][wave] = a.x;
         red[1][wave] = a.y;

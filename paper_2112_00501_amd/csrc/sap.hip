@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "dslash_core.hpp"
+#include "wave.hpp"
 
 namespace cs {
 
@@ -24,13 +25,13 @@ namespace {
 
 // Rows 0 and 1 of the block's links, kept in LDS in float for the MR loop.
 template <bool ON>
-struct LinkSmem { cpx<float> u[4][6][BLOCK_SITES]; };
+struct LinkSmem { lds_cpx<float> u[4][6][BLOCK_SITES]; };
 template <>
-struct LinkSmem<false> { cpx<float> u[1][1][1]; };
+struct LinkSmem<false> { lds_cpx<float> u[1][1][1]; };
 
 template <typename R>
 struct LdsSpinor {  // in-block neighbours of the Dirichlet operator
-    cpx<R> (*s)[BLOCK_SITES];
+    lds_cpx<R> (*s)[BLOCK_SITES];
     __device__ __forceinline__ bool want(bool inside) const { return inside; }
     template <typename RR>
     __device__ __forceinline__ void load_nb(int, int l, bool, cpx<RR>* c) const {
@@ -179,12 +180,9 @@ __device__ __forceinline__ int eo_site(int t) {
 // Sum of three values over the 256 lanes; every lane receives the same total.
 template <typename R>
 __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-        c += __shfl_xor(c, off);
-    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[0][wave] = a;
@@ -227,11 +225,11 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                                               int tile, int nitems) {
     using R = typename Arith<P>::R;
     constexpr bool F32PATH = std::is_same<R, float>::value;
-    __shared__ cpx<R> s_rho[12][BLOCK_SITES];
+    __shared__ lds_cpx<R> s_rho[12][BLOCK_SITES];
     // FP64 Jacobi keeps the block residual in LDS instead of registers (the
     // FP64 kernel runs one workgroup per compute unit either way)
     constexpr bool RHO_LDS = BS == BLOCK_JACOBI && !F32PATH;
-    __shared__ cpx<R> s_rho0[RHO_LDS ? 12 : 1][RHO_LDS ? BLOCK_SITES : 1];
+    __shared__ lds_cpx<R> s_rho0[RHO_LDS ? 12 : 1][RHO_LDS ? BLOCK_SITES : 1];
     __shared__ LinkSmem<F32PATH> s_lk;
     __shared__ R s_red[3][4];
 
@@ -321,7 +319,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 }
                 __syncthreads();  // every lane has read x from rho
 #pragma unroll
-                for (int k = 0; k < 12; ++k) s_rho[k][l] = rho0[k];
+                for (int k = 0; k < 12; ++k) s_rho[k][l].set(rho0[k]);
             } else if constexpr (BS != BLOCK_JACOBI) {
                 cpx<R> acc[12];
 #pragma unroll
@@ -356,7 +354,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 for (int k = 0; k < 12; ++k) rho0[k] = {(R)t[k].re - acc[k].re, (R)t[k].im - acc[k].im};
                 __syncthreads();  // the previous right-hand side's readers of rho are done
 #pragma unroll
-                for (int k = 0; k < 12; ++k) s_rho[k][l] = rho0[k];
+                for (int k = 0; k < 12; ++k) s_rho[k][l].set(rho0[k]);
             } else {
                 // Jacobi: rho = C^-1 (b + kappa hop) - x
                 cpx<R> acc[12];
@@ -389,7 +387,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 }
                 __syncthreads();  // the previous right-hand side's readers of rho are done
 #pragma unroll
-                for (int k = 0; k < 12; ++k) s_rho[k][l] = rho0[k];
+                for (int k = 0; k < 12; ++k) s_rho[k][l].set(rho0[k]);
             }
 
             cpx<R> delta[12];
@@ -403,7 +401,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 }
                 if constexpr (RHO_LDS) {
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) s_rho0[k][l] = rho0[k];
+                    for (int k = 0; k < 12; ++k) s_rho0[k][l].set(rho0[k]);
                 }
                 for (int it = 1; it < n_mr; ++it) {
                     __syncthreads();  // delta of every site is in LDS
@@ -421,12 +419,12 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                     }
 #pragma unroll
                     for (int k = 0; k < 12; ++k) {
-                        const cpx<R> r0 = RHO_LDS ? s_rho0[k][l] : rho0[k];
+                        const cpx<R> r0 = RHO_LDS ? s_rho0[k][l].get() : rho0[k];
                         delta[k] = {r0.re + kappa * delta[k].re, r0.im + kappa * delta[k].im};
                     }
                     __syncthreads();  // every lane has read the previous delta
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) s_rho[k][l] = delta[k];
+                    for (int k = 0; k < 12; ++k) s_rho[k][l].set(delta[k]);
                 }
             }
             // ---- MR on the Dirichlet block operator; rho lives in LDS only
@@ -481,7 +479,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                     t.re = fma(alpha.im, q[k].im, t.re);
                     t.im = fma(-alpha.re, q[k].im, t.im);
                     t.im = fma(-alpha.im, q[k].re, t.im);
-                    s_rho[k][l] = t;
+                    s_rho[k][l].set(t);
                 }
             }
 
@@ -505,7 +503,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                     cpx<R> t[12];
                     clover_apply_by_chirality<R>(cinv, blk, l, rho0, t);
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) s_rho[k][l] = t[k];
+                    for (int k = 0; k < 12; ++k) s_rho[k][l].set(t[k]);
                 }
                 __syncthreads();
                 cpx<R> rr[12];
@@ -518,7 +516,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 __syncthreads();  // every even lane has read the odd entries
                 if (!odd) {
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) s_rho[k][l] = rr[k];
+                    for (int k = 0; k < 12; ++k) s_rho[k][l].set(rr[k]);
                 }
                 for (int it = 0; it < n_mr; ++it) {
                     __syncthreads();  // the even residual is in LDS
@@ -567,7 +565,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                             t.re = fma(alpha.im, q[k].im, t.re);
                             t.im = fma(-alpha.re, q[k].im, t.im);
                             t.im = fma(-alpha.im, q[k].re, t.im);
-                            s_rho[k][l] = t;
+                            s_rho[k][l].set(t);
                         }
                     }
                 }
@@ -575,7 +573,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                 __syncthreads();
                 if (!odd) {
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) s_rho[k][l] = delta[k];
+                    for (int k = 0; k < 12; ++k) s_rho[k][l].set(delta[k]);
                 }
                 __syncthreads();
                 if (odd) {

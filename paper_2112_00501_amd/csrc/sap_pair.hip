@@ -14,6 +14,7 @@
 //     6x6 block of the clover term (the term is block diagonal in chirality),
 //     and holds that half of rho, q and delta.
 #include "dslash_core.hpp"
+#include "wave.hpp"
 
 namespace cs {
 
@@ -37,8 +38,8 @@ __device__ __forceinline__ PairLane pair_lane() {
 }
 
 struct PairSmem {
-    cpx<float> rho[12][BLOCK_SITES];    // rho (or the staged x) of the whole block
-    cpx<float> u[4][6][BLOCK_SITES];    // rows 0, 1 of the block's links
+    lds_cpx<float> rho[12][BLOCK_SITES];  // rho (or the staged x) of the whole block
+    lds_cpx<float> u[4][6][BLOCK_SITES];  // rows 0, 1 of the block's links
     float red[3][PAIR_TPB / 64];
 };
 
@@ -118,10 +119,10 @@ __device__ __forceinline__ void pair_hop_lds(const Geom& g, const BlockPos& p, c
     if (!in) return;
     cpx<float> psi[12], u[9];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = sm.rho[k][nl];
+    for (int k = 0; k < 12; ++k) psi[k] = sm.rho[k][nl].get();
     const int li = q.h ? nl : q.l;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) u[k] = sm.u[MU][k][li];
+    for (int k = 0; k < 6; ++k) u[k] = sm.u[MU][k][li].get();
     su3_row2(u);
     pair_hop<MU>(u, q.h, q.sg, psi, acc);
 }
@@ -163,23 +164,18 @@ __device__ __forceinline__ void pair_faces(const Geom& g, const BlockPos& p, con
 
 // The hop sum of the site: own chirality half of (this lane's sum + the
 // partner's sum).  Every lane of the wave must call it.
-__device__ __forceinline__ void pair_combine(const cpx<float>* acc, int h, cpx<float>* mine) {
+__device__ __forceinline__ void pair_combine(const cpx<float>* acc, cpx<float>* mine) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        const cpx<float> send = h ? acc[i] : acc[6 + i];
-        const cpx<float> keep = h ? acc[6 + i] : acc[i];
-        const cpx<float> recv = {__shfl_xor(send.re, 32), __shfl_xor(send.im, 32)};
-        mine[i] = keep + recv;
-    }
+    for (int i = 0; i < 6; ++i)
+        mine[i] = {pair_split_sum(acc[i].re, acc[6 + i].re), pair_split_sum(acc[i].im, acc[6 + i].im)};
 }
 
 // Full spinor of the site from the two halves.  Every lane of the wave must call it.
-__device__ __forceinline__ void pair_gather(const cpx<float>* half, int h, cpx<float>* full) {
+__device__ __forceinline__ void pair_gather(const cpx<float>* half, cpx<float>* full) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        const cpx<float> other = {__shfl_xor(half[i].re, 32), __shfl_xor(half[i].im, 32)};
-        full[i] = h ? other : half[i];
-        full[6 + i] = h ? half[i] : other;
+        pair_share(half[i].re, full[i].re, full[6 + i].re);
+        pair_share(half[i].im, full[i].im, full[6 + i].im);
     }
 }
 
@@ -224,7 +220,7 @@ __device__ __forceinline__ void store_update(void* base, int nblk, int blk, cons
     } else {
         // the per-site scale covers all 24 reals: lane half 0 writes the site
         cpx<float> full[12];
-        pair_gather(delta, q.h, full);
+        pair_gather(delta, full);
         if (q.h == 0) {
             if (add) {
                 cpx<float> t[12];
@@ -267,12 +263,9 @@ __device__ __forceinline__ void clover_apply_half(const float* d, const cpx<floa
 
 // Sum of three values over the workgroup; every lane receives the same total.
 __device__ __forceinline__ void pair_sum3(float& a, float& b, float& c, float (*red)[PAIR_TPB / 64]) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-        c += __shfl_xor(c, off);
-    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[0][wave] = a;
@@ -312,7 +305,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
             cpx<typename LinkIO<PLINK>::R> u[6];
             LinkIO<PLINK>::load6(links, blk, q.l, mu, u);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) sm.u[mu][k][q.l] = {(float)u[k].re, (float)u[k].im};
+            for (int k = 0; k < 6; ++k) sm.u[mu][k][q.l].set({(float)u[k].re, (float)u[k].im});
         }
         float cl[36];
         load_clover_half(clover, blk, q, cl);
@@ -339,7 +332,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                         load_half<P>(xr, g.nblk, blk, q, xh);
                         __syncthreads();  // the previous right-hand side's readers of rho are done
 #pragma unroll
-                        for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l] = xh[i];
+                        for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l].set(xh[i]);
                         __syncthreads();
                         pair_hop_lds<0>(g, p, q, sm, acc);
                         pair_hop_lds<1>(g, p, q, sm, acc);
@@ -349,7 +342,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                     }
                     pair_faces<0, 1, P, PLINK>(g, p, q, xr, links, acc);
                     pair_faces<2, 3, P, PLINK>(g, p, q, xr, links, acc);
-                    pair_combine(acc, q.h, hop);
+                    pair_combine(acc, hop);
                 }
                 cpx<float> bh[6];
                 load_half<P>(br, g.nblk, blk, q, bh);
@@ -364,12 +357,12 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                     clover_apply_half(cl, bh, rho);
                     if (mode == 0) {
 #pragma unroll
-                        for (int i = 0; i < 6; ++i) rho[i] = rho[i] - sm.rho[6 * q.h + i][q.l];
+                        for (int i = 0; i < 6; ++i) rho[i] = rho[i] - sm.rho[6 * q.h + i][q.l].get();
                     }
                 }
                 __syncthreads();  // every lane has read x (or the previous rho) from LDS
 #pragma unroll
-                for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l] = rho[i];
+                for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l].set(rho[i]);
             }
 
             cpx<float> delta[6];
@@ -391,14 +384,14 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                     pair_hop_lds<2>(g, p, q, sm, acc);
                     pair_hop_lds<3>(g, p, q, sm, acc);
                     cpx<float> hop[6];
-                    pair_combine(acc, q.h, hop);
+                    pair_combine(acc, hop);
                     clover_apply_half(cl, hop, delta);
 #pragma unroll
                     for (int i = 0; i < 6; ++i)
                         delta[i] = {rho[i].re + kappa * delta[i].re, rho[i].im + kappa * delta[i].im};
                     __syncthreads();  // every lane has read the previous delta
 #pragma unroll
-                    for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l] = delta[i];
+                    for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l].set(delta[i]);
                 }
             }
             // ---- MR on the Dirichlet block operator
@@ -414,7 +407,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                     pair_hop_lds<2>(g, p, q, sm, acc);
                     pair_hop_lds<3>(g, p, q, sm, acc);
                     cpx<float> hop[6];
-                    pair_combine(acc, q.h, hop);
+                    pair_combine(acc, hop);
                     clover_apply_half(cl, rho, qv);
 #pragma unroll
                     for (int i = 0; i < 6; ++i)
@@ -444,7 +437,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                     t.im = fmaf(-alpha.re, qv[i].im, t.im);
                     t.im = fmaf(-alpha.im, qv[i].re, t.im);
                     rho[i] = t;
-                    sm.rho[6 * q.h + i][q.l] = t;
+                    sm.rho[6 * q.h + i][q.l].set(t);
                 }
             }
 
