@@ -37,9 +37,17 @@ __device__ __forceinline__ PairLane pair_lane() {
     return q;
 }
 
+// LDS of one block.  rho rows have RHO_STRIDE sites so that row offsets stay
+// multiples of 512 bytes (one immediate offset pairs two rows); site
+// ZERO_SITE of every row holds zero and is never written, so a lane whose
+// neighbour lies outside the block reads zeros instead of branching.  The
+// links are kept whole (all three rows), rebuilt once when staged.
+constexpr int RHO_STRIDE = BLOCK_SITES + 64;
+constexpr int ZERO_SITE = BLOCK_SITES;
+
 struct PairSmem {
-    lds_cpx<float> rho[12][BLOCK_SITES];  // rho (or the staged x) of the whole block
-    lds_cpx<float> u[4][6][BLOCK_SITES];  // rows 0, 1 of the block's links
+    lds_cpx<float> rho[12][RHO_STRIDE];      // rho (or the staged x) of the whole block
+    lds_cpx<float> u[4][9][BLOCK_SITES];     // the block's links
     float red[3][PAIR_TPB / 64];
 };
 
@@ -63,7 +71,8 @@ __device__ __forceinline__ void pair_neighbour(const Geom& g, const BlockPos& p,
 // [[0, A],[A^dag, 0]] with A_x = -i s1, A_y = -i s2, A_z = -i s3, A_t = 1:
 // the upper half of (1 + S gamma_mu) psi is hh = psi_up + S A psi_lo and the
 // lower half is S A^dag hh.
-template <int MU>
+// FIRST: acc holds nothing yet and is set rather than added to.
+template <int MU, bool FIRST = false>
 __device__ __forceinline__ void pair_hop(const cpx<float>* u, int h, float sg, const cpx<float>* psi,
                                          cpx<float>* acc) {
     cpx<float> hh[6];
@@ -96,35 +105,52 @@ __device__ __forceinline__ void pair_hop(const cpx<float>* u, int h, float sg, c
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const cpx<float> v0 = v[a], v1 = v[3 + a];
-        acc[a] = acc[a] + v0;
-        acc[3 + a] = acc[3 + a] + v1;
         cpx<float> b0, b1;  // A^dag v
         if (MU == 0) { b0 = mul_i(v1); b1 = mul_i(v0); }
         else if (MU == 1) { b0 = v1; b1 = {-v0.re, -v0.im}; }
         else if (MU == 2) { b0 = mul_i(v0); b1 = mul_mi(v1); }
         else { b0 = v0; b1 = v1; }
-        acc[6 + a] = {fmaf(sg, b0.re, acc[6 + a].re), fmaf(sg, b0.im, acc[6 + a].im)};
-        acc[9 + a] = {fmaf(sg, b1.re, acc[9 + a].re), fmaf(sg, b1.im, acc[9 + a].im)};
+        if constexpr (FIRST) {
+            acc[a] = v0;
+            acc[3 + a] = v1;
+            acc[6 + a] = {sg * b0.re, sg * b0.im};
+            acc[9 + a] = {sg * b1.re, sg * b1.im};
+        } else {
+            acc[a] = acc[a] + v0;
+            acc[3 + a] = acc[3 + a] + v1;
+            acc[6 + a] = {fmaf(sg, b0.re, acc[6 + a].re), fmaf(sg, b0.im, acc[6 + a].im)};
+            acc[9 + a] = {fmaf(sg, b1.re, acc[9 + a].re), fmaf(sg, b1.im, acc[9 + a].im)};
+        }
     }
 }
 
 // Hop in direction MU inside the block: psi from LDS, the link from LDS
-// (U_mu(x) for forward lanes, U_mu(x - mu) at the neighbour for backward ones).
-template <int MU>
+// (U_mu(x) for forward lanes, U_mu(x - mu) at the neighbour for backward
+// ones).  A lane whose neighbour is outside the block reads the zero site and
+// adds nothing; no lane branches.
+template <int MU, bool FIRST = false>
 __device__ __forceinline__ void pair_hop_lds(const Geom& g, const BlockPos& p, const PairLane& q,
                                              const PairSmem& sm, cpx<float>* acc) {
     int nb, nl;
     bool in;
     pair_neighbour<MU>(g, p, q, &nb, &nl, &in);
-    if (!in) return;
+    const int sl = in ? nl : ZERO_SITE;
     cpx<float> psi[12], u[9];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = sm.rho[k][nl].get();
+    for (int k = 0; k < 12; ++k) psi[k] = sm.rho[k][sl].get();
     const int li = q.h ? nl : q.l;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) u[k] = sm.u[MU][k][li].get();
-    su3_row2(u);
-    pair_hop<MU>(u, q.h, q.sg, psi, acc);
+    for (int k = 0; k < 9; ++k) u[k] = sm.u[MU][k][li].get();
+    pair_hop<MU, FIRST>(u, q.h, q.sg, psi, acc);
+}
+
+// The four hops inside the block, acc set by the first.
+__device__ __forceinline__ void pair_hops_lds(const Geom& g, const BlockPos& p, const PairLane& q,
+                                              const PairSmem& sm, cpx<float>* acc) {
+    pair_hop_lds<0, true>(g, p, q, sm, acc);
+    pair_hop_lds<1>(g, p, q, sm, acc);
+    pair_hop_lds<2>(g, p, q, sm, acc);
+    pair_hop_lds<3>(g, p, q, sm, acc);
 }
 
 // Hops in directions MA and MB that leave the block, from global memory (the
@@ -291,6 +317,8 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
     const int ncb = g.nblk / 2;
     const float kappa = (float)kappa_d;
 
+    if (threadIdx.x < 12) sm.rho[threadIdx.x][ZERO_SITE].set({0.f, 0.f});  // read after the barrier below
+
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int w = xcd_remap(item, nitems);
         const int blk = colour_block(g, colour, w % ncb);
@@ -302,10 +330,14 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
 #pragma unroll
         for (int j = 0; j < 2; ++j) {  // lane half h stages directions 2h and 2h + 1
             const int mu = 2 * q.h + j;
-            cpx<typename LinkIO<PLINK>::R> u[6];
-            LinkIO<PLINK>::load6(links, blk, q.l, mu, u);
+            cpx<typename LinkIO<PLINK>::R> w[6];
+            LinkIO<PLINK>::load6(links, blk, q.l, mu, w);
+            cpx<float> u[9];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) sm.u[mu][k][q.l].set({(float)u[k].re, (float)u[k].im});
+            for (int k = 0; k < 6; ++k) u[k] = {(float)w[k].re, (float)w[k].im};
+            su3_row2(u);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) sm.u[mu][k][q.l].set(u[k]);
         }
         float cl[36];
         load_clover_half(clover, blk, q, cl);
@@ -334,10 +366,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
 #pragma unroll
                         for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l].set(xh[i]);
                         __syncthreads();
-                        pair_hop_lds<0>(g, p, q, sm, acc);
-                        pair_hop_lds<1>(g, p, q, sm, acc);
-                        pair_hop_lds<2>(g, p, q, sm, acc);
-                        pair_hop_lds<3>(g, p, q, sm, acc);
+                        pair_hops_lds(g, p, q, sm, acc);
                         if constexpr (BS == BLOCK_MR) clover_apply_half(cl, xh, cx);
                     }
                     pair_faces<0, 1, P, PLINK>(g, p, q, xr, links, acc);
@@ -377,12 +406,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                 for (int it = 1; it < n_mr; ++it) {
                     __syncthreads();  // delta of the whole block is in LDS
                     cpx<float> acc[12];
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
-                    pair_hop_lds<0>(g, p, q, sm, acc);
-                    pair_hop_lds<1>(g, p, q, sm, acc);
-                    pair_hop_lds<2>(g, p, q, sm, acc);
-                    pair_hop_lds<3>(g, p, q, sm, acc);
+                    pair_hops_lds(g, p, q, sm, acc);
                     cpx<float> hop[6];
                     pair_combine(acc, hop);
                     clover_apply_half(cl, hop, delta);
@@ -400,12 +424,7 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
                 cpx<float> qv[6];
                 {
                     cpx<float> acc[12];
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
-                    pair_hop_lds<0>(g, p, q, sm, acc);
-                    pair_hop_lds<1>(g, p, q, sm, acc);
-                    pair_hop_lds<2>(g, p, q, sm, acc);
-                    pair_hop_lds<3>(g, p, q, sm, acc);
+                    pair_hops_lds(g, p, q, sm, acc);
                     cpx<float> hop[6];
                     pair_combine(acc, hop);
                     clover_apply_half(cl, rho, qv);
