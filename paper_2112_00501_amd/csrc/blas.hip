@@ -222,52 +222,91 @@ __global__ __launch_bounds__(TPB) void k_norm2_f64(Geom g, const void* v, size_t
     wg_reduce_store<1>(acc, 1, partials, NORM_SLOT);
 }
 
-// partial <W_{j0 + j}, W_k> for j < n (n <= MULTIDOT_CHUNK); W stored [k][rhs]
+// Basis vectors whose loads are issued together: enough to keep several
+// loads of a lane in flight, few enough to stay in registers.
+template <int P>
+constexpr int load_group() {
+    return sizeof(typename SpinorIO<P>::R) == 8 ? 2 : 4;
+}
+
+template <typename R>
+__device__ __forceinline__ cpx<double> to64(cpx<R> a) {
+    return {(double)a.re, (double)a.im};
+}
+
+// partial <W_{j0 + j}, W_k> for j < n (n <= MULTIDOT_CHUNK); W stored [k][rhs].
+// The vectors are read in groups whose loads are all issued before any is
+// used; inside the last group, indices past n repeat vector n - 1 and their
+// sums are never stored.
 template <int PB>
 __global__ __launch_bounds__(TPB) void k_multidot(Geom g, const char* W, size_t ws, int nrhs, int j0, int n,
                                                   int k, const int* active, double2* partials) {
     if (skip(active)) return;
+    using RS = typename SpinorIO<PB>::R;
+    constexpr int G = load_group<PB>();
     const int r = blockIdx.y;
+    const char* base = W + (size_t)r * ws;
+    const size_t vs = (size_t)nrhs * ws;  // from one basis vector to the next
     cpx<double> acc[MULTIDOT_CHUNK];
 #pragma unroll
     for (int j = 0; j < MULTIDOT_CHUNK; ++j) acc[j] = {0.0, 0.0};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
-        cpx<double> v[12];
-        ld64<PB>(W + ((size_t)k * nrhs + r) * ws, g.nblk, blk, threadIdx.x, v);
+        cpx<RS> v[12];
+        SpinorIO<PB>::load(base + (size_t)k * vs, g.nblk, blk, threadIdx.x, v);
 #pragma unroll
-        for (int j = 0; j < MULTIDOT_CHUNK; ++j) {
-            if (j < n) {
-                cpx<double> w[12];
-                ld64<PB>(W + ((size_t)(j0 + j) * nrhs + r) * ws, g.nblk, blk, threadIdx.x, w);
+        for (int jb = 0; jb < MULTIDOT_CHUNK; jb += G) {
+            if (jb < n) {
+                cpx<RS> t[G][12];
 #pragma unroll
-                for (int c = 0; c < 12; ++c) cmac_conj(acc[j], w[c], v[c]);
+                for (int q = 0; q < G; ++q) {
+                    const int j = jb + q < n ? jb + q : n - 1;
+                    SpinorIO<PB>::load(base + (size_t)(j0 + j) * vs, g.nblk, blk, threadIdx.x, t[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < G; ++q)
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) cmac_conj(acc[jb + q], to64(t[q][c]), to64(v[c]));
             }
         }
     }
     wg_reduce_store<MULTIDOT_CHUNK>(acc, n, partials);
 }
 
-// W_k -= sum_{j<k} coef_j W_j; partials |W_k|^2 and <W_k, r>
+// W_k -= sum_{j<k} coef_j W_j (in increasing j, loads issued a group at a
+// time); partials |W_k|^2 and <W_k, r>
 template <int PB>
 __global__ __launch_bounds__(TPB) void k_ortho(Geom g, char* W, size_t ws, int nrhs, int k, const void* rv,
                                                size_t rs, const GcrScalars* sc, const int* active,
                                                double2* partials) {
     if (skip(active)) return;
+    using RS = typename SpinorIO<PB>::R;
+    constexpr int G = load_group<PB>();
     const int r = blockIdx.y;
     const GcrScalars* S = sc + r;
     const char* rr_base = (const char*)rv + r * rs;
+    char* base = W + (size_t)r * ws;
+    const size_t vs = (size_t)nrhs * ws;
     cpx<double> acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> v[12];
-        ld64<PB>(W + ((size_t)k * nrhs + r) * ws, g.nblk, blk, threadIdx.x, v);
-        for (int j = 0; j < k; ++j) {
-            const cpx<double> cf = {S->coef[j].x, S->coef[j].y};
-            cpx<double> w[12];
-            ld64<PB>(W + ((size_t)j * nrhs + r) * ws, g.nblk, blk, threadIdx.x, w);
+        ld64<PB>(base + (size_t)k * vs, g.nblk, blk, threadIdx.x, v);
+        for (int jb = 0; jb < k; jb += G) {
+            cpx<RS> t[G][12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) v[c] = v[c] - cf * w[c];
+            for (int q = 0; q < G; ++q) {
+                const int j = jb + q < k ? jb + q : k - 1;
+                SpinorIO<PB>::load(base + (size_t)j * vs, g.nblk, blk, threadIdx.x, t[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (jb + q < k) {
+                    const cpx<double> cf = {S->coef[jb + q].x, S->coef[jb + q].y};
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) v[c] = v[c] - cf * to64(t[q][c]);
+                }
+            }
         }
-        if (k > 0) st64<PB>(W + ((size_t)k * nrhs + r) * ws, g.nblk, blk, threadIdx.x, v);
+        if (k > 0) st64<PB>(base + (size_t)k * vs, g.nblk, blk, threadIdx.x, v);
         cpx<double> rr[12];
         ld64<P_F64>(rr_base, g.nblk, blk, threadIdx.x, rr);
 #pragma unroll

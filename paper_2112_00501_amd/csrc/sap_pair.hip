@@ -224,7 +224,8 @@ __device__ __forceinline__ void load_half(const void* base, int nblk, int blk, c
     }
 }
 
-// x_B = (mode 0: x_B +) delta, delta given as this lane's chirality half.
+// x_B = (add: x_B +) delta, delta given as this lane's chirality half; x_B
+// is read again here rather than kept in registers through the block solve.
 // Every lane of the wave must call it.
 template <int P>
 __device__ __forceinline__ void store_update(void* base, int nblk, int blk, const PairLane& q, bool add,
@@ -326,28 +327,36 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
         const int r1 = r0 + tile < nrhs ? r0 + tile : nrhs;
         const BlockPos p = block_pos(g, blk);
 
-        __syncthreads();  // the previous item's readers of the staged links are done
+        // every global load of the item that does not depend on the
+        // right-hand side is issued before the barrier: lane half h stages
+        // the links of directions 2h and 2h + 1
+        cpx<typename LinkIO<PLINK>::R> lw[2][6];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {  // lane half h stages directions 2h and 2h + 1
-            const int mu = 2 * q.h + j;
-            cpx<typename LinkIO<PLINK>::R> w[6];
-            LinkIO<PLINK>::load6(links, blk, q.l, mu, w);
-            cpx<float> u[9];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) u[k] = {(float)w[k].re, (float)w[k].im};
-            su3_row2(u);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) sm.u[mu][k][q.l].set(u[k]);
-        }
+        for (int j = 0; j < 2; ++j) LinkIO<PLINK>::load6(links, blk, q.l, 2 * q.h + j, lw[j]);
         float cl[36];
         load_clover_half(clover, blk, q, cl);
+        // keep the clover loads here, in flight with the link loads, rather
+        // than sunk towards their first use
+#pragma unroll
+        for (int k = 0; k < 36; ++k) asm volatile("" ::"v"(cl[k]));
+        __syncthreads();  // the previous item's readers of the staged links are done
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            cpx<float> u[9];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) u[k] = {(float)lw[j][k].re, (float)lw[j][k].im};
+            su3_row2(u);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) sm.u[2 * q.h + j][k][q.l].set(u[k]);
+        }
 
         for (int r = r0; r < r1; ++r) {
             char* xr = (char*)x + (size_t)r * stride;
             const char* br = (const char*)b + (size_t)r * stride;
 
             // ---- block residual r_B = b_B - (D x)_B
-            cpx<float> rho[6];
+            cpx<float> rho[6], xh[6];
+            if (mode == 0) load_half<P>(xr, g.nblk, blk, q, xh);
             {
                 cpx<float> hop[6], cx[6];
 #pragma unroll
@@ -360,8 +369,6 @@ __global__ __launch_bounds__(PAIR_TPB) void k_sap_pair(Geom g, const void* __res
 #pragma unroll
                     for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
                     if (mode == 0) {  // own x staged in LDS for the hops inside the block
-                        cpx<float> xh[6];
-                        load_half<P>(xr, g.nblk, blk, q, xh);
                         __syncthreads();  // the previous right-hand side's readers of rho are done
 #pragma unroll
                         for (int i = 0; i < 6; ++i) sm.rho[6 * q.h + i][q.l].set(xh[i]);
