@@ -28,6 +28,7 @@
 // clover); each keeps its own scalars and stops, freezes or restarts on its
 // own criteria.  The kernels of one iteration can be captured once per k as a
 // HIP graph and replayed.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -72,6 +73,10 @@ void GcrWork::release() {
     if (host_sc) hipHostFree(host_sc);
     if (host_tail) hipHostFree(host_tail);
     if (host_active) hipHostFree(host_active);
+    for (hipEvent_t& e : tail_ready) {
+        if (e) hipEventDestroy(e);
+        e = nullptr;
+    }
     if (stream) hipStreamDestroy(stream);
     partials = nullptr;
     sc = nullptr;
@@ -109,8 +114,11 @@ hipError_t GcrWork::ensure(const Geom& g, int m_, int inner_, int basis_, int nr
     if ((e = hipMalloc((void**)&tail, sizeof(GcrTail) * nrhs)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&active, sizeof(int) * nrhs)) != hipSuccess) return e;
     if ((e = hipHostMalloc((void**)&host_sc, sizeof(GcrScalars) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
-    if ((e = hipHostMalloc((void**)&host_tail, sizeof(GcrTail) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
-    if ((e = hipHostMalloc((void**)&host_active, sizeof(int) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&host_tail, sizeof(GcrTail) * 2 * nrhs, hipHostMallocDefault)) != hipSuccess)
+        return e;
+    if ((e = hipHostMalloc((void**)&host_active, sizeof(int) * 2 * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
+    for (hipEvent_t& ev : tail_ready)
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking)) != hipSuccess) return e;
     return hipSuccess;
 }
@@ -134,14 +142,31 @@ struct Solver {
     // precision of the residual copy the smoother reads (none without smoother)
     int lo_prec() const { return (p.n_cy > 0 || p.mg) ? p.inner : -1; }
 
+    // The copy may run after the host has gone on (an iteration can be queued
+    // ahead of it), so consecutive uploads use alternate pinned slots.
     hipError_t upload_mask(const std::vector<char>& m) {
-        for (int r = 0; r < n; ++r) w.host_active[r] = m[r] ? 1 : 0;
-        return hipMemcpyAsync(w.active, w.host_active, sizeof(int) * n, hipMemcpyHostToDevice, s);
+        w.mask_slot ^= 1;
+        int* h = w.host_active + w.mask_slot * n;
+        for (int r = 0; r < n; ++r) h[r] = m[r] ? 1 : 0;
+        return hipMemcpyAsync(w.active, h, sizeof(int) * n, hipMemcpyHostToDevice, s);
     }
 
+    // synchronous read of the tails into slot 0 (nothing queued behind it)
     hipError_t read_tails() {
         GCR_CHK(hipMemcpyAsync(w.host_tail, w.tail, sizeof(GcrTail) * n, hipMemcpyDeviceToHost, s));
         return hipStreamSynchronize(s);
+    }
+
+    // Iteration k and the copy of its tails into slot k & 1, queued without
+    // waiting; wait_tails(k) returns once that slot holds them.
+    hipError_t enqueue_iteration(int k) {
+        GCR_CHK(run_iteration(k));
+        GCR_CHK(hipMemcpyAsync(w.host_tail + (k & 1) * n, w.tail, sizeof(GcrTail) * n, hipMemcpyDeviceToHost, s));
+        return hipEventRecord(w.tail_ready[k & 1], s);
+    }
+    const GcrTail* wait_tails(int k, hipError_t* e) {
+        *e = hipEventSynchronize(w.tail_ready[k & 1]);
+        return w.host_tail + (k & 1) * n;
     }
 
     // w = D z for all right-hand sides
@@ -303,13 +328,38 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
             r_true[r] = rel[r] * bnorm[r];
         }
         GCR_CHK(S.upload_mask(cyc));
+        // Iteration k + 1 is queued before the host reads the tails of k, so
+        // the device does not idle through that round trip.  When every
+        // active column is predicted to stop at k (its residual falling by
+        // the last step's ratio once more), k + 1 is not queued ahead.  A
+        // column that stops at k while k + 1 is already queued runs k + 1
+        // once more; that iteration writes only its own slots (W, Z, column
+        // k + 1 of R, c_{k+1}) and the residual, which the back substitution
+        // (first k_used directions) and the true residual below do not read.
+        std::vector<double> rr_prev(n, 0.0), ratio(n, 1.0);
+        for (int r = 0; r < n; ++r) rr_prev[r] = r_true[r];
+        auto likely_last = [&](int k) {
+            for (int r = 0; r < n; ++r) {
+                if (!cyc[r]) continue;
+                const double pred = rr_prev[r] * ratio[r];
+                const bool stop = pred <= p.tol * bnorm[r] || iters[r] + 1 >= p.max_iter ||
+                                  (p.reliable_delta > 0.0 && pred < p.reliable_delta * r_true[r]);
+                if (!stop) return false;
+            }
+            (void)k;
+            return true;
+        };
+        GCR_CHK(S.enqueue_iteration(0));
         for (int k = 0; k < p.restart; ++k) {
-            GCR_CHK(S.run_iteration(k));
-            GCR_CHK(S.read_tails());
+            const bool ahead = k + 1 < p.restart && !likely_last(k);
+            if (ahead) GCR_CHK(S.enqueue_iteration(k + 1));
+            hipError_t we;
+            const GcrTail* tails = S.wait_tails(k, &we);
+            if (we != hipSuccess) return we;
             bool changed = false, left = false;
             for (int r = 0; r < n; ++r) {
                 if (!cyc[r]) continue;
-                const GcrTail& t = w.host_tail[r];
+                const GcrTail& t = tails[r];
                 if (!(t.nu > 0.0)) {
                     brk[r] = 1;
                     cyc[r] = 0;
@@ -324,10 +374,13 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
                     cyc[r] = 0;
                     changed = true;
                 }
+                ratio[r] = rr_prev[r] > 0.0 ? std::min(1.0, rr / rr_prev[r]) : 1.0;
+                rr_prev[r] = rr;
                 left = left || cyc[r];
             }
             if (!left) break;
             if (changed) GCR_CHK(S.upload_mask(cyc));
+            if (!ahead && k + 1 < p.restart) GCR_CHK(S.enqueue_iteration(k + 1));
         }
         // back substitution R gamma = c on the host, then x += sum gamma_k z_k
         std::vector<char> upd(n, 0);

@@ -43,9 +43,11 @@ struct GcrWork {
     GcrScalars* sc = nullptr;
     GcrScalars* host_sc = nullptr;  // pinned
     GcrTail* tail = nullptr;
-    GcrTail* host_tail = nullptr;   // pinned
+    GcrTail* host_tail = nullptr;   // pinned, two slots of [nrhs] (iteration parity)
     int* active = nullptr;
-    int* host_active = nullptr;     // pinned
+    int* host_active = nullptr;     // pinned, two slots of [nrhs] (alternating uploads)
+    int mask_slot = 0;
+    hipEvent_t tail_ready[2] = {nullptr, nullptr};  // host_tail slot filled
     hipStream_t stream = nullptr;   // private stream (graph capture needs a non-null stream)
     std::vector<hipGraphExec_t> graphs;
     std::vector<char> graph_key;
