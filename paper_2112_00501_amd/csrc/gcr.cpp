@@ -157,11 +157,10 @@ struct Solver {
         return hipStreamSynchronize(s);
     }
 
-    // Iteration k and the copy of its tails into slot k & 1, queued without
-    // waiting; wait_tails(k) returns once that slot holds them.
+    // Iteration k, queued without waiting; its kernels write the tails into
+    // pinned slot k & 1, and wait_tails(k) returns once they are there.
     hipError_t enqueue_iteration(int k) {
         GCR_CHK(run_iteration(k));
-        GCR_CHK(hipMemcpyAsync(w.host_tail + (k & 1) * n, w.tail, sizeof(GcrTail) * n, hipMemcpyDeviceToHost, s));
         return hipEventRecord(w.tail_ready[k & 1], s);
     }
     const GcrTail* wait_tails(int k, hipError_t* e) {
@@ -200,9 +199,13 @@ struct Solver {
             GCR_CHK(blas_convert(bc, p.inner, zk, P_F64, w.r, true, s));
         }
         GCR_CHK(apply_w(wk, zk));
-        if (k > 0) GCR_CHK(blas_gcr_project(bc, w.basis, w.W, w.wstride, k, s));
-        GCR_CHK(blas_gcr_orthonormalise(bc, w.basis, w.W, w.wstride, k, w.r, s));
-        GCR_CHK(blas_gcr_residual_update(bc, w.basis, w.W, w.wstride, k, w.r, lo_prec(), w.rlo, s));
+        // the kernels write this iteration's tails straight into pinned host
+        // slot k & 1, which the host reads once the iteration's event is done
+        BlasCtx bk = bc;
+        bk.tail = w.host_tail + (k & 1) * n;
+        if (k > 0) GCR_CHK(blas_gcr_project(bk, w.basis, w.W, w.wstride, k, s));
+        GCR_CHK(blas_gcr_orthonormalise(bk, w.basis, w.W, w.wstride, k, w.r, s));
+        GCR_CHK(blas_gcr_residual_update(bk, w.basis, w.W, w.wstride, k, w.r, lo_prec(), w.rlo, s));
         return hipSuccess;
     }
 
