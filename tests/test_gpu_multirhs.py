@@ -79,6 +79,35 @@ def test_batched_gcr_columns_equal_single_solves(case, inner):
         assert rel <= 1e-10
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_columns_stopping_at_different_iterations(case, use_graph):
+    """Columns with start vectors of different quality stop at different
+    iterations.  The solver queues iteration k + 1 before it reads the
+    residuals of iteration k, so a column that stops at k still runs k + 1
+    once; that must leave its solution untouched: every column equals its
+    single solve bit for bit."""
+    c = case
+    bs = synth.source(c.dims, 21, nrhs=4)
+    x0 = np.zeros_like(bs)
+    for r, tol in ((1, 1e-3), (2, 1e-6)):  # columns 0 and 3 start from zero
+        x1 = c.lat.new_field(cs.F64).zero_()
+        c.op.gcr_solve(x1, c.to_dev(bs[r], cs.F64), cs.SolverParams(tol=tol, use_graph=False))
+        x0[r] = c.to_host(x1, cs.F64)
+    xd = c.to_dev(x0, cs.F64)
+    st, stats = c.op.gcr_solve(xd, c.to_dev(bs, cs.F64), cs.SolverParams(rhs_tile=4, use_graph=use_graph),
+                               nrhs=4)
+    xb = c.to_host(xd, cs.F64, 4)
+    its = [s["iters"] for s in stats]
+    assert st == 0 and len(set(its)) >= 3, its
+    for r in range(4):
+        x1 = c.to_dev(x0[r], cs.F64)
+        st1, s1 = c.op.gcr_solve(x1, c.to_dev(bs[r], cs.F64), cs.SolverParams(use_graph=use_graph))
+        assert st1 == 0 and s1[0]["iters"] == its[r], (r, s1[0]["iters"], its)
+        assert np.array_equal(c.to_host(x1, cs.F64), xb[r]), r
+        rel = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, bs[r], xb[r]) / np.linalg.norm(bs[r])
+        assert rel <= 1e-10
+
+
 def test_graph_replay_equals_eager(case):
     c = case
     bs = synth.source(c.dims, 10, nrhs=NRHS)
