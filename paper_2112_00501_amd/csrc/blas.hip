@@ -369,19 +369,43 @@ __global__ __launch_bounds__(TPB) void k_residual_update(Geom g, const char* W, 
 }
 
 // x += sum_{j < nk} gamma_j Z_j
+// x += sum_{j < nk} gamma_j Z_j.  Every workgroup first solves the
+// triangular system R gamma = c over the first nk directions (R[k][k] = nu_k
+// is real) in the same order, so all use the same gamma.
 template <int PZ>
 __global__ __launch_bounds__(TPB) void k_solution_update(Geom g, const char* Z, size_t zs, int nrhs, void* xv,
-                                                         size_t xs, const GcrScalars* sc, const int* active) {
-    if (skip(active)) return;
+                                                         size_t xs, const GcrScalars* sc, const int* ku) {
     const int r = blockIdx.y;
     const GcrScalars* S = sc + r;
-    const int nk = S->nk;
+    __shared__ double2 gam[GCR_MAX_RESTART], cs[GCR_MAX_RESTART], Rs[GCR_MAX_RESTART][GCR_MAX_RESTART];
+    __shared__ int nks;
+    if (threadIdx.x == 0) nks = ku[r];
+    __syncthreads();
+    const int nk = nks;
+    if (nk <= 0) return;
+    // R and c to LDS with all lanes, then one lane solves from LDS
+    for (int i = threadIdx.x; i < nk * nk; i += TPB) Rs[i / nk][i % nk] = S->R[i / nk][i % nk];
+    if ((int)threadIdx.x < nk) cs[threadIdx.x] = S->c[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = nk - 1; k >= 0; --k) {
+            double2 acc = cs[k];
+            for (int j = k + 1; j < nk; ++j) {
+                const double2 a = Rs[k][j], b = gam[j];
+                acc.x -= a.x * b.x - a.y * b.y;
+                acc.y -= a.x * b.y + a.y * b.x;
+            }
+            const double nu = Rs[k][k].x;
+            gam[k] = make_double2(acc.x / nu, acc.y / nu);
+        }
+    }
+    __syncthreads();
     char* x_base = (char*)xv + r * xs;
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<double> xx[12];
         ld64<P_F64>(x_base, g.nblk, blk, threadIdx.x, xx);
         for (int j = 0; j < nk; ++j) {
-            const cpx<double> gm = {S->gamma[j].x, S->gamma[j].y};
+            const cpx<double> gm = {gam[j].x, gam[j].y};
             cpx<double> z[12];
             ld64<PZ>(Z + ((size_t)j * nrhs + r) * zs, g.nblk, blk, threadIdx.x, z);
 #pragma unroll
@@ -727,10 +751,11 @@ hipError_t blas_gcr_residual_update(const BlasCtx& c, int pb, const void* W, siz
     return finalize(c, 1, NORM_SLOT, STEP_NORM, 0, 0, s);
 }
 
-hipError_t blas_gcr_solution_update(const BlasCtx& c, int pz, const void* Z, size_t zs, void* x, hipStream_t s) {
+hipError_t blas_gcr_solution_update(const BlasCtx& c, int pz, const void* Z, size_t zs, void* x, const int* ku,
+                                    hipStream_t s) {
     ProfScope ps("blas", s);
     const dim3 grid(nwg_for(c.g), c.nrhs);
-    CS_DISPATCH_P(pz, hipLaunchKernelGGL((k_solution_update<PP>), grid, dim3(TPB), 0, s, c.g, (const char*)Z, zs, c.nrhs, x, f64_stride(c.g), c.sc, c.active));
+    CS_DISPATCH_P(pz, hipLaunchKernelGGL((k_solution_update<PP>), grid, dim3(TPB), 0, s, c.g, (const char*)Z, zs, c.nrhs, x, f64_stride(c.g), c.sc, ku));
     return hipGetLastError();
 }
 

@@ -26,9 +26,6 @@ struct GcrScalars {
     double inv_nu[GCR_MAX_RESTART];
     double2 c[GCR_MAX_RESTART];
     double2 coef[GCR_MAX_RESTART];                // coefficients of the next update kernel
-    double2 gamma[GCR_MAX_RESTART];               // back-substitution result (host -> device)
-    int nk;                                       // number of gamma_k (host -> device)
-    int pad;
     double rnorm2;                                // |r|^2 of the current residual
     double inv_rnorm;                             // 1 / |r| (0 when r = 0)
     double nu;                                    // norm of the newest orthogonalised w
@@ -72,9 +69,11 @@ hipError_t blas_gcr_orthonormalise(const BlasCtx& c, int basis_prec, void* W, si
 // With lo_prec >= 0 also writes the new r / |old r| in that precision to lo.
 hipError_t blas_gcr_residual_update(const BlasCtx& c, int basis_prec, const void* W, size_t wstride,
                                     int k, void* r, int lo_prec, void* lo, hipStream_t s);
-// x += sum_{j < sc.nk} gamma_j Z_j
+// x += sum_{j < nk} gamma_j Z_j, gamma solving R gamma = c over the first nk
+// directions, nk = ku[r] for column r (ku may live in pinned host memory;
+// columns with nk = 0 are left alone)
 hipError_t blas_gcr_solution_update(const BlasCtx& c, int zprec, const void* Z, size_t zstride,
-                                    void* x, hipStream_t s);
+                                    void* x, const int* ku, hipStream_t s);
 // Deterministic non-zero test pattern (for timing runs).
 hipError_t blas_fill_pattern(const BlasCtx& c, int prec, void* dst, hipStream_t s);
 

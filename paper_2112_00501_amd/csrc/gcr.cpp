@@ -31,7 +31,6 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <complex>
 #include <cstring>
 #include <vector>
 
@@ -70,7 +69,7 @@ void GcrWork::release() {
     if (sc) hipFree(sc);
     if (tail) hipFree(tail);
     if (active) hipFree(active);
-    if (host_sc) hipHostFree(host_sc);
+    if (host_ku) hipHostFree(host_ku);
     if (host_tail) hipHostFree(host_tail);
     if (host_active) hipHostFree(host_active);
     for (hipEvent_t& e : tail_ready) {
@@ -82,7 +81,7 @@ void GcrWork::release() {
     sc = nullptr;
     tail = nullptr;
     active = nullptr;
-    host_sc = nullptr;
+    host_ku = nullptr;
     host_tail = nullptr;
     host_active = nullptr;
     stream = nullptr;
@@ -113,7 +112,7 @@ hipError_t GcrWork::ensure(const Geom& g, int m_, int inner_, int basis_, int nr
     if ((e = hipMalloc((void**)&sc, sizeof(GcrScalars) * nrhs)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&tail, sizeof(GcrTail) * nrhs)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&active, sizeof(int) * nrhs)) != hipSuccess) return e;
-    if ((e = hipHostMalloc((void**)&host_sc, sizeof(GcrScalars) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&host_ku, sizeof(int) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
     if ((e = hipHostMalloc((void**)&host_tail, sizeof(GcrTail) * 2 * nrhs, hipHostMallocDefault)) != hipSuccess)
         return e;
     if ((e = hipHostMalloc((void**)&host_active, sizeof(int) * 2 * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
@@ -144,7 +143,10 @@ struct Solver {
 
     // The copy may run after the host has gone on (an iteration can be queued
     // ahead of it), so consecutive uploads use alternate pinned slots.
+    std::vector<char> mask_now;  // the mask last uploaded by this solve
     hipError_t upload_mask(const std::vector<char>& m) {
+        if (m == mask_now) return hipSuccess;
+        mask_now = m;
         w.mask_slot ^= 1;
         int* h = w.host_active + w.mask_slot * n;
         for (int r = 0; r < n; ++r) h[r] = m[r] ? 1 : 0;
@@ -282,11 +284,16 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
     std::vector<int> status(n, GCR_NOT_CONVERGED), iters(n, 0), cycles(n, 0), k_used(n, 0);
     std::vector<char> done(n, 0), cyc(n, 0), brk(n, 0);
 
+    // |b| into pinned slot 1, then the first true residual r = b - D x
+    // (every column) into slot 0: one wait for both
     GCR_CHK(S.upload_mask(all));
     GCR_CHK(blas_norm_to_scalars(S.bc, rhs, -1, nullptr, s));
+    GCR_CHK(hipMemcpyAsync(w.host_tail + n, w.tail, sizeof(GcrTail) * n, hipMemcpyDeviceToHost, s));
+    GCR_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, rhs, n, s));
+    GCR_CHK(blas_norm_to_scalars(S.bc, w.r, S.lo_prec(), w.rlo, s));
     GCR_CHK(S.read_tails());
     for (int r = 0; r < n; ++r) {
-        bnorm[r] = std::sqrt(w.host_tail[r].rnorm2);
+        bnorm[r] = std::sqrt(w.host_tail[n + r].rnorm2);
         if (!std::isfinite(bnorm[r])) {
             status[r] = GCR_NONFINITE;
             rel[r] = bnorm[r];
@@ -312,7 +319,8 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
             if (!done[r]) rel[r] = std::sqrt(w.host_tail[r].rnorm2) / bnorm[r];
         return hipSuccess;
     };
-    GCR_CHK(true_residual());
+    for (int r = 0; r < n; ++r)
+        if (!done[r]) rel[r] = std::sqrt(w.host_tail[r].rnorm2) / bnorm[r];
 
     for (;;) {
         bool any = false;
@@ -385,34 +393,16 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
             if (changed) GCR_CHK(S.upload_mask(cyc));
             if (!ahead && k + 1 < p.restart) GCR_CHK(S.enqueue_iteration(k + 1));
         }
-        // back substitution R gamma = c on the host, then x += sum gamma_k z_k
-        std::vector<char> upd(n, 0);
+        // x += sum_k gamma_k z_k with R gamma = c over each column's first
+        // k_used directions; the solution-update kernel solves the small
+        // triangular system itself, reading k_used from pinned host memory
+        // (nothing reads host_ku once the true residual below has been read)
         bool any_upd = false;
-        for (int r = 0; r < n; ++r) any_upd = any_upd || k_used[r] > 0;
-        if (any_upd) {
-            GCR_CHK(hipMemcpyAsync(w.host_sc, w.sc, sizeof(GcrScalars) * n, hipMemcpyDeviceToHost, s));
-            GCR_CHK(hipStreamSynchronize(s));
-            for (int r = 0; r < n; ++r) {
-                const int ku = k_used[r];
-                if (ku == 0) continue;
-                upd[r] = 1;
-                GcrScalars& h = w.host_sc[r];
-                std::vector<std::complex<double>> gam(ku);
-                for (int k = ku - 1; k >= 0; --k) {
-                    std::complex<double> acc(h.c[k].x, h.c[k].y);
-                    for (int j = k + 1; j < ku; ++j) acc -= std::complex<double>(h.R[k][j].x, h.R[k][j].y) * gam[j];
-                    gam[k] = acc / std::complex<double>(h.R[k][k].x, h.R[k][k].y);
-                }
-                for (int k = 0; k < ku; ++k) h.gamma[k] = make_double2(gam[k].real(), gam[k].imag());
-                h.nk = ku;
-                const size_t goff = offsetof(GcrScalars, gamma);
-                const size_t glen = offsetof(GcrScalars, pad) - goff;
-                GCR_CHK(hipMemcpyAsync((char*)(w.sc + r) + goff, (char*)(w.host_sc + r) + goff, glen,
-                                       hipMemcpyHostToDevice, s));
-            }
-            GCR_CHK(S.upload_mask(upd));
-            GCR_CHK(blas_gcr_solution_update(S.bc, p.inner, w.Z, w.zstride, x, s));
+        for (int r = 0; r < n; ++r) {
+            w.host_ku[r] = k_used[r];
+            any_upd = any_upd || k_used[r] > 0;
         }
+        if (any_upd) GCR_CHK(blas_gcr_solution_update(S.bc, p.inner, w.Z, w.zstride, x, w.host_ku, s));
         // reliable update: true FP64 residual
         GCR_CHK(true_residual());
         for (int r = 0; r < n; ++r) {

@@ -41,7 +41,7 @@ struct GcrWork {
     void* wtmp = nullptr;  // D z before conversion to the basis precision [nrhs]
     double2* partials = nullptr;
     GcrScalars* sc = nullptr;
-    GcrScalars* host_sc = nullptr;  // pinned
+    int* host_ku = nullptr;         // pinned [nrhs]: directions each column's solution update uses
     GcrTail* tail = nullptr;
     GcrTail* host_tail = nullptr;   // pinned, two slots of [nrhs] (iteration parity)
     int* active = nullptr;
