@@ -64,12 +64,10 @@ void BicgWork::release() {
     }
     if (partials) hipFree(partials);
     if (sc) hipFree(sc);
-    if (tail) hipFree(tail);
     if (host_tail) hipHostFree(host_tail);
     if (stream) hipStreamDestroy(stream);
     partials = nullptr;
     sc = nullptr;
-    tail = nullptr;
     host_tail = nullptr;
     stream = nullptr;
     inner = -1;
@@ -100,7 +98,6 @@ hipError_t BicgWork::ensure(const Geom& g, int inner_, int pv_) {
     }
     E_(hipMalloc((void**)&partials, sizeof(double2) * BLAS_MAX_WG * (MULTIDOT_CHUNK + 2)));
     E_(hipMalloc((void**)&sc, sizeof(BiScalars)));
-    E_(hipMalloc((void**)&tail, sizeof(BiTail)));
     E_(hipHostMalloc((void**)&host_tail, sizeof(BiTail), hipHostMallocDefault));
     E_(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
 #undef E_
@@ -129,10 +126,8 @@ struct Bicg {
         f = BiFields{x, w.r, w.rh, w.p, w.v, w.s, w.t, w.plo, w.slo, zp, zs, w.w};
     }
 
-    hipError_t read_tail() {
-        BI_CHK(hipMemcpyAsync(w.host_tail, w.tail, sizeof(BiTail), hipMemcpyDeviceToHost, s));
-        return hipStreamSynchronize(s);
-    }
+    // the finalize kernels write the tail straight into pinned host memory
+    hipError_t read_tail() { return hipStreamSynchronize(s); }
 
     // z = SAP(v) from zero (z is v itself without smoothing), then w = D z
     hipError_t precondition_apply(void* lo, void* z) {
@@ -153,7 +148,7 @@ struct Bicg {
         BI_CHK(bicg_update_s(bc, w.sc, f, pv, p.inner, s));
         BI_CHK(precondition_apply(f.slo, f.zs));
         BI_CHK(bicg_omega(bc, w.sc, f, pv, natural_out(p.inner), s));
-        return bicg_update_xr(bc, w.sc, w.tail, f, pv, p.inner, s);
+        return bicg_update_xr(bc, w.sc, w.host_tail, f, pv, p.inner, s);
     }
 
     // the pieces of an iteration with the multigrid preconditioner: before
@@ -170,7 +165,7 @@ struct Bicg {
         BI_CHK(mg_finish(op, *p.mg, f.zs, f.slo, s));
         BI_CHK(launch_dslash(op, p.inner, nout, nout, false, w.w, f.zs, nullptr, 1, s));
         BI_CHK(bicg_omega(bc, w.sc, f, pv, nout, s));
-        return bicg_update_xr(bc, w.sc, w.tail, f, pv, p.inner, s);
+        return bicg_update_xr(bc, w.sc, w.host_tail, f, pv, p.inner, s);
     }
 
     std::vector<char> key(const void* x) const {
@@ -250,7 +245,7 @@ struct Bicg {
         BI_CHK(launch_dslash(op, pv, pv, pv, false, w.r, x, b, 1, s));
         BI_CHK(hipMemsetAsync(w.p, 0, vec, s));
         BI_CHK(hipMemsetAsync(w.v, 0, vec, s));
-        BI_CHK(bicg_restart(bc, w.sc, w.tail, f, pv, s));
+        BI_CHK(bicg_restart(bc, w.sc, w.host_tail, f, pv, s));
         BI_CHK(read_tail());
         *rnorm = std::sqrt(w.host_tail->rr);
         return hipSuccess;
@@ -290,7 +285,7 @@ hipError_t bicgstab_solve(const OpData& op, const GcrParams& p, BicgWork& w, voi
     int status = GCR_NOT_CONVERGED, iters = 0, restarts = 0;
     double rel = 0.0;
 
-    BI_CHK(bicg_norm2(B.bc, w.sc, w.tail, b, P_F64, s));
+    BI_CHK(bicg_norm2(B.bc, w.sc, w.host_tail, b, P_F64, s));
     BI_CHK(B.read_tail());
     const double bnorm = std::sqrt(w.host_tail->rr);
     if (!std::isfinite(bnorm)) {
@@ -306,7 +301,7 @@ hipError_t bicgstab_solve(const OpData& op, const GcrParams& p, BicgWork& w, voi
             double rt;
             if (single) {
                 BI_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r64, x, b, 1, s));
-                BI_CHK(bicg_norm2(B.bc, w.sc, w.tail, w.r64, P_F64, s));
+                BI_CHK(bicg_norm2(B.bc, w.sc, w.host_tail, w.r64, P_F64, s));
                 BI_CHK(B.read_tail());
                 rt = std::sqrt(w.host_tail->rr);
             } else {

@@ -20,8 +20,7 @@ struct BicgWork {
     void *r64 = nullptr, *bin = nullptr, *e = nullptr;
     double2* partials = nullptr;
     BiScalars* sc = nullptr;
-    BiTail* tail = nullptr;
-    BiTail* host_tail = nullptr;    // pinned
+    BiTail* host_tail = nullptr;    // pinned; the finalize kernels write it directly
     hipStream_t stream = nullptr;   // private stream (graph capture needs a non-null stream)
     hipGraphExec_t graph = nullptr;
     hipGraphExec_t mg_graph[3] = {nullptr, nullptr, nullptr};  // the pieces around two coarse phases

@@ -153,12 +153,6 @@ struct Solver {
         return hipMemcpyAsync(w.active, h, sizeof(int) * n, hipMemcpyHostToDevice, s);
     }
 
-    // synchronous read of the tails into slot 0 (nothing queued behind it)
-    hipError_t read_tails() {
-        GCR_CHK(hipMemcpyAsync(w.host_tail, w.tail, sizeof(GcrTail) * n, hipMemcpyDeviceToHost, s));
-        return hipStreamSynchronize(s);
-    }
-
     // Iteration k, queued without waiting; its kernels write the tails into
     // pinned slot k & 1, and wait_tails(k) returns once they are there.
     hipError_t enqueue_iteration(int k) {
@@ -269,7 +263,6 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
     hipStream_t s = S.s;
     const size_t f64 = S.f64();
     const int n = nrhs;
-    std::vector<char> all(n, 1);
 
     const void* rhs = b;
     if (dagger) {  // D^dag x = b  <=>  D (g5 x) = g5 b
@@ -285,13 +278,15 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
     std::vector<char> done(n, 0), cyc(n, 0), brk(n, 0);
 
     // |b| into pinned slot 1, then the first true residual r = b - D x
-    // (every column) into slot 0: one wait for both
-    GCR_CHK(S.upload_mask(all));
-    GCR_CHK(blas_norm_to_scalars(S.bc, rhs, -1, nullptr, s));
-    GCR_CHK(hipMemcpyAsync(w.host_tail + n, w.tail, sizeof(GcrTail) * n, hipMemcpyDeviceToHost, s));
+    // (every column) into slot 0, written there by the kernels: one wait
+    BlasCtx b_slot1 = S.bc, b_slot0 = S.bc;
+    b_slot1.active = b_slot0.active = nullptr;
+    b_slot1.tail = w.host_tail + n;
+    b_slot0.tail = w.host_tail;
+    GCR_CHK(blas_norm_to_scalars(b_slot1, rhs, -1, nullptr, s));
     GCR_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, rhs, n, s));
-    GCR_CHK(blas_norm_to_scalars(S.bc, w.r, S.lo_prec(), w.rlo, s));
-    GCR_CHK(S.read_tails());
+    GCR_CHK(blas_norm_to_scalars(b_slot0, w.r, S.lo_prec(), w.rlo, s));
+    GCR_CHK(hipStreamSynchronize(s));
     for (int r = 0; r < n; ++r) {
         bnorm[r] = std::sqrt(w.host_tail[n + r].rnorm2);
         if (!std::isfinite(bnorm[r])) {
@@ -313,8 +308,10 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
     auto true_residual = [&]() -> hipError_t {
         GCR_CHK(S.upload_mask(not_done()));
         GCR_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, rhs, n, s));
-        GCR_CHK(blas_norm_to_scalars(S.bc, w.r, S.lo_prec(), w.rlo, s));
-        GCR_CHK(S.read_tails());
+        BlasCtx bh = S.bc;
+        bh.tail = w.host_tail;  // the norm lands in pinned slot 0
+        GCR_CHK(blas_norm_to_scalars(bh, w.r, S.lo_prec(), w.rlo, s));
+        GCR_CHK(hipStreamSynchronize(s));
         for (int r = 0; r < n; ++r)
             if (!done[r]) rel[r] = std::sqrt(w.host_tail[r].rnorm2) / bnorm[r];
         return hipSuccess;
