@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Dslash/SAP HBM GB/s (% peak); time-to-1e-10 residual, mixed vs FP64, 1 GPU"
-SAP_KERNEL_SOURCES = ["sap.hip", "sap_pair.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp"]
+SAP_KERNEL_SOURCES = ["sap.hip", "sap_pair.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp", "wave.hpp"]
 
 # Algorithmic bytes per visited site of one SAP half-sweep, FP32 storage:
 # every field the visit needs, counted once per site: b (96), x (96), the two
