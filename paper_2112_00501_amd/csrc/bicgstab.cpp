@@ -98,7 +98,8 @@ hipError_t BicgWork::ensure(const Geom& g, int inner_, int pv_) {
     }
     E_(hipMalloc((void**)&partials, sizeof(double2) * BLAS_MAX_WG * (MULTIDOT_CHUNK + 2)));
     E_(hipMalloc((void**)&sc, sizeof(BiScalars)));
-    E_(hipHostMalloc((void**)&host_tail, sizeof(BiTail), hipHostMallocDefault));
+    // coherent: the finalize kernels write it and the host reads it after a stream wait
+    E_(hipHostMalloc((void**)&host_tail, sizeof(BiTail), hipHostMallocCoherent));
     E_(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
 #undef E_
     return hipSuccess;

@@ -112,8 +112,10 @@ hipError_t GcrWork::ensure(const Geom& g, int m_, int inner_, int basis_, int nr
     if ((e = hipMalloc((void**)&sc, sizeof(GcrScalars) * nrhs)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&tail, sizeof(GcrTail) * nrhs)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&active, sizeof(int) * nrhs)) != hipSuccess) return e;
-    if ((e = hipHostMalloc((void**)&host_ku, sizeof(int) * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
-    if ((e = hipHostMalloc((void**)&host_tail, sizeof(GcrTail) * 2 * nrhs, hipHostMallocDefault)) != hipSuccess)
+    // coherent host memory for what kernels read or write directly: no device
+    // cache holds a stale copy across solves
+    if ((e = hipHostMalloc((void**)&host_ku, sizeof(int) * nrhs, hipHostMallocCoherent)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&host_tail, sizeof(GcrTail) * 2 * nrhs, hipHostMallocCoherent)) != hipSuccess)
         return e;
     if ((e = hipHostMalloc((void**)&host_active, sizeof(int) * 2 * nrhs, hipHostMallocDefault)) != hipSuccess) return e;
     for (hipEvent_t& ev : tail_ready)
