@@ -75,3 +75,19 @@ def test_zero_rhs_warm_start_and_cap(cfg1):
     assert st == 0 and r <= 1e-10
     st, s, _ = solve(c, b, cs.F64, max_iter=2, n_cy=0)
     assert st == cs.CS_NOT_CONVERGED and s["iters"] == 2
+
+
+@pytest.mark.parametrize("restart", [1, 3, 32])
+def test_restart_lengths(cfg1, restart):
+    """Restart cycles of one direction (every iteration ends a cycle), of a
+    few, and of the largest supported length: the back substitution of each
+    cycle runs on the device over that cycle's directions, and the solution
+    must reach 1e-10 as re-verified by the oracle."""
+    c = cfg1
+    b = synth.source(c.dims, 2010)
+    st, s, x = solve(c, b, cs.F32, restart=restart, max_iter=400)
+    r = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, b, x) / np.linalg.norm(b)
+    print(f"restart={restart} iters={s['iters']} restarts={s['restarts']} relres={r:.3e}")
+    assert st == 0 and r <= 1e-10
+    if restart == 1:
+        assert s["restarts"] >= s["iters"] - 1
