@@ -270,8 +270,11 @@ void cs_solver_params_default(cs_solver_params* p);
  * stats (host, may be NULL) has nrhs entries; seconds is the wall time of the
  * whole call.  Device workspace (2 m nrhs fields plus scalars) is allocated on
  * first use and kept with the clover handle.  The work runs on a private
- * stream after the caller's stream has been synchronised.  Returns CS_OK when
- * every right-hand side converged, else the first non-zero status. */
+ * stream after the caller's stream has been synchronised.  The host decides
+ * after every iteration whether to go on; the next iteration is queued before
+ * that decision, so the device may run one iteration past a stop, which
+ * changes neither x nor the reported counts.  Returns CS_OK when every
+ * right-hand side converged, else the first non-zero status. */
 int cs_gcr_solve(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x,
                  const void* b, int nrhs, cs_solver_stats* stats, void* stream);
 
