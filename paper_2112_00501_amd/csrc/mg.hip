@@ -124,7 +124,7 @@ struct LdsColumn {  // in-block neighbours for the self term
 // chiralities, re and im), which are summed over the lanes through a
 // lane-major LDS array in a fixed order.  The +mu blocks follow afterwards
 // from gamma5-hermiticity (k_mg_assemble_fwd).
-constexpr int ASM_R = 4;                 // rows per reduction round
+constexpr int ASM_R = 2;                 // rows per reduction round
 constexpr int ASM_VALS = 20 * ASM_R;     // partial sums per lane and round
 constexpr int ASM_LD = ASM_VALS + 1;     // padded row of the lane-major array
 
@@ -160,7 +160,7 @@ __device__ __forceinline__ void back_face(const Geom& g, const BlockPos& p, int 
     for (int k = 0; k < 12; ++k) y[k] = {-kappa * y[k].re, -kappa * y[k].im};
 }
 
-__global__ __launch_bounds__(TPB) void k_mg_assemble(Geom g, const void* links, const void* clover, float kappa,
+__global__ __launch_bounds__(TPB, 2) void k_mg_assemble(Geom g, const void* links, const void* clover, float kappa,
                                                      const char* P, size_t fs, int nv, float2* Dc) {
     const int blk = blockIdx.x, l = threadIdx.x, nc = 2 * nv;
     const BlockPos p = block_pos(g, blk);
