@@ -17,30 +17,52 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
 
-BUILD_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fcx-limited-range"]
+# Plain ISO C11 (so no floating-point contraction and no reassociation): the
+# arithmetic is exactly what the source says.  The default library is built
+# for generic x86-64 so that it runs on any host it is copied to; the native
+# build (-march=native, for timing the oracle on the host it runs on) gives
+# the same results, since neither build contracts or reorders operations.
+BUILD_FLAGS = ["-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared"]
 
 
-def build() -> str:
-    """Compile liboracle.so (plain gcc; no GPU code)."""
-    tmp = _LIB + ".tmp"
-    cmd = ["gcc"] + BUILD_FLAGS + [_SRC, "-o", tmp, "-lm"]
+def build(native: bool = False) -> str:
+    """Compile the oracle library (plain gcc; no GPU code)."""
+    out = _LIB_NATIVE if native else _LIB
+    tmp = out + ".tmp"
+    cmd = ["gcc"] + BUILD_FLAGS + (["-march=native"] if native else []) + [_SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None
+_native = False
+
+
+def use_native_build() -> None:
+    """Load the -march=native build (built here on first use) instead of the
+    generic one; must be called before the first oracle call."""
+    global _native
+    if _lib is not None and not _native:
+        raise RuntimeError("the generic oracle library is already loaded")
+    _native = True
+
+
+def build_flags() -> str:
+    return " ".join(["gcc"] + BUILD_FLAGS + (["-march=native"] if _native else []))
 
 
 def lib():
     global _lib
     if _lib is None:
+        path = _LIB_NATIVE if _native else _LIB
         hdr = os.path.join(os.path.dirname(_SRC), "oracle.h")
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
-                                                                    os.path.getmtime(hdr)):
-            build()
-        _lib = C.CDLL(_LIB)
+        if not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(_SRC),
+                                                                     os.path.getmtime(hdr)):
+            build(native=_native)
+        _lib = C.CDLL(path)
         _declare(_lib)
     return _lib
 

@@ -377,3 +377,46 @@ def test_eo_sap_exact_block_limit_equals_mr_sap_limit(system):
     x1 = oracle.sap_eo(DIMS, BDIM, U, T, KAPPA, 2, 4, b)
     x2 = oracle.sap_eo(DIMS, BDIM, Ug, Tg, KAPPA, 2, 4, gauge_transform_spinor(g, b))
     assert np.linalg.norm(x2 - gauge_transform_spinor(g, x1)) < 1e-12 * np.linalg.norm(x1)
+
+
+def test_jacobi_block_equals_dense_jacobi_iteration(system):
+    """The QWS block solve (paper Section 2: a fixed number of Jacobi steps on
+    a domain of A = C^-1 D) against the same iteration written with dense
+    numpy matrices: rho = C_B^-1 r_B with C_B^-1 from numpy.linalg.inv of the
+    12 x 12 site matrices 1 + T, A_BB = C_B^-1 (D restricted to the block's
+    rows and columns), delta_0 = 0 and delta += rho - A_BB delta.  A dropped
+    C^-1 in rho, a wrong sign or a hop leaking over the block's faces each
+    fail it."""
+    U, T, M = system
+    r = synth.source(DIMS, 51)
+    eye = np.eye(12)
+    for blk in (0, 5):
+        sites = block_sites(DIMS, BDIM, blk)
+        idx = dof_indices(sites)
+        Cinv = np.zeros((idx.size, idx.size), np.complex128)
+        for i, s in enumerate(sites):
+            Cinv[12 * i:12 * i + 12, 12 * i:12 * i + 12] = np.linalg.inv(eye + T[s])
+        A = Cinv @ M[np.ix_(idx, idx)]
+        rho = Cinv @ r.reshape(-1)[idx]
+        for n_jac in (1, 2, 5):
+            ref = np.zeros_like(rho)
+            for _ in range(n_jac):
+                ref = ref + rho - A @ ref
+            got = oracle.jacobi_block(DIMS, BDIM, blk, U, T, KAPPA, n_jac, r)
+            assert np.abs(got.reshape(-1)[idx] - ref).max() < 1e-13 * np.abs(ref).max()
+            # nothing outside the block is written
+            rest = np.setdiff1d(np.arange(got.size), idx)
+            assert np.abs(got.reshape(-1)[rest]).max() == 0.0
+
+
+def test_jacobi_block_is_the_first_colour_of_a_jacobi_sap_cycle(system):
+    """From x = 0 the colour-0 half-sweep of the Jacobi smoother solves every
+    colour-0 block with r_B = b_B, and the colour-1 half-sweep leaves those
+    blocks alone: after one cycle they hold the single-block solve."""
+    U, T, M = system
+    b = synth.source(DIMS, 52)
+    x = oracle.sap_jacobi(DIMS, BDIM, U, T, KAPPA, 1, 3, b)
+    for blk in _colour_blocks(0)[:3]:
+        idx = dof_indices(block_sites(DIMS, BDIM, blk))
+        d = oracle.jacobi_block(DIMS, BDIM, blk, U, T, KAPPA, 3, b)
+        assert np.abs(x.reshape(-1)[idx] - d.reshape(-1)[idx]).max() < 1e-14 * np.abs(d).max()
