@@ -1,16 +1,22 @@
 """Benchmark: mixed-precision SAP-preconditioned flexible GCR on one MI355X.
 
 One step = one solve of D x = b to a true relative residual of 1e-10 on the
-16^3 x 32 synthetic gauge field (eps 0.3, kappa 0.1355, c_sw 1.0): FP32 SAP
-smoother (2 red/black cycles of 4 MR steps on 4^4 blocks) and FP32 w = D z
-inside an FP64 flexible GCR(16) with FP64 residual recomputation.  b is
-resident in HBM and x starts at zero.
+HBM-resident 32^3 x 64 synthetic gauge field (eps 0.25, kappa 0.1370, c_sw
+1.1): FP32 SAP smoother (2 red/black cycles of 4 MR steps on 4^4 blocks) and
+FP32 w = D z inside an FP64 flexible GCR(16) with FP64 residual
+recomputation.  b is resident in HBM and x starts at zero; iterations are
+replayed as captured HIP graphs.
 
-Prints one JSON line.  Besides the timed steps it reports the FP64-only GPU
-solve of the same system (mixed vs FP64), the roofline of the dominant kernel
-from HIP events recorded around every launch in the timed region, HBM
-bandwidth of the operator and the smoother on the HBM-resident 32^3 x 64
-lattice, and the FP64 CPU oracle timed on the host as a reference.
+Prints one JSON line: the timed solves (value = solves per second), the
+FP64-only GPU solve of the same system and the mixed/FP64 ratio, the
+roofline of the dominant kernel (the SAP half-sweep with x nonzero, HIP
+events around every launch in an eager pass of the same solves, against
+1008 algorithmic bytes per visited site), the operator's bandwidth, the
+library's plain copy kernel in the same run, the FP16 / BF16 smoothers, and
+the FP64 CPU oracle timed on the host.  Side measurements (cache-resident
+16^3 x 32, the 16^4 low-precision sub-run against the oracle, 24 right-hand
+sides on 24^3 x 48, the gradient, multigrid and the solver variants) follow
+unless --no-extras.
 """
 from __future__ import annotations
 
@@ -18,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -27,6 +34,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "Dslash/SAP HBM GB/s (% peak); time-to-1e-10 residual, mixed vs FP64, 1 GPU"
 SAP_KERNEL_SOURCES = ["sap.hip", "sap_pair.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp", "wave.hpp"]
+DSLASH_KERNEL_SOURCES = ["dslash.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp"]
 
 # Algorithmic bytes per visited site of one SAP half-sweep, FP32 storage:
 # every field the visit needs, counted once per site: b (96), x (96), the two
@@ -64,142 +72,109 @@ def source_hash(names):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, per_launch_alg_bytes: float):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+def load_traffic(record: str, sources):
+    """HBM bytes per launch from a committed rocprofv3 counter record, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{record}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_hash") != source_hash(SAP_KERNEL_SOURCES):
+    if rec.get("source_hash") != source_hash(sources):
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def sap_kernel_name(nblk: int) -> str:
-    """The FP32 SAP kernel the library launches by default: the lane-pair
-    kernel while a colour has at most 256 blocks (one per compute unit)."""
-    return "k_sap_pair<f32>" if nblk // 2 <= 256 else "k_sap_halfsweep<f32>"
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
-def sap_flops_per_application(V: int, n_cy: int) -> float:
-    """Flops of one SAP application from x = 0 (the four half-sweep modes of
-    n_cy = 2: 1, 2, then 0, 0), V / 2 sites per half-sweep."""
-    return V / 2 * (SAP_FLOPS[1] + SAP_FLOPS[2] + (2 * n_cy - 2) * SAP_FLOPS[0])
+def timed_events(torch, fn, n):
+    """Average duration (us) of fn() over n calls, HIP events on the current
+    stream (the one the library launches on), after one untimed call."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n * 1e3
 
 
-def sap_bytes_per_application(V: int, n_cy: int) -> float:
-    modes = [1, 2] + [0, 0] * (n_cy - 1)
-    return sum(SAP_BYTES_F32[m] for m in modes) * V / 2
+def copy_bandwidth(cs, torch, nbytes=1 << 30, reps=10):
+    """Read + write bandwidth of the library's plain copy kernel (GB/s)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    c = torch.empty_like(a)
+    us = timed_events(torch, lambda: cs.device_copy(c, a), reps)
+    del a, c
+    torch.cuda.empty_cache()
+    return dict(bytes_copied=nbytes, reps=reps, avg_us=round(us, 2), GBps=round(2 * nbytes / (us * 1e-6) / 1e9, 1),
+                kernel="k_stream_copy (cs_device_copy): one 16-byte word per lane, read + write counted")
 
 
-def cpu_baseline(dims, U, b, kappa, csw):
+def cpu_baseline(U, b, c, gpu_fp64_iters, small):
+    """The FP64 oracle (plain C, -O3 -march=native, OpenMP over sites and
+    blocks) on this host.  The metric's unit is solves/s on the 32^3x64
+    system; a full oracle solve there takes hours, so the sample is two
+    FGCR(16) iterations of that solve on all host threads, scaled by the
+    iteration count of the GPU's FP64-only solve.  Beside it: the operator
+    and one SAP application at 16^3x32 and 32^3x64 on all threads and at
+    16^3x32 on one thread."""
     import numpy as np
 
     import oracle
+    dims, kappa, csw = c["dims"], c["kappa"], c["csw"]
     threads = min(16, len(os.sched_getaffinity(0)))
+    res = dict(kind="oracle", cpu_model=cpu_model(), affinity_cpus=len(os.sched_getaffinity(0)),
+               build=oracle.build_flags())
     oracle.set_threads(threads)
     t0 = time.perf_counter()
     T = oracle.clover_field(dims, U, kappa, csw)
-    t1 = time.perf_counter()
-    x, st, it, rel, _ = oracle.fgcr(dims, (4, 4, 4, 4), U, T, kappa, b, n_cy=2, n_mr=4,
-                                    restart=16, tol=1e-10)
-    t2 = time.perf_counter()
-    return dict(value=1.0 / (t2 - t1), unit="solves/s", cores=threads, kind="oracle",
-                sample=(f"one complete FP64 SAP-FGCR(16) solve of the same "
-                        f"{'x'.join(map(str, dims))} field and source to 1e-10 by the plain-C "
-                        f"oracle ({it} iterations, status {st}, true relres {rel:.2e}); "
-                        f"clover build ({t1 - t0:.2f} s) excluded like on the GPU"),
-                seconds=t2 - t1, iterations=it), x
-
-
-def hbm_resident_measurement(cs, synth, torch, reps_d=20, reps_sap=10):
-    """Dslash and SAP bandwidth on 32^3 x 64 (working set far above the
-    256 MB last-level cache), FP32 storage, HIP events per launch; then
-    time-to-1e-10 for the FP32, FP16 and BF16 smoothers and the FP64-only
-    solve on the same field (low-precision storage: iteration penalty)."""
-    import numpy as np
-    c = synth.CONFIGS["lowprec_32x32x32x64"]
-    dims = c["dims"]
-    U = synth.gauge_field(dims, c["eps"], c["gauge_seed"])
-    b = synth.source(dims, c["src_seed"])
-    lat = cs.Lattice(dims)
-    op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
-    V = lat.volume
-    bin32 = lat.import_field(torch.from_numpy(b).cuda(), cs.F32)
-    out32 = lat.new_field(cs.F32)
-    for _ in range(3):
-        op.apply_D(out32, bin32, cs.F32)
-        op.sap_smooth(out32, bin32, cs.F32)
-    torch.cuda.synchronize()
-    cs.profile_reset()
-    cs.profile_enable(True)
-    for _ in range(reps_d):
-        op.apply_D(out32, bin32, cs.F32)
-    for _ in range(reps_sap):
-        op.sap_smooth(out32, bin32, cs.F32, n_cy=2, n_mr=4)
-    torch.cuda.synchronize()
-    cs.profile_enable(False)
-    nd, msd = cs.profile_query("dslash")
-    ns, mss = cs.profile_query("sap_halfsweep")
-    d_us = msd / nd * 1e3
-    sap_app_us = mss / reps_sap * 1e3
-    d_gbs = DSLASH_BYTES_F32 * V / (d_us * 1e-6) / 1e9
-    s_gbs = sap_bytes_per_application(V, 2) / (sap_app_us * 1e-6) / 1e9
-    res = dict(lattice="32x32x32x64", eps=c["eps"], kappa=c["kappa"], csw=c["csw"], storage="f32",
-               dslash_us=round(d_us, 2), dslash_GBps=round(d_gbs, 1),
-               dslash_frac_hbm_peak=round(d_gbs / HBM_PEAK_GBS, 4),
-               sap_application_us=round(sap_app_us, 2), sap_GBps=round(s_gbs, 1),
-               sap_frac_hbm_peak=round(s_gbs / HBM_PEAK_GBS, 4))
-    del bin32, out32
-    bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
-    xd = lat.new_field(cs.F64)
-    import oracle
-    for name, inner, basis in (("mixed_f32", cs.F32, cs.F32), ("mixed_f16", cs.F16, cs.F32),
-                               ("mixed_bf16", cs.BF16, cs.F32), ("fp64", cs.F64, cs.F64)):
-        p = cs.SolverParams(inner_prec=inner, basis_prec=basis)
-        xd.zero_()
-        op.gcr_solve(xd, bd, p, allow_fail=True)  # warm-up (workspace, graphs)
-        xd.zero_()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        st, stats = op.gcr_solve(xd, bd, p, allow_fail=True)
-        torch.cuda.synchronize()
-        res[f"{name}_time_to_1e-10_s"] = round(time.perf_counter() - t, 4)
-        res[f"{name}_iterations"] = stats[0]["iters"]
-        res[f"{name}_status"] = st
-        if name == "mixed_f32":
-            x = lat.export_field(xd, cs.F64).cpu().numpy()
-            res["mixed_f32_oracle_checked_relres"] = float(
-                f"{oracle.residual_norm(dims, U, c['kappa'], c['csw'], b, x) / np.linalg.norm(b):.3e}")
-    res["speedup_mixed_f32_vs_fp64"] = round(res["fp64_time_to_1e-10_s"] / res["mixed_f32_time_to_1e-10_s"], 3)
-    # the paper's outer solver, flexible BiCGStab, with the same FP32 smoother
-    t, it, st = time_bicgstab(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F64), 1)
-    res["fbicgstab_mixed_f32_time_to_1e-10_s"] = round(t, 4)
-    res["fbicgstab_mixed_f32_iterations"] = it
-    res["fbicgstab_mixed_f32_status"] = st
-    t, it, st = time_bicgstab(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32), 1)
-    res["sp_bicgstab_richardson_f32_time_to_1e-10_s"] = round(t, 4)
-    res["sp_bicgstab_richardson_f32_iterations"] = it
-    res["sp_bicgstab_richardson_f32_status"] = st
-    # FGCR with the even-odd block solver in the smoother
-    t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32,
-                                                                 block_solver=2), 1)
-    res["eo_smoother_f32_time_to_1e-10_s"] = round(t, 4)
-    res["eo_smoother_f32_iterations"] = it
-    res["eo_smoother_f32_status"] = st
-    # SAP-FGCR again right before the multigrid runs (median of 3), then MG
-    t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32), 3)
-    log("[bench] 32^3x64 two-level multigrid")
-    res["multigrid"] = multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, t, it)
-    log("[bench] 32^3x64 two-level multigrid, FP16 coarse matrices and prolongator")
-    res["multigrid_f16_storage"] = multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, t, it,
-                                                         half=True)
-    del op, bd, xd
-    torch.cuda.empty_cache()
-    log("[bench] 32^3x64 kappa scan towards the critical mass, SAP-FGCR vs MG-FGCR")
-    res["kappa_scan"] = kappa_scan(cs, synth, torch, lat, c, U, b)
+    t_cl = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.apply_D(dims, U, T, kappa, b)
+    t_d = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, st, it, rel, _ = oracle.fgcr(dims, (4, 4, 4, 4), U, T, kappa, b, n_cy=2, n_mr=4, restart=16, tol=1e-10,
+                                    max_iter=2)
+    t_2 = time.perf_counter() - t0
+    per_iter = t_2 / 2
+    solve_s = per_iter * gpu_fp64_iters
+    res.update(value=round(1.0 / solve_s, 6), unit="solves/s", cores=threads,
+               sample=(f"2 FGCR(16) iterations of the FP64 oracle on the {'x'.join(map(str, dims))} system "
+                       f"({t_2:.2f} s on {threads} threads, clover build {t_cl:.2f} s excluded), per-iteration "
+                       f"time x {gpu_fp64_iters} iterations (the FP64-only GPU solve's count) = "
+                       f"{solve_s:.1f} s per solve"),
+               seconds_per_iteration=round(per_iter, 3), estimated_solve_s=round(solve_s, 1))
+    per = {}
+    t0 = time.perf_counter()
+    oracle.sap(dims, (4, 4, 4, 4), U, T, kappa, 2, 4, b)
+    per["32x32x32x64"] = dict(threads=threads, apply_D_s=round(t_d, 3), sap_application_s=round(time.perf_counter() - t0, 3))
+    del T
+    Us, bs, cs_ = small
+    ds = cs_["dims"]
+    Ts = oracle.clover_field(ds, Us, cs_["kappa"], cs_["csw"])
+    for th in sorted({1, threads}):
+        oracle.set_threads(th)
+        t0 = time.perf_counter()
+        oracle.apply_D(ds, Us, Ts, cs_["kappa"], bs)
+        td = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.sap(ds, (4, 4, 4, 4), Us, Ts, cs_["kappa"], 2, 4, bs)
+        per[f"16x16x16x32_{th}_threads"] = dict(threads=th, apply_D_s=round(td, 4),
+                                                sap_application_s=round(time.perf_counter() - t0, 4))
+    oracle.set_threads(threads)
+    res["per_lattice"] = per
     return res
 
 
@@ -212,8 +187,8 @@ MG_PARAMS = dict(nv=16, n_cy_setup=4, n_mr=4, n_adapt=4, n_coarse=50, n_cy_post=
 def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap_it, reps=3, half=False):
     """MG-preconditioned FGCR to 1e-10 on the same system as SAP-FGCR:
     setup time, solve time (median of reps), iterations, per-family kernel
-    time of one solve, and the paper's comparison of one and of twelve
-    equations with the setup included."""
+    time of one solve, and the paper's outer solver (flexible BiCGStab)
+    around the same hierarchy."""
     import numpy as np
 
     import oracle
@@ -273,9 +248,6 @@ def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap
                 iterations=stats["iters"], status=st, oracle_checked_relres=float(f"{rel:.3e}"),
                 sap_fgcr_solve_s=round(sap_s, 4), sap_fgcr_iterations=sap_it,
                 solve_speedup_vs_sap_fgcr=round(sap_s / solve_s, 3),
-                one_equation_incl_setup_s=round(setup_s + solve_s, 4),
-                twelve_equations_incl_setup_s=round(setup_s + 12 * solve_s, 4),
-                twelve_equations_sap_fgcr_s=round(12 * sap_s, 4),
                 kernels_ms_one_solve={k: round(v[1], 3) for k, v in fam.items()},
                 fbicgstab=dict(solve_s=round(bsolve_s, 4), iterations=bstats["iters"], status=bst,
                                oracle_checked_relres=float(f"{brel:.3e}"),
@@ -497,218 +469,282 @@ def gradient_measurement(cs, synth, torch):
                 grad_U_maxabs=float(f"{gn:.4e}"), loss=float(f"{float(L):.6e}"))
 
 
+def cached_field(synth, cfg, cache_dir):
+    """Gauge field and source of a configuration, generated once and kept as
+    .npy files in cache_dir (if given) for later processes of the same job."""
+    import numpy as np
+    dims = cfg["dims"]
+    if cache_dir:
+        os.makedirs(cache_dir, exist_ok=True)
+        tag = f"{'x'.join(map(str, dims))}_{cfg['gauge_seed']}_{cfg['src_seed']}_{cfg['eps']}"
+        pu, pb = os.path.join(cache_dir, f"U_{tag}.npy"), os.path.join(cache_dir, f"b_{tag}.npy")
+        if os.path.exists(pu) and os.path.exists(pb):
+            return np.load(pu), np.load(pb)
+    U = synth.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    b = synth.source(dims, cfg["src_seed"])
+    if cache_dir:
+        np.save(pu + ".tmp.npy", U)
+        np.save(pb + ".tmp.npy", b)
+        os.replace(pu + ".tmp.npy", pu)
+        os.replace(pb + ".tmp.npy", pb)
+    return U, b
+
+
+def probe32(cs, synth, torch, prec, cache_dir, n_sap=10, n_d=10, n_copy=5):
+    """A short fixed workload on the 32^3x64 field for profiler passes:
+    n_sap SAP applications (2 cycles of 4 MR steps) from a nonzero start
+    vector, so that every half-sweep is a general (mode 0) visit, n_d
+    operator launches, and n_copy 1 GiB device copies by the library's
+    copy kernel (the bandwidth reference and counter calibration)."""
+    c = synth.CONFIGS["lowprec_32x32x32x64"]
+    U, b = cached_field(synth, c, cache_dir)
+    lat = cs.Lattice(c["dims"])
+    op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
+    del U
+    bd = lat.import_field(torch.from_numpy(b).cuda(), prec)
+    xd = lat.import_field(torch.from_numpy(b).cuda(), prec)
+    out = lat.new_field(prec)
+    torch.cuda.synchronize()
+    log(f"[probe32] {n_sap} SAP applications, prec {prec}")
+    for _ in range(n_sap):
+        op.sap_smooth(xd, bd, prec, n_cy=2, n_mr=4, x0_is_zero=False)
+    log(f"[probe32] {n_d} operator launches")
+    for _ in range(n_d):
+        op.apply_D(out, bd, prec)
+    torch.cuda.synchronize()
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    d = torch.empty_like(a)
+    log(f"[probe32] {n_copy} device copies of 1 GiB")
+    for _ in range(n_copy):
+        cs.device_copy(d, a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(probe="32x32x32x64", prec=prec, sap_applications=n_sap, sap_mode=0,
+                          dslash_launches=n_d, copies=n_copy, copy_bytes=n)), flush=True)
+
+
+def headline(cs, synth, torch, steps, warmup, cache_dir):
+    """The metric's configuration: time-to-1e-10 on 32^3 x 64, mixed FP32 vs
+    FP64-only, the SAP and operator rooflines, the copy reference, and the
+    FP16 / BF16 smoothers."""
+    import numpy as np
+
+    import oracle
+    c = synth.CONFIGS["lowprec_32x32x32x64"]
+    dims = c["dims"]
+    log(f"[bench] generating the {dims} gauge field and source")
+    U, b = cached_field(synth, c, cache_dir)
+    lat = cs.Lattice(dims)
+    V = lat.volume
+    op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
+    bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
+    xd = lat.new_field(cs.F64)
+    mixed = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, restart=16, n_cy=2, n_mr=4, tol=1e-10)
+    fp64 = cs.SolverParams(inner_prec=cs.F64, basis_prec=cs.F64, restart=16, n_cy=2, n_mr=4, tol=1e-10)
+
+    log(f"[bench] warmup {warmup}")
+    for _ in range(max(1, warmup)):
+        xd.zero_()
+        op.gcr_solve(xd, bd, mixed)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {steps} mixed-precision solves")
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        xd.zero_()
+        _, stats = op.gcr_solve(xd, bd, mixed)
+        iters.append(stats[0]["iters"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) / steps * 1e3
+    x_gpu = lat.export_field(xd, cs.F64).cpu().numpy()
+    oracle.set_threads(min(16, len(os.sched_getaffinity(0))))
+    rel_or = oracle.residual_norm(dims, U, c["kappa"], c["csw"], b, x_gpu) / np.linalg.norm(b)
+    del x_gpu
+
+    # The same solve again with HIP events around every kernel launch on the
+    # stream it runs on (events cannot sit inside the replayed graphs, so
+    # this pass runs the kernels eagerly).
+    log("[bench] profiled pass")
+    cs.profile_reset()
+    cs.profile_enable(True)
+    tp0 = time.perf_counter()
+    xd.zero_()
+    op.gcr_solve(xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, use_graph=False))
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    cs.profile_enable(False)
+    fam = {k: cs.profile_query(k) for k in ("sap_halfsweep", "sap_general", "sap_from_zero", "dslash", "blas")}
+    n_gen, ms_gen = fam["sap_general"]
+    sap_us = ms_gen / n_gen * 1e3
+    sap_bytes = SAP_BYTES_F32[0] * V / 2
+    achieved = sap_bytes / (sap_us * 1e-6) / 1e9
+    sap_flops = SAP_FLOPS[0] * V / 2
+    n_d, ms_d = fam["dslash"]
+    d_us_solve = ms_d / n_d * 1e3
+
+    log("[bench] copy reference and operator launches")
+    copy = copy_bandwidth(cs, torch)
+    b32 = lat.import_field(torch.from_numpy(b).cuda(), cs.F32)
+    o32 = lat.new_field(cs.F32)
+    d_us = timed_events(torch, lambda: op.apply_D(o32, b32, cs.F32), 20)
+    d_gbs = DSLASH_BYTES_F32 * V / (d_us * 1e-6) / 1e9
+    x32 = lat.import_field(torch.from_numpy(b).cuda(), cs.F32)
+    app_us = timed_events(torch, lambda: op.sap_smooth(x32, b32, cs.F32, n_cy=2, n_mr=4, x0_is_zero=False), 5)
+    del b32, o32, x32
+
+    roofline = dict(
+        bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+        frac=round(achieved / HBM_PEAK_GBS, 4),
+        traffic=load_traffic("sap_halfsweep_32x32x32x64", SAP_KERNEL_SOURCES),
+        kernel="k_sap_halfsweep<1, 1, 0> (FP32, one lane per site), general visits (x nonzero)",
+        lattice="32x32x32x64", avg_launch_us=round(sap_us, 2), launches=n_gen,
+        alg_bytes_per_launch=int(sap_bytes), alg_bytes_per_visited_site=SAP_BYTES_F32[0],
+        visited_sites_per_launch=V // 2,
+        frac_of_copy=round(achieved / copy["GBps"], 4),
+        alu=dict(achieved=round(sap_flops / (sap_us * 1e-6) / 1e12, 2), peak=round(FP32_VALU_PEAK_TFLOPS, 1),
+                 unit="TFLOP/s", frac=round(sap_flops / (sap_us * 1e-6) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4),
+                 flops_per_visited_site=SAP_FLOPS[0]),
+        note=("average duration of the general (mode 0) half-sweeps, HIP events around every launch in an "
+              "eager pass of the timed solve; traffic = FETCH_SIZE x 2 + WRITE_SIZE per launch from the "
+              "committed counter record (null when the kernel sources changed since)"))
+
+    log("[bench] FP64-only GPU solves")
+    fp64_s, fp64_it, fp64_st = time_gcr(cs, torch, op, xd, bd, fp64, 2)
+    lowp = {}
+    for name, inner in (("f16", cs.F16), ("bf16", cs.BF16)):
+        log(f"[bench] {name} smoother solves")
+        t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=inner, basis_prec=cs.F32), 2)
+        lowp[name] = dict(time_to_1e10_ms=round(t * 1e3, 2), iterations=it, status=st,
+                          speedup_vs_fp64=round(fp64_s / t, 3))
+    del op, bd, xd
+    torch.cuda.empty_cache()
+    out = dict(metric=METRIC, value=round(steps / (t1 - t0), 4), unit="solves/s",
+               n_gpus=1, steps=steps, warmup=warmup, ms_per_step=round(ms_per_step, 3),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32/f64",
+               data="synthetic",
+               config=dict(workload=("mixed_32x32x32x64: SAP(2 cycles x 4 MR, 4^4 blocks, FP32)-preconditioned "
+                                     "FP64 flexible GCR(16) to a true relative residual of 1e-10, HIP-graph replay"),
+                           lattice="32x32x32x64", eps=c["eps"], kappa=c["kappa"], csw=c["csw"],
+                           gauge_seed=c["gauge_seed"], source_seed=c["src_seed"]),
+               time_to_1e10_ms=round(ms_per_step, 2), iterations=int(np.median(iters)),
+               fp64_time_to_1e10_ms=round(fp64_s * 1e3, 2), fp64_iterations=fp64_it, fp64_status=fp64_st,
+               speedup_mixed_vs_fp64=round(fp64_s * 1e3 / ms_per_step, 3),
+               oracle_checked_relres=float(f"{rel_or:.3e}"),
+               low_precision_smoothers=lowp,
+               dslash=dict(kernel="FP32 operator, one launch", avg_us=round(d_us, 2), GBps=round(d_gbs, 1),
+                           frac_hbm_peak=round(d_gbs / HBM_PEAK_GBS, 4), frac_of_copy=round(d_gbs / copy["GBps"], 4),
+                           alg_bytes_per_site=DSLASH_BYTES_F32, avg_us_in_solve=round(d_us_solve, 2),
+                           traffic=load_traffic("dslash_32x32x32x64", DSLASH_KERNEL_SOURCES)),
+               sap_application=dict(avg_us=round(app_us, 1),
+                                    GBps=round(4 * sap_bytes / (app_us * 1e-6) / 1e9, 1),
+                                    note="2 cycles of 4 MR steps from a nonzero x (four general half-sweeps)"),
+               copy_reference=copy,
+               kernels_in_profiled_solve={k: dict(launches=v[0], total_ms=round(v[1], 3),
+                                                  avg_us=round(v[1] / max(v[0], 1) * 1e3, 2))
+                                          for k, v in fam.items()},
+               profiled_solve_ms=round((tp1 - tp0) * 1e3, 2),
+               roofline=roofline)
+    return out, (U, b, c)
+
+
+def cache_resident_16(cs, synth, torch, reps=10):
+    """The 16^3 x 32 system (working set inside the 256 MB last-level cache):
+    mixed and FP64-only time to 1e-10."""
+    c = synth.CONFIGS["mixed_16x16x16x32"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["eps"], c["gauge_seed"])
+    b = synth.source(dims, c["src_seed"])
+    lat = cs.Lattice(dims)
+    op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
+    bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
+    xd = lat.new_field(cs.F64)
+    tm, itm, stm = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32), reps)
+    t64, it64, st64 = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F64, basis_prec=cs.F64), reps)
+    return dict(lattice="16x16x16x32", eps=c["eps"], kappa=c["kappa"], csw=c["csw"],
+                mixed_time_to_1e10_ms=round(tm * 1e3, 3), mixed_iterations=itm, mixed_status=stm,
+                fp64_time_to_1e10_ms=round(t64 * 1e3, 3), fp64_iterations=it64, fp64_status=st64,
+                speedup_mixed_vs_fp64=round(t64 / tm, 3),
+                note="cache-resident: the working set fits the 256 MB last-level cache; no HBM fraction quoted")
+
+
+def solver_variants(cs, synth, torch, U, b, c):
+    """The smoother and outer-solver variants and the two-level multigrid
+    preconditioner on the 32^3 x 64 system."""
+    import numpy as np
+
+    import oracle
+    dims = c["dims"]
+    lat = cs.Lattice(dims)
+    op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
+    bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
+    xd = lat.new_field(cs.F64)
+    res = {}
+    t, it, st = time_bicgstab(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F64), 1)
+    res["fbicgstab_f32_smoother"] = dict(time_to_1e10_ms=round(t * 1e3, 2), iterations=it, status=st)
+    t, it, st = time_bicgstab(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32), 1)
+    res["sp_bicgstab_in_fp64_richardson"] = dict(time_to_1e10_ms=round(t * 1e3, 2), iterations=it, status=st)
+    t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32,
+                                                                block_solver=1), 1)
+    res["fgcr_jacobi_smoother"] = dict(time_to_1e10_ms=round(t * 1e3, 2), iterations=it, status=st)
+    t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32,
+                                                                block_solver=2), 1)
+    res["fgcr_even_odd_block_mr"] = dict(time_to_1e10_ms=round(t * 1e3, 2), iterations=it, status=st)
+    t, it, st = time_gcr(cs, torch, op, xd, bd, cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32), 1)
+    log("[bench] 32^3x64 two-level multigrid")
+    res["multigrid"] = multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, t, it)
+    del op, bd, xd
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-hbm", action="store_true", help="skip the 32^3x64 side measurement")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the low-precision, multi-RHS and gradient side measurements")
-    ap.add_argument("--hbm-only", action="store_true",
-                    help="only the 32^3x64 HBM-resident operator, smoother and solve measurement")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a device copy of 1 GiB five times (counter calibration)")
-    ap.add_argument("--sap-probe", action="store_true",
-                    help="only 10 FP32 SAP applications and 10 FP32 operator launches on the 16^3x32 "
-                         "benchmark field (a short run for hardware-counter passes)")
+                    help="skip the side measurements (cache-resident lattice, low-precision sub-run, multi-RHS, "
+                         "gradient, solver variants and multigrid)")
+    ap.add_argument("--paper-comparisons", action="store_true",
+                    help="also run the kappa scan towards the critical mass and the one/twelve-equation costs "
+                         "with the multigrid setup (the shape of the paper's comparisons; off by default)")
+    ap.add_argument("--field-cache", default="",
+                    help="directory in which generated gauge fields are kept between runs")
+    ap.add_argument("--probe32", action="store_true",
+                    help="only mode-0 SAP applications, operator launches and device copies on the "
+                         "32^3x64 field (a short run for kernel-trace and hardware-counter passes)")
+    ap.add_argument("--probe-prec", default="f32", choices=["f64", "f32", "f16", "bf16"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    if args.copy_calibration:
-        n = 1 << 30
-        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
-        c = torch.empty_like(a)
-        for _ in range(5):
-            c.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps(dict(copy_bytes=n, copies=5)), flush=True)
-        return
 
     from paper_2112_00501_amd import cloversap as cs
     from paper_2112_00501_amd import synth
 
-    if args.sap_probe:
-        cfg = synth.CONFIGS["mixed_16x16x16x32"]
-        dims = cfg["dims"]
-        lat = cs.Lattice(dims)
-        op = cs.Operator(lat, torch.from_numpy(synth.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])).cuda(),
-                         cfg["kappa"], cfg["csw"])
-        b32 = lat.import_field(torch.from_numpy(synth.source(dims, cfg["src_seed"])).cuda(), cs.F32)
-        x32 = lat.new_field(cs.F32)
-        for _ in range(10):
-            op.sap_smooth(x32, b32, cs.F32, n_cy=2, n_mr=4)
-            op.apply_D(x32, b32, cs.F32)
-        torch.cuda.synchronize()
-        print(json.dumps(dict(sap_applications=10, dslash_launches=10, lattice="16x16x16x32")), flush=True)
-        return
-
-    if args.hbm_only:
-        log("[bench] 32^3x64 HBM-resident measurement")
-        print(json.dumps(dict(hbm_resident_32x32x32x64=hbm_resident_measurement(cs, synth, torch))), flush=True)
-        return
-
-    cfg = synth.CONFIGS["mixed_16x16x16x32"]
-    dims, kappa, csw = cfg["dims"], cfg["kappa"], cfg["csw"]
-    log(f"[bench] generating {dims} gauge field and source")
-    U = synth.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
-    b = synth.source(dims, cfg["src_seed"])
-    lat = cs.Lattice(dims)
-    V = lat.volume
-    op = cs.Operator(lat, torch.from_numpy(U).cuda(), kappa, csw)
-    bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
-    xd = lat.new_field(cs.F64)
-    mixed = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, restart=16, n_cy=2, n_mr=4,
-                            tol=1e-10)
-    fp64 = cs.SolverParams(inner_prec=cs.F64, basis_prec=cs.F64, restart=16, n_cy=2, n_mr=4,
-                           tol=1e-10)
-
-    log(f"[bench] warmup {args.warmup}")
-    for _ in range(args.warmup):
-        xd.zero_()
-        op.gcr_solve(xd, bd, mixed)
-    torch.cuda.synchronize()
-
-    log(f"[bench] timing {args.steps} mixed-precision solves")
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        xd.zero_()
-        _, stats = op.gcr_solve(xd, bd, mixed)
-        iters.append(stats[0]["iters"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) / args.steps * 1e3
-    x_gpu = lat.export_field(xd, cs.F64).cpu().numpy()
-
-    # The same steps again with HIP events recorded around every kernel launch
-    # on the stream it runs on (per-launch events cannot be placed inside the
-    # captured graphs of the timed pass, so this pass runs the kernels eagerly).
-    log(f"[bench] profiled pass of {args.steps} solves")
-    cs.profile_reset()
-    cs.profile_enable(True)
-    torch.cuda.synchronize()
-    tp0 = time.perf_counter()
-    for _ in range(args.steps):
-        xd.zero_()
-        op.gcr_solve(xd, bd, mixed)
-    torch.cuda.synchronize()
-    tp1 = time.perf_counter()
-    cs.profile_enable(False)
-    fam = {k: cs.profile_query(k) for k in ("sap_halfsweep", "dslash", "blas")}
-
-    # dominant kernel: the SAP half-sweep (largest summed time)
-    n_sap, ms_sap = fam["sap_halfsweep"]
-    n_apps = n_sap // 4
-    alg_bytes = sap_bytes_per_application(V, 2) * n_apps
-    per_launch_bytes = alg_bytes / n_sap
-    avg_us = ms_sap / n_sap * 1e3
-    achieved = per_launch_bytes / (avg_us * 1e-6) / 1e9
-    per_launch_flops = sap_flops_per_application(V, 2) * n_apps / n_sap
-    alu_tflops = per_launch_flops / (avg_us * 1e-6) / 1e12
-    dominant = max(fam, key=lambda k: fam[k][1])
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=load_traffic("sap_halfsweep_16x16x16x32", per_launch_bytes),
-                    kernel=sap_kernel_name(V // 256), avg_launch_us=round(avg_us, 2),
-                    alg_bytes_per_launch=int(per_launch_bytes), launches=n_sap,
-                    dominant_by_time=dominant,
-                    profiled_pass_ms_per_step=round((tp1 - tp0) / args.steps * 1e3, 3),
-                    alu=dict(achieved=round(alu_tflops, 2), peak=round(FP32_VALU_PEAK_TFLOPS, 1),
-                             unit="TFLOP/s", frac=round(alu_tflops / FP32_VALU_PEAK_TFLOPS, 4),
-                             flops_per_launch=int(per_launch_flops),
-                             note="FP32 vector arithmetic without packed FP32; at this lattice the "
-                                  "half-sweep is bound by instruction issue, not by HBM"),
-                    note=("kernel durations from HIP events around every launch in a profiled pass of "
-                          "the same steps (eager); working set ~90 MB fits the 256 MB last-level cache "
-                          "at this lattice; the HBM-resident figure is hbm_resident_32x32x32x64.sap_GBps"))
-
-    log("[bench] FP64-only GPU solves")
-    fp64_times, fp64_iters = [], []
-    for _ in range(4):
-        xd.zero_()
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        _, st64 = op.gcr_solve(xd, bd, fp64)
-        torch.cuda.synchronize()
-        fp64_times.append(time.perf_counter() - ta)
-        fp64_iters.append(st64[0]["iters"])
-    fp64_ms = float(np.median(fp64_times[1:])) * 1e3
-
-    log("[bench] flexible BiCGStab solves")
-    bi64 = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F64, n_cy=2, n_mr=4, tol=1e-10)
-    bi_s, bi_it, bi_st = time_bicgstab(cs, torch, op, xd, bd, bi64, 5)
-    x_bi = lat.export_field(xd, cs.F64).cpu().numpy()
-    bi32 = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10)
-    sp_s, sp_it, sp_st = time_bicgstab(cs, torch, op, xd, bd, bi32, 5)
-    x_sp = lat.export_field(xd, cs.F64).cpu().numpy()
-    log("[bench] solves with the Jacobi smoother on C^-1 D")
-    jac_gcr = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10, block_solver=1)
-    jg_s, jg_it, jg_st = time_gcr(cs, torch, op, xd, bd, jac_gcr, 5)
-    jq_s, jq_it, jq_st = time_bicgstab(cs, torch, op, xd, bd, cs.SolverParams(
-        inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10, block_solver=1), 5)
-    log("[bench] solves with even-odd preconditioned block MR")
-    eo_gcr = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, n_cy=2, n_mr=4, tol=1e-10, block_solver=2)
-    eg_s, eg_it, eg_st = time_gcr(cs, torch, op, xd, bd, eo_gcr, 5)
-
-    log("[bench] two-level multigrid on the same system")
-    mg16 = multigrid_measurement(cs, synth, torch, op, lat, cfg, U, b, bd, xd, ms_per_step / 1e3,
-                                 int(np.median(iters)), reps=5)
-
     import oracle
-    rel_or = oracle.residual_norm(dims, U, kappa, csw, b, x_gpu) / np.linalg.norm(b)
-    rel_bi = oracle.residual_norm(dims, U, kappa, csw, b, x_bi) / np.linalg.norm(b)
-    rel_sp = oracle.residual_norm(dims, U, kappa, csw, b, x_sp) / np.linalg.norm(b)
+    # the oracle built for this host's CPU (same arithmetic as the generic
+    # build: no contraction, no reordering), for the residual checks and the
+    # CPU baseline
+    oracle.use_native_build()
 
-    out = dict(metric=METRIC, value=round(args.steps / (t1 - t0), 3), unit="solves/s",
-               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 3),
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32/f64",
-               data="synthetic",
-               config=dict(workload=("mixed_16x16x16x32: SAP(2 cycles x 4 MR, 4^4 blocks, FP32)-"
-                                     "preconditioned FP64 flexible GCR(16) to 1e-10, HIP-graph replay"),
-                           lattice="16x16x16x32", eps=cfg["eps"], kappa=kappa, csw=csw,
-                           gauge_seed=cfg["gauge_seed"], source_seed=cfg["src_seed"]),
-               time_to_1e10_ms=round(ms_per_step, 3), iterations=int(np.median(iters)),
-               fp64_time_to_1e10_ms=round(fp64_ms, 3), fp64_iterations=int(np.median(fp64_iters)),
-               speedup_mixed_vs_fp64=round(fp64_ms / ms_per_step, 3),
-               oracle_checked_relres=float(f"{rel_or:.3e}"),
-               fbicgstab=dict(time_to_1e10_ms=round(bi_s * 1e3, 3), iterations=bi_it, status=bi_st,
-                              oracle_checked_relres=float(f"{rel_bi:.3e}"),
-                              note="flexible BiCGStab (two SAP and two operator applications per "
-                                   "iteration), same FP32 smoother, median of 5"),
-               jacobi_smoother=dict(fgcr_time_to_1e10_ms=round(jg_s * 1e3, 3), fgcr_iterations=jg_it,
-                                    fgcr_status=jg_st,
-                                    sp_bicgstab_richardson_time_to_1e10_ms=round(jq_s * 1e3, 3),
-                                    sp_bicgstab_richardson_iterations=jq_it, sp_bicgstab_richardson_status=jq_st,
-                                    note="SAP on C^-1 D with 4 Jacobi steps per block (the QWS smoother form), "
-                                         "FP32, median of 5"),
-               eo_smoother=dict(fgcr_time_to_1e10_ms=round(eg_s * 1e3, 3), fgcr_iterations=eg_it, fgcr_status=eg_st,
-                                note="SAP with 4 even-odd preconditioned MR steps per block (Schur complement on "
-                                     "the even sites), FP32, one lane per site, median of 5"),
-               sp_bicgstab_richardson=dict(time_to_1e10_ms=round(sp_s * 1e3, 3), iterations=sp_it, status=sp_st,
-                                           oracle_checked_relres=float(f"{rel_sp:.3e}"),
-                                           note="FP32-vector BiCGStab inner solves to 1e-5 inside an FP64 "
-                                                "Richardson iteration, same FP32 smoother, median of 5"),
-               multigrid=mg16,
-               kernels={k: dict(launches=v[0], total_ms=round(v[1], 3),
-                                avg_us=round(v[1] / max(v[0], 1) * 1e3, 2))
-                        for k, v in fam.items()},
-               roofline=roofline)
-    del op, lat, bd, xd
+    if args.probe32:
+        probe32(cs, synth, torch, cs.PREC[args.probe_prec], args.field_cache)
+        return
+
+    out, (U, b, c) = headline(cs, synth, torch, args.steps, args.warmup, args.field_cache)
     torch.cuda.empty_cache()
-    if not args.no_hbm:
-        log("[bench] 32^3x64 HBM-resident measurement")
-        out["hbm_resident_32x32x32x64"] = hbm_resident_measurement(cs, synth, torch)
-        torch.cuda.empty_cache()
     if not args.no_extras:
+        log("[bench] 16^3x32 cache-resident solves")
+        out["cache_resident_16x16x16x32"] = cache_resident_16(cs, synth, torch)
+        log("[bench] 32^3x64 solver variants and multigrid")
+        out["variants_32x32x32x64"] = solver_variants(cs, synth, torch, U, b, c)
         log("[bench] 16^4 low-precision sub-run against the oracle")
         out["lowprec_sub_16x16x16x16"] = lowprec_subrun(cs, synth, torch)
         log("[bench] 24 right-hand sides on 24^3x48")
@@ -716,10 +752,16 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] gradient on 32^3x64")
         out["grad_32x32x32x64"] = gradient_measurement(cs, synth, torch)
+        torch.cuda.empty_cache()
+    if args.paper_comparisons:
+        log("[bench] kappa scan towards the critical mass, SAP-FGCR vs MG-FGCR")
+        out["kappa_scan_32x32x32x64"] = kappa_scan(cs, synth, torch, cs.Lattice(c["dims"]), c, U, b)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
-        cb, _ = cpu_baseline(dims, U, b, kappa, csw)
-        out["cpu_baseline"] = cb
+        cs16 = synth.CONFIGS["mixed_16x16x16x32"]
+        small = (synth.gauge_field(cs16["dims"], cs16["eps"], cs16["gauge_seed"]),
+                 synth.source(cs16["dims"], cs16["src_seed"]), cs16)
+        out["cpu_baseline"] = cpu_baseline(U, b, c, out["fp64_iterations"], small)
     print(json.dumps(out), flush=True)
 
 

@@ -439,10 +439,19 @@ int cs_force(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_li
  * launches and their summed duration (ms) for a kernel family name (one of
  * "dslash", "sap_halfsweep", "blas", "convert", "clover_build"), after
  * synchronising the recorded events ("force" covers cs_force).
- * cs_profile_reset clears the counters. */
+ * "copy" covers cs_device_copy; "sap_general" and "sap_from_zero" split the
+ * "sap_halfsweep" launches into those with x nonzero everywhere and the two
+ * half-sweeps of a cycle that start from x = 0.  cs_profile_reset clears the counters. */
 int cs_profile_enable(int on);
 int cs_profile_query(const char* name, long long* count, double* total_ms);
 int cs_profile_reset(void);
+
+/* Bandwidth reference (not part of the method): dst = src for `bytes` bytes
+ * of device memory by a plain streaming-copy kernel, so that the field
+ * kernels' HBM rates can be set beside what a copy reaches on the same GPU
+ * in the same run.  bytes and both pointers must be multiples of 16 and the
+ * buffers must not overlap (CS_ERR_INVALID); asynchronous on the stream. */
+int cs_device_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,27 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+
+
+def _host_tag() -> str:
+    """Short tag of this host's CPU (model and feature flags), so that a
+    -march=native build is only ever loaded on the kind of CPU it was built
+    for."""
+    import hashlib
+    h = hashlib.sha1()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith(("model name", "flags")):
+                    h.update(line.encode())
+                    if line.startswith("flags"):
+                        break
+    except OSError:
+        h.update(b"unknown")
+    return h.hexdigest()[:10]
+
+
+_LIB_NATIVE = os.path.join(_HERE, f"liboracle_native_{_host_tag()}.so")
 
 # Plain ISO C11 (so no floating-point contraction and no reassociation): the
 # arithmetic is exactly what the source says.  The default library is built

@@ -68,7 +68,7 @@ EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_des
             "cs_mg_export", "cs_mg_restrict", "cs_mg_prolong", "cs_mg_coarse_apply",
             "cs_mg_coarse_solve", "cs_mg_apply", "cs_gcr_solve_mg", "cs_bicgstab_solve_mg", "cs_force",
             "cs_profile_enable",
-            "cs_profile_query", "cs_profile_reset"]
+            "cs_profile_query", "cs_profile_reset", "cs_device_copy"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -128,6 +128,7 @@ def load_library(path: str = LIB_PATH):
     L.cs_profile_enable.argtypes = [I]
     L.cs_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
     L.cs_profile_reset.argtypes = []
+    L.cs_device_copy.argtypes = [P, P, C.c_size_t, P]
     _lib = L
     return L
 
@@ -523,6 +524,15 @@ def profile_enable(on: bool = True):
 
 def profile_reset():
     _check(_lib.cs_profile_reset(), "cs_profile_reset")
+
+
+def device_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    """dst = src by the library's plain streaming-copy kernel (the bandwidth
+    reference of the field kernels); both contiguous device tensors."""
+    nbytes = src.numel() * src.element_size()
+    _need(dst, nbytes, "device_copy dst")
+    load_library()
+    _check(_lib.cs_device_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)), "cs_device_copy")
 
 
 def profile_query(name: str):

@@ -793,6 +793,17 @@ int cs_force(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_li
     return ok();
 }
 
+int cs_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src) return fail(CS_ERR_NULL, "dst and src must be non-NULL");
+    if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)
+        return fail(CS_ERR_INVALID, "bytes and both pointers must be multiples of 16");
+    const char* d = (const char*)dst;
+    const char* sp = (const char*)src;
+    if (d < sp + bytes && sp < d + bytes) return fail(CS_ERR_INVALID, "dst and src overlap");
+    CS_HIP(cs::stream_copy(dst, src, bytes, (hipStream_t)stream));
+    return ok();
+}
+
 int cs_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_pm);
     g_prof_on = on != 0;

@@ -892,4 +892,26 @@ hipError_t bicg_promote_add(const BlasCtx& c, void* x64, const void* e32, double
     return hipGetLastError();
 }
 
+// ------------------------------------------------------- bandwidth reference
+
+// dst = src over n 16-byte words: a plain streaming copy, the measured
+// bandwidth reference for the field kernels.  One word per lane and one
+// launch-wide pass (no grid-stride loop): on MI355X this pattern copies
+// faster than a persistent grid that keeps several loads in flight per lane.
+__global__ __launch_bounds__(TPB) void k_stream_copy(float4* __restrict__ dst, const float4* __restrict__ src,
+                                                     size_t n) {
+    const size_t i = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    ProfScope ps("copy", s);
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    const size_t wgs = (n + TPB - 1) / TPB;
+    if (wgs > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)wgs), dim3(TPB), 0, s, (float4*)dst, (const float4*)src, n);
+    return hipGetLastError();
+}
+
 }  // namespace cs

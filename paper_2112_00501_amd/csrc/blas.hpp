@@ -123,4 +123,8 @@ hipError_t bicg_norm2(const BlasCtx& c, BiScalars* sc, BiTail* tail, const void*
 hipError_t bicg_demote(const BlasCtx& c, const void* src64, void* dst32, double scale, hipStream_t s);
 hipError_t bicg_promote_add(const BlasCtx& c, void* x64, const void* e32, double scale, hipStream_t s);
 
+// dst = src for bytes (a multiple of 16; both 16-byte aligned): the plain
+// copy kernel the field kernels' bandwidth is compared with.
+hipError_t stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 }  // namespace cs

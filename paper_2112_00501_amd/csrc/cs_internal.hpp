@@ -55,6 +55,11 @@ constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
 #ifndef CS_DSLASH_ROLLED
 #define CS_DSLASH_ROLLED 1
 #endif
+// Float-arithmetic operator: 0 = every neighbour read through the caches,
+// 1 = the block's spinor staged in LDS, 2 = its spinor and links staged.
+#ifndef CS_DSLASH_STAGED
+#define CS_DSLASH_STAGED 1
+#endif
 #ifndef CS_SAP_LDS_RESIDUAL
 #define CS_SAP_LDS_RESIDUAL 1
 #endif

@@ -54,6 +54,124 @@ __global__ CS_DSLASH_BOUNDS void k_dslash(Geom g, const void* __restrict__ links
     SpinorIO<POUT>::store((char*)out + r * out_stride, g.nblk, blk, l, o);
 }
 
+// Staged form of the same operator (float arithmetic): the block's input
+// spinor is copied to LDS once (converted to float, with the gamma5 sign of
+// D^dag applied), and every in-block hop reads its neighbour from there;
+// only the hops that leave the block read HBM.  With LINKS_LDS the block's
+// links (rows 0 and 1) are staged too, so the backward hops inside the block
+// take the neighbour lane's link from LDS instead of re-reading it.  Each
+// spinor and link word of the block is then fetched from HBM once by its own
+// workgroup; the plain kernel above fetches each spinor once per hop and
+// relies on the caches for the reuse.
+template <int P, bool DAG>
+struct StagedSpinor {
+    const lds_cpx<float> (*s)[BLOCK_SITES];
+    const void* base;
+    int nblk;
+    __device__ __forceinline__ bool want(bool) const { return true; }
+    template <typename R>
+    __device__ __forceinline__ void load_nb(int blk, int l, bool inside, cpx<R>* c) const {
+        if (inside) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) c[k] = {(R)s[k][l].re, (R)s[k][l].im};
+        } else {
+            using RS = typename SpinorIO<P>::R;
+            cpx<RS> t[12];
+            SpinorIO<P>::load(base, nblk, blk, l, t);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) c[k] = {(R)t[k].re, (R)t[k].im};
+            if (DAG) negate_lower(c);
+        }
+    }
+};
+
+template <int PLINK>
+struct StagedLinks {
+    const lds_cpx<float> (*sm)[6][BLOCK_SITES];
+    const void* base;
+    template <typename R>
+    __device__ __forceinline__ void load(int blk, int l, int mu, bool inside, cpx<R>* u) const {
+        if (inside) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) u[k] = {(R)sm[mu][k][l].re, (R)sm[mu][k][l].im};
+            su3_row2(u);
+        } else {
+            load_link<PLINK, R, false>(base, blk, l, mu, u);
+        }
+    }
+};
+
+template <bool ON>
+struct StagedLinkSmem { lds_cpx<float> u[4][6][BLOCK_SITES]; };
+template <>
+struct StagedLinkSmem<false> { lds_cpx<float> u[1][6][1]; };
+
+template <int PIN, int POUT, int PLINK, bool DAG, bool SUB, bool LINKS_LDS>
+__global__ CS_DSLASH_BOUNDS void k_dslash_staged(Geom g, const void* __restrict__ links,
+                                                 const void* __restrict__ clover, float kappa,
+                                                 void* __restrict__ out, const void* __restrict__ in,
+                                                 const void* __restrict__ sub, size_t in_stride,
+                                                 size_t out_stride) {
+    __shared__ lds_cpx<float> s_psi[12][BLOCK_SITES];
+    __shared__ StagedLinkSmem<LINKS_LDS> s_lk;
+    const int blk = xcd_remap(blockIdx.x, g.nblk), l = threadIdx.x, r = blockIdx.y;
+    const char* src = (const char*)in + r * in_stride;
+    const BlockPos p = block_pos(g, blk);
+
+    {
+        using RS = typename SpinorIO<PIN>::R;
+        cpx<RS> t[12];
+        SpinorIO<PIN>::load(src, g.nblk, blk, l, t);
+        cpx<float> v[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = {(float)t[k].re, (float)t[k].im};
+        if (DAG) negate_lower(v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s_psi[k][l].set(v[k]);
+    }
+    if constexpr (LINKS_LDS) {
+        for (int mu = 0; mu < 4; ++mu) {
+            cpx<typename LinkIO<PLINK>::R> u[6];
+            LinkIO<PLINK>::load6(links, blk, l, mu, u);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) s_lk.u[mu][k][l] = {(float)u[k].re, (float)u[k].im};
+        }
+    }
+    __syncthreads();
+
+    cpx<float> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
+    StagedSpinor<PIN, DAG> ls{s_psi, src, g.nblk};
+    if constexpr (LINKS_LDS) {
+        StagedLinks<PLINK> lk{s_lk.u, links};
+        hopping_sum_rolled<float>(g, p, l, ls, lk, acc);
+    } else {
+        GlobalLinks<PLINK, false> lk{links};
+        hopping_sum_rolled<float>(g, p, l, ls, lk, acc);
+    }
+
+    cpx<float> self[12], res[12];
+    ls.load_nb(blk, l, true, self);
+    float cl[72];
+    CloverIO<float>::load(clover, blk, l, cl);
+    clover_apply(cl, self, res);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) res[i] = {res[i].re - kappa * acc[i].re, res[i].im - kappa * acc[i].im};
+    if (DAG) negate_lower(res);
+    using RO = typename SpinorIO<POUT>::R;
+    cpx<RO> o[12];
+    if (SUB) {
+        SpinorIO<POUT>::load((const char*)sub + r * out_stride, g.nblk, blk, l, o);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) o[i] = {o[i].re - (RO)res[i].re, o[i].im - (RO)res[i].im};
+    } else {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) o[i] = {(RO)res[i].re, (RO)res[i].im};
+    }
+    SpinorIO<POUT>::store((char*)out + r * out_stride, g.nblk, blk, l, o);
+}
+
 // Multi-right-hand-side variant: work item = (block, tile of right-hand
 // sides).  The block's links go to LDS once and its clover term to registers
 // once per item; every right-hand side of the tile reuses them.  Backward
@@ -155,6 +273,18 @@ hipError_t launch3(const OpData& op, bool dagger, void* out, const void* in, con
     const size_t is = spinor_bytes_per_site(PIN) * op.g.V, os = spinor_bytes_per_site(POUT) * op.g.V;
     const void* cl = PIN == P_F64 ? op.clover64 : op.clover32;
     const void* lk = op.links[PLINK];
+    if constexpr (PIN != P_F64 && CS_DSLASH_STAGED) {
+        constexpr bool LL = CS_DSLASH_STAGED == 2;
+        const float k = (float)op.kappa;
+        if (dagger) {
+            if (sub) hipLaunchKernelGGL((k_dslash_staged<PIN, POUT, PLINK, true, true, LL>), grid, block, 0, s, op.g, lk, cl, k, out, in, sub, is, os);
+            else hipLaunchKernelGGL((k_dslash_staged<PIN, POUT, PLINK, true, false, LL>), grid, block, 0, s, op.g, lk, cl, k, out, in, sub, is, os);
+        } else {
+            if (sub) hipLaunchKernelGGL((k_dslash_staged<PIN, POUT, PLINK, false, true, LL>), grid, block, 0, s, op.g, lk, cl, k, out, in, sub, is, os);
+            else hipLaunchKernelGGL((k_dslash_staged<PIN, POUT, PLINK, false, false, LL>), grid, block, 0, s, op.g, lk, cl, k, out, in, sub, is, os);
+        }
+        return hipGetLastError();
+    }
     if (dagger) {
         if (sub) hipLaunchKernelGGL((k_dslash<PIN, POUT, PLINK, true, true>), grid, block, 0, s, op.g, lk, cl, op.kappa, out, in, sub, is, os);
         else hipLaunchKernelGGL((k_dslash<PIN, POUT, PLINK, true, false>), grid, block, 0, s, op.g, lk, cl, op.kappa, out, in, sub, is, os);

@@ -70,7 +70,10 @@ struct OutsideSpinor {
 // Hops that leave the block, for the directions MU0 and MU1 together (a lane
 // has at most one face neighbour per direction).  All lanes issue the loads
 // (lanes without a face neighbour read their own site, which is in cache) so
-// that the loads of both directions are in flight at once.
+// that the loads of both directions are in flight at once.  Only a backward
+// hop needs a link from the neighbour block, U_mu(x - mu); the other lanes
+// point their link load at their own link, which the block has just staged
+// (a cache hit), so no unused link crosses from HBM.
 template <int MU, int P, typename R>
 __device__ __forceinline__ void face_load(const Geom& g, const BlockPos& p, int l, const void* xr,
                                           const void* links, cpx<R>* psi, cpx<R>* ug, int* kind) {
@@ -92,7 +95,8 @@ __device__ __forceinline__ void face_load(const Geom& g, const BlockPos& p, int 
     SpinorIO<P>::load(xr, g.nblk, nb, nl, t);
 #pragma unroll
     for (int k = 0; k < 12; ++k) psi[k] = {(R)t[k].re, (R)t[k].im};
-    load_link<P == P_F64 ? P_F64 : (P == P_F32 ? P_F32 : P), R, false>(links, nb, nl, MU, ug);
+    const bool back = *kind == 2;
+    load_link<P, R, false>(links, back ? nb : p.blk, back ? nl : l, MU, ug);
 }
 
 template <int MU, typename R>
@@ -639,6 +643,9 @@ static int default_lanes_per_site(const Geom& g) { return g.nblk / 2 <= 256 ? 2 
 hipError_t launch_sap_halfsweep(const OpData& op, int prec, int colour, int n_mr, int mode, void* x,
                                 const void* b, int nrhs, const LaunchCfg& cfg, hipStream_t s, int bs) {
     ProfScope ps("sap_halfsweep", s);
+    // general visits (x nonzero everywhere) separately: their bytes per site
+    // differ from those of the two half-sweeps that start from x = 0
+    ProfScope pm(mode == 0 ? "sap_general" : "sap_from_zero", s);
     if (bs != BLOCK_MR && bs != BLOCK_JACOBI && bs != BLOCK_EO) return hipErrorInvalidValue;
     const int lanes = cfg.lanes_per_site > 0 ? cfg.lanes_per_site : default_lanes_per_site(op.g);
     // the even-odd block solver has the one-lane form only

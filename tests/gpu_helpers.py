@@ -7,6 +7,12 @@ from paper_2112_00501_amd import cloversap as cs
 from paper_2112_00501_amd import synth
 
 TOL_D = {cs.F64: 1e-13, cs.F32: 5e-6, cs.F16: 2e-3, cs.BF16: 1.5e-2}
+# Largest error of a single site, relative to the RMS site norm of the
+# reference (site_err below).  Rounding noise of n independent sites has a
+# maximum of about 4-5 times its RMS, so these are 4x the global bounds; a
+# wrong hop, sign or face on even one site gives an error of the order of
+# kappa |psi| ~ 0.1 at that site and fails them all.
+TOL_D_SITE = {p: 4 * t for p, t in TOL_D.items()}
 
 
 class Case:
@@ -31,3 +37,13 @@ class Case:
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def site_err(a, b):
+    """max over sites of |a_s - b_s| / RMS over sites of |b_s| (a, b: [..., V, 4, 3]
+    or [V, 12]): catches an error confined to a few sites (one face, one
+    block) that a global norm would average away."""
+    a = np.asarray(a).reshape(-1, 12)
+    b = np.asarray(b).reshape(-1, 12)
+    d = np.linalg.norm(a - b, axis=1)
+    return float(d.max() / np.sqrt(np.mean(np.linalg.norm(b, axis=1) ** 2)))

@@ -27,13 +27,17 @@ import torch
 import oracle
 from paper_2112_00501_amd import cloversap as cs
 from paper_2112_00501_amd import synth
-from tests.gpu_helpers import Case, TOL_D, rel
+from tests.gpu_helpers import Case, TOL_D, TOL_D_SITE, rel, site_err
 from tests.oracle_helpers import block_sites, coords
 
 pytestmark = pytest.mark.gpu
 
 BDIM = (4, 4, 4, 4)
-TOL_SAP_F32 = 1e-4
+# one SAP cycle on a sampled block against the oracle's block solve from the
+# same inputs: global and single-site (site_err) bounds by storage precision
+TOL_SAP = {cs.F32: 2e-6, cs.F16: 1.5e-3, cs.BF16: 1.2e-2}
+TOL_SAP_SITE = {p: 4 * t for p, t in TOL_SAP.items()}
+TOL_SAP_F32 = TOL_SAP[cs.F32]
 
 
 @pytest.fixture(scope="module")
@@ -54,14 +58,15 @@ def test_dslash_full_size_sampled(big):
     corners = [0, 3, 4, 31, 32 * 32 * 32 * 63 + 31, V - 1]
     sites = np.unique(np.concatenate([rng.choice(V, 500, replace=False), corners]))
     ref = oracle.apply_D_sites(dims, c.U, c.kappa, c.csw, psi, sites)
-    for prec in (cs.F64, cs.F32):
+    for prec in (cs.F64, cs.F32, cs.F16, cs.BF16):
         fin = c.to_dev(psi, prec)
         fout = c.lat.new_field(prec)
         c.op.apply_D(fout, fin, prec)
         got = c.to_host(fout, prec)[sites]
-        err = rel(got, ref)
-        print(f"32^3x64 prec={prec} sampled rel.err={err:.3e}")
+        err, serr = rel(got, ref), site_err(got, ref)
+        print(f"32^3x64 prec={prec} sampled rel.err={err:.3e} site.err={serr:.3e}")
         assert err <= TOL_D[prec]
+        assert serr <= TOL_D_SITE[prec]
 
 
 def _check_sap_cycle_on_sampled_blocks(c, prec, solver, tol, nblocks=6):
@@ -109,13 +114,21 @@ def _check_sap_cycle_on_sampled_blocks(c, prec, solver, tol, nblocks=6):
                 ref = oracle.mr_eo_block(dims, BDIM, blk, c.U, T, c.kappa, 4, r)[sites]
             else:
                 ref = oracle.mr_block(dims, BDIM, blk, c.U, T, c.kappa, 4, r)[sites]
-            err = rel(x[sites], ref)
-            print(f"{dims} block {blk} colour {col} rel.err={err:.3e}")
+            err, serr = rel(x[sites], ref), site_err(x[sites], ref)
+            print(f"{dims} prec {prec} block {blk} colour {col} rel.err={err:.3e} site.err={serr:.3e}")
             assert err <= tol
+            assert serr <= 4 * tol
 
 
 def test_sap_full_size_sampled_blocks(big):
     _check_sap_cycle_on_sampled_blocks(big, cs.F32, "mr", tol=TOL_SAP_F32)
+
+
+@pytest.mark.parametrize("prec", [cs.F16, cs.BF16])
+def test_low_precision_sap_full_size_sampled_blocks(big, prec):
+    """The FP16 / BF16 one-lane kernels the low-precision solves run at
+    32^3 x 64."""
+    _check_sap_cycle_on_sampled_blocks(big, prec, "mr", tol=TOL_SAP[prec], nblocks=4)
 
 
 def test_jacobi_sap_full_size_sampled_blocks(big):
