@@ -432,6 +432,21 @@ int cs_bicgstab_solve_mg(cs_gauge g, cs_clover c, cs_mg m, const cs_solver_param
 int cs_force(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_lie,
              void* grad_U, void* stream);
 
+/* cs_force for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid allocation): the same
+ * kernels and results, with the insertion-matrix workspace taken from a
+ * fixed 128 MiB device array of the library instead of memory allocated on
+ * the first call.  No device memory is allocated or freed.  The lattice may
+ * have at most 155,344 sites (864 bytes each; a 16^3 x 32 lattice fits,
+ * 32^3 x 64 does not): larger lattices return CS_ERR_INVALID.  Every GPU
+ * that runs it holds its own copy of the array until the process ends (its
+ * address is looked up on the first call on that device).  The workspace is
+ * written in full before it is read, and its contents are left from the last
+ * call; calls that overlap in time on one GPU (on different streams, or from
+ * different threads) share it and race. */
+int cs_force_noalloc(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_lie,
+                     void* grad_U, void* stream);
+
 /* -------------------------------------------------------------- profiling */
 
 /* When enabled, every kernel launch of the library is bracketed by HIP

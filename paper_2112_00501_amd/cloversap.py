@@ -67,6 +67,7 @@ EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_des
             "cs_bicgstab_solve", "cs_mg_params_default", "cs_mg_create", "cs_mg_destroy",
             "cs_mg_export", "cs_mg_restrict", "cs_mg_prolong", "cs_mg_coarse_apply",
             "cs_mg_coarse_solve", "cs_mg_apply", "cs_gcr_solve_mg", "cs_bicgstab_solve_mg", "cs_force",
+            "cs_force_noalloc",
             "cs_profile_enable",
             "cs_profile_query", "cs_profile_reset", "cs_device_copy"]
 
@@ -125,6 +126,7 @@ def load_library(path: str = LIB_PATH):
     L.cs_gcr_solve_mg.argtypes = [P, P, P, C.POINTER(_Params), P, P, C.POINTER(_Stats), P]
     L.cs_bicgstab_solve_mg.argtypes = [P, P, P, C.POINTER(_Params), P, P, C.POINTER(_Stats), P]
     L.cs_force.argtypes = [P, P, P, P, P, P, P]
+    L.cs_force_noalloc.argtypes = [P, P, P, P, P, P, P]
     L.cs_profile_enable.argtypes = [I]
     L.cs_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
     L.cs_profile_reset.argtypes = []
@@ -375,6 +377,21 @@ class Operator:
                              None if g is None else _ptr(g), None if G is None else _ptr(G),
                              _stream(stream)), "cs_force")
         return g, G
+
+    def force_noalloc(self, x, y, g_lie=None, grad_U=None, stream=None):
+        """cs_force with the library's fixed workspace (no device allocation
+        by the library): writes into the caller's g_lie (float64 [V][4][8])
+        and/or grad_U (complex128 [V][4][3][3]) device tensors."""
+        self._fields((x, y), F64, 1)
+        V = self.lat.volume
+        if g_lie is not None:
+            _need(g_lie, V * 4 * 8 * 8, "g_lie")
+        if grad_U is not None:
+            _need(grad_U, V * 4 * 9 * 16, "grad_U")
+        _check(_lib.cs_force_noalloc(self.gauge.handle, self.clover.handle, _ptr(x), _ptr(y),
+                                     None if g_lie is None else _ptr(g_lie),
+                                     None if grad_U is None else _ptr(grad_U), _stream(stream)),
+               "cs_force_noalloc")
 
 
 @dataclass

@@ -793,6 +793,24 @@ int cs_force(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_li
     return ok();
 }
 
+int cs_force_noalloc(cs_gauge g, cs_clover c, const void* x, const void* y, double* g_lie, void* grad_U,
+                     void* stream) {
+    int st = check_op(g, c);
+    if (st) return st;
+    if (!x || !y) return fail(CS_ERR_NULL, "x and y must be non-NULL");
+    if (!g_lie && !grad_U) return fail(CS_ERR_NULL, "at least one of g_lie and grad_U must be non-NULL");
+    const size_t need = (size_t)864 * g->g.V;
+    if (need > cs::FORCE_SCRATCH_BYTES)
+        return fail(CS_ERR_INVALID, "lattice of %lld sites needs %zu bytes of force workspace; the fixed "
+                    "workspace holds %zu bytes (%zu sites)", g->g.V, need, cs::FORCE_SCRATCH_BYTES,
+                    cs::FORCE_SCRATCH_BYTES / 864);
+    void* H = nullptr;
+    CS_HIP(cs::force_scratch_address(&H));
+    CS_HIP(cs::launch_force(g->g, g->links[cs::P_F64], c->kappa, c->csw, x, y, H, g_lie, grad_U,
+                            (hipStream_t)stream));
+    return ok();
+}
+
 int cs_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
     if (!dst || !src) return fail(CS_ERR_NULL, "dst and src must be non-NULL");
     if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)

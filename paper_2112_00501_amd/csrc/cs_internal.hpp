@@ -360,6 +360,13 @@ hipError_t launch_sap_pair(const OpData& op, int prec, int colour, int n_block, 
 // may be null.  Hbuf holds 864 bytes per site (insertion matrices).
 hipError_t launch_force(const Geom& g, const void* links64, double kappa, double csw, const void* x,
                         const void* y, void* Hbuf, double* glie, void* gradU, hipStream_t s);
+// Fixed workspace of the allocation-free force (force.hip): 128 MiB per
+// device, i.e. the insertion matrices of up to 155,344 sites (a 16^3 x 32
+// lattice).  force_scratch_address gives its device address on the current
+// device (looked up once per device).
+constexpr size_t FORCE_SCRATCH_BYTES = size_t(128) << 20;
+constexpr int FORCE_SCRATCH_MAX_DEVICES = 64;
+hipError_t force_scratch_address(void** out);
 
 // blas.hip
 struct BlasWork;  // defined in blas.hip

@@ -19,6 +19,8 @@
 // corners).  For a leaf L U R the derivative contributes U R H L, for a leaf
 // L U^dag R it contributes -R H L U^dag, and g_a = (kappa c_sw / 8)
 // Re tr(T^a W) for the sum W of these terms.
+#include <mutex>
+
 #include "dslash_core.hpp"
 #include "su3.hpp"
 
@@ -326,7 +328,34 @@ __global__ __launch_bounds__(TPB) void k_force_link(Geom g, const void* __restri
     }
 }
 
+// Workspace of the allocation-free entry point: the insertion matrices of
+// up to FORCE_SCRATCH_BYTES / 864 sites, in a fixed device array that every
+// GPU the library runs on holds until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): the address comes from hipGetSymbolAddress, once per
+// device, on that device.
+__device__ __align__(256) double2 scratch[FORCE_SCRATCH_BYTES / sizeof(double2)];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[FORCE_SCRATCH_MAX_DEVICES] = {};
+
 }  // namespace
+
+hipError_t force_scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= FORCE_SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_force(const Geom& g, const void* links64, double kappa, double csw, const void* x,
                         const void* y, void* Hbuf, double* glie, void* gradU, hipStream_t s) {
