@@ -155,6 +155,28 @@ def get_threads() -> int:
     return lib().or_get_threads()
 
 
+def antiperiodic_t_links(dims, U) -> np.ndarray:
+    """Links for the operator with antiperiodic boundary conditions in time.
+
+    The paper states no boundary conditions; fermion fields are usually taken
+    antiperiodic in time, psi(x + L_t e_t) = -psi(x).  In the operator this
+    puts a factor -1 on the two hops that cross the time boundary: the
+    forward hop out of the last time slice, which carries U_t(x), and the
+    backward hop into it, which carries the same link as U_t(x)^dag.  Both
+    are obtained by negating U_t(x) on the last time slice, so every oracle
+    routine (operator, smoothers, solvers, force) given these links computes
+    the antiperiodic case.  The clover term is unchanged, since every
+    plaquette holds either none or two of the negated links; it is built from
+    the original links (or, equally, from these).  The negated links have
+    determinant -1, so they are input to the oracle only, never to the GPU
+    library, which takes the boundary condition as a lattice flag."""
+    out = np.array(U, dtype=np.complex128, copy=True)
+    lx, ly, lz, lt = (int(d) for d in dims)
+    last = slice((lt - 1) * lx * ly * lz, lt * lx * ly * lz)
+    out[last, 3] *= -1.0
+    return out
+
+
 def gamma(mu: int) -> np.ndarray:
     g = np.zeros((4, 4), np.complex128)
     lib().or_gamma(mu, _ptr(g))

@@ -163,3 +163,79 @@ def test_sitewise_and_residual_routes_agree(field):
     b = synth.source(DIMS, 7)
     r = oracle.residual_norm(DIMS, U, kappa, csw, b, psi)
     assert np.isclose(r, np.linalg.norm(b - full), rtol=1e-13)
+
+
+# ---- antiperiodic boundary conditions in time (psi(x + L_t e_t) = -psi(x))
+
+@pytest.mark.parametrize("n", [(0, 0, 0, 0), (1, 0, 0, 0), (0, 2, 1, 3), (3, 5, 2, 7), (2, 3, 2, 5)])
+def test_antiperiodic_free_field_plane_wave(n):
+    """Free field with antiperiodic time: the plane waves with p_t = (2n+1)
+    pi / L_t (and the periodic spatial momenta) are the eigenvectors, with
+    the same closed-form symbol D(p)."""
+    kappa = 0.137
+    p = 2 * np.pi * np.array(n[:3]) / np.array(DIMS[:3])
+    p = np.append(p, (2 * n[3] + 1) * np.pi / DIMS[3])
+    U = oracle.antiperiodic_t_links(DIMS, synth.unit_gauge(DIMS))
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    psi, ph = plane_wave(DIMS, p, u)
+    out = oracle.apply_D(DIMS, U, None, kappa, psi)
+    ref = ph[:, None, None] * (symbol(p, kappa) @ u)[None]
+    assert np.abs(out - ref).max() < 1e-14 * max(1.0, np.abs(ref).max())
+
+
+def test_antiperiodic_differs_from_periodic_only_on_the_boundary_slices():
+    """The two operators agree on every time slice except the first and the
+    last.  There the difference is twice the hop that crosses the boundary:
+    D_P psi - D_AP psi = -2 kappa (1 - gamma_t) U_t(x) psi(x + t) on the last
+    slice and -2 kappa (1 + gamma_t) U_t(x - t)^dag psi(x - t) on the first
+    (written here with numpy and the explicit gamma_t)."""
+    kappa = 0.13
+    U = synth.gauge_field(DIMS, 0.3, 61)
+    Ua = oracle.antiperiodic_t_links(DIMS, U)
+    T = oracle.clover_field(DIMS, U, kappa, 1.0)
+    psi = synth.source(DIMS, 62)
+    dp = oracle.apply_D(DIMS, U, T, kappa, psi)
+    da = oracle.apply_D(DIMS, Ua, T, kappa, psi)
+    V = int(np.prod(DIMS))
+    t = coords(DIMS, V)[:, 3]
+    inner = (t > 0) & (t < DIMS[3] - 1)
+    assert np.array_equal(dp[inner], da[inner])
+    vol3 = DIMS[0] * DIMS[1] * DIMS[2]
+    eye, gt = np.eye(4), GAMMA[3]
+    last = np.nonzero(t == DIMS[3] - 1)[0]
+    first = np.nonzero(t == 0)[0]
+    fwd = last - (DIMS[3] - 1) * vol3          # x + t wraps to t = 0
+    bwd = first + (DIMS[3] - 1) * vol3         # x - t wraps to t = L_t - 1
+    ref_last = -2 * kappa * np.einsum("st,vab,vtb->vsa", eye - gt, U[last, 3], psi[fwd])
+    ref_first = -2 * kappa * np.einsum("st,vba,vtb->vsa", eye + gt, U[bwd, 3].conj(), psi[bwd])
+    scale = np.abs(dp).max()
+    assert np.abs((dp - da)[last] - ref_last).max() < 1e-14 * scale
+    assert np.abs((dp - da)[first] - ref_first).max() < 1e-14 * scale
+    assert np.abs(ref_last).max() > 0.01 * scale
+
+
+def test_antiperiodic_clover_unchanged_and_gamma5_hermitian():
+    kappa, csw = 0.13, 1.1
+    U = synth.gauge_field(DIMS, 0.3, 63)
+    Ua = oracle.antiperiodic_t_links(DIMS, U)
+    T = oracle.clover_field(DIMS, U, kappa, csw)
+    assert np.abs(oracle.clover_field(DIMS, Ua, kappa, csw) - T).max() < 1e-15
+    x, y = synth.source(DIMS, 64), synth.source(DIMS, 65)
+    lhs = np.vdot(x, oracle.apply_D(DIMS, Ua, T, kappa, y))
+    rhs = np.vdot(g5_apply(oracle.apply_D(DIMS, Ua, T, kappa, g5_apply(x))), y)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_antiperiodic_gauge_covariance():
+    kappa, csw = 0.13, 1.0
+    U = synth.gauge_field(DIMS, 0.3, 66)
+    Om = synth.gauge_transform(DIMS, 4010)
+    Ug = gauge_transform_links(DIMS, U, Om)
+    Ua, Uga = oracle.antiperiodic_t_links(DIMS, U), oracle.antiperiodic_t_links(DIMS, Ug)
+    T = oracle.clover_field(DIMS, U, kappa, csw)
+    Tg = oracle.clover_field(DIMS, Ug, kappa, csw)
+    psi = synth.source(DIMS, 67)
+    out = oracle.apply_D(DIMS, Ua, T, kappa, psi)
+    outg = oracle.apply_D(DIMS, Uga, Tg, kappa, gauge_transform_spinor(Om, psi))
+    assert np.abs(outg - gauge_transform_spinor(Om, out)).max() < 1e-13
