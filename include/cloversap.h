@@ -23,7 +23,9 @@
  *   links    U[V][4][3][3]            U_mu(x)[row][col], each exactly SU(3)
  *   spinor   psi[nrhs][V][4][3]       index 3*spin + colour
  *   clover   T[V][12][12]             the term T of C = 1 + T (export only)
- * Boundary conditions are periodic in all four directions.  Gamma matrices
+ * Boundary conditions are periodic in all four directions for the links;
+ * fermion fields are periodic too unless the lattice was created with
+ * CS_ANTIPERIODIC_T (antiperiodic in time).  Gamma matrices
  * are those of the chiral basis with gamma5 = diag(1, 1, -1, -1):
  *   gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = x, y, z),
  *   gamma_t = [[0, 1], [1, 0]].
@@ -65,6 +67,13 @@ typedef enum {
 
 typedef enum { CS_F64 = 0, CS_F32 = 1, CS_F16 = 2, CS_BF16 = 3 } cs_prec;
 
+/* Lattice flags (cs_lattice_create). */
+typedef enum {
+    CS_PERIODIC = 0,       /* fermion fields periodic in all four directions */
+    CS_ANTIPERIODIC_T = 1  /* fermion fields antiperiodic in time:
+                              psi(x + Lt e_t) = -psi(x) */
+} cs_lattice_flags;
+
 typedef struct cs_lattice_s* cs_lattice;
 typedef struct cs_gauge_s* cs_gauge;
 typedef struct cs_clover_s* cs_clover;
@@ -81,8 +90,14 @@ const char* cs_strerror(int status);
  * extent a multiple of 4 (CS_ERR_GEOMETRY otherwise).  The red/black block
  * colouring of the SAP smoother (paper Section 2 and Section 3; colour of a
  * block = sum of its block coordinates mod 2) also needs an even number of
- * blocks in every direction; that is checked by the SAP and solver calls. */
-int cs_lattice_create(const int dims[4], const int block[4], cs_lattice* out);
+ * blocks in every direction; that is checked by the SAP and solver calls.
+ * flags: CS_PERIODIC or CS_ANTIPERIODIC_T, the boundary condition of the
+ * fermion fields in time (the paper does not state one).  With
+ * CS_ANTIPERIODIC_T every hop of the operator of Eq. (1) that crosses the
+ * time boundary changes sign, in D, D^dag, the smoothers, the solvers, the
+ * multigrid operators and the force; the clover term is unaffected.  Other
+ * flag bits: CS_ERR_INVALID. */
+int cs_lattice_create(const int dims[4], const int block[4], int flags, cs_lattice* out);
 int cs_lattice_destroy(cs_lattice lat);
 /* Number of sites V. */
 long long cs_lattice_volume(cs_lattice lat);

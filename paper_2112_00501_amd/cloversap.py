@@ -21,6 +21,7 @@ PREC = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 SITE_BYTES = {F64: 192, F32: 96, F16: 52, BF16: 52}
 
 CS_OK, CS_NOT_CONVERGED, CS_BREAKDOWN, CS_NONFINITE = 0, 1, 2, 3
+CS_ANTIPERIODIC_T = 1
 
 
 class CloverSapError(RuntimeError):
@@ -86,7 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.cs_last_error.restype = C.c_char_p
     L.cs_strerror.restype = C.c_char_p
     L.cs_strerror.argtypes = [I]
-    L.cs_lattice_create.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(P)]
+    L.cs_lattice_create.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int), I, C.POINTER(P)]
     L.cs_lattice_destroy.argtypes = [P]
     L.cs_lattice_volume.argtypes = [P]
     L.cs_lattice_volume.restype = C.c_longlong
@@ -166,15 +167,18 @@ def _ptr(t: torch.Tensor):
 
 
 class Lattice:
-    """Geometry with 4^4 blocks.  dims = (Lx, Ly, Lz, Lt)."""
+    """Geometry with 4^4 blocks.  dims = (Lx, Ly, Lz, Lt); antiperiodic_t:
+    fermion fields antiperiodic in time (default periodic)."""
 
-    def __init__(self, dims, block=(4, 4, 4, 4)):
+    def __init__(self, dims, block=(4, 4, 4, 4), antiperiodic_t=False):
         L = load_library()
         self.dims = tuple(int(d) for d in dims)
         self.block = tuple(int(b) for b in block)
+        self.antiperiodic_t = bool(antiperiodic_t)
         h = C.c_void_p()
         _check(L.cs_lattice_create((C.c_int * 4)(*self.dims), (C.c_int * 4)(*self.block),
-                                   C.byref(h)), "cs_lattice_create")
+                                   CS_ANTIPERIODIC_T if self.antiperiodic_t else 0, C.byref(h)),
+               "cs_lattice_create")
         self.handle = h
         self.volume = int(L.cs_lattice_volume(h))
 

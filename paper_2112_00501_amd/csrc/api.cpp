@@ -188,9 +188,11 @@ const char* cs_strerror(int status) {
     }
 }
 
-int cs_lattice_create(const int dims[4], const int block[4], cs_lattice* out) {
+int cs_lattice_create(const int dims[4], const int block[4], int flags, cs_lattice* out) {
     if (!dims || !block || !out) return fail(CS_ERR_NULL, "dims, block and out must be non-NULL");
+    if (flags & ~CS_ANTIPERIODIC_T) return fail(CS_ERR_INVALID, "unknown lattice flags 0x%x", (unsigned)flags);
     cs::Geom g{};
+    g.antiperiodic_t = (flags & CS_ANTIPERIODIC_T) ? 1 : 0;
     long long V = 1;
     for (int m = 0; m < 4; ++m) {
         if (block[m] != 4)

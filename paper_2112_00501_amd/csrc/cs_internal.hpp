@@ -117,6 +117,8 @@ struct Geom {
     int NB[4];     // blocks per direction
     int nblk;      // number of blocks
     long long V;   // number of sites
+    int antiperiodic_t;  // 1: fermion fields antiperiodic in time (the hops
+                         // that cross the time boundary change sign)
 };
 
 // Per-thread block coordinates and block-index strides.
@@ -158,6 +160,24 @@ __device__ __forceinline__ int neighbour(const Geom& g, const BlockPos& p, int l
     *nl = l + (3 << sh);
     *inside = false;
     return p.bc[mu] == 0 ? p.blk + (g.NB[mu] - 1) * p.stride[mu] : p.blk - p.stride[mu];
+}
+
+// True when the hop from block p in direction mu (dir = +1 or -1) to a site
+// outside the block (inside = false) crosses the lattice boundary in time.
+__device__ __forceinline__ bool wraps_time(const Geom& g, const BlockPos& p, int mu, int dir, bool inside) {
+    return mu == 3 && !inside && (dir > 0 ? p.bc[3] == g.NB[3] - 1 : p.bc[3] == 0);
+}
+
+// Boundary condition in time on a neighbour spinor about to enter a hop:
+// with antiperiodic fields, psi(x + L_t e_t) = -psi(x), so a hop that wraps
+// around in time takes the negated spinor.  The branch is uniform over a
+// wave (a wave holds one time slice of a block).
+template <typename R>
+__device__ __forceinline__ void time_boundary_phase(const Geom& g, bool wraps, R* psi, int n) {
+    if (wraps && g.antiperiodic_t) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) psi[k] = -psi[k];
+    }
 }
 
 // The c-th block of colour `colour` (colour = sum of block coordinates mod 2),

@@ -48,6 +48,7 @@ __device__ __forceinline__ void hop_dir(const Geom& g, const BlockPos& p, int l,
     if (ls.want(in)) {
         cpx<R> psi[12], u[9];
         ls.template load_nb<R>(nb, nl, in, psi);
+        if (MU == 3) time_boundary_phase(g, wraps_time(g, p, MU, +1, in), &psi[0].re, 24);
         lk.template load<R>(p.blk, l, MU, true, u);
         hop_term<MU, -1>(u, psi, acc);
     }
@@ -55,6 +56,7 @@ __device__ __forceinline__ void hop_dir(const Geom& g, const BlockPos& p, int l,
     if (ls.want(in)) {
         cpx<R> psi[12], u[9];
         ls.template load_nb<R>(nb, nl, in, psi);
+        if (MU == 3) time_boundary_phase(g, wraps_time(g, p, MU, -1, in), &psi[0].re, 24);
         lk.template load<R>(nb, nl, MU, in, u);
         hop_term<MU, +1>(u, psi, acc);
     }
@@ -99,6 +101,7 @@ __device__ __forceinline__ void hopping_sum_rolled(const Geom& g, const BlockPos
         if (!ls.want(in)) continue;
         cpx<R> psi[12], u[9];
         ls.template load_nb<R>(nb, nl, in, psi);
+        if (mu == 3) time_boundary_phase(g, !in && (dir > 0 ? bc == nbm - 1 : bc == 0), &psi[0].re, 24);
         if (dir > 0) lk.template load<R>(p.blk, l, mu, true, u);
         else lk.template load<R>(nb, nl, mu, in, u);
         switch (h) {

@@ -271,8 +271,11 @@ __global__ __launch_bounds__(TPB) void k_force_link(Geom g, const void* __restri
         for (int i = 0; i < 9; ++i) M[i] = M[i] - t[i];
         double re[8], im[8];
         trace_generators(M, re, im);
+        // both hop terms of the link U_t(x) on the last time slice cross the
+        // time boundary: with antiperiodic fields they carry a factor -1
+        const double hs = (mu == 3 && g.antiperiodic_t && x[3] == g.L[3] - 1) ? -1.0 : 1.0;
 #pragma unroll
-        for (int a = 0; a < 8; ++a) gh[a] = -kappa * im[a];
+        for (int a = 0; a < 8; ++a) gh[a] = -hs * kappa * im[a];
     }
 
     // clover part

@@ -154,6 +154,7 @@ __device__ __forceinline__ void back_face(const Geom& g, const BlockPos& p, int 
     const int nb = neighbour(g, p, l, MU, -1, &nl, &in);
     cpx<float> psi[12], u[9];
     column_site(P, fs, nv, col, g.nblk, nb, nl, psi);
+    if (MU == 3) time_boundary_phase(g, wraps_time(g, p, MU, -1, in), &psi[0].re, 24);
     load_link<P_F32, float, false>(links, nb, nl, MU, u);  // U_mu(x - mu)
     hop_term<MU, +1>(u, psi, y);
 #pragma unroll

@@ -95,6 +95,8 @@ __device__ __forceinline__ void face_load(const Geom& g, const BlockPos& p, int 
     SpinorIO<P>::load(xr, g.nblk, nb, nl, t);
 #pragma unroll
     for (int k = 0; k < 12; ++k) psi[k] = {(R)t[k].re, (R)t[k].im};
+    if (MU == 3)
+        time_boundary_phase(g, *kind == 1 ? p.bc[3] == g.NB[3] - 1 : (*kind == 2 && p.bc[3] == 0), &psi[0].re, 24);
     const bool back = *kind == 2;
     load_link<P, R, false>(links, back ? nb : p.blk, back ? nl : l, MU, ug);
 }

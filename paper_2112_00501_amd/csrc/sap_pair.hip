@@ -173,6 +173,8 @@ __device__ __forceinline__ void pair_face_load(const Geom& g, const BlockPos& p,
     SpinorIO<P>::load(xr, g.nblk, sb, sl, t);
 #pragma unroll
     for (int k = 0; k < 12; ++k) psi[k] = {(float)t[k].re, (float)t[k].im};
+    if (MU == 3)
+        time_boundary_phase(g, !in && (q.h == 0 ? p.bc[3] == g.NB[3] - 1 : p.bc[3] == 0), &psi[0].re, 24);
     const bool nbr_link = !in && q.h == 1;
     load_link<PLINK, float, false>(links, nbr_link ? nb : p.blk, nbr_link ? nl : q.l, MU, u);
 }

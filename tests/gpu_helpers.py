@@ -18,11 +18,13 @@ TOL_D_SITE = {p: 4 * t for p, t in TOL_D.items()}
 class Case:
     """One gauge field on the oracle side (numpy) and the GPU side (handles)."""
 
-    def __init__(self, dims, eps, kappa, csw, seed, oracle_T=True):
+    def __init__(self, dims, eps, kappa, csw, seed, oracle_T=True, antiperiodic_t=False):
         self.dims, self.kappa, self.csw = tuple(dims), kappa, csw
         self.U = synth.gauge_field(dims, eps, seed)
+        # the oracle takes the boundary condition in time through its links
+        self.Uo = oracle.antiperiodic_t_links(dims, self.U) if antiperiodic_t else self.U
         self.T = oracle.clover_field(dims, self.U, kappa, csw) if oracle_T else None
-        self.lat = cs.Lattice(dims)
+        self.lat = cs.Lattice(dims, antiperiodic_t=antiperiodic_t)
         self.op = cs.Operator(self.lat, torch.from_numpy(self.U).cuda(), kappa, csw)
         torch.cuda.synchronize()
 

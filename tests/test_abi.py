@@ -39,11 +39,15 @@ def test_every_declared_symbol_is_exported(lib):
 def test_geometry_validation_on_host(lib):
     h = C.c_void_p()
     I4 = C.c_int * 4
-    assert lib.cs_lattice_create(I4(8, 8, 8, 6), I4(4, 4, 4, 4), C.byref(h)) == -2
+    assert lib.cs_lattice_create(I4(8, 8, 8, 6), I4(4, 4, 4, 4), 0, C.byref(h)) == -2
     assert b"multiple of 4" in lib.cs_last_error()
-    assert lib.cs_lattice_create(I4(8, 8, 8, 8), I4(2, 4, 4, 4), C.byref(h)) == -2
-    assert lib.cs_lattice_create(None, I4(4, 4, 4, 4), C.byref(h)) == -3
-    assert lib.cs_lattice_create(I4(8, 4, 12, 16), I4(4, 4, 4, 4), C.byref(h)) == 0
+    assert lib.cs_lattice_create(I4(8, 8, 8, 8), I4(2, 4, 4, 4), 0, C.byref(h)) == -2
+    assert lib.cs_lattice_create(None, I4(4, 4, 4, 4), 0, C.byref(h)) == -3
+    assert lib.cs_lattice_create(I4(8, 4, 12, 16), I4(4, 4, 4, 4), 2, C.byref(h)) == -1
+    assert b"flags" in lib.cs_last_error()
+    assert lib.cs_lattice_create(I4(8, 4, 12, 16), I4(4, 4, 4, 4), 1, C.byref(h)) == 0
+    assert lib.cs_lattice_destroy(h) == 0
+    assert lib.cs_lattice_create(I4(8, 4, 12, 16), I4(4, 4, 4, 4), 0, C.byref(h)) == 0
     assert lib.cs_lattice_volume(h) == 8 * 4 * 12 * 16
     assert lib.cs_field_bytes(h, 0, 1) == 192 * 6144
     assert lib.cs_field_bytes(h, 1, 3) == 96 * 6144 * 3
