@@ -445,28 +445,38 @@ def multirhs_measurement(cs, synth, torch, nrhs=24):
 
 def gradient_measurement(cs, synth, torch):
     """Forward solve and backward pass (adjoint solve + force) of
-    L = Re(eta^dag D^-1 b) on 32^3 x 64 through torch.autograd."""
-    import numpy as np
+    L = Re(eta^dag D^-1 b) on 32^3 x 64 through torch.autograd, with the
+    forward solution and operator kept for the backward pass, and with both
+    recomputed in the backward pass instead (nothing held in between)."""
     c = synth.CONFIGS["grad_32x32x32x64"]
     dims = c["dims"]
-    U = torch.from_numpy(synth.gauge_field(dims, c["eps"], c["gauge_seed"])).cuda().requires_grad_(True)
-    b = torch.from_numpy(synth.source(dims, c["src_seed"])).cuda().requires_grad_(True)
+    U0 = torch.from_numpy(synth.gauge_field(dims, c["eps"], c["gauge_seed"])).cuda()
+    b0 = torch.from_numpy(synth.source(dims, c["src_seed"])).cuda()
     eta = torch.from_numpy(synth.source(dims, c["eta_seed"])).cuda()
     lat = cs.Lattice(dims)
     params = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x = cs.CloverSolve.apply(U, b, lat, c["kappa"], c["csw"], params)
-    L = (torch.conj(eta) * x).sum().real
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    L.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    gn = float(U.grad.abs().max())
-    return dict(lattice="32x32x32x64", forward_s=round(t1 - t0, 4), backward_s=round(t2 - t1, 4),
-                note="forward includes gauge import and clover build; backward = adjoint solve + force",
-                grad_U_maxabs=float(f"{gn:.4e}"), loss=float(f"{float(L):.6e}"))
+    res = dict(lattice="32x32x32x64")
+    for recompute in (False, True):
+        U = U0.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = cs.CloverSolve.apply(U, b, lat, c["kappa"], c["csw"], params, recompute)
+        L = (torch.conj(eta) * x).sum().real
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        key = "recompute" if recompute else "stored"
+        res[key] = dict(forward_s=round(t1 - t0, 4), backward_s=round(t2 - t1, 4),
+                        grad_U_maxabs=float(f"{float(U.grad.abs().max()):.4e}"),
+                        loss=float(f"{float(L.detach()):.6e}"))
+        del U, b, x, L
+        torch.cuda.empty_cache()
+    res["note"] = ("forward includes gauge import and clover build; backward = adjoint solve + force (and, "
+                   "with recompute, the operator rebuild and the forward solve again)")
+    return res
 
 
 def cached_field(synth, cfg, cache_dir):

@@ -566,34 +566,55 @@ def profile_query(name: str):
 class CloverSolve(torch.autograd.Function):
     """x = D(U)^{-1} b as a differentiable torch operation.
 
-    forward(U, b, lat, kappa, csw, params): U complex128 [V][4][3][3] (SU(3)),
-    b complex128 [V][4][3], both on the GPU; returns x (complex128).
+    forward(U, b, lat, kappa, csw, params, recompute): U complex128
+    [V][4][3][3] (SU(3)), b complex128 [V][4][3], both on the GPU; returns x
+    (complex128).
     backward: the adjoint solve y = D^{-dag} grad_x (D^dag = gamma5 D gamma5,
     same solver), grad_b = y, and grad_U from the force kernel: the
     tangent-space gradient 2 i (sum_a g_a T^a) U, exact for any SU(3)-valued
-    parametrisation of U.  The forward solution is kept (one FP64 field) for
-    the backward pass.
+    parametrisation of U.
+    recompute = False keeps the operator (links and clover term in the
+    library) and the FP64 solution between forward and backward; recompute =
+    True keeps only references to U and b and rebuilds the operator and
+    solves D x = b again in the backward pass (the solve is deterministic, so
+    the gradient is the same bit for bit), for when device memory is short.
     """
 
     @staticmethod
-    def forward(ctx, U, b, lat, kappa, csw, params=None):
+    def forward(ctx, U, b, lat, kappa, csw, params=None, recompute=False):
         params = params or SolverParams(inner_prec=F32, basis_prec=F32)
         op = Operator(lat, U.detach().contiguous(), kappa, csw)
         bd = lat.import_field(b.detach().contiguous(), F64)
         xd = lat.new_field(F64).zero_()
         op.gcr_solve(xd, bd, params)
-        ctx.op, ctx.lat, ctx.params = op, lat, params
-        ctx.xd = xd
-        return lat.export_field(xd, F64)
+        x = lat.export_field(xd, F64)
+        ctx.lat, ctx.params, ctx.kappa, ctx.csw, ctx.recompute = lat, params, kappa, csw, recompute
+        if recompute:
+            ctx.save_for_backward(U, b)
+            ctx.op = ctx.xd = None
+            del op, xd, bd
+        else:
+            ctx.op, ctx.xd = op, xd
+        return x
 
     @staticmethod
     def backward(ctx, grad_x):
-        op, lat = ctx.op, ctx.lat
+        lat = ctx.lat
+        if ctx.recompute:
+            U, b = ctx.saved_tensors
+            op = Operator(lat, U.detach().contiguous(), ctx.kappa, ctx.csw)
+            bd = lat.import_field(b.detach().contiguous(), F64)
+            xd = lat.new_field(F64).zero_()
+            op.gcr_solve(xd, bd, ctx.params)
+            del bd
+        else:
+            op, xd = ctx.op, ctx.xd
         gd = lat.import_field(grad_x.detach().contiguous().to(torch.complex128), F64)
         yd = lat.new_field(F64).zero_()
         op.gcr_solve(yd, gd, ctx.params, dagger=True)
         grad_b = lat.export_field(yd, F64) if ctx.needs_input_grad[1] else None
         grad_U = None
         if ctx.needs_input_grad[0]:
-            _, grad_U = op.force(ctx.xd, yd, want_lie=False, want_grad=True)
-        return grad_U, grad_b, None, None, None, None
+            _, grad_U = op.force(xd, yd, want_lie=False, want_grad=True)
+        ctx.op = ctx.xd = None
+        return grad_U, grad_b, None, None, None, None, None

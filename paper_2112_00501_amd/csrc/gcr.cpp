@@ -361,7 +361,11 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
         };
         GCR_CHK(S.enqueue_iteration(0));
         for (int k = 0; k < p.restart; ++k) {
-            const bool ahead = k + 1 < p.restart && !likely_last(k);
+            // With the multigrid preconditioner nothing is queued ahead: its
+            // coarse phase reads a stop flag on the host between chunks, so
+            // queuing k + 1 would make the host wait for k + 1's coarse solve
+            // before it could read the tails of k.
+            const bool ahead = !p.mg && k + 1 < p.restart && !likely_last(k);
             if (ahead) GCR_CHK(S.enqueue_iteration(k + 1));
             hipError_t we;
             const GcrTail* tails = S.wait_tails(k, &we);

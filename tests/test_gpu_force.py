@@ -103,3 +103,23 @@ def test_force_against_oracle_gradient_of_solutions(grad8):
     err = rel(g.cpu().numpy(), gh + gc)
     print(f"gradient vs oracle rel.err={err:.3e}")
     assert err < 1e-9
+
+
+def test_recomputed_forward_gives_the_same_gradient(grad8):
+    """CloverSolve with recompute=True keeps only U and b between the passes
+    and solves D x = b again in the backward pass: the gradients equal those
+    of the stored-solution form bit for bit."""
+    c = grad8
+    b, eta = synth.source(c.dims, 2026), synth.source(c.dims, 3026)
+    etat = torch.from_numpy(eta).cuda()
+    grads = []
+    for recompute in (False, True):
+        Ut = torch.from_numpy(c.U).cuda().requires_grad_(True)
+        bt = torch.from_numpy(b).cuda().requires_grad_(True)
+        x = cs.CloverSolve.apply(Ut, bt, c.lat, c.kappa, c.csw, cs.SolverParams(), recompute)
+        L = (torch.conj(etat) * x).sum().real
+        L.backward()
+        torch.cuda.synchronize()
+        grads.append((x.detach().cpu().numpy(), Ut.grad.cpu().numpy(), bt.grad.cpu().numpy()))
+    for a, r in zip(grads[0], grads[1]):
+        assert np.array_equal(a, r)
