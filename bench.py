@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Dslash/SAP HBM GB/s (% peak); time-to-1e-10 residual, mixed vs FP64, 1 GPU"
-SAP_KERNEL_SOURCES = ["sap.hip", "sap_pair.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp", "wave.hpp"]
+SAP_KERNEL_SOURCES = ["sap.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp", "wave.hpp"]
 DSLASH_KERNEL_SOURCES = ["dslash.hip", "dslash_core.hpp", "fields.hpp", "cs_internal.hpp"]
 
 # Algorithmic bytes per visited site of one SAP half-sweep, FP32 storage:
@@ -608,7 +608,7 @@ def headline(cs, synth, torch, steps, warmup, cache_dir):
         bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
         frac=round(achieved / HBM_PEAK_GBS, 4),
         traffic=load_traffic("sap_halfsweep_32x32x32x64", SAP_KERNEL_SOURCES),
-        kernel="k_sap_halfsweep<1, 1, 0> (FP32, one lane per site), general visits (x nonzero)",
+        kernel="k_sap_halfsweep<1, 1, 0, true> (FP32, one lane per site, general visits: x nonzero)",
         lattice="32x32x32x64", avg_launch_us=round(sap_us, 2), launches=n_gen,
         alg_bytes_per_launch=int(sap_bytes), alg_bytes_per_visited_site=SAP_BYTES_F32[0],
         visited_sites_per_launch=V // 2,

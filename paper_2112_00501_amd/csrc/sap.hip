@@ -222,11 +222,16 @@ __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R (*red)[4]) {
 //   delta = rho;  n_mr - 1 times: delta = rho + kappa C^-1 hop_BB(delta)
 //   x_B += delta
 // (hop = the hopping sum, D = C - kappa hop), with no reductions.
-template <int P, int PLINK, int BS>
+//
+// GEN: the general visit (mode 0, x nonzero everywhere), compiled on its own
+// so that its launches carry their own name in a kernel trace; the two
+// half-sweeps of a cycle that start from x = 0 (modes 1 and 2) share the
+// other instantiation.
+template <int P, int PLINK, int BS, bool GEN>
 __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ links,
                                               const void* __restrict__ clover,
                                               const void* __restrict__ cinv, double kappa_d,
-                                              int colour, int n_mr, int mode, void* __restrict__ x,
+                                              int colour, int n_mr, int mode_in, void* __restrict__ x,
                                               const void* __restrict__ b, size_t stride, int nrhs,
                                               int tile, int nitems) {
     using R = typename Arith<P>::R;
@@ -245,6 +250,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
     const int l = BS == BLOCK_EO ? eo_site(threadIdx.x) : (int)threadIdx.x;
     const int ncb = g.nblk / 2;
     const R kappa = (R)kappa_d;
+    const int mode = GEN ? 0 : mode_in;
     LdsSpinor<R> ls{s_rho};
 
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
@@ -608,6 +614,25 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
     }
 }
 
+template <int P, int PLINK, bool GEN>
+void launch_pm(const OpData& op, int colour, int n_mr, int mode, void* x, const void* b, size_t stride, int nrhs,
+               int tile, int nitems, int grid, hipStream_t s, int bs) {
+    const void* cl = P == P_F64 ? op.clover64 : op.clover32;
+    const void* ci = P == P_F64 ? op.cinv64 : op.cinv32;
+    if (bs == BLOCK_JACOBI) {
+        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_JACOBI, GEN>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
+                           op.links[PLINK], ci, nullptr, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile,
+                           nitems);
+    } else if (bs == BLOCK_EO) {
+        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_EO, GEN>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
+                           op.links[PLINK], cl, ci, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
+    } else {
+        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_MR, GEN>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
+                           op.links[PLINK], cl, nullptr, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile,
+                           nitems);
+    }
+}
+
 template <int P, int PLINK>
 hipError_t launch_p(const OpData& op, int colour, int n_mr, int mode, void* x, const void* b,
                     int nrhs, const LaunchCfg& cfg, hipStream_t s, int bs) {
@@ -615,20 +640,8 @@ hipError_t launch_p(const OpData& op, int colour, int n_mr, int mode, void* x, c
     const int nitems = (op.g.nblk / 2) * ((nrhs + tile - 1) / tile);
     const int grid = cfg.persistent_wgs > 0 && cfg.persistent_wgs < nitems ? cfg.persistent_wgs : nitems;
     const size_t stride = spinor_bytes_per_site(P) * op.g.V;
-    const void* cl = P == P_F64 ? op.clover64 : op.clover32;
-    const void* ci = P == P_F64 ? op.cinv64 : op.cinv32;
-    if (bs == BLOCK_JACOBI) {
-        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_JACOBI>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
-                           op.links[PLINK], ci, nullptr, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile,
-                           nitems);
-    } else if (bs == BLOCK_EO) {
-        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_EO>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
-                           op.links[PLINK], cl, ci, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems);
-    } else {
-        hipLaunchKernelGGL((k_sap_halfsweep<P, PLINK, BLOCK_MR>), dim3(grid), dim3(BLOCK_SITES), 0, s, op.g,
-                           op.links[PLINK], cl, nullptr, op.kappa, colour, n_mr, mode, x, b, stride, nrhs, tile,
-                           nitems);
-    }
+    if (mode == 0) launch_pm<P, PLINK, true>(op, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems, grid, s, bs);
+    else launch_pm<P, PLINK, false>(op, colour, n_mr, mode, x, b, stride, nrhs, tile, nitems, grid, s, bs);
     return hipGetLastError();
 }
 
