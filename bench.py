@@ -55,9 +55,12 @@ DSLASH_BYTES_F32 = 96 + 96 + 192 + 288  # in, out, four links, clover
 # mode 1 (x = 0) = 4 MR steps; mode 2 (own block zero) = 2 face hops on
 # average + combine (384) + 4 MR steps.
 SAP_FLOPS = {0: 1968 + 4 * 1944 + 24, 1: 4 * 1944, 2: 384 + 4 * 1944}
-# FP32 vector peak without packed FP32 instructions (this library disables
-# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Published FP32 vector peak of MI355X (256 CUs at 2.4 GHz).  The library
+# emits no packed FP32 instructions; FMA-dense code without them reached
+# 105 TFLOP/s on this part (bench.py --mfma-probe), above the 78.6 TFLOP/s
+# that 16 FMA lanes per SIMD would allow, so the published figure is the
+# ceiling used.
+FP32_VALU_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -709,6 +712,45 @@ def solver_variants(cs, synth, torch, U, b, c):
     return res
 
 
+def mfma_probe(cs, torch, nsites=1 << 21, reps=1024):
+    """The batched link x half-spinor product (8 right-hand sides, 16 complex
+    columns per link) chained in registers: FP32 vector arithmetic against
+    the bfloat16 matrix cores (cs_probe_link_product).  Unitary links keep
+    the chain bounded.  Per-step time = (t(1 + reps) - t(1)) / reps, so the
+    loads and stores drop out."""
+    g = torch.Generator(device="cuda").manual_seed(77)
+    z = torch.randn(nsites, 2, 3, dtype=torch.complex64, device="cuda", generator=g)
+    r0 = z[:, 0] / z[:, 0].norm(dim=1, keepdim=True)
+    r1 = z[:, 1] - (r0.conj() * z[:, 1]).sum(dim=1, keepdim=True) * r0
+    r1 = r1 / r1.norm(dim=1, keepdim=True)
+    r2 = torch.linalg.cross(r0, r1).conj()
+    U = torch.view_as_real(torch.stack([r0, r1, r2], dim=1).contiguous()).reshape(nsites, 9, 2).contiguous()
+    del z, r0, r1, r2
+    h = torch.randn(nsites, 16, 3, dtype=torch.complex64, device="cuda", generator=g)
+    H = torch.view_as_real(h).reshape(nsites, 16, 3, 2).contiguous()
+    V0 = torch.empty_like(H)
+    V1 = torch.empty_like(H)
+    res = dict(nsites=nsites, columns=16, reps=reps,
+               useful_flops_per_step=nsites * 16 * 72)
+    cs.probe_link_product(0, U, H, V0, 1)
+    cs.probe_link_product(1, U, H, V1, 1)
+    torch.cuda.synchronize()
+    res["mfma_vs_valu_rel_diff_one_step"] = float(f"{float((V1 - V0).norm() / V0.norm()):.3e}")
+    cs.probe_link_product(0, U, H, V0, 8)
+    cs.probe_link_product(1, U, H, V1, 8)
+    torch.cuda.synchronize()
+    res["mfma_vs_valu_rel_diff_eight_steps"] = float(f"{float((V1 - V0).norm() / V0.norm()):.3e}")
+    for kind, name in ((0, "valu_f32"), (1, "mfma_bf16")):
+        log(f"[mfma-probe] {name}")
+        t1 = timed_events(torch, lambda: cs.probe_link_product(kind, U, H, V0, 1), 3)
+        tr = timed_events(torch, lambda: cs.probe_link_product(kind, U, H, V0, 1 + reps), 3)
+        step = (tr - t1) / reps
+        res[name] = dict(one_step_us=round(t1, 1), per_step_us=round(step, 2),
+                         useful_TFLOPs=round(nsites * 16 * 72 / (step * 1e-6) / 1e12, 2))
+    res["mfma_speedup_per_step"] = round(res["valu_f32"]["per_step_us"] / res["mfma_bf16"]["per_step_us"], 2)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -727,6 +769,9 @@ def main():
                     help="only mode-0 SAP applications, operator launches and device copies on the "
                          "32^3x64 field (a short run for kernel-trace and hardware-counter passes)")
     ap.add_argument("--probe-prec", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="only the link x half-spinor product probe: FP32 vector arithmetic against the "
+                         "bfloat16 matrix cores")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -746,6 +791,9 @@ def main():
 
     if args.probe32:
         probe32(cs, synth, torch, cs.PREC[args.probe_prec], args.field_cache)
+        return
+    if args.mfma_probe:
+        print(json.dumps(dict(link_product_probe=mfma_probe(cs, torch))), flush=True)
         return
 
     out, (U, b, c) = headline(cs, synth, torch, args.steps, args.warmup, args.field_cache)

@@ -483,6 +483,21 @@ int cs_profile_reset(void);
  * buffers must not overlap (CS_ERR_INVALID); asynchronous on the stream. */
 int cs_device_copy(void* dst, const void* src, size_t bytes, void* stream);
 
+/* Measurement probe (not part of the method), for the question whether the
+ * product of a link with the half spinors of a tile of right-hand sides
+ * pays on the matrix cores: per site V = U^reps H (the product chained reps
+ * times), U a complex 3x3 matrix, H a complex 3 x 16 matrix (two spin
+ * components for 8 right-hand sides).  kind 0: FP32 vector arithmetic, one
+ * lane per site; kind 1: v_mfma_f32_16x16x16_bf16 on two sites at a time
+ * (the real 6x6 forms of their links block-diagonal in one operand; four
+ * independent pairs per wave), bfloat16 inputs and FP32 accumulation, each
+ * step's result rounded to bfloat16 for the next.  Layouts (device, float):
+ * U [nsites][9][2], H and V [nsites][16][3][2] (column, colour, re/im).
+ * nsites must be a multiple of 8 for kind 1 (CS_ERR_INVALID).  Asynchronous
+ * on the stream. */
+int cs_probe_link_product(int kind, long long nsites, int reps, const float* U, const float* H, float* V,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,8 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcloversap.so")
 
-SOURCES = ["setup.hip", "dslash.hip", "sap.hip", "sap_pair.hip", "blas.hip", "force.hip", "mg.hip", "gcr.cpp",
-           "bicgstab.cpp", "mg.cpp", "api.cpp"]
+SOURCES = ["setup.hip", "dslash.hip", "sap.hip", "sap_pair.hip", "blas.hip", "force.hip", "mg.hip", "probe.hip",
+           "gcr.cpp", "bicgstab.cpp", "mg.cpp", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -70,7 +70,7 @@ EXPORTED = ["cs_last_error", "cs_strerror", "cs_lattice_create", "cs_lattice_des
             "cs_mg_coarse_solve", "cs_mg_apply", "cs_gcr_solve_mg", "cs_bicgstab_solve_mg", "cs_force",
             "cs_force_noalloc",
             "cs_profile_enable",
-            "cs_profile_query", "cs_profile_reset", "cs_device_copy"]
+            "cs_profile_query", "cs_profile_reset", "cs_device_copy", "cs_probe_link_product"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -132,6 +132,7 @@ def load_library(path: str = LIB_PATH):
     L.cs_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_longlong), C.POINTER(C.c_double)]
     L.cs_profile_reset.argtypes = []
     L.cs_device_copy.argtypes = [P, P, C.c_size_t, P]
+    L.cs_probe_link_product.argtypes = [I, C.c_longlong, I, P, P, P, P]
     _lib = L
     return L
 
@@ -554,6 +555,19 @@ def device_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
     _need(dst, nbytes, "device_copy dst")
     load_library()
     _check(_lib.cs_device_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)), "cs_device_copy")
+
+
+def probe_link_product(kind: int, U: torch.Tensor, H: torch.Tensor, V: torch.Tensor, reps: int, stream=None):
+    """cs_probe_link_product: U float32 [n][9][2], H and V float32 [n][16][3][2]
+    device tensors; kind 0 FP32 VALU, 1 bfloat16 MFMA."""
+    n = U.shape[0]
+    for t, per in ((U, 18), (H, 96), (V, 96)):
+        if t.dtype != torch.float32:
+            raise ValueError("probe tensors are float32")
+        _need(t, n * per * 4, "probe tensor")
+    load_library()
+    _check(_lib.cs_probe_link_product(int(kind), int(n), int(reps), _ptr(U), _ptr(H), _ptr(V), _stream(stream)),
+           "cs_probe_link_product")
 
 
 def profile_query(name: str):

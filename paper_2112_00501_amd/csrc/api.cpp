@@ -813,6 +813,16 @@ int cs_force_noalloc(cs_gauge g, cs_clover c, const void* x, const void* y, doub
     return ok();
 }
 
+int cs_probe_link_product(int kind, long long nsites, int reps, const float* U, const float* H, float* V,
+                          void* stream) {
+    if (!U || !H || !V) return fail(CS_ERR_NULL, "U, H and V must be non-NULL");
+    if (kind != 0 && kind != 1) return fail(CS_ERR_INVALID, "kind must be 0 (VALU) or 1 (MFMA)");
+    if (nsites <= 0 || reps < 0 || (kind == 1 && nsites % 8 != 0) || nsites > (1LL << 31))
+        return fail(CS_ERR_INVALID, "nsites must be positive (a multiple of 8 for the MFMA form) and reps >= 0");
+    CS_HIP(cs::launch_probe_link_product(kind, nsites, reps, U, H, V, (hipStream_t)stream));
+    return ok();
+}
+
 int cs_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
     if (!dst || !src) return fail(CS_ERR_NULL, "dst and src must be non-NULL");
     if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)
