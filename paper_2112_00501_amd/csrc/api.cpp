@@ -18,6 +18,7 @@
 #include "bicgstab.hpp"
 #include "gcr.hpp"
 #include "mg.hpp"
+#include "probe.hpp"
 
 struct cs_lattice_s {
     cs::Geom g;

@@ -388,11 +388,6 @@ constexpr size_t FORCE_SCRATCH_BYTES = size_t(128) << 20;
 constexpr int FORCE_SCRATCH_MAX_DEVICES = 64;
 hipError_t force_scratch_address(void** out);
 
-// probe.hip: the link-times-half-spinors measurement probe (kind 0: FP32
-// VALU, 1: bfloat16 MFMA with FP32 accumulation).
-hipError_t launch_probe_link_product(int kind, long long nsites, int reps, const float* U, const float* H, float* V,
-                                     hipStream_t s);
-
 // blas.hip
 struct BlasWork;  // defined in blas.hip
 

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cs_internal.hpp"
+#include "probe.hpp"
 
 namespace cs {
 
