@@ -132,7 +132,8 @@ def cpu_baseline(U, b, c, gpu_fp64_iters, small):
     FGCR(16) iterations of that solve on all host threads, scaled by the
     iteration count of the GPU's FP64-only solve.  Beside it: the operator
     and one SAP application at 16^3x32 and 32^3x64 on all threads and at
-    16^3x32 on one thread."""
+    16^3x32 on one thread, at 16^4 and 24^3x48 on all threads, and complete
+    FP64 solves to 1e-10 at 8^4 and 16^3x32."""
     import numpy as np
 
     import oracle
@@ -162,7 +163,8 @@ def cpu_baseline(U, b, c, gpu_fp64_iters, small):
     per = {}
     t0 = time.perf_counter()
     oracle.sap(dims, (4, 4, 4, 4), U, T, kappa, 2, 4, b)
-    per["32x32x32x64"] = dict(threads=threads, apply_D_s=round(t_d, 3), sap_application_s=round(time.perf_counter() - t0, 3))
+    per["x".join(map(str, dims))] = dict(threads=threads, apply_D_s=round(t_d, 3),
+                                         sap_application_s=round(time.perf_counter() - t0, 3))
     del T
     Us, bs, cs_ = small
     ds = cs_["dims"]
@@ -177,8 +179,49 @@ def cpu_baseline(U, b, c, gpu_fp64_iters, small):
         per[f"16x16x16x32_{th}_threads"] = dict(threads=th, apply_D_s=round(td, 4),
                                                 sap_application_s=round(time.perf_counter() - t0, 4))
     oracle.set_threads(threads)
+    # complete FP64 SAP-FGCR(16) solves to 1e-10 where they take seconds, and
+    # the operator and one SAP application on the other lattices
+    for name, cfgname in (("8x8x8x8", "plain_fp64_8x8x8x8"), ("16x16x16x32", "mixed_16x16x16x32")):
+        cc = synth_configs()[cfgname]
+        if cfgname == "mixed_16x16x16x32":
+            Uc, bc, Tc = Us, bs, Ts
+        else:
+            Uc = synth_gauge(cc)
+            bc = synth_source(cc)
+            Tc = oracle.clover_field(cc["dims"], Uc, cc["kappa"], cc["csw"])
+        t0 = time.perf_counter()
+        _, st_, it_, rel_, _ = oracle.fgcr(cc["dims"], (4, 4, 4, 4), Uc, Tc, cc["kappa"], bc, n_cy=2, n_mr=4,
+                                           restart=16, tol=1e-10)
+        per[f"{name}_fgcr_solve"] = dict(threads=threads, seconds=round(time.perf_counter() - t0, 3),
+                                         iterations=it_, status=st_, true_relres=float(f"{rel_:.2e}"))
+    for name, cfgname in (("16x16x16x16", "lowprec_sub_16x16x16x16"), ("24x24x24x48", "multirhs_24x24x24x48")):
+        cc = synth_configs()[cfgname]
+        Uc, bc = synth_gauge(cc), synth_source(cc)
+        Tc = oracle.clover_field(cc["dims"], Uc, cc["kappa"], cc["csw"])
+        t0 = time.perf_counter()
+        oracle.apply_D(cc["dims"], Uc, Tc, cc["kappa"], bc)
+        td = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.sap(cc["dims"], (4, 4, 4, 4), Uc, Tc, cc["kappa"], 2, 4, bc)
+        per[name] = dict(threads=threads, apply_D_s=round(td, 4), sap_application_s=round(time.perf_counter() - t0, 4))
+        del Uc, bc, Tc
     res["per_lattice"] = per
     return res
+
+
+def synth_configs():
+    from paper_2112_00501_amd import synth
+    return synth.CONFIGS
+
+
+def synth_gauge(c):
+    from paper_2112_00501_amd import synth
+    return synth.gauge_field(c["dims"], c["eps"], c["gauge_seed"])
+
+
+def synth_source(c):
+    from paper_2112_00501_amd import synth
+    return synth.source(c["dims"], c["src_seed"])
 
 
 # Two-level multigrid of the paper's Section 3: N_vec = 16 null vectors from
