@@ -381,8 +381,11 @@ void cs_mg_params_default(cs_mg_params* p);
 /* Build the hierarchy for operator (g, c).  etas: nv consecutive CS_F32
  * internal fields (device, caller-owned, read only; random vectors), so the
  * caller controls the random numbers.  Allocates 2 nv + 1 CS_F32 fields,
- * D_c (nblk * 9 * nc^2 float2, 288 nv^2 bytes per aggregate) and eight
- * coarse vectors; the handle refers to c, which must outlive it.  Asynchronous on
+ * D_c (nblk * 9 * nc^2 float2, 288 nv^2 bytes per aggregate) and thirteen
+ * coarse vectors of workspace (the coarse BiCGStab's vectors and the +mu
+ * terms of a product), shared by every call on the handle, so calls on one
+ * handle must be ordered (one stream); the handle refers to c, which must
+ * outlive it.  Asynchronous on
  * the stream.  Errors: CS_ERR_NULL, CS_ERR_INVALID (parameters out of
  * range), CS_ERR_GEOMETRY (an odd number of blocks in some direction),
  * CS_ERR_ALLOC, CS_ERR_HIP. */

@@ -745,7 +745,7 @@ int cs_mg_coarse_apply(cs_mg m, const void* x, void* y, void* stream) {
     if (!m || !x || !y) return fail(CS_ERR_NULL, "handle, x and y must be non-NULL");
     if (overlap(x, y, m->data.coarse_bytes())) return fail(CS_ERR_INVALID, "x and y overlap");
     CS_HIP(cs::mg_coarse_apply(m->data.g, m->data.coarse(), m->data.nc(), (const float2*)x, (float2*)y,
-                               (hipStream_t)stream));
+                               m->data.cv.tau, (hipStream_t)stream));
     return ok();
 }
 

@@ -90,9 +90,9 @@ hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
     MG_CHK(hipMalloc((void**)&Dc, dc_bytes()));
     if (p.coarse_half) MG_CHK(hipMalloc(&Dc16, dc_bytes() / 2));
     MG_CHK(hipMalloc((void**)&rc, coarse_bytes()));
-    // the nine coarse vectors in one allocation (cv.x owns it)
+    // the nine coarse vectors and tau (4 vectors) in one allocation (cv.x owns it)
     float2* base = nullptr;
-    MG_CHK(hipMalloc((void**)&base, coarse_bytes() * 9));
+    MG_CHK(hipMalloc((void**)&base, coarse_bytes() * 13));
     const size_t n = (size_t)g.nblk * nc();
     cv.x = base;
     cv.r = base + n;
@@ -103,12 +103,13 @@ hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
     cv.v[1] = base + 6 * n;
     cv.s = base + 7 * n;
     cv.t = base + 8 * n;
+    cv.tau = base + 9 * n;
     MG_CHK(hipMalloc((void**)&sc, sizeof(CbScalars)));
     // partial sums, two complex values per workgroup (pa.A owns the allocation)
-    const size_t na = 2 * (size_t)MG_ELEM_WG, nb = 2 * (size_t)g.nblk;
+    const size_t na = 2 * (size_t)MG_ELEM_WG;
     double2* pb = nullptr;
-    MG_CHK(hipMalloc((void**)&pb, sizeof(double2) * (na + 2 * nb)));
-    pa = CbPartials{pb, pb + na, pb + na + nb};
+    MG_CHK(hipMalloc((void**)&pb, sizeof(double2) * 3 * na));
+    pa = CbPartials{pb, pb + na, pb + 2 * na};
     MG_CHK(hipHostMalloc((void**)&host_flag, sizeof(int), hipHostMallocDefault));
     return hipSuccess;
 }

@@ -307,22 +307,36 @@ __global__ __launch_bounds__(TPB) void k_mg_prolong(Geom g, const char* P, size_
 
 // ---------------------------------------------------------- coarse solver
 //
-// Matrix-vector products with D_c: one workgroup of 256 lanes per coarse
-// site a.  The 9 nc x nc blocks of the site are one K x nc matrix
-// M[k][row] (k = d nc + col, row fastest), applied to the gathered vector
-// xg[k] = x_{n(a,d), col} staged in LDS.  Lane t owns row t % nc and the
-// column chunk t / nc (every (256 / nc)-th k), so a wave reads whole
-// consecutive rows of M (coalesced) and each lane keeps several independent
-// loads in flight; the chunks are then added in a fixed order.
+// Matrix-vector products with D_c read 5 of the 9 stencil blocks of every
+// aggregate.  The +mu blocks are fixed by the -mu blocks of the neighbours
+// through gamma5-hermiticity, D_c[b - mu][+mu] = G5 D_c[b][-mu]^dag G5 (G5 =
+// +1 on chirality 0, -1 on chirality 1), so the product runs in two passes:
+//   pass 1, one workgroup of 256 lanes per aggregate a: y_a = D_c[a][0] x_a
+//     + sum_mu D_c[a][-mu] x_{a - mu}, and tau[a][mu] = G5 D_c[a][-mu]^dag G5
+//     x_a, the +mu contribution of a to the aggregate a - mu;
+//   pass 2, elementwise: y_a += sum_mu tau[a + mu][mu], mu in increasing order.
+// Each -mu block is read from HBM once (its adjoint re-reads it from cache).
+// In pass 1 the five blocks are one K5 x nc matrix M[k][row] (k = slot nc +
+// col, slot 0 the aggregate itself, slot 1 + mu its -mu block, row fastest)
+// applied to the gathered vector xg[k] = x_{n(a, slot), col} staged in LDS.
+// Lane t owns row t % nc and the column chunk t / nc (every (256 / nc)-th
+// k), so a wave reads whole consecutive rows of M (coalesced) and each lane
+// keeps several independent loads in flight; the chunks are then added in a
+// fixed order.  The adjoints give lane t the outputs o = t, t + 256, ... of
+// the 4 nc values tau[a][mu][i] (o = mu nc + i), each a sum over the nc
+// entries of one stored column.
 
 constexpr int CMV_TPB = 256;
-constexpr int CMV_KMAX = 9 * 2 * MG_MAX_NV;
+constexpr int CMV_KMAX = 5 * 2 * MG_MAX_NV;
 
 __device__ __forceinline__ int coarse_nb(const Geom& g, const BlockPos& p, int d) {
     return d == 0 ? p.blk : block_step(g, p, (d - 1) >> 1, (d & 1) ? +1 : -1);
 }
 
-// Entry (k, row) of a site's coarse matrix, FP32 or FP16 storage.
+// stencil direction of gather slot sl: the aggregate itself, then -mu
+__device__ __forceinline__ int slot_dir(int sl) { return sl == 0 ? 0 : 2 * sl; }
+
+// Entry i of the coarse matrices, FP32 or FP16 storage
 template <bool HALF>
 __device__ __forceinline__ float2 cm_load(const void* M, size_t i) {
     if (HALF) {
@@ -333,27 +347,28 @@ __device__ __forceinline__ float2 cm_load(const void* M, size_t i) {
     return ((const float2*)M)[i];
 }
 
-// y_row = sum_k M[k][row] xs[k] for the coarse matrix M of site a; valid in
-// lanes t < nc (others return 0)
+// y_row = sum over the self and -mu blocks of aggregate a of M[k][row] xs[k];
+// valid in lanes t < nc (others return 0)
 template <bool HALF>
-__device__ __forceinline__ float2 cmv_rows(const void* __restrict__ Dc, int a, int nc, const float2* xs,
-                                           float2* red) {
-    const int t = threadIdx.x, kch = CMV_TPB / nc, row = t % nc, kc = t / nc, K = 9 * nc;
-    const size_t base = (size_t)a * K * nc + row;
+__device__ __forceinline__ float2 cmv_rows5(const void* __restrict__ Dc, int a, int nc, const float2* xs,
+                                            float2* red) {
+    const int t = threadIdx.x, kch = CMV_TPB / nc, row = t % nc, kc = t / nc, K5 = 5 * nc;
+    const size_t base = (size_t)a * 9 * nc * nc + row;
     float re = 0.f, im = 0.f, re2 = 0.f, im2 = 0.f;
     if (kc < kch) {
         int k = kc;
-        for (; k + kch < K; k += 2 * kch) {
-            const float2 m0 = cm_load<HALF>(Dc, base + (size_t)k * nc);
-            const float2 m1 = cm_load<HALF>(Dc, base + (size_t)(k + kch) * nc);
-            const float2 x0 = xs[k], x1 = xs[k + kch];
+        for (; k + kch < K5; k += 2 * kch) {
+            const int k1 = k + kch;
+            const float2 m0 = cm_load<HALF>(Dc, base + (size_t)(slot_dir(k / nc) * nc + k % nc) * nc);
+            const float2 m1 = cm_load<HALF>(Dc, base + (size_t)(slot_dir(k1 / nc) * nc + k1 % nc) * nc);
+            const float2 x0 = xs[k], x1 = xs[k1];
             re = fmaf(m0.x, x0.x, re); re = fmaf(-m0.y, x0.y, re);
             im = fmaf(m0.x, x0.y, im); im = fmaf(m0.y, x0.x, im);
             re2 = fmaf(m1.x, x1.x, re2); re2 = fmaf(-m1.y, x1.y, re2);
             im2 = fmaf(m1.x, x1.y, im2); im2 = fmaf(m1.y, x1.x, im2);
         }
-        if (k < K) {
-            const float2 m0 = cm_load<HALF>(Dc, base + (size_t)k * nc), x0 = xs[k];
+        if (k < K5) {
+            const float2 m0 = cm_load<HALF>(Dc, base + (size_t)(slot_dir(k / nc) * nc + k % nc) * nc), x0 = xs[k];
             re = fmaf(m0.x, x0.x, re); re = fmaf(-m0.y, x0.y, re);
             im = fmaf(m0.x, x0.y, im); im = fmaf(m0.y, x0.x, im);
         }
@@ -370,33 +385,79 @@ __device__ __forceinline__ float2 cmv_rows(const void* __restrict__ Dc, int a, i
     return y;
 }
 
-// Workgroup sums of a and b (FP64) from lanes of wave 0 into partials[2 wg], [2 wg + 1]
-__device__ __forceinline__ void wave0_partials(double2 a, double2 b, double2* partials) {
-    if (threadIdx.x >= 64) return;
-    a = make_double2(wave_sum(a.x), wave_sum(a.y));
-    b = make_double2(wave_sum(b.x), wave_sum(b.y));
-    if (threadIdx.x == 0) {
-        partials[(size_t)blockIdx.x * 2] = a;
-        partials[(size_t)blockIdx.x * 2 + 1] = b;
+// tau[a][mu][i] = sum_c g5(i) g5(c) conj(D_c[a][-mu][col i][row c]) xa[c],
+// xa the aggregate's own entries (LDS)
+template <bool HALF>
+__device__ __forceinline__ void cmv_adjoint4(const void* __restrict__ Dc, int a, int nc, const float2* xa,
+                                             float2* __restrict__ tau) {
+    const int nv = nc / 2;
+    for (int o = threadIdx.x; o < 4 * nc; o += CMV_TPB) {
+        const int mu = o / nc, i = o % nc;
+        const size_t base = (((size_t)a * 9 + 2 + 2 * mu) * nc + i) * nc;
+        float re = 0.f, im = 0.f;
+        for (int c = 0; c < nc; ++c) {
+            const float2 m = cm_load<HALF>(Dc, base + c);
+            const float2 x = xa[c];
+            const float sg = (i < nv) == (c < nv) ? 1.f : -1.f;
+            // conj(m) x
+            re = fmaf(sg * m.x, x.x, re); re = fmaf(sg * m.y, x.y, re);
+            im = fmaf(sg * m.x, x.y, im); im = fmaf(-sg * m.y, x.x, im);
+        }
+        tau[((size_t)a * 4 + mu) * nc + i] = make_float2(re, im);
     }
+}
+
+// Gather of slot sl's entries of x for aggregate p (n(a, slot))
+__device__ __forceinline__ size_t gather_index(const Geom& g, const BlockPos& p, int nc, int k) {
+    return (size_t)coarse_nb(g, p, slot_dir(k / nc)) * nc + k % nc;
+}
+
+// Pass 2 for entry i = a nc + row: the +mu contributions of the four +mu
+// neighbours, in increasing mu
+__device__ __forceinline__ float2 tau_sum(const Geom& g, int nc, const float2* __restrict__ tau, size_t i) {
+    const int a = (int)(i / nc), row = (int)(i % nc);
+    const BlockPos p = block_pos(g, a);
+    float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int b = block_step(g, p, mu, +1);
+        const float2 v = tau[((size_t)b * 4 + mu) * nc + row];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    return s;
 }
 
 __device__ __forceinline__ double2 cdot_d(float2 a, float2 b) {  // conj(a) b
     return make_double2((double)a.x * b.x + (double)a.y * b.y, (double)a.x * b.y - (double)a.y * b.x);
 }
 
-// y = D_c x
+// y = D_c x, pass 1 (y holds the self and -mu terms afterwards, tau the
+// adjoint terms)
 template <bool HALF>
 __global__ __launch_bounds__(CMV_TPB) void k_mg_coarse_apply(Geom g, const void* __restrict__ Dc, int nc,
-                                                             const float2* __restrict__ x, float2* __restrict__ y) {
+                                                             const float2* __restrict__ x, float2* __restrict__ y,
+                                                             float2* __restrict__ tau) {
     __shared__ float2 xs[CMV_KMAX];
     __shared__ float2 red[CMV_TPB];
-    const int a = blockIdx.x, K = 9 * nc;
+    const int a = blockIdx.x, K5 = 5 * nc;
     const BlockPos p = block_pos(g, a);
-    for (int k = threadIdx.x; k < K; k += CMV_TPB) xs[k] = x[(size_t)coarse_nb(g, p, k / nc) * nc + k % nc];
+    for (int k = threadIdx.x; k < K5; k += CMV_TPB) xs[k] = x[gather_index(g, p, nc, k)];
     __syncthreads();
-    const float2 v = cmv_rows<HALF>(Dc, a, nc, xs, red);
+    const float2 v = cmv_rows5<HALF>(Dc, a, nc, xs, red);
     if ((int)threadIdx.x < nc) y[(size_t)a * nc + threadIdx.x] = v;
+    cmv_adjoint4<HALF>(Dc, a, nc, xs, tau);
+}
+
+// y = D_c x, pass 2
+__global__ __launch_bounds__(256) void k_mg_coarse_complete(Geom g, int nc, float2* __restrict__ y,
+                                                            const float2* __restrict__ tau) {
+    const size_t n = (size_t)g.nblk * nc;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float2 t = tau_sum(g, nc, tau, i);
+        const float2 v = y[i];
+        y[i] = make_float2(v.x + t.x, v.y + t.y);
+    }
 }
 
 __device__ __forceinline__ double2 cdiv2(double2 a, double2 b) {
@@ -408,13 +469,14 @@ __device__ __forceinline__ double2 cmul_d(double2 a, double2 b) {
 }
 
 // Coarse BiCGStab.  The start (x = 0, r = rh = r_c) is followed by the stop
-// test F1 of iteration 0; iteration it (parity q = it & 1) is then six
+// test F1 of iteration 0; iteration it (parity q = it & 1) is then eight
 // launches, the last of which is the stop test of iteration it + 1:
-//   M1  p = r + beta (p_prev - omega v_prev) formed while gathering, v = D_c p,
-//       partials B = <rh, v>
+//   M1  p = r + beta (p_prev - omega v_prev) formed while gathering, pass 1
+//       of v = D_c p
+//   C1  pass 2 of v = D_c p, partials B = <rh, v>
 //   F2  alpha = rho_new / <rh, v> (a zero denominator ends the solve)
-//   M2  s = r - alpha v formed while gathering, t = D_c s, partials C =
-//       <t, s>, |t|^2
+//   M2  s = r - alpha v formed while gathering, pass 1 of t = D_c s
+//   C2  pass 2 of t = D_c s, partials C = <t, s>, |t|^2
 //   F3  omega = <t, s> / |t|^2 (0 when t = 0)
 //   U   x += alpha p + omega s, r = s - omega t, partials A
 //   F1  rho_new = <rh, r>, |r|^2 from the partials A; stop before the next
@@ -481,89 +543,8 @@ __global__ __launch_bounds__(1024) void k_cb_f1(const double2* partials, int nwg
     sc->stopped[q] = stop;
 }
 
-template <bool HALF>
-__global__ __launch_bounds__(CMV_TPB) void k_cb_m1(Geom g, const void* __restrict__ Dc, int nc, CbVecs cv,
-                                                   const CbScalars* sc, int q, double2* partials) {
-    if (sc->stopped[q]) return;
-    __shared__ float2 xs[CMV_KMAX];
-    __shared__ float2 red[CMV_TPB];
-    const int a = blockIdx.x, K = 9 * nc;
-    const BlockPos p = block_pos(g, a);
-    const float br = (float)sc->beta[q].x, bi = (float)sc->beta[q].y;
-    const float wr = (float)sc->omega.x, wi = (float)sc->omega.y;
-    const float2 *pp = cv.p[q ^ 1], *vp = cv.v[q ^ 1];
-    float2* pn = cv.p[q];
-    for (int k = threadIdx.x; k < K; k += CMV_TPB) {
-        const int d = k / nc, col = k % nc;
-        const size_t i = (size_t)coarse_nb(g, p, d) * nc + col;
-        const float2 r = cv.r[i], po = pp[i], vo = vp[i];
-        const float tr = po.x - (wr * vo.x - wi * vo.y), ti = po.y - (wr * vo.y + wi * vo.x);
-        const float2 pv = make_float2(r.x + (br * tr - bi * ti), r.y + (br * ti + bi * tr));
-        xs[k] = pv;
-        if (d == 0) pn[i] = pv;
-    }
-    __syncthreads();
-    const float2 v = cmv_rows<HALF>(Dc, a, nc, xs, red);
-    double2 d0 = make_double2(0.0, 0.0);
-    if ((int)threadIdx.x < nc) {
-        const size_t i = (size_t)a * nc + threadIdx.x;
-        cv.v[q][i] = v;
-        d0 = cdot_d(cv.rh[i], v);
-    }
-    wave0_partials(d0, make_double2(0.0, 0.0), partials);
-}
-
-__global__ __launch_bounds__(1024) void k_cb_f2(const double2* partials, int nwg, CbScalars* sc, int q) {
-    if (sc->stopped[q]) return;
-    double tot[3];
-    sum3_partials(partials, nwg, tot);
-    if (threadIdx.x != 0) return;
-    const double2 rv = make_double2(tot[0], tot[1]);
-    const bool brk = rv.x == 0.0 && rv.y == 0.0;
-    sc->brk[q] = brk;
-    if (!brk) sc->alpha = cdiv2(sc->rho[q], rv);
-}
-
-template <bool HALF>
-__global__ __launch_bounds__(CMV_TPB) void k_cb_m2(Geom g, const void* __restrict__ Dc, int nc, CbVecs cv,
-                                                   const CbScalars* sc, int q, double2* partials) {
-    if (sc->stopped[q] || sc->brk[q]) return;
-    __shared__ float2 xs[CMV_KMAX];
-    __shared__ float2 red[CMV_TPB];
-    const int a = blockIdx.x, K = 9 * nc;
-    const BlockPos p = block_pos(g, a);
-    const float ar = (float)sc->alpha.x, ai = (float)sc->alpha.y;
-    const float2* vq = cv.v[q];
-    for (int k = threadIdx.x; k < K; k += CMV_TPB) {
-        const int d = k / nc, col = k % nc;
-        const size_t i = (size_t)coarse_nb(g, p, d) * nc + col;
-        const float2 r = cv.r[i], v = vq[i];
-        const float2 sv = make_float2(r.x - (ar * v.x - ai * v.y), r.y - (ar * v.y + ai * v.x));
-        xs[k] = sv;
-        if (d == 0) cv.s[i] = sv;
-    }
-    __syncthreads();
-    const float2 tv = cmv_rows<HALF>(Dc, a, nc, xs, red);
-    double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
-    if ((int)threadIdx.x < nc) {
-        const size_t i = (size_t)a * nc + threadIdx.x;
-        cv.t[i] = tv;
-        ts = cdot_d(tv, xs[threadIdx.x]);  // own entries of s sit at d = 0
-        tt.x = (double)tv.x * tv.x + (double)tv.y * tv.y;
-    }
-    wave0_partials(ts, tt, partials);
-}
-
-__global__ __launch_bounds__(1024) void k_cb_f3(const double2* partials, int nwg, CbScalars* sc, int q) {
-    if (sc->stopped[q] || sc->brk[q]) return;
-    double tot[3];
-    sum3_partials(partials, nwg, tot);
-    if (threadIdx.x != 0) return;
-    const double tt = tot[2];
-    sc->omega = tt > 0.0 ? make_double2(tot[0] / tt, tot[1] / tt) : make_double2(0.0, 0.0);
-}
-
-// partials A of <rh, r>, |r|^2 over 256-entry chunks
+// Workgroup partials (a, b) over 256-entry chunks: partials A of <rh, r>,
+// |r|^2, B of <rh, v> and C of <t, s>, |t|^2
 __device__ __forceinline__ void chunk_partials(double2 a, double b, double2* partials) {
     __shared__ double red[3][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -581,6 +562,112 @@ __device__ __forceinline__ void chunk_partials(double2 a, double b, double2* par
         partials[(size_t)blockIdx.x * 2 + 1] =
             make_double2((red[2][0] + red[2][1]) + (red[2][2] + red[2][3]), 0.0);
     }
+}
+
+template <bool HALF>
+__global__ __launch_bounds__(CMV_TPB) void k_cb_m1(Geom g, const void* __restrict__ Dc, int nc, CbVecs cv,
+                                                   const CbScalars* sc, int q) {
+    if (sc->stopped[q]) return;
+    __shared__ float2 xs[CMV_KMAX];
+    __shared__ float2 red[CMV_TPB];
+    const int a = blockIdx.x, K5 = 5 * nc;
+    const BlockPos p = block_pos(g, a);
+    const float br = (float)sc->beta[q].x, bi = (float)sc->beta[q].y;
+    const float wr = (float)sc->omega.x, wi = (float)sc->omega.y;
+    const float2 *pp = cv.p[q ^ 1], *vp = cv.v[q ^ 1];
+    float2* pn = cv.p[q];
+    for (int k = threadIdx.x; k < K5; k += CMV_TPB) {
+        const size_t i = gather_index(g, p, nc, k);
+        const float2 r = cv.r[i], po = pp[i], vo = vp[i];
+        const float tr = po.x - (wr * vo.x - wi * vo.y), ti = po.y - (wr * vo.y + wi * vo.x);
+        const float2 pv = make_float2(r.x + (br * tr - bi * ti), r.y + (br * ti + bi * tr));
+        xs[k] = pv;
+        if (k < nc) pn[i] = pv;
+    }
+    __syncthreads();
+    const float2 v = cmv_rows5<HALF>(Dc, a, nc, xs, red);
+    if ((int)threadIdx.x < nc) cv.v[q][(size_t)a * nc + threadIdx.x] = v;
+    cmv_adjoint4<HALF>(Dc, a, nc, xs, cv.tau);
+}
+
+// v += the +mu terms, partials B of <rh, v>
+__global__ __launch_bounds__(256) void k_cb_c1(Geom g, int nc, CbVecs cv, const CbScalars* sc, int q,
+                                               double2* partials) {
+    if (sc->stopped[q]) return;
+    const size_t n = (size_t)g.nblk * nc;
+    float2* vq = cv.v[q];
+    double2 d = make_double2(0.0, 0.0);
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float2 t = tau_sum(g, nc, cv.tau, i), v0 = vq[i];
+        const float2 v = make_float2(v0.x + t.x, v0.y + t.y);
+        vq[i] = v;
+        const double2 hv = cdot_d(cv.rh[i], v);
+        d.x += hv.x;
+        d.y += hv.y;
+    }
+    chunk_partials(d, 0.0, partials);
+}
+
+__global__ __launch_bounds__(1024) void k_cb_f2(const double2* partials, int nwg, CbScalars* sc, int q) {
+    if (sc->stopped[q]) return;
+    double tot[3];
+    sum3_partials(partials, nwg, tot);
+    if (threadIdx.x != 0) return;
+    const double2 rv = make_double2(tot[0], tot[1]);
+    const bool brk = rv.x == 0.0 && rv.y == 0.0;
+    sc->brk[q] = brk;
+    if (!brk) sc->alpha = cdiv2(sc->rho[q], rv);
+}
+
+template <bool HALF>
+__global__ __launch_bounds__(CMV_TPB) void k_cb_m2(Geom g, const void* __restrict__ Dc, int nc, CbVecs cv,
+                                                   const CbScalars* sc, int q) {
+    if (sc->stopped[q] || sc->brk[q]) return;
+    __shared__ float2 xs[CMV_KMAX];
+    __shared__ float2 red[CMV_TPB];
+    const int a = blockIdx.x, K5 = 5 * nc;
+    const BlockPos p = block_pos(g, a);
+    const float ar = (float)sc->alpha.x, ai = (float)sc->alpha.y;
+    const float2* vq = cv.v[q];
+    for (int k = threadIdx.x; k < K5; k += CMV_TPB) {
+        const size_t i = gather_index(g, p, nc, k);
+        const float2 r = cv.r[i], v = vq[i];
+        const float2 sv = make_float2(r.x - (ar * v.x - ai * v.y), r.y - (ar * v.y + ai * v.x));
+        xs[k] = sv;
+        if (k < nc) cv.s[i] = sv;
+    }
+    __syncthreads();
+    const float2 tv = cmv_rows5<HALF>(Dc, a, nc, xs, red);
+    if ((int)threadIdx.x < nc) cv.t[(size_t)a * nc + threadIdx.x] = tv;
+    cmv_adjoint4<HALF>(Dc, a, nc, xs, cv.tau);
+}
+
+// t += the +mu terms, partials C of <t, s>, |t|^2
+__global__ __launch_bounds__(256) void k_cb_c2(Geom g, int nc, CbVecs cv, const CbScalars* sc, int q,
+                                               double2* partials) {
+    if (sc->stopped[q] || sc->brk[q]) return;
+    const size_t n = (size_t)g.nblk * nc;
+    double2 ts = make_double2(0.0, 0.0);
+    double tt = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float2 u = tau_sum(g, nc, cv.tau, i), t0 = cv.t[i];
+        const float2 t = make_float2(t0.x + u.x, t0.y + u.y);
+        cv.t[i] = t;
+        const double2 d = cdot_d(t, cv.s[i]);
+        ts.x += d.x;
+        ts.y += d.y;
+        tt += (double)t.x * t.x + (double)t.y * t.y;
+    }
+    chunk_partials(ts, tt, partials);
+}
+
+__global__ __launch_bounds__(1024) void k_cb_f3(const double2* partials, int nwg, CbScalars* sc, int q) {
+    if (sc->stopped[q] || sc->brk[q]) return;
+    double tot[3];
+    sum3_partials(partials, nwg, tot);
+    if (threadIdx.x != 0) return;
+    const double tt = tot[2];
+    sc->omega = tt > 0.0 ? make_double2(tot[0] / tt, tot[1] / tt) : make_double2(0.0, 0.0);
 }
 
 // x = 0, r = rh = rc, p_prev = v_prev = 0 (slot 1), partials A
@@ -680,10 +767,14 @@ hipError_t mg_coarse_half(const float2* Dc, void* Dc16, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t mg_coarse_apply(const Geom& g, CoarseMat M, int nc, const float2* x, float2* y, hipStream_t s) {
+hipError_t mg_coarse_apply(const Geom& g, CoarseMat M, int nc, const float2* x, float2* y, float2* tau,
+                           hipStream_t s) {
     ProfScope ps("mg", s);
-    if (M.half) hipLaunchKernelGGL(k_mg_coarse_apply<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, x, y);
-    else hipLaunchKernelGGL(k_mg_coarse_apply<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, x, y);
+    if (M.half) hipLaunchKernelGGL(k_mg_coarse_apply<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, x, y, tau);
+    else hipLaunchKernelGGL(k_mg_coarse_apply<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, x, y, tau);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mg_coarse_complete, dim3(cb_grid(g.nblk * nc)), dim3(256), 0, s, g, nc, y, tau);
     return hipGetLastError();
 }
 
@@ -709,12 +800,14 @@ hipError_t mg_coarse_iters(const Geom& g, CoarseMat M, int nc, const CbVecs& cv,
     const int n = g.nblk * nc, grid = cb_grid(n);
     for (int it = it0; it < it1; ++it) {
         const int q = it & 1;
-        if (M.half) CB_LAUNCH(k_cb_m1<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q, pa.B);
-        else CB_LAUNCH(k_cb_m1<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q, pa.B);
-        CB_LAUNCH(k_cb_f2, dim3(1), dim3(1024), 0, s, pa.B, g.nblk, sc, q);
-        if (M.half) CB_LAUNCH(k_cb_m2<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q, pa.C);
-        else CB_LAUNCH(k_cb_m2<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q, pa.C);
-        CB_LAUNCH(k_cb_f3, dim3(1), dim3(1024), 0, s, pa.C, g.nblk, sc, q);
+        if (M.half) CB_LAUNCH(k_cb_m1<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q);
+        else CB_LAUNCH(k_cb_m1<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q);
+        CB_LAUNCH(k_cb_c1, dim3(grid), dim3(256), 0, s, g, nc, cv, sc, q, pa.B);
+        CB_LAUNCH(k_cb_f2, dim3(1), dim3(1024), 0, s, pa.B, grid, sc, q);
+        if (M.half) CB_LAUNCH(k_cb_m2<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q);
+        else CB_LAUNCH(k_cb_m2<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q);
+        CB_LAUNCH(k_cb_c2, dim3(grid), dim3(256), 0, s, g, nc, cv, sc, q, pa.C);
+        CB_LAUNCH(k_cb_f3, dim3(1), dim3(1024), 0, s, pa.C, grid, sc, q);
         CB_LAUNCH(k_cb_update, dim3(grid), dim3(256), 0, s, n, sc, q, cv, pa.A);
         CB_LAUNCH(k_cb_f1, dim3(1), dim3(1024), 0, s, pa.A, grid, sc, it + 1, 0.0);
     }

@@ -25,10 +25,11 @@ struct CbScalars {
 
 struct CbVecs {
     float2 *x, *r, *rh, *p[2], *v[2], *s, *t;
+    float2* tau;  // the +mu terms of a product, [aggregate][mu][nc]
 };
 
-// Workgroup partial sums: A from the elementwise kernels (at most
-// MG_ELEM_WG workgroups), B and C from the two products (one per coarse site).
+// Workgroup partial sums of the elementwise kernels (at most MG_ELEM_WG
+// workgroups each): A of <rh, r>, |r|^2, B of <rh, v>, C of <t, s>, |t|^2.
 struct CbPartials {
     double2 *A, *B, *C;
 };
@@ -101,7 +102,8 @@ hipError_t mg_prolong(const Geom& g, Transfer T, int nv, const float2* ec, void*
 // Dc16 = FP16 copy of the n complex entries of Dc
 hipError_t mg_coarse_half(const float2* Dc, void* Dc16, size_t n, hipStream_t s);
 // y = D_c x
-hipError_t mg_coarse_apply(const Geom& g, CoarseMat M, int nc, const float2* x, float2* y, hipStream_t s);
+hipError_t mg_coarse_apply(const Geom& g, CoarseMat M, int nc, const float2* x, float2* y, float2* tau,
+                           hipStream_t s);
 // cv.x = BiCGStab(D_c, rc) from zero: at most max_iter iterations, fewer once
 // |r| <= tol |rc| or on a breakdown (all decided on the device)
 hipError_t mg_coarse_bicgstab(const Geom& g, CoarseMat M, int nc, const float2* rc, const CbVecs& cv,
