@@ -40,15 +40,49 @@ struct LdsSpinor {  // in-block neighbours of the Dirichlet operator
     }
 };
 
-struct LdsLinks {
-    const LinkSmem<true>* sm;
-    template <typename R>
-    __device__ __forceinline__ void load(int, int l, int mu, bool, cpx<R>* u) const {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) u[k] = {(R)sm->u[mu][k][l].re, (R)sm->u[mu][k][l].im};
-        su3_row2(u);
-    }
+// Row 2 of the site's own four links, rebuilt once per work item from the
+// staged rows and kept in registers: every forward hop inside the block
+// uses the own link U_mu(x), so only the backward hops rebuild a row.
+struct OwnRow2 {
+    cpx<float> r[4][3];
 };
+
+// acc += the two hops of direction MU that stay inside the block (Dirichlet
+// block operator), neighbours and links read from LDS; the same terms in the
+// same order as the general hopping sum
+template <int MU, typename R>
+__device__ __forceinline__ void block_hop_dir(int l, const LdsSpinor<R>& ls, const LinkSmem<true>& sm,
+                                              const OwnRow2& own, cpx<R>* acc) {
+    constexpr int sh = 2 * MU;
+    const int lc = (l >> sh) & 3;
+    if (lc < 3) {  // forward neighbour, own link U_mu(x)
+        cpx<R> psi[12], u[9];
+        ls.load_nb(0, l + (1 << sh), true, psi);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u[k] = {(R)sm.u[MU][k][l].re, (R)sm.u[MU][k][l].im};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) u[6 + k] = {(R)own.r[MU][k].re, (R)own.r[MU][k].im};
+        hop_term<MU, -1>(u, psi, acc);
+    }
+    if (lc > 0) {  // backward neighbour, its link U_mu(x - mu)
+        const int nl = l - (1 << sh);
+        cpx<R> psi[12], u[9];
+        ls.load_nb(0, nl, true, psi);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u[k] = {(R)sm.u[MU][k][nl].re, (R)sm.u[MU][k][nl].im};
+        su3_row2(u);
+        hop_term<MU, +1>(u, psi, acc);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void block_hops(int l, const LdsSpinor<R>& ls, const LinkSmem<true>& sm,
+                                           const OwnRow2& own, cpx<R>* acc) {
+    block_hop_dir<0>(l, ls, sm, own, acc);
+    block_hop_dir<1>(l, ls, sm, own, acc);
+    block_hop_dir<2>(l, ls, sm, own, acc);
+    block_hop_dir<3>(l, ls, sm, own, acc);
+}
 
 // x is zero on the blocks of the current colour: only hops that leave the
 // block contribute to D x.
@@ -101,29 +135,87 @@ __device__ __forceinline__ void face_load(const Geom& g, const BlockPos& p, int 
     load_link<P, R, false>(links, back ? nb : p.blk, back ? nl : l, MU, ug);
 }
 
+// acc += the hop across a face of direction MU for a lane on it: the forward
+// hop (kind 1) with the lane's own link, the backward hop (kind 2) with
+// U_mu(x - mu); ug holds the link face_load fetched.  Used for t, whose faces
+// are whole waves.
 template <int MU, typename R>
-__device__ __forceinline__ void face_apply(int l, int kind, const cpx<R>* psi, const cpx<R>* ug,
-                                           const LinkSmem<true>& sm, cpx<R>* acc) {
-    if (kind == 1) {  // forward: own link U_mu(x) from LDS
-        cpx<R> u[9];
+__device__ __forceinline__ void face_apply(int kind, const cpx<R>* psi, const cpx<R>* ug, cpx<R>* acc) {
+    if (kind == 1) hop_term<MU, -1>(ug, psi, acc);
+    else if (kind == 2) hop_term<MU, +1>(ug, psi, acc);
+}
+
+// acc += (1 + S gamma_mu) U' psi with the sign S and the link U' chosen per
+// lane: a lane on the +MU face (kind 1) takes the forward hop (S = -1, U),
+// a lane on the -MU face (kind 2) the backward hop (S = +1, U^dag), in one
+// pass.  For x, y and z a quarter of the lanes of every wave lies on each
+// face, so one merged pass replaces two passes at a quarter occupancy each.
+// The spin algebra is that of spin_project and spin_reconstruct_add with S
+// as a factor.
+template <int MU, typename R>
+__device__ __forceinline__ void face_apply_merged(int kind, const cpx<R>* psi, const cpx<R>* ug, cpx<R>* acc) {
+    if (kind == 0) return;
+    const bool fwd = kind == 1;
+    const R S = fwd ? (R)-1 : (R)1;
+    cpx<R> u[9];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) u[k] = {(R)sm.u[MU][k][l].re, (R)sm.u[MU][k][l].im};
-        su3_row2(u);
-        hop_term<MU, -1>(u, psi, acc);
-    } else if (kind == 2) {  // backward: U_mu(x - mu) of the neighbour block
-        hop_term<MU, +1>(ug, psi, acc);
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const cpx<R> t = ug[b * 3 + a];
+            u[a * 3 + b] = fwd ? ug[a * 3 + b] : cpx<R>{t.re, -t.im};
+        }
+    auto axpy = [](cpx<R> y, R a, cpx<R> x) { return cpx<R>{(R)fma(a, x.re, y.re), (R)fma(a, x.im, y.im)}; };
+    cpx<R> h[6], v[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cpx<R> s0 = psi[a], s1 = psi[3 + a], s2 = psi[6 + a], s3 = psi[9 + a];
+        if (MU == 0) {
+            h[a] = axpy(s0, S, mul_mi(s3));
+            h[3 + a] = axpy(s1, S, mul_mi(s2));
+        } else if (MU == 1) {
+            h[a] = axpy(s0, -S, s3);
+            h[3 + a] = axpy(s1, S, s2);
+        } else if (MU == 2) {
+            h[a] = axpy(s0, S, mul_mi(s2));
+            h[3 + a] = axpy(s1, S, mul_i(s3));
+        } else {
+            h[a] = axpy(s0, S, s2);
+            h[3 + a] = axpy(s1, S, s3);
+        }
+    }
+    su3_mul_half<false>(u, h, v);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cpx<R> v0 = v[a], v1 = v[3 + a];
+        acc[a] = acc[a] + v0;
+        acc[3 + a] = acc[3 + a] + v1;
+        if (MU == 0) {
+            acc[6 + a] = axpy(acc[6 + a], S, mul_i(v1));
+            acc[9 + a] = axpy(acc[9 + a], S, mul_i(v0));
+        } else if (MU == 1) {
+            acc[6 + a] = axpy(acc[6 + a], S, v1);
+            acc[9 + a] = axpy(acc[9 + a], -S, v0);
+        } else if (MU == 2) {
+            acc[6 + a] = axpy(acc[6 + a], S, mul_i(v0));
+            acc[9 + a] = axpy(acc[9 + a], S, mul_mi(v1));
+        } else {
+            acc[6 + a] = axpy(acc[6 + a], S, v0);
+            acc[9 + a] = axpy(acc[9 + a], S, v1);
+        }
     }
 }
 
 template <int MA, int MB, int P, typename R>
 __device__ __forceinline__ void face_pair(const Geom& g, const BlockPos& p, int l, const void* xr,
-                                          const void* links, const LinkSmem<true>& sm, cpx<R>* acc) {
+                                          const void* links, cpx<R>* acc) {
     cpx<R> pa[12], ua[9], pb[12], ub[9];
     int ka, kb;
     face_load<MA, P>(g, p, l, xr, links, pa, ua, &ka);
     face_load<MB, P>(g, p, l, xr, links, pb, ub, &kb);
-    face_apply<MA>(l, ka, pa, ua, sm, acc);
-    face_apply<MB>(l, kb, pb, ub, sm, acc);
+    face_apply_merged<MA>(ka, pa, ua, acc);
+    if (MB == 3) face_apply<MB>(kb, pb, ub, acc);
+    else face_apply_merged<MB>(kb, pb, ub, acc);
 }
 
 // out = M in for a packed clover-format matrix M read from global memory one
@@ -261,12 +353,21 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
         const BlockPos p = block_pos(g, blk);
 
         __syncthreads();  // the previous item's readers of s_lk are done
+        OwnRow2 own;
         if constexpr (F32PATH) {
+#pragma unroll
             for (int mu = 0; mu < 4; ++mu) {
                 cpx<typename LinkIO<PLINK>::R> u[6];
                 LinkIO<PLINK>::load6(links, blk, l, mu, u);
+                cpx<float> uf[9];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) s_lk.u[mu][k][l] = {(float)u[k].re, (float)u[k].im};
+                for (int k = 0; k < 6; ++k) {
+                    uf[k] = {(float)u[k].re, (float)u[k].im};
+                    s_lk.u[mu][k][l].set(uf[k]);
+                }
+                su3_row2(uf);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) own.r[mu][k] = uf[6 + k];
             }
         }
         // The FP32 path keeps the clover term in registers for the whole
@@ -296,12 +397,11 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
 #pragma unroll
                     for (int k = 0; k < 12; ++k) s_rho[k][l] = {(R)t[k].re, (R)t[k].im};
                     __syncthreads();
-                    LdsLinks lk{&s_lk};
-                    hopping_sum<R>(g, p, l, ls, lk, acc);
+                    block_hops<R>(l, ls, s_lk, own, acc);
                 }
                 if (mode != 1) {
-                    face_pair<0, 1, P, R>(g, p, l, xr, links, s_lk, acc);
-                    face_pair<2, 3, P, R>(g, p, l, xr, links, s_lk, acc);
+                    face_pair<0, 1, P, R>(g, p, l, xr, links, acc);
+                    face_pair<2, 3, P, R>(g, p, l, xr, links, acc);
                 }
                 cpx<R> cx[12];
                 cpx<R> self[12];
@@ -421,8 +521,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
 #pragma unroll
                     for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
                     if constexpr (F32PATH) {
-                        LdsLinks lk{&s_lk};
-                        hopping_sum<R>(g, p, l, ls, lk, acc);
+                        block_hops<R>(l, ls, s_lk, own, acc);
                         clover_apply(cl, acc, delta);
                     } else {
                         GlobalLinks<PLINK, false> lk{links};
@@ -448,8 +547,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
 #pragma unroll
                     for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
                     if constexpr (F32PATH) {
-                        LdsLinks lk{&s_lk};
-                        hopping_sum<R>(g, p, l, ls, lk, acc);
+                        block_hops<R>(l, ls, s_lk, own, acc);
                     } else {
                         GlobalLinks<PLINK, false> lk{links};
                         hopping_sum_rolled<R>(g, p, l, ls, lk, acc);
@@ -504,8 +602,7 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
 #pragma unroll
                     for (int k = 0; k < 12; ++k) acc[k] = {(R)0, (R)0};
                     if constexpr (F32PATH) {
-                        LdsLinks lk{&s_lk};
-                        hopping_sum<R>(g, p, l, ls, lk, acc);
+                        block_hops<R>(l, ls, s_lk, own, acc);
                     } else {
                         GlobalLinks<PLINK, false> lk{links};
                         hopping_sum_rolled<R>(g, p, l, ls, lk, acc);
