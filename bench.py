@@ -206,6 +206,130 @@ def cpu_baseline(U, b, c, gpu_fp64_iters, small):
         per[name] = dict(threads=threads, apply_D_s=round(td, 4), sap_application_s=round(time.perf_counter() - t0, 4))
         del Uc, bc, Tc
     res["per_lattice"] = per
+    res["next_rows"] = next_rows_oracle(Us, bs, cs_, Ts)
+    return res
+
+
+def next_rows_oracle(U, b, c, T):
+    """The oracle on the work that next_rows() times on the GPU: one Jacobi
+    and one even-odd SAP application and complete flexible-BiCGStab
+    (reliable updates at 1e-5, as the library's default) and Richardson
+    solves on the 16^3x32 system, and the two-level multigrid (setup, then
+    MG-FGCR to 1e-10) on 8^4 with 8 null vectors, all FP64 on the threads
+    set by the caller."""
+    import oracle
+    from oracle import mg
+    dims, kappa, bdim = c["dims"], c["kappa"], (4, 4, 4, 4)
+    out = {}
+    t0 = time.perf_counter()
+    oracle.sap_jacobi(dims, bdim, U, T, kappa, 2, 4, b)
+    out["sap_jacobi_application_s"] = round(time.perf_counter() - t0, 4)
+    t0 = time.perf_counter()
+    oracle.sap_eo(dims, bdim, U, T, kappa, 2, 4, b)
+    out["sap_eo_application_s"] = round(time.perf_counter() - t0, 4)
+    t0 = time.perf_counter()
+    _, st, it, rs, rel, _ = oracle.fbicgstab(dims, bdim, U, T, kappa, b, n_cy=2, n_mr=4, tol=1e-10, delta=1e-5)
+    out["fbicgstab_solve"] = dict(seconds=round(time.perf_counter() - t0, 3), iterations=it, restarts=rs,
+                                  status=st, true_relres=float(f"{rel:.2e}"))
+    t0 = time.perf_counter()
+    _, st, it, outer, rel = oracle.richardson_bicgstab(dims, bdim, U, T, kappa, b, n_cy=2, n_mr=4, tol=1e-10)
+    out["richardson_bicgstab_solve"] = dict(seconds=round(time.perf_counter() - t0, 3), inner_iterations=it,
+                                            outer_steps=outer, status=st, true_relres=float(f"{rel:.2e}"))
+    res = {"16x16x16x32": out}
+    c8 = synth_configs()["mg_8x8x8x8"]
+    d8, k8 = c8["dims"], c8["kappa"]
+    U8, b8 = synth_gauge(c8), synth_source(c8)
+    T8 = oracle.clover_field(d8, U8, k8, c8["csw"])
+    from paper_2112_00501_amd import synth
+    q = MG8_PARAMS
+    etas = [synth.source(d8, c8["mg_eta_seed"] + i) for i in range(q["nv"])]
+    t0 = time.perf_counter()
+    P, Dc, aggs, _ = mg.setup(d8, bdim, U8, T8, k8, etas, n_cy_setup=q["n_cy_setup"], n_mr=q["n_mr"],
+                              n_adapt=q["n_adapt"], n_coarse=q["n_coarse"], n_cy_post=q["n_cy_post"],
+                              tol_coarse=q["tol_coarse"])
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, it, rel = mg.fgcr(lambda v: oracle.apply_D(d8, U8, T8, k8, v),
+                         lambda r: mg.mg_apply(d8, bdim, U8, T8, k8, P, aggs, Dc, r, q["n_coarse"], q["n_cy_post"],
+                                               q["n_mr"], q["tol_coarse"]), b8, restart=16, tol=1e-10)
+    res["8x8x8x8"] = dict(mg_setup_s=round(t_setup, 3),
+                          mg_fgcr_solve=dict(seconds=round(time.perf_counter() - t0, 3), iterations=it,
+                                             true_relres=float(f"{rel:.2e}")),
+                          params=dict(q))
+    return res
+
+
+def next_rows(cs, synth, torch, reps=3):
+    """The rows beyond the SAP-FGCR path, timed where the oracle's timing of
+    the same work (cpu_baseline's next_rows) is quick: one application of
+    the Jacobi and even-odd SAP smoothers (FP64 and FP32) and complete
+    flexible-BiCGStab (FP64 and FP32 smoother) and Richardson solves on the
+    16^3x32 system, and the two-level multigrid on 8^4 (setup, then MG-FGCR
+    to 1e-10).  Wall times of whole calls, medians after a warm-up."""
+    c = synth.CONFIGS["mixed_16x16x16x32"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["eps"], c["gauge_seed"])
+    b = synth.source(dims, c["src_seed"])
+    lat = cs.Lattice(dims)
+    op = cs.Operator(lat, torch.from_numpy(U).cuda(), c["kappa"], c["csw"])
+    out = {}
+    for prec, name in ((cs.F64, "f64"), (cs.F32, "f32")):
+        bp = lat.import_field(torch.from_numpy(b).cuda(), prec)
+        xp = lat.new_field(prec)
+        out[f"sap_jacobi_application_us_{name}"] = round(timed_events(
+            torch, lambda: op.sap_smooth_jacobi(xp, bp, prec, n_cy=2, n_jac=4, x0_is_zero=True), 10), 1)
+        out[f"sap_eo_application_us_{name}"] = round(timed_events(
+            torch, lambda: op.sap_smooth_eo(xp, bp, prec, n_cy=2, n_mr=4, x0_is_zero=True), 10), 1)
+        del bp, xp
+    bd = lat.import_field(torch.from_numpy(b).cuda(), cs.F64)
+    xd = lat.new_field(cs.F64)
+    for name, p in (("fbicgstab_fp64_smoother", cs.SolverParams(inner_prec=cs.F64, basis_prec=cs.F64)),
+                    ("fbicgstab_fp32_smoother", cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F64)),
+                    ("sp_bicgstab_in_fp64_richardson", cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32))):
+        t, it, st = time_bicgstab(cs, torch, op, xd, bd, p, reps)
+        out[name] = dict(ms=round(t * 1e3, 3), iterations=it, status=st)
+    del op, bd, xd
+    res = {"16x16x16x32": out}
+    c8 = synth.CONFIGS["mg_8x8x8x8"]
+    d8 = c8["dims"]
+    U8, b8 = synth.gauge_field(d8, c8["eps"], c8["gauge_seed"]), synth.source(d8, c8["src_seed"])
+    lat8 = cs.Lattice(d8)
+    op8 = cs.Operator(lat8, torch.from_numpy(U8).cuda(), c8["kappa"], c8["csw"])
+    prm = cs.MgParams(**MG8_PARAMS)
+    fb = lat8.field_bytes(cs.F32)
+    etas = lat8.new_field(cs.F32, prm.nv)
+    for i in range(prm.nv):
+        lat8.import_field(torch.from_numpy(synth.source(d8, c8["mg_eta_seed"] + i)).cuda(), cs.F32,
+                          out=etas[i * fb:(i + 1) * fb])
+    bd8 = lat8.import_field(torch.from_numpy(b8).cuda(), cs.F64)
+    xd8 = lat8.new_field(cs.F64)
+    setups = []
+    for i in range(reps + 1):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m = cs.Multigrid(op8, etas, prm)
+        torch.cuda.synchronize()
+        if i:
+            setups.append(time.perf_counter() - t)
+        if i < reps:
+            del m
+    p = cs.SolverParams(inner_prec=cs.F32, basis_prec=cs.F32, tol=1e-10)
+    times = []
+    for i in range(reps + 1):
+        xd8.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats = m.gcr_solve(xd8, bd8, p, allow_fail=True)
+        torch.cuda.synchronize()
+        if i:
+            times.append(time.perf_counter() - t)
+    res["8x8x8x8"] = dict(mg_setup_ms=round(sorted(setups)[len(setups) // 2] * 1e3, 3),
+                          mg_fgcr_solve=dict(ms=round(sorted(times)[len(times) // 2] * 1e3, 3),
+                                             iterations=stats["iters"], status=st),
+                          params=dict(MG8_PARAMS),
+                          note="FP32 hierarchy inside FP64 FGCR; 16 aggregates, latency-bound at this size")
+    del m, op8
+    torch.cuda.empty_cache()
     return res
 
 
@@ -228,6 +352,9 @@ def synth_source(c):
 # SAP-smoothed random vectors and 4 adaptive passes, coarse BiCGStab to 5%
 # (at most 50 iterations), 2 SAP post-smoothing cycles of 4 MR steps.
 MG_PARAMS = dict(nv=16, n_cy_setup=4, n_mr=4, n_adapt=4, n_coarse=50, n_cy_post=2, tol_coarse=0.05)
+# The same hierarchy with 8 null vectors, for the 8^4 comparison with the
+# oracle (whose dense coarse operator is assembled column by column).
+MG8_PARAMS = dict(MG_PARAMS, nv=8)
 
 
 def multigrid_measurement(cs, synth, torch, op, lat, c, U, b, bd, xd, sap_s, sap_it, reps=3, half=False):
@@ -854,6 +981,8 @@ def main():
         log("[bench] gradient on 32^3x64")
         out["grad_32x32x32x64"] = gradient_measurement(cs, synth, torch)
         torch.cuda.empty_cache()
+        log("[bench] next rows on 16^3x32 and 8^4 (the oracle's timings of the same work: cpu_baseline)")
+        out["next_rows"] = next_rows(cs, synth, torch)
     if args.paper_comparisons:
         log("[bench] kappa scan towards the critical mass, SAP-FGCR vs MG-FGCR")
         out["kappa_scan_32x32x32x64"] = kappa_scan(cs, synth, torch, cs.Lattice(c["dims"]), c, U, b)

@@ -163,4 +163,6 @@ CONFIGS = {
                             gauge_seed=1015, src_seed=2015, eta_seed=3015),
     "grad_8x8x8x8": dict(dims=(8, 8, 8, 8), eps=0.3, kappa=0.1355, csw=1.0,
                          gauge_seed=1025, src_seed=2025, eta_seed=3025),
+    "mg_8x8x8x8": dict(dims=(8, 8, 8, 8), eps=0.3, kappa=0.1355, csw=1.0,
+                       gauge_seed=1006, src_seed=2006, mg_eta_seed=4006),
 }
