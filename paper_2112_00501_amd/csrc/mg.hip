@@ -10,6 +10,8 @@
 // direction d = 0 the aggregate itself, 1 + 2 mu its +mu neighbour, 2 + 2 mu
 // its -mu neighbour (entries that reach the same aggregate through different
 // faces stay separate, so the stencil is exact on any lattice).
+#include <type_traits>
+
 #include "blas.hpp"
 #include "dslash_core.hpp"
 #include "wave.hpp"
@@ -407,6 +409,100 @@ __device__ __forceinline__ void cmv_adjoint4(const void* __restrict__ Dc, int a,
     }
 }
 
+// Sum over aligned groups of G = 16, 32 or 64 lanes (a row of the wave, a
+// half or the whole wave); every lane of the group receives the total.
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+    using namespace wave_detail;
+    v += dpp_move<DPP_XOR1>(v);
+    v += dpp_move<DPP_XOR2>(v);
+    v += dpp_move<DPP_HALF_MIRROR>(v);
+    v += dpp_move<DPP_MIRROR>(v);
+    if constexpr (G >= 32) v = cross_add<16>(v);
+    if constexpr (G >= 64) v = cross_add<32>(v);
+    return v;
+}
+
+// Pass 1 of the product for nc = NC in {16, 32, 64}: the adjoint terms come
+// from the same loads as the forward ones.  The NC lanes of the group kc
+// all hold entry k of one stored column (rows 0..NC-1), so each lane forms
+// g5(col) g5(row) conj(M[k][row]) xa[row] and a group sum gives
+// tau[a][mu][col] for the -mu slots (it is formed, and dropped, for the
+// self slot too, so that every lane takes part in every exchange).  The
+// loads of a lane are issued in batches (5 FP32 or 10 FP16 entries) before
+// their arithmetic, and the sums are stored after the loop, so no store
+// sits between loads.
+// The forward chunks are reduced as in cmv_rows5.
+template <bool HALF, int NC>
+__device__ __forceinline__ float2 cmv5_fused(const void* __restrict__ Dc, int a, const float2* xs, float2* red,
+                                             float2* __restrict__ tau) {
+    constexpr int KCH = CMV_TPB / NC, NJ = 5 * NC / KCH, NV = NC / 2;
+    // loads issued together before their arithmetic (NJ is 5, 20 or 80)
+    constexpr int CH = NJ < (HALF ? 10 : 5) ? NJ : (HALF ? 10 : 5);
+    static_assert(NJ % CH == 0 && NJ <= 2 * NC, "batches cover the loop; a lane keeps at most two sums");
+    const int t = threadIdx.x, row = t % NC, kc = t / NC;
+    const size_t base = (size_t)a * 9 * NC * NC + row;
+    const float2 xa = xs[row];
+    float re = 0.f, im = 0.f;
+    // the adjoint sums this lane stores: j = row and j = row + NC
+    float2 keep0 = make_float2(0.f, 0.f), keep1 = make_float2(0.f, 0.f);
+#pragma unroll 1
+    for (int j0 = 0; j0 < NJ; j0 += CH) {
+        float2 m[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int k = kc + (j0 + c) * KCH;
+            m[c] = cm_load<HALF>(Dc, base + (size_t)(slot_dir(k / NC) * NC + k % NC) * NC);
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int j = j0 + c, k = kc + j * KCH, col = k % NC;
+            const float2 x = xs[k];
+            re = fmaf(m[c].x, x.x, re);
+            re = fmaf(-m[c].y, x.y, re);
+            im = fmaf(m[c].x, x.y, im);
+            im = fmaf(m[c].y, x.x, im);
+            const float sg = (col < NV) == (row < NV) ? 1.f : -1.f;
+            float ar = sg * fmaf(m[c].x, xa.x, m[c].y * xa.y), ai = sg * fmaf(m[c].x, xa.y, -m[c].y * xa.x);
+            ar = group_sum<NC>(ar);
+            ai = group_sum<NC>(ai);
+            if (j == row) keep0 = make_float2(ar, ai);
+            if (j == row + NC) keep1 = make_float2(ar, ai);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int j = i * NC + row;
+        if (j < NJ) {
+            const int k = kc + j * KCH, sl = k / NC;
+            if (sl > 0) tau[((size_t)a * 4 + sl - 1) * NC + k % NC] = i ? keep1 : keep0;
+        }
+    }
+    red[t] = make_float2(re, im);
+    __syncthreads();
+    float2 y = make_float2(0.f, 0.f);
+    if (t < NC)
+        for (int c = 0; c < KCH; ++c) {
+            const float2 v = red[c * NC + t];
+            y.x += v.x;
+            y.y += v.y;
+        }
+    return y;
+}
+
+// Pass 1 for any nc: NC = 0 takes the two-step form
+template <bool HALF, int NC>
+__device__ __forceinline__ float2 cmv5(const void* __restrict__ Dc, int a, int nc, const float2* xs, float2* red,
+                                       float2* __restrict__ tau) {
+    if constexpr (NC > 0) {
+        return cmv5_fused<HALF, NC>(Dc, a, xs, red, tau);
+    } else {
+        const float2 y = cmv_rows5<HALF>(Dc, a, nc, xs, red);
+        cmv_adjoint4<HALF>(Dc, a, nc, xs, tau);
+        return y;
+    }
+}
+
 // Gather of slot sl's entries of x for aggregate p (n(a, slot))
 __device__ __forceinline__ size_t gather_index(const Geom& g, const BlockPos& p, int nc, int k) {
     return (size_t)coarse_nb(g, p, slot_dir(k / nc)) * nc + k % nc;
@@ -434,7 +530,7 @@ __device__ __forceinline__ double2 cdot_d(float2 a, float2 b) {  // conj(a) b
 
 // y = D_c x, pass 1 (y holds the self and -mu terms afterwards, tau the
 // adjoint terms)
-template <bool HALF>
+template <bool HALF, int NC>
 __global__ __launch_bounds__(CMV_TPB) void k_mg_coarse_apply(Geom g, const void* __restrict__ Dc, int nc,
                                                              const float2* __restrict__ x, float2* __restrict__ y,
                                                              float2* __restrict__ tau) {
@@ -444,9 +540,8 @@ __global__ __launch_bounds__(CMV_TPB) void k_mg_coarse_apply(Geom g, const void*
     const BlockPos p = block_pos(g, a);
     for (int k = threadIdx.x; k < K5; k += CMV_TPB) xs[k] = x[gather_index(g, p, nc, k)];
     __syncthreads();
-    const float2 v = cmv_rows5<HALF>(Dc, a, nc, xs, red);
+    const float2 v = cmv5<HALF, NC>(Dc, a, nc, xs, red, tau);
     if ((int)threadIdx.x < nc) y[(size_t)a * nc + threadIdx.x] = v;
-    cmv_adjoint4<HALF>(Dc, a, nc, xs, tau);
 }
 
 // y = D_c x, pass 2
@@ -564,7 +659,7 @@ __device__ __forceinline__ void chunk_partials(double2 a, double b, double2* par
     }
 }
 
-template <bool HALF>
+template <bool HALF, int NC>
 __global__ __launch_bounds__(CMV_TPB) void k_cb_m1(Geom g, const void* __restrict__ Dc, int nc, CbVecs cv,
                                                    const CbScalars* sc, int q) {
     if (sc->stopped[q]) return;
@@ -585,9 +680,8 @@ __global__ __launch_bounds__(CMV_TPB) void k_cb_m1(Geom g, const void* __restric
         if (k < nc) pn[i] = pv;
     }
     __syncthreads();
-    const float2 v = cmv_rows5<HALF>(Dc, a, nc, xs, red);
+    const float2 v = cmv5<HALF, NC>(Dc, a, nc, xs, red, cv.tau);
     if ((int)threadIdx.x < nc) cv.v[q][(size_t)a * nc + threadIdx.x] = v;
-    cmv_adjoint4<HALF>(Dc, a, nc, xs, cv.tau);
 }
 
 // v += the +mu terms, partials B of <rh, v>
@@ -619,7 +713,7 @@ __global__ __launch_bounds__(1024) void k_cb_f2(const double2* partials, int nwg
     if (!brk) sc->alpha = cdiv2(sc->rho[q], rv);
 }
 
-template <bool HALF>
+template <bool HALF, int NC>
 __global__ __launch_bounds__(CMV_TPB) void k_cb_m2(Geom g, const void* __restrict__ Dc, int nc, CbVecs cv,
                                                    const CbScalars* sc, int q) {
     if (sc->stopped[q] || sc->brk[q]) return;
@@ -637,9 +731,8 @@ __global__ __launch_bounds__(CMV_TPB) void k_cb_m2(Geom g, const void* __restric
         if (k < nc) cv.s[i] = sv;
     }
     __syncthreads();
-    const float2 tv = cmv_rows5<HALF>(Dc, a, nc, xs, red);
+    const float2 tv = cmv5<HALF, NC>(Dc, a, nc, xs, red, cv.tau);
     if ((int)threadIdx.x < nc) cv.t[(size_t)a * nc + threadIdx.x] = tv;
-    cmv_adjoint4<HALF>(Dc, a, nc, xs, cv.tau);
 }
 
 // t += the +mu terms, partials C of <t, s>, |t|^2
@@ -720,6 +813,22 @@ int cb_grid(int n) {
     return b < MG_ELEM_WG ? b : MG_ELEM_WG;
 }
 
+// f(half, nc) with the storage flag and the product's nc as compile-time
+// constants: 16, 32 and 64 take the fused pass 1, other sizes NC = 0
+template <typename F>
+void with_nc(int nc, bool half, F&& f) {
+    auto go = [&](auto h) {
+        switch (nc) {
+        case 16: f(h, std::integral_constant<int, 16>{}); break;
+        case 32: f(h, std::integral_constant<int, 32>{}); break;
+        case 64: f(h, std::integral_constant<int, 64>{}); break;
+        default: f(h, std::integral_constant<int, 0>{}); break;
+        }
+    };
+    if (half) go(std::true_type{});
+    else go(std::false_type{});
+}
+
 }  // namespace
 
 hipError_t mg_orthonormalize(const Geom& g, void* P, int nv, hipStream_t s) {
@@ -770,19 +879,25 @@ hipError_t mg_coarse_half(const float2* Dc, void* Dc16, size_t n, hipStream_t s)
 hipError_t mg_coarse_apply(const Geom& g, CoarseMat M, int nc, const float2* x, float2* y, float2* tau,
                            hipStream_t s) {
     ProfScope ps("mg", s);
-    if (M.half) hipLaunchKernelGGL(k_mg_coarse_apply<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, x, y, tau);
-    else hipLaunchKernelGGL(k_mg_coarse_apply<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, x, y, tau);
+    with_nc(nc, M.half, [&](auto half, auto ncc) {
+        hipLaunchKernelGGL((k_mg_coarse_apply<decltype(half)::value, decltype(ncc)::value>), dim3(g.nblk),
+                           dim3(CMV_TPB), 0, s, g, M.m, nc, x, y, tau);
+    });
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mg_coarse_complete, dim3(cb_grid(g.nblk * nc)), dim3(256), 0, s, g, nc, y, tau);
     return hipGetLastError();
 }
 
+#define CB_CHECK()                               \
+    do {                                         \
+        hipError_t e_ = hipGetLastError();       \
+        if (e_ != hipSuccess) return e_;         \
+    } while (0)
 #define CB_LAUNCH(...)                           \
     do {                                         \
         hipLaunchKernelGGL(__VA_ARGS__);         \
-        hipError_t e_ = hipGetLastError();       \
-        if (e_ != hipSuccess) return e_;         \
+        CB_CHECK();                              \
     } while (0)
 
 hipError_t mg_coarse_begin(const Geom& g, int nc, const float2* rc, const CbVecs& cv, CbScalars* sc,
@@ -800,12 +915,18 @@ hipError_t mg_coarse_iters(const Geom& g, CoarseMat M, int nc, const CbVecs& cv,
     const int n = g.nblk * nc, grid = cb_grid(n);
     for (int it = it0; it < it1; ++it) {
         const int q = it & 1;
-        if (M.half) CB_LAUNCH(k_cb_m1<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q);
-        else CB_LAUNCH(k_cb_m1<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q);
+        with_nc(nc, M.half, [&](auto half, auto ncc) {
+            hipLaunchKernelGGL((k_cb_m1<decltype(half)::value, decltype(ncc)::value>), dim3(g.nblk), dim3(CMV_TPB),
+                               0, s, g, M.m, nc, cv, sc, q);
+        });
+        CB_CHECK();
         CB_LAUNCH(k_cb_c1, dim3(grid), dim3(256), 0, s, g, nc, cv, sc, q, pa.B);
         CB_LAUNCH(k_cb_f2, dim3(1), dim3(1024), 0, s, pa.B, grid, sc, q);
-        if (M.half) CB_LAUNCH(k_cb_m2<true>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q);
-        else CB_LAUNCH(k_cb_m2<false>, dim3(g.nblk), dim3(CMV_TPB), 0, s, g, M.m, nc, cv, sc, q);
+        with_nc(nc, M.half, [&](auto half, auto ncc) {
+            hipLaunchKernelGGL((k_cb_m2<decltype(half)::value, decltype(ncc)::value>), dim3(g.nblk), dim3(CMV_TPB),
+                               0, s, g, M.m, nc, cv, sc, q);
+        });
+        CB_CHECK();
         CB_LAUNCH(k_cb_c2, dim3(grid), dim3(256), 0, s, g, nc, cv, sc, q, pa.C);
         CB_LAUNCH(k_cb_f3, dim3(1), dim3(1024), 0, s, pa.C, grid, sc, q);
         CB_LAUNCH(k_cb_update, dim3(grid), dim3(256), 0, s, n, sc, q, cv, pa.A);
@@ -815,6 +936,7 @@ hipError_t mg_coarse_iters(const Geom& g, CoarseMat M, int nc, const CbVecs& cv,
 }
 
 #undef CB_LAUNCH
+#undef CB_CHECK
 
 hipError_t mg_coarse_bicgstab(const Geom& g, CoarseMat M, int nc, const float2* rc, const CbVecs& cv,
                               CbScalars* sc, const CbPartials& pa, int max_iter, double tol, hipStream_t s) {
