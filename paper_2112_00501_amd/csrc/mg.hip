@@ -118,10 +118,13 @@ struct LdsColumn {  // in-block neighbours for the self term
 
 // Assembly of D_c[a][d][col][row] = <p_{a,row}, D p_{n(a,d),col}> restricted
 // to the terms of D that couple aggregate a to its neighbour in direction d.
-// One workgroup per aggregate (lane = site).  Each column is applied once:
-// the self term (clover and the in-aggregate hops of the column, staged in
-// LDS) and the four -mu face terms (hops from the neighbouring aggregates)
-// stay in registers while every row of P streams past; per row each lane
+// One workgroup per (aggregate, column), lane = site; the nc workgroups of an
+// aggregate are consecutive on one XCD, so the aggregate's rows of P, links
+// and clover term come from HBM once and from that XCD's L2 for the others.
+// The column is applied once: the self term (clover and the in-aggregate
+// hops of the column, staged in LDS) and the four -mu face terms (hops from
+// the neighbouring aggregates) stay in registers while every row of P
+// streams past; per row each lane
 // forms 20 partial dot products (self term and four faces, two row
 // chiralities, re and im), which are summed over the lanes through a
 // lane-major LDS array in a fixed order.  The +mu blocks follow afterwards
@@ -165,17 +168,18 @@ __device__ __forceinline__ void back_face(const Geom& g, const BlockPos& p, int 
 
 __global__ __launch_bounds__(TPB, 2) void k_mg_assemble(Geom g, const void* links, const void* clover, float kappa,
                                                      const char* P, size_t fs, int nv, float2* Dc) {
-    const int blk = blockIdx.x, l = threadIdx.x, nc = 2 * nv;
+    const int l = threadIdx.x, nc = 2 * nv;
+    const int w = xcd_remap(blockIdx.x, g.nblk * nc), blk = w / nc;
     const BlockPos p = block_pos(g, blk);
     __shared__ lds_cpx<float> s[12][BLOCK_SITES];
     __shared__ float red[BLOCK_SITES * ASM_LD];
     __shared__ float part[ASM_VALS][4];
-    for (int col = 0; col < nc; ++col) {
+    {
+        const int col = w % nc;
         cpx<float> y0[12], yf[4][12];
         {
             cpx<float> c[12], acc[12];
             column_site(P, fs, nv, col, g.nblk, blk, l, c);
-            __syncthreads();  // the previous column's readers of s are done
 #pragma unroll
             for (int k = 0; k < 12; ++k) s[k][l].set(c[k]);
             __syncthreads();
@@ -840,7 +844,7 @@ hipError_t mg_orthonormalize(const Geom& g, void* P, int nv, hipStream_t s) {
 
 hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipStream_t s) {
     ProfScope ps("mg", s);
-    hipLaunchKernelGGL(k_mg_assemble, dim3(op.g.nblk), dim3(TPB), 0, s, op.g, op.links[P_F32], op.clover32,
+    hipLaunchKernelGGL(k_mg_assemble, dim3(op.g.nblk * 2 * nv), dim3(TPB), 0, s, op.g, op.links[P_F32], op.clover32,
                        (float)op.kappa, (const char*)P, spinor_bytes_per_site(P_F32) * op.g.V, nv, Dc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
