@@ -921,6 +921,18 @@ def mfma_probe(cs, torch, nsites=1 << 21, reps=1024):
     return res
 
 
+# Side measurements that --only runs alone (the 32^3x64 variants take the
+# headline's field, generated or read from --field-cache).
+LEGS = {
+    "cache_resident_16x16x16x32": cache_resident_16,
+    "variants_32x32x32x64": None,
+    "lowprec_sub_16x16x16x16": lowprec_subrun,
+    "multirhs_24x24x24x48": multirhs_measurement,
+    "grad_32x32x32x64": gradient_measurement,
+    "next_rows": next_rows,
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -939,6 +951,9 @@ def main():
                     help="only mode-0 SAP applications, operator launches and device copies on the "
                          "32^3x64 field (a short run for kernel-trace and hardware-counter passes)")
     ap.add_argument("--probe-prec", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--only", choices=sorted(LEGS),
+                    help="only one side measurement (no headline, no CPU baseline): a short run for "
+                         "kernel-trace and hardware-counter passes")
     ap.add_argument("--mfma-probe", action="store_true",
                     help="only the link x half-spinor product probe: FP32 vector arithmetic against the "
                          "bfloat16 matrix cores")
@@ -964,6 +979,16 @@ def main():
         return
     if args.mfma_probe:
         print(json.dumps(dict(link_product_probe=mfma_probe(cs, torch))), flush=True)
+        return
+    if args.only:
+        log(f"[bench] only {args.only}")
+        if args.only == "variants_32x32x32x64":
+            c = synth.CONFIGS["lowprec_32x32x32x64"]
+            U, b = cached_field(synth, c, args.field_cache)
+            res = solver_variants(cs, synth, torch, U, b, c)
+        else:
+            res = LEGS[args.only](cs, synth, torch)
+        print(json.dumps({args.only: res}), flush=True)
         return
 
     out, (U, b, c) = headline(cs, synth, torch, args.steps, args.warmup, args.field_cache)
