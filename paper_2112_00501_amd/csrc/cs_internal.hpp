@@ -38,8 +38,11 @@ constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
 // Minimum waves per SIMD requested from the register allocator for the
 // operator and smoother kernels (0 = compiler default); XCD-aware ordering of
 // workgroups; non-temporal loads of the fields that are read exactly once
-// (links, clover); the operator's hopping sum as a rolled loop (bounded
-// registers, 4 waves per SIMD) instead of fully unrolled.
+// (links, clover) and non-temporal stores of FP32 spinor fields, which keeps
+// the caches for the face neighbours that are read twice; the operator's
+// hopping sum as a rolled loop (bounded registers, 4 waves per SIMD) instead
+// of fully unrolled; a raised wave priority during the loads of a SAP block
+// visit.
 #ifndef CS_DSLASH_WAVES
 #define CS_DSLASH_WAVES 0
 #endif
@@ -52,6 +55,9 @@ constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
 #ifndef CS_NT_LOADS
 #define CS_NT_LOADS 0
 #endif
+#ifndef CS_NT_STORES
+#define CS_NT_STORES 1
+#endif
 #ifndef CS_DSLASH_ROLLED
 #define CS_DSLASH_ROLLED 1
 #endif
@@ -59,6 +65,9 @@ constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
 // 1 = the block's spinor staged in LDS, 2 = its spinor and links staged.
 #ifndef CS_DSLASH_STAGED
 #define CS_DSLASH_STAGED 1
+#endif
+#ifndef CS_SAP_PRIO
+#define CS_SAP_PRIO 1
 #endif
 #ifndef CS_SAP_LDS_RESIDUAL
 #define CS_SAP_LDS_RESIDUAL 1
@@ -105,6 +114,22 @@ __device__ __forceinline__ T ld_once(const T* p) {
     }
 #else
     return *p;
+#endif
+}
+
+// Store of data that this kernel does not read again (streamed past the
+// caches' reuse set when CS_NT_STORES is on).
+template <typename T>
+__device__ __forceinline__ void st_once(T* p, const T& v) {
+#if CS_NT_STORES
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 16) {
+        __builtin_nontemporal_store(__builtin_bit_cast(v4u, v), (v4u*)p);
+    } else {
+        *p = v;
+    }
+#else
+    *p = v;
 #endif
 }
 

@@ -85,7 +85,7 @@ struct SpinorIO<P_F32> {
         float4* p = (float4*)base + (size_t)blk * 6 * BLOCK_SITES + l;
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            p[k * BLOCK_SITES] = make_float4(c[2 * k].re, c[2 * k].im, c[2 * k + 1].re, c[2 * k + 1].im);
+            st_once(p + k * BLOCK_SITES, make_float4(c[2 * k].re, c[2 * k].im, c[2 * k + 1].re, c[2 * k + 1].im));
     }
 };
 

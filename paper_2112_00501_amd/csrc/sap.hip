@@ -353,6 +353,12 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
         const BlockPos p = block_pos(g, blk);
 
         __syncthreads();  // the previous item's readers of s_lk are done
+#if CS_SAP_PRIO
+        // raised wave priority while the visit's loads are issued, so that
+        // they go out ahead of the block-solver arithmetic of the other
+        // workgroup resident on the compute unit
+        __builtin_amdgcn_s_setprio(1);
+#endif
         OwnRow2 own;
         if constexpr (F32PATH) {
 #pragma unroll
@@ -538,6 +544,9 @@ __global__ CS_SAP_BOUNDS void k_sap_halfsweep(Geom g, const void* __restrict__ l
                     for (int k = 0; k < 12; ++k) s_rho[k][l].set(delta[k]);
                 }
             }
+#if CS_SAP_PRIO
+            __builtin_amdgcn_s_setprio(0);
+#endif
             // ---- MR on the Dirichlet block operator; rho lives in LDS only
             for (int it = 0; BS == BLOCK_MR && it < n_mr; ++it) {
                 __syncthreads();
