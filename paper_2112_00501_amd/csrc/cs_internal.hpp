@@ -28,6 +28,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 #include <string>
 
 namespace cs {
@@ -53,7 +54,7 @@ constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
 #define CS_XCD_REMAP 1
 #endif
 #ifndef CS_NT_LOADS
-#define CS_NT_LOADS 0
+#define CS_NT_LOADS 1
 #endif
 #ifndef CS_NT_STORES
 #define CS_NT_STORES 1
@@ -99,13 +100,18 @@ __host__ __device__ __forceinline__ int xcd_remap(int i, int n) {
 }
 
 // Load of data that is used once per kernel (kept out of the caches' reuse
-// set when CS_NT_LOADS is on).
+// set when CS_NT_LOADS is on).  FP64 data keeps ordinary loads: the FP64
+// operator kernels (one and several right-hand sides per launch) must agree
+// bit for bit, and the non-temporal form changed the code generated for one
+// of them in the last bit of some sums.
 template <typename T>
 __device__ __forceinline__ T ld_once(const T* p) {
 #if CS_NT_LOADS
     typedef unsigned int v4u __attribute__((ext_vector_type(4)));
     typedef unsigned int v2u __attribute__((ext_vector_type(2)));
-    if constexpr (sizeof(T) == 16) {
+    if constexpr (std::is_same<T, double2>::value) {
+        return *p;
+    } else if constexpr (sizeof(T) == 16) {
         return __builtin_bit_cast(T, __builtin_nontemporal_load((const v4u*)p));
     } else if constexpr (sizeof(T) == 8) {
         return __builtin_bit_cast(T, __builtin_nontemporal_load((const v2u*)p));
