@@ -247,7 +247,11 @@ typedef struct {
     int n_cy, n_mr;       /* SAP cycles and MR steps; n_cy = 0: no preconditioner */
     double tol;           /* stop when |b - D x| <= tol |b| (true FP64 residual)  */
     cs_prec inner_prec;   /* precision of the SAP preconditioner and of w = D z   */
-    cs_prec basis_prec;   /* storage of the Krylov basis w_k: CS_F64 or CS_F32    */
+    cs_prec basis_prec;   /* storage of the Krylov basis w_k: CS_F64, CS_F32, or
+                             CS_F16 / CS_BF16 (one scale per site; inner_prec
+                             CS_F32 or the same 16-bit type; not with the
+                             multigrid preconditioner).  The orthogonalisation
+                             arithmetic is FP64 whatever the storage          */
     double reliable_delta;/* restart early when |r_iter| < delta |r_true| (0: off) */
     int rhs_tile;         /* right-hand sides per workgroup in the batched SAP and
                              operator launches (0: autotuned, see cs_autotune)    */

@@ -535,10 +535,14 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
     if (!(p->tol >= 0.0)) return fail(CS_ERR_INVALID, "tol must be >= 0");
     if (p->block_solver < 0 || p->block_solver > 2) return fail(CS_ERR_INVALID, "block_solver must be 0, 1 or 2");
     if (!valid_prec(p->inner_prec)) return fail(CS_ERR_PRECISION, "unknown inner precision");
-    if (p->basis_prec != CS_F64 && p->basis_prec != CS_F32)
-        return fail(CS_ERR_PRECISION, "basis precision must be CS_F64 or CS_F32");
+    if (!valid_prec(p->basis_prec)) return fail(CS_ERR_PRECISION, "unknown basis precision");
     if (p->inner_prec == CS_F64 && p->basis_prec != CS_F64)
         return fail(CS_ERR_PRECISION, "an FP64 inner solve needs an FP64 basis");
+    if ((p->basis_prec == CS_F16 || p->basis_prec == CS_BF16) && p->inner_prec != CS_F32 &&
+        p->inner_prec != p->basis_prec)
+        return fail(CS_ERR_PRECISION, "a 16-bit basis needs inner_prec CS_F32 or the basis' own type");
+    if (mg && p->basis_prec != CS_F32 && p->basis_prec != CS_F64)
+        return fail(CS_ERR_PRECISION, "the multigrid preconditioner takes basis_prec CS_F32 or CS_F64");
     if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
     if (p->rhs_tile < 0) return fail(CS_ERR_INVALID, "rhs_tile must be >= 0");
     if ((p->n_cy > 0 || mg) && !sap_geometry_ok(g->g))

@@ -238,38 +238,66 @@ __device__ __forceinline__ cpx<double> to64(cpx<R> a) {
 // The vectors are read in groups whose loads are all issued before any is
 // used; inside the last group, indices past n repeat vector n - 1 and their
 // sums are never stored.
+// Dots handled by one multi-dot pass: MULTIDOT_CHUNK, or half of it for a
+// 16-bit basis (whose pass keeps all of its vectors' packed words in flight)
+template <int PB>
+constexpr int multidot_chunk() {
+    return PB == P_F16 || PB == P_BF16 ? MULTIDOT_CHUNK / 2 : MULTIDOT_CHUNK;
+}
+
 template <int PB>
 __global__ __launch_bounds__(TPB) void k_multidot(Geom g, const char* W, size_t ws, int nrhs, int j0, int n,
                                                   int k, const int* active, double2* partials) {
     if (skip(active)) return;
     using RS = typename SpinorIO<PB>::R;
     constexpr int G = load_group<PB>();
+    constexpr int CH = multidot_chunk<PB>();
     const int r = blockIdx.y;
     const char* base = W + (size_t)r * ws;
     const size_t vs = (size_t)nrhs * ws;  // from one basis vector to the next
-    cpx<double> acc[MULTIDOT_CHUNK];
+    cpx<double> acc[CH];
 #pragma unroll
-    for (int j = 0; j < MULTIDOT_CHUNK; ++j) acc[j] = {0.0, 0.0};
+    for (int j = 0; j < CH; ++j) acc[j] = {0.0, 0.0};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
         cpx<RS> v[12];
         SpinorIO<PB>::load(base + (size_t)k * vs, g.nblk, blk, threadIdx.x, v);
+        if constexpr (PB == P_F16 || PB == P_BF16) {
+            // 16-bit basis: the packed words of all CH vectors in flight at
+            // once (the bytes of four FP32 vectors), unpacked one at a time
+            typename SpinorIO16<PB>::Raw raw[CH];
 #pragma unroll
-        for (int jb = 0; jb < MULTIDOT_CHUNK; jb += G) {
-            if (jb < n) {
-                cpx<RS> t[G][12];
+            for (int q = 0; q < CH; ++q) {
+                const int j = q < n ? q : n - 1;
+                SpinorIO16<PB>::load_raw(base + (size_t)(j0 + j) * vs, g.nblk, blk, threadIdx.x, raw[q]);
+            }
 #pragma unroll
-                for (int q = 0; q < G; ++q) {
-                    const int j = jb + q < n ? jb + q : n - 1;
-                    SpinorIO<PB>::load(base + (size_t)(j0 + j) * vs, g.nblk, blk, threadIdx.x, t[q]);
+            for (int q = 0; q < CH; ++q) {
+                if (q < n) {
+                    cpx<float> t[12];
+                    SpinorIO16<PB>::unpack(raw[q], t);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) cmac_conj(acc[q], to64(t[c]), to64(v[c]));
                 }
+            }
+        } else {
 #pragma unroll
-                for (int q = 0; q < G; ++q)
+            for (int jb = 0; jb < CH; jb += G) {
+                if (jb < n) {
+                    cpx<RS> t[G][12];
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) cmac_conj(acc[jb + q], to64(t[q][c]), to64(v[c]));
+                    for (int q = 0; q < G; ++q) {
+                        const int j = jb + q < n ? jb + q : n - 1;
+                        SpinorIO<PB>::load(base + (size_t)(j0 + j) * vs, g.nblk, blk, threadIdx.x, t[q]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < G; ++q)
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) cmac_conj(acc[jb + q], to64(t[q][c]), to64(v[c]));
+                }
             }
         }
     }
-    wg_reduce_store<MULTIDOT_CHUNK>(acc, n, partials);
+    wg_reduce_store<CH>(acc, n, partials);
 }
 
 // W_k -= sum_{j<k} coef_j W_j (in increasing j, loads issued a group at a
@@ -700,8 +728,9 @@ hipError_t blas_norm_to_scalars(const BlasCtx& c, const void* v, int lo_prec, vo
 
 hipError_t blas_gcr_project(const BlasCtx& c, int pb, const void* W, size_t ws, int k, hipStream_t s) {
     ProfScope ps("blas", s);
-    for (int j0 = 0; j0 < k; j0 += MULTIDOT_CHUNK) {
-        const int n = k - j0 < MULTIDOT_CHUNK ? k - j0 : MULTIDOT_CHUNK;
+    const int chunk = pb == P_F16 || pb == P_BF16 ? MULTIDOT_CHUNK / 2 : MULTIDOT_CHUNK;
+    for (int j0 = 0; j0 < k; j0 += chunk) {
+        const int n = k - j0 < chunk ? k - j0 : chunk;
         const dim3 grid(nwg_for(c.g), c.nrhs);
         CS_DISPATCH_P(pb, hipLaunchKernelGGL((k_multidot<PP>), grid, dim3(TPB), 0, s, c.g, (const char*)W, ws, c.nrhs, j0, n, k, c.active, c.partials));
         hipError_t e = hipGetLastError();
@@ -745,6 +774,8 @@ hipError_t blas_gcr_residual_update(const BlasCtx& c, int pb, const void* W, siz
     switch (pb) {
     case P_F64: with_lo(std::integral_constant<int, P_F64>{}); break;
     case P_F32: with_lo(std::integral_constant<int, P_F32>{}); break;
+    case P_F16: with_lo(std::integral_constant<int, P_F16>{}); break;
+    case P_BF16: with_lo(std::integral_constant<int, P_BF16>{}); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;

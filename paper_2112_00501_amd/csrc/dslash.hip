@@ -329,6 +329,16 @@ hipError_t launch_dslash(const OpData& op, int in_prec, int out_prec, int link_p
         return launch3<P_F16, P_F32, P_F32>(op, dagger, out, in, sub, nrhs, s);
     if (in_prec == P_BF16 && out_prec == P_F32 && link_prec == P_F32)
         return launch3<P_BF16, P_F32, P_F32>(op, dagger, out, in, sub, nrhs, s);
+    // FP32 or 16-bit input with FP32 links, written straight into a 16-bit
+    // field (the 16-bit Krylov basis of the outer solver)
+    if (link_prec == P_F32 && out_prec == P_F16 && in_prec == P_F32)
+        return launch3<P_F32, P_F16, P_F32>(op, dagger, out, in, sub, nrhs, s);
+    if (link_prec == P_F32 && out_prec == P_BF16 && in_prec == P_F32)
+        return launch3<P_F32, P_BF16, P_F32>(op, dagger, out, in, sub, nrhs, s);
+    if (link_prec == P_F32 && out_prec == P_F16 && in_prec == P_F16)
+        return launch3<P_F16, P_F16, P_F32>(op, dagger, out, in, sub, nrhs, s);
+    if (link_prec == P_F32 && out_prec == P_BF16 && in_prec == P_BF16)
+        return launch3<P_BF16, P_BF16, P_F32>(op, dagger, out, in, sub, nrhs, s);
     return hipErrorInvalidValue;
 }
 

@@ -94,6 +94,29 @@ struct SpinorIO<P_F32> {
 template <int P>
 struct SpinorIO16 {
     using R = float;
+    // the packed words and the scale of one site, unpacked later by unpack()
+    // into the values load() gives (for kernels that keep many sites' loads
+    // in flight at once)
+    struct Raw {
+        uint4 w[3];
+        float s;
+    };
+    __device__ static void load_raw(const void* base, int nblk, int blk, int l, Raw& r) {
+        const uint4* p = (const uint4*)base + (size_t)blk * 3 * BLOCK_SITES + l;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r.w[k] = p[k * BLOCK_SITES];
+        r.s = scales(base, nblk)[(size_t)blk * BLOCK_SITES + l];
+    }
+    __device__ static void unpack(const Raw& r, cpx<R>* c) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float a, b;
+            unpack2<P>(r.w[k].x, a, b); c[4 * k + 0] = {a * r.s, b * r.s};
+            unpack2<P>(r.w[k].y, a, b); c[4 * k + 1] = {a * r.s, b * r.s};
+            unpack2<P>(r.w[k].z, a, b); c[4 * k + 2] = {a * r.s, b * r.s};
+            unpack2<P>(r.w[k].w, a, b); c[4 * k + 3] = {a * r.s, b * r.s};
+        }
+    }
     __device__ static const float* scales(const void* base, int nblk) {
         return (const float*)((const char*)base + (size_t)nblk * BLOCK_SITES * 48);
     }

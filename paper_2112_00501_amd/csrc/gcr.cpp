@@ -104,7 +104,7 @@ hipError_t GcrWork::ensure(const Geom& g, int m_, int inner_, int basis_, int nr
     if ((e = hipMalloc(&rlo, zstride * nrhs)) != hipSuccess) return e;
     if ((e = hipMalloc(&Z, zstride * m * nrhs)) != hipSuccess) return e;
     if ((e = hipMalloc(&W, wstride * m * nrhs)) != hipSuccess) return e;
-    if (natural_out(inner) != basis) {
+    if (natural_out(inner) != basis && basis != P_F16 && basis != P_BF16) {
         if ((e = hipMalloc(&wtmp, spinor_bytes_per_site(natural_out(inner)) * g.V * nrhs)) != hipSuccess) return e;
     }
     if ((e = hipMalloc((void**)&partials, sizeof(double2) * BLAS_MAX_WG * (MULTIDOT_CHUNK + 2) * nrhs)) != hipSuccess)
@@ -168,6 +168,10 @@ struct Solver {
 
     // w = D z for all right-hand sides
     hipError_t apply_w(void* wk, const void* zk) {
+        if (w.basis == P_F16 || w.basis == P_BF16) {
+            // a 16-bit basis: the operator writes w_k in it directly
+            return launch_dslash(op, p.inner, w.basis, P_F32, false, wk, zk, nullptr, n, s);
+        }
         const int nout = natural_out(p.inner);
         const bool tiled = n > 1 && p.dslash_cfg.rhs_tile > 1 && p.inner == nout;
         void* dst = nout == w.basis ? wk : w.wtmp;

@@ -52,6 +52,32 @@ def test_mixed_precision_gcr_reaches_fp64_accuracy(cfg1, inner):
     assert st == 0 and r <= 1e-10
 
 
+@pytest.mark.parametrize("basis,inner", [(cs.F16, cs.F32), (cs.BF16, cs.F32), (cs.F16, cs.F16)])
+def test_16bit_krylov_basis_reaches_fp64_accuracy(cfg1, basis, inner):
+    # the basis w_k stored in 16 bits with one scale per site (the
+    # orthogonalisation arithmetic stays FP64); the early restart at a
+    # 1e-3 drop keeps the recursive residual within the storage accuracy
+    c = cfg1
+    b = synth.source(c.dims, 2001)
+    _, s32, _ = solve(c, b, cs.F32)
+    for restart in (16, 9):  # a 16-bit multi-dot pass holds 8 dots: two passes from k = 9 on
+        st, s, x = solve(c, b, inner, basis=basis, reliable_delta=1e-3, restart=restart)
+        r = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, b, x) / np.linalg.norm(b)
+        print(f"basis={basis} inner={inner} restart={restart} iters={s['iters']} (FP32 basis {s32['iters']}) "
+              f"oracle-checked={r:.3e}")
+        assert st == 0 and r <= 1e-10
+        assert s["iters"] <= 1.25 * s32["iters"] + 2
+
+
+def test_16bit_basis_argument_errors(cfg1):
+    c = cfg1
+    bd = c.to_dev(synth.source(c.dims, 2001), cs.F64)
+    xd = c.lat.new_field(cs.F64).zero_()
+    for inner, basis in ((cs.F64, cs.F16), (cs.BF16, cs.F16)):
+        with pytest.raises(cs.CloverSapError):
+            c.op.gcr_solve(xd, bd, cs.SolverParams(inner_prec=inner, basis_prec=basis))
+
+
 def test_mixed_16x16x16x32():
     c = Case((16, 16, 16, 32), 0.3, 0.1355, 1.0, 1002, oracle_T=False)
     b = synth.source(c.dims, 2002)
