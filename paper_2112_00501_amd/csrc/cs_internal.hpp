@@ -67,6 +67,9 @@ constexpr int BLOCK_SITES = 256;  // one 4^4 block = one workgroup
 #ifndef CS_DSLASH_STAGED
 #define CS_DSLASH_STAGED 1
 #endif
+#ifndef CS_BLOCK_ORDER_TZ
+#define CS_BLOCK_ORDER_TZ 2
+#endif
 #ifndef CS_SAP_PRIO
 #define CS_SAP_PRIO 1
 #endif
@@ -219,10 +222,51 @@ __host__ __device__ __forceinline__ int colour_block(const Geom& g, int colour, 
     int r = c / half;
     const int by = r % g.NB[1];
     r /= g.NB[1];
+#if CS_BLOCK_ORDER_TZ
+    const int bt = r % g.NB[3];
+    const int bz = r / g.NB[3];
+#else
     const int bz = r % g.NB[2];
     const int bt = r / g.NB[2];
+#endif
     const int bx = 2 * hx + ((colour + by + bz + bt) & 1);
     return bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+}
+
+// Block visited by work item w of an operator launch (w after the XCD
+// remapping).  CS_BLOCK_ORDER_TZ 1: x fastest, then y, then t, then z, so
+// that every XCD holds whole t columns of blocks (a block's t neighbours are
+// visited next to it; only z faces cross XCDs); 2: the same with the xy
+// plane walked in 4 x 4 tiles of blocks, which brings the y neighbours
+// closer in visiting order as well (the L2 of an XCD keeps the spinor lines
+// of roughly the last twenty blocks).  0: the block index itself.
+__host__ __device__ __forceinline__ int block_of_item(const Geom& g, int w) {
+#if CS_BLOCK_ORDER_TZ
+    int bx, by, r;
+#if CS_BLOCK_ORDER_TZ == 2
+    if ((g.NB[0] & 3) == 0 && (g.NB[1] & 3) == 0) {
+        // 4 x 4 tiles of blocks in the xy plane, x fastest inside a tile
+        const int nxy = g.NB[0] * g.NB[1];
+        const int q = w % nxy, tile = q >> 4, in = q & 15;
+        const int tx = g.NB[0] >> 2;
+        bx = 4 * (tile % tx) + (in & 3);
+        by = 4 * (tile / tx) + (in >> 2);
+        r = w / nxy;
+    } else
+#endif
+    {
+        bx = w % g.NB[0];
+        r = w / g.NB[0];
+        by = r % g.NB[1];
+        r /= g.NB[1];
+    }
+    const int bt = r % g.NB[3];
+    const int bz = r / g.NB[3];
+    return bx + g.NB[0] * (by + g.NB[1] * (bz + g.NB[2] * bt));
+#else
+    (void)g;
+    return w;
+#endif
 }
 
 // Internal (blk, l) of the site with global coordinates c (already wrapped).

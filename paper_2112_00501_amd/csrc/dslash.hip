@@ -20,7 +20,7 @@ __global__ CS_DSLASH_BOUNDS void k_dslash(Geom g, const void* __restrict__ links
                                                         const void* __restrict__ sub,
                                                         size_t in_stride, size_t out_stride) {
     using R = typename Arith<PIN>::R;
-    const int blk = xcd_remap(blockIdx.x, g.nblk), l = threadIdx.x, r = blockIdx.y;
+    const int blk = block_of_item(g, xcd_remap(blockIdx.x, g.nblk)), l = threadIdx.x, r = blockIdx.y;
     const char* src = (const char*)in + r * in_stride;
     const BlockPos p = block_pos(g, blk);
 
@@ -114,7 +114,7 @@ __global__ CS_DSLASH_BOUNDS void k_dslash_staged(Geom g, const void* __restrict_
                                                  size_t out_stride) {
     __shared__ lds_cpx<float> s_psi[12][BLOCK_SITES];
     __shared__ StagedLinkSmem<LINKS_LDS> s_lk;
-    const int blk = xcd_remap(blockIdx.x, g.nblk), l = threadIdx.x, r = blockIdx.y;
+    const int blk = block_of_item(g, xcd_remap(blockIdx.x, g.nblk)), l = threadIdx.x, r = blockIdx.y;
     const char* src = (const char*)in + r * in_stride;
     const BlockPos p = block_pos(g, blk);
 
@@ -210,7 +210,7 @@ __global__ CS_DSLASH_BOUNDS void k_dslash_tiled(Geom g, const void* __restrict__
     const int l = threadIdx.x;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int w = xcd_remap(item, nitems);
-        const int blk = w % g.nblk;
+        const int blk = block_of_item(g, w % g.nblk);
         const int r0 = (w / g.nblk) * tile;
         const int r1 = r0 + tile < nrhs ? r0 + tile : nrhs;
         const BlockPos p = block_pos(g, blk);
