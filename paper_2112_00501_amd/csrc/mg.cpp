@@ -114,18 +114,64 @@ hipError_t MgData::alloc(const Geom& g_, const MgParams& p_) {
     return hipSuccess;
 }
 
+namespace {
+
+// e_c = coarse BiCGStab on D_c from a given coarse right-hand side rc, left
+// in cv.x; MG_CHUNK iterations between host reads of the stop flag
+hipError_t coarse_solve_from(const MgData& m, const float2* rc, hipStream_t s) {
+    const int cap = m.p.n_coarse;
+    int done = cap < MG_CHUNK ? cap : MG_CHUNK;
+    MG_CHK(mg_coarse_begin(m.g, m.nc(), rc, m.cv, m.sc, m.pa, m.p.tol_coarse, s));
+    MG_CHK(mg_coarse_iters(m.g, m.coarse(), m.nc(), m.cv, m.sc, m.pa, 0, done, s));
+    while (done < cap) {
+        MG_CHK(hipMemcpyAsync(m.host_flag, &m.sc->stopped[done & 1], sizeof(int), hipMemcpyDeviceToHost, s));
+        MG_CHK(hipStreamSynchronize(s));
+        if (*m.host_flag) break;
+        const int to = done + MG_CHUNK < cap ? done + MG_CHUNK : cap;
+        MG_CHK(mg_coarse_iters(m.g, m.coarse(), m.nc(), m.cv, m.sc, m.pa, done, to, s));
+        done = to;
+    }
+    return hipSuccess;
+}
+
+// One adaptive pass, v_i <- M_MG v_i for all null vectors at once: one
+// restriction of all of them, the coarse solves one after another, one
+// prolongation of all, and the post-smoothing as one batched SAP launch per
+// half-sweep (the results are those of M_MG applied to each v_i in turn).
+// W: nv FP32 fields, rcs and ecs: nv coarse vectors each.
+hipError_t adaptive_pass(const OpData& op, MgData& m, void* W, float2* rcs, float2* ecs, hipStream_t s) {
+    const size_t n = (size_t)m.g.nblk * m.nc();
+    MG_CHK(mg_restrict_many(m.g, m.transfer(), m.p.nv, m.V, m.p.nv, rcs, s));
+    for (int i = 0; i < m.p.nv; ++i) {
+        MG_CHK(coarse_solve_from(m, rcs + (size_t)i * n, s));
+        MG_CHK(hipMemcpyAsync(ecs + (size_t)i * n, m.cv.x, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    }
+    MG_CHK(mg_prolong_many(m.g, m.transfer(), m.p.nv, ecs, m.p.nv, W, s));
+    MG_CHK(sap_cycles(op, m.sap_cfg, m.p.n_cy_post, m.p.n_mr, false, W, m.V, m.p.nv, s));
+    return hipMemcpyAsync(m.V, W, m.field_bytes() * m.p.nv, hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace
+
 hipError_t mg_setup(const OpData& op, MgData& m, const void* etas, hipStream_t s) {
     MG_CHK(sap_cycles(op, m.sap_cfg, m.p.n_cy_setup, m.p.n_mr, true, m.V, etas, m.p.nv, s));
     MG_CHK(rebuild(op, m, s));
-    for (int pass = 0; pass < m.p.n_adapt; ++pass) {
-        for (int i = 0; i < m.p.nv; ++i) {
-            char* vi = (char*)m.V + (size_t)i * m.field_bytes();
-            MG_CHK(mg_apply(op, m, m.tmp, vi, s));
-            MG_CHK(hipMemcpyAsync(vi, m.tmp, m.field_bytes(), hipMemcpyDeviceToDevice, s));
-        }
-        MG_CHK(rebuild(op, m, s));
+    if (m.p.n_adapt <= 0) return hipSuccess;
+    // workspace of the batched passes, released once the passes are done
+    void* W = nullptr;
+    float2* cvs = nullptr;
+    const size_t n = (size_t)m.g.nblk * m.nc();
+    hipError_t e = hipMalloc(&W, m.field_bytes() * m.p.nv);
+    if (e == hipSuccess) e = hipMalloc((void**)&cvs, 2 * n * m.p.nv * sizeof(float2));
+    for (int pass = 0; e == hipSuccess && pass < m.p.n_adapt; ++pass) {
+        e = adaptive_pass(op, m, W, cvs, cvs + n * m.p.nv, s);
+        if (e == hipSuccess) e = rebuild(op, m, s);
     }
-    return hipSuccess;
+    // the frees wait for the queued work that uses the workspace
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (W) hipFree(W);
+    if (cvs) hipFree(cvs);
+    return e;
 }
 
 namespace {

@@ -291,6 +291,49 @@ __global__ __launch_bounds__(TPB) void k_mg_restrict(Geom g, const char* P, size
     }
 }
 
+// The restriction of nr FP32 fields r_j (stride rs) into nr coarse vectors
+// (stride rcs), R fields per workgroup: each P row read serves all R, and
+// every r_j gets the sums of k_mg_restrict (same terms, same order).
+template <int PP, int R>
+__global__ __launch_bounds__(TPB) void k_mg_restrict_many(Geom g, const char* P, size_t fs, int nv,
+                                                          const char* rbase, size_t rs, int nr, float2* rcbase,
+                                                          size_t rcs) {
+    const int blk = blockIdx.x, l = threadIdx.x, j0 = blockIdx.y * R;
+    __shared__ float red[4][8 * R];
+    __shared__ float tot[8 * R];
+    cpx<float> rv[R][12];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+        SpinorIO<P_F32>::load(rbase + (size_t)(j0 + u < nr ? j0 + u : nr - 1) * rs, g.nblk, blk, l, rv[u]);
+    for (int i0 = 0; i0 < nv; i0 += 2) {
+        float dd[8 * R];
+#pragma unroll
+        for (int k = 0; k < 8 * R; ++k) dd[k] = 0.f;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (i0 + u < nv) {
+                cpx<float> q[12];
+                SpinorIO<PP>::load(P + (size_t)(i0 + u) * fs, g.nblk, blk, l, q);
+#pragma unroll
+                for (int j = 0; j < R; ++j)
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        const int o = 8 * j + 4 * u + (k < 6 ? 0 : 2);
+                        dd[o] += q[k].re * rv[j][k].re + q[k].im * rv[j][k].im;
+                        dd[o + 1] += q[k].re * rv[j][k].im - q[k].im * rv[j][k].re;
+                    }
+            }
+        }
+        block_sum<8 * R>(dd, red, tot);
+        if (l < 4 * R) {
+            const int j = l >> 2, u = (l >> 1) & 1, chi = l & 1, i = i0 + u;
+            if (i < nv && j0 + j < nr)
+                rcbase[(size_t)(j0 + j) * rcs + (size_t)blk * 2 * nv + chi * nv + i] =
+                    make_float2(tot[8 * j + 4 * u + 2 * chi], tot[8 * j + 4 * u + 2 * chi + 1]);
+        }
+    }
+}
+
 // z = P ec (an FP32 field)
 template <int PP>
 __global__ __launch_bounds__(TPB) void k_mg_prolong(Geom g, const char* P, size_t fs, int nv, const float2* ec,
@@ -309,6 +352,36 @@ __global__ __launch_bounds__(TPB) void k_mg_prolong(Geom g, const char* P, size_
         for (int k = 0; k < 12; ++k) cmac(o[k], k < 6 ? c0 : c1, q[k]);
     }
     SpinorIO<P_F32>::store(z, g.nblk, blk, l, o);
+}
+
+// The prolongation of nr coarse vectors (stride ecs) into nr FP32 fields
+// (stride zs), R per workgroup: each P row read serves all R, every z_j
+// gets the sums of k_mg_prolong (same terms, same order).
+template <int PP, int R>
+__global__ __launch_bounds__(TPB) void k_mg_prolong_many(Geom g, const char* P, size_t fs, int nv,
+                                                         const float2* ecbase, size_t ecs, int nr, char* zbase,
+                                                         size_t zs) {
+    const int blk = blockIdx.x, l = threadIdx.x, j0 = blockIdx.y * R;
+    cpx<float> o[R][12];
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o[j][k] = {0.f, 0.f};
+    for (int i = 0; i < nv; ++i) {
+        cpx<float> q[12];
+        SpinorIO<PP>::load(P + (size_t)i * fs, g.nblk, blk, l, q);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const float2* e = ecbase + (size_t)(j0 + j < nr ? j0 + j : nr - 1) * ecs + (size_t)blk * 2 * nv;
+            const float2 e0 = e[i], e1 = e[nv + i];
+            const cpx<float> c0 = {e0.x, e0.y}, c1 = {e1.x, e1.y};
+#pragma unroll
+            for (int k = 0; k < 12; ++k) cmac(o[j][k], k < 6 ? c0 : c1, q[k]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        if (j0 + j < nr) SpinorIO<P_F32>::store(zbase + (size_t)(j0 + j) * zs, g.nblk, blk, l, o[j]);
 }
 
 // ---------------------------------------------------------- coarse solver
@@ -869,6 +942,37 @@ hipError_t mg_prolong(const Geom& g, Transfer T, int nv, const float2* ec, void*
         hipLaunchKernelGGL(k_mg_prolong<P_F16>, dim3(g.nblk), dim3(TPB), 0, s, g, (const char*)T.P, fs, nv, ec, z);
     else
         hipLaunchKernelGGL(k_mg_prolong<P_F32>, dim3(g.nblk), dim3(TPB), 0, s, g, (const char*)T.P, fs, nv, ec, z);
+    return hipGetLastError();
+}
+
+hipError_t mg_restrict_many(const Geom& g, Transfer T, int nv, const void* r, int nr, float2* rc,
+                            hipStream_t s) {
+    ProfScope ps("mg", s);
+    constexpr int R = 4;
+    const size_t fs = spinor_bytes_per_site(T.prec) * g.V, rs = spinor_bytes_per_site(P_F32) * g.V;
+    const size_t rcs = (size_t)g.nblk * 2 * nv;
+    const dim3 grid(g.nblk, (nr + R - 1) / R);
+    if (T.prec == P_F16)
+        hipLaunchKernelGGL((k_mg_restrict_many<P_F16, R>), grid, dim3(TPB), 0, s, g, (const char*)T.P, fs, nv,
+                           (const char*)r, rs, nr, rc, rcs);
+    else
+        hipLaunchKernelGGL((k_mg_restrict_many<P_F32, R>), grid, dim3(TPB), 0, s, g, (const char*)T.P, fs, nv,
+                           (const char*)r, rs, nr, rc, rcs);
+    return hipGetLastError();
+}
+
+hipError_t mg_prolong_many(const Geom& g, Transfer T, int nv, const float2* ec, int nr, void* z, hipStream_t s) {
+    ProfScope ps("mg", s);
+    constexpr int R = 4;
+    const size_t fs = spinor_bytes_per_site(T.prec) * g.V, zs = spinor_bytes_per_site(P_F32) * g.V;
+    const size_t ecs = (size_t)g.nblk * 2 * nv;
+    const dim3 grid(g.nblk, (nr + R - 1) / R);
+    if (T.prec == P_F16)
+        hipLaunchKernelGGL((k_mg_prolong_many<P_F16, R>), grid, dim3(TPB), 0, s, g, (const char*)T.P, fs, nv, ec,
+                           ecs, nr, (char*)z, zs);
+    else
+        hipLaunchKernelGGL((k_mg_prolong_many<P_F32, R>), grid, dim3(TPB), 0, s, g, (const char*)T.P, fs, nv, ec,
+                           ecs, nr, (char*)z, zs);
     return hipGetLastError();
 }
 

@@ -99,6 +99,12 @@ hipError_t mg_orthonormalize(const Geom& g, void* P, int nv, hipStream_t s);
 hipError_t mg_assemble(const OpData& op, const void* P, int nv, float2* Dc, hipStream_t s);
 hipError_t mg_restrict(const Geom& g, Transfer T, int nv, const void* r, float2* rc, hipStream_t s);
 hipError_t mg_prolong(const Geom& g, Transfer T, int nv, const float2* ec, void* z, hipStream_t s);
+// the same for nr consecutive FP32 fields and nr consecutive coarse vectors
+// (the null vectors of an adaptive setup pass), every field with the sums of
+// the one-field launches
+hipError_t mg_restrict_many(const Geom& g, Transfer T, int nv, const void* r, int nr, float2* rc,
+                            hipStream_t s);
+hipError_t mg_prolong_many(const Geom& g, Transfer T, int nv, const float2* ec, int nr, void* z, hipStream_t s);
 // Dc16 = FP16 copy of the n complex entries of Dc
 hipError_t mg_coarse_half(const float2* Dc, void* Dc16, size_t n, hipStream_t s);
 // y = D_c x
