@@ -316,7 +316,12 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
         GCR_CHK(launch_dslash(op, P_F64, P_F64, P_F64, false, w.r, x, rhs, n, s));
         BlasCtx bh = S.bc;
         bh.tail = w.host_tail;  // the norm lands in pinned slot 0
-        GCR_CHK(blas_norm_to_scalars(bh, w.r, S.lo_prec(), w.rlo, s));
+        // The smoother's copy is r / |r| with this norm, written once the
+        // norm is known: a scale left in the scalars by the last iteration
+        // would differ for a column that ran one queued-ahead iteration past
+        // its stop, and the copy's rounding with it.
+        GCR_CHK(blas_norm_to_scalars(bh, w.r, -1, nullptr, s));
+        if (S.lo_prec() >= 0) GCR_CHK(blas_convert(S.bc, S.lo_prec(), w.rlo, P_F64, w.r, true, s));
         GCR_CHK(hipStreamSynchronize(s));
         for (int r = 0; r < n; ++r)
             if (!done[r]) rel[r] = std::sqrt(w.host_tail[r].rnorm2) / bnorm[r];
@@ -348,8 +353,9 @@ hipError_t gcr_solve(const OpData& op, const GcrParams& p, GcrWork& w, void* x, 
         // the last step's ratio once more), k + 1 is not queued ahead.  A
         // column that stops at k while k + 1 is already queued runs k + 1
         // once more; that iteration writes only its own slots (W, Z, column
-        // k + 1 of R, c_{k+1}) and the residual, which the back substitution
-        // (first k_used directions) and the true residual below do not read.
+        // k + 1 of R, c_{k+1}), the residual and its norm, which the back
+        // substitution (first k_used directions) and the true residual below
+        // (residual, norm and smoother copy recomputed from x) do not read.
         std::vector<double> rr_prev(n, 0.0), ratio(n, 1.0);
         for (int r = 0; r < n; ++r) rr_prev[r] = r_true[r];
         auto likely_last = [&](int k) {

@@ -57,13 +57,15 @@ def test_autotune_returns_valid_shapes(case):
     assert sap.persistent_wgs >= 0 and d.persistent_wgs >= 0
 
 
-@pytest.mark.parametrize("inner", [cs.F32, cs.F64])
-def test_batched_gcr_columns_equal_single_solves(case, inner):
+# rd = 1e-3 restarts every few iterations, so columns often stop while the
+# next iteration is already queued for the batch but not for the lone solve
+@pytest.mark.parametrize("inner,basis,rd", [(cs.F32, cs.F32, 1e-5), (cs.F64, cs.F64, 1e-5),
+                                            (cs.F32, cs.F32, 1e-3), (cs.F32, cs.F16, 1e-3)])
+def test_batched_gcr_columns_equal_single_solves(case, inner, basis, rd):
     c = case
     bs = synth.source(c.dims, 9, nrhs=NRHS)
     bs[2] = 0.0  # a zero right-hand side is solved by x = 0 without iterations
-    basis = cs.F64 if inner == cs.F64 else cs.F32
-    p_batch = cs.SolverParams(inner_prec=inner, basis_prec=basis, rhs_tile=4, use_graph=False)
+    p_batch = cs.SolverParams(inner_prec=inner, basis_prec=basis, reliable_delta=rd, rhs_tile=4, use_graph=False)
     bd = c.to_dev(bs, cs.F64)
     xd = c.lat.new_field(cs.F64, NRHS).zero_()
     st, stats = c.op.gcr_solve(xd, bd, p_batch, nrhs=NRHS)
@@ -72,7 +74,8 @@ def test_batched_gcr_columns_equal_single_solves(case, inner):
     for r in (0, 3, 5):
         x1 = c.lat.new_field(cs.F64).zero_()
         st1, s1 = c.op.gcr_solve(x1, c.to_dev(bs[r], cs.F64),
-                                 cs.SolverParams(inner_prec=inner, basis_prec=basis, use_graph=False))
+                                 cs.SolverParams(inner_prec=inner, basis_prec=basis, reliable_delta=rd,
+                                                 use_graph=False))
         assert s1[0]["iters"] == stats[r]["iters"]
         assert np.array_equal(c.to_host(x1, cs.F64), xb[r])
         rel = oracle.residual_norm(c.dims, c.U, c.kappa, c.csw, bs[r], xb[r]) / np.linalg.norm(bs[r])
@@ -130,6 +133,13 @@ def test_graph_replay_equals_eager(case):
     c.op.gcr_solve(x1, b1, cs.SolverParams(use_graph=False))
     c.op.gcr_solve(x2, b1, cs.SolverParams(use_graph=True))
     c.op.gcr_solve(x2.zero_(), b1, cs.SolverParams(use_graph=True))
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2)
+    # and with a 16-bit basis (the operator writes w_k into it directly)
+    p16 = dict(basis_prec=cs.F16, reliable_delta=1e-3)
+    c.op.gcr_solve(x1.zero_(), b1, cs.SolverParams(use_graph=False, **p16))
+    c.op.gcr_solve(x2.zero_(), b1, cs.SolverParams(use_graph=True, **p16))
+    c.op.gcr_solve(x2.zero_(), b1, cs.SolverParams(use_graph=True, **p16))
     torch.cuda.synchronize()
     assert torch.equal(x1, x2)
 
