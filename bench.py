@@ -1027,6 +1027,14 @@ def main():
         small = (synth.gauge_field(cs16["dims"], cs16["eps"], cs16["gauge_seed"]),
                  synth.source(cs16["dims"], cs16["src_seed"]), cs16)
         out["cpu_baseline"] = cpu_baseline(U, b, c, out["fp64_iterations"], small)
+    # the contract's fields first, then the mixed-vs-FP64 comparison, the
+    # roofline and CPU baseline objects, and after them the headline details
+    # and the side measurements
+    front = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+             "scaling", "vs_baseline", "dtype", "data", "config", "time_to_1e10_ms", "iterations",
+             "fp64_time_to_1e10_ms", "fp64_iterations", "fp64_status", "speedup_mixed_vs_fp64",
+             "oracle_checked_relres", "roofline", "cpu_baseline"]
+    out = {**{k: out[k] for k in front if k in out}, **{k: v for k, v in out.items() if k not in front}}
     print(json.dumps(out), flush=True)
 
 
