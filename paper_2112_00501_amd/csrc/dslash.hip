@@ -198,6 +198,54 @@ struct MixedLinks {
     }
 };
 
+// The rolled hopping sum for two right-hand sides at once: each hop loads
+// its link once and the two neighbour spinors together, so two loads are in
+// flight where the one-right-hand-side loop waits on one.  Each sum gets the
+// same terms in the same order as hopping_sum_rolled.
+template <typename R, typename LS, typename LL>
+__device__ __forceinline__ void hopping_sum_rolled2(const Geom& g, const BlockPos& p, int l, const LS& ls0,
+                                                    const LS& ls1, const LL& lk, cpx<R>* acc0, cpx<R>* acc1) {
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+        const int mu = h >> 1, dir = (h & 1) ? -1 : +1;
+        const int bc = mu == 0 ? p.bc[0] : mu == 1 ? p.bc[1] : mu == 2 ? p.bc[2] : p.bc[3];
+        const int nbm = mu == 0 ? g.NB[0] : mu == 1 ? g.NB[1] : mu == 2 ? g.NB[2] : g.NB[3];
+        const int st = mu == 0 ? p.stride[0] : mu == 1 ? p.stride[1] : mu == 2 ? p.stride[2] : p.stride[3];
+        const int sh = 2 * mu, lc = (l >> sh) & 3;
+        int nl, nb;
+        bool in;
+        if (dir > 0) {
+            in = lc < 3;
+            nl = in ? l + (1 << sh) : l - (3 << sh);
+            nb = in ? p.blk : (bc == nbm - 1 ? p.blk - (nbm - 1) * st : p.blk + st);
+        } else {
+            in = lc > 0;
+            nl = in ? l - (1 << sh) : l + (3 << sh);
+            nb = in ? p.blk : (bc == 0 ? p.blk + (nbm - 1) * st : p.blk - st);
+        }
+        cpx<R> psi0[12], psi1[12], u[9];
+        ls0.template load_nb<R>(nb, nl, in, psi0);
+        ls1.template load_nb<R>(nb, nl, in, psi1);
+        if (mu == 3) {
+            const bool wraps = !in && (dir > 0 ? bc == nbm - 1 : bc == 0);
+            time_boundary_phase(g, wraps, &psi0[0].re, 24);
+            time_boundary_phase(g, wraps, &psi1[0].re, 24);
+        }
+        if (dir > 0) lk.template load<R>(p.blk, l, mu, true, u);
+        else lk.template load<R>(nb, nl, mu, in, u);
+        switch (h) {
+        case 0: hop_term<0, -1>(u, psi0, acc0); hop_term<0, -1>(u, psi1, acc1); break;
+        case 1: hop_term<0, +1>(u, psi0, acc0); hop_term<0, +1>(u, psi1, acc1); break;
+        case 2: hop_term<1, -1>(u, psi0, acc0); hop_term<1, -1>(u, psi1, acc1); break;
+        case 3: hop_term<1, +1>(u, psi0, acc0); hop_term<1, +1>(u, psi1, acc1); break;
+        case 4: hop_term<2, -1>(u, psi0, acc0); hop_term<2, -1>(u, psi1, acc1); break;
+        case 5: hop_term<2, +1>(u, psi0, acc0); hop_term<2, +1>(u, psi1, acc1); break;
+        case 6: hop_term<3, -1>(u, psi0, acc0); hop_term<3, -1>(u, psi1, acc1); break;
+        default: hop_term<3, +1>(u, psi0, acc0); hop_term<3, +1>(u, psi1, acc1); break;
+        }
+    }
+}
+
 template <int PIN, int POUT, int PLINK, bool DAG>
 __global__ CS_DSLASH_BOUNDS void k_dslash_tiled(Geom g, const void* __restrict__ links,
                                                 const void* __restrict__ clover, double kappa,
@@ -226,13 +274,8 @@ __global__ CS_DSLASH_BOUNDS void k_dslash_tiled(Geom g, const void* __restrict__
         __syncthreads();
         MixedLinks<RS, PLINK> lk{s_lk, links};
         const R k = (R)kappa;
-        for (int r = r0; r < r1; ++r) {
-            const char* src = (const char*)in + (size_t)r * in_stride;
-            cpx<R> acc[12];
-#pragma unroll
-            for (int i = 0; i < 12; ++i) acc[i] = {(R)0, (R)0};
-            GlobalSpinor<PIN, DAG> ld{src, g.nblk};
-            hopping_sum_rolled<R>(g, p, l, ld, lk, acc);
+        // the clover term and the output of one right-hand side
+        auto finish = [&](int r, const GlobalSpinor<PIN, DAG>& ld, const cpx<R>* acc) {
             cpx<R> self[12], res[12];
             ld.load(blk, l, self);
             clover_apply(cl, self, res);
@@ -244,6 +287,29 @@ __global__ CS_DSLASH_BOUNDS void k_dslash_tiled(Geom g, const void* __restrict__
 #pragma unroll
             for (int i = 0; i < 12; ++i) o[i] = {(RO)res[i].re, (RO)res[i].im};
             SpinorIO<POUT>::store((char*)out + (size_t)r * out_stride, g.nblk, blk, l, o);
+        };
+        int r = r0;
+        if constexpr (PIN != P_F64) {
+            // right-hand sides two at a time (the FP64 form keeps one: its
+            // registers are full)
+            for (; r + 1 < r1; r += 2) {
+                GlobalSpinor<PIN, DAG> ld0{(const char*)in + (size_t)r * in_stride, g.nblk};
+                GlobalSpinor<PIN, DAG> ld1{(const char*)in + (size_t)(r + 1) * in_stride, g.nblk};
+                cpx<R> acc0[12], acc1[12];
+#pragma unroll
+                for (int i = 0; i < 12; ++i) acc0[i] = acc1[i] = {(R)0, (R)0};
+                hopping_sum_rolled2<R>(g, p, l, ld0, ld1, lk, acc0, acc1);
+                finish(r, ld0, acc0);
+                finish(r + 1, ld1, acc1);
+            }
+        }
+        for (; r < r1; ++r) {
+            GlobalSpinor<PIN, DAG> ld{(const char*)in + (size_t)r * in_stride, g.nblk};
+            cpx<R> acc[12];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) acc[i] = {(R)0, (R)0};
+            hopping_sum_rolled<R>(g, p, l, ld, lk, acc);
+            finish(r, ld, acc);
         }
     }
 }
