@@ -438,6 +438,11 @@ struct LaunchCfg {
 hipError_t launch_dslash_tiled(const OpData& op, int prec, bool dagger, void* out, const void* in, int nrhs,
                                const LaunchCfg& cfg, hipStream_t s);
 
+// The same batched launch from FP32 input (FP32 links) into FP16 or BF16
+// output with a per-site scale (the 16-bit Krylov basis of the outer solver).
+hipError_t launch_dslash_tiled_to16(const OpData& op, int out_prec, void* out, const void* in, int nrhs,
+                                    const LaunchCfg& cfg, hipStream_t s);
+
 // sap.hip: one half-sweep over the blocks of one colour.  mode 0: general;
 // 1: x is zero everywhere (r = b); 2: x is zero on the blocks of this colour.
 // Block solver: BLOCK_MR, n_block MR steps on D_BB; BLOCK_JACOBI, n_block

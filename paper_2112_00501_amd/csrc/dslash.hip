@@ -375,6 +375,16 @@ hipError_t launch_dslash_tiled(const OpData& op, int prec, bool dagger, void* ou
     }
 }
 
+hipError_t launch_dslash_tiled_to16(const OpData& op, int out_prec, void* out, const void* in, int nrhs,
+                                    const LaunchCfg& cfg, hipStream_t s) {
+    ProfScope ps("dslash", s);
+    switch (out_prec) {
+    case P_F16: return launch_tiled<P_F32, P_F16, P_F32>(op, false, out, in, nrhs, cfg, s);
+    case P_BF16: return launch_tiled<P_F32, P_BF16, P_F32>(op, false, out, in, nrhs, cfg, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_dslash(const OpData& op, int in_prec, int out_prec, int link_prec, bool dagger,
                          void* out, const void* in, const void* sub, int nrhs, hipStream_t s) {
     ProfScope ps("dslash", s);

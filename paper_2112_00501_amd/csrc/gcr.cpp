@@ -170,6 +170,8 @@ struct Solver {
     hipError_t apply_w(void* wk, const void* zk) {
         if (w.basis == P_F16 || w.basis == P_BF16) {
             // a 16-bit basis: the operator writes w_k in it directly
+            if (n > 1 && p.dslash_cfg.rhs_tile > 1 && p.inner == P_F32)
+                return launch_dslash_tiled_to16(op, w.basis, wk, zk, n, p.dslash_cfg, s);
             return launch_dslash(op, p.inner, w.basis, P_F32, false, wk, zk, nullptr, n, s);
         }
         const int nout = natural_out(p.inner);
