@@ -60,7 +60,8 @@ def test_autotune_returns_valid_shapes(case):
 # rd = 1e-3 restarts every few iterations, so columns often stop while the
 # next iteration is already queued for the batch but not for the lone solve
 @pytest.mark.parametrize("inner,basis,rd", [(cs.F32, cs.F32, 1e-5), (cs.F64, cs.F64, 1e-5),
-                                            (cs.F32, cs.F32, 1e-3), (cs.F32, cs.F16, 1e-3)])
+                                            (cs.F32, cs.F32, 1e-3), (cs.F32, cs.F16, 1e-3),
+                                            (cs.F32, cs.BF16, 1e-3)])
 def test_batched_gcr_columns_equal_single_solves(case, inner, basis, rd):
     c = case
     bs = synth.source(c.dims, 9, nrhs=NRHS)
