@@ -943,6 +943,20 @@ LEGS = {
 }
 
 
+# The contract's fields first, then the mixed-vs-FP64 comparison, the
+# roofline and CPU baseline objects, and after them the headline details and
+# the side measurements (readers that keep only the start of the line still
+# see all of these).
+FRONT_KEYS = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "time_to_1e10_ms", "iterations",
+              "fp64_time_to_1e10_ms", "fp64_iterations", "fp64_status", "speedup_mixed_vs_fp64",
+              "oracle_checked_relres", "roofline", "cpu_baseline"]
+
+
+def ordered_line(out: dict) -> dict:
+    return {**{k: out[k] for k in FRONT_KEYS if k in out}, **{k: v for k, v in out.items() if k not in FRONT_KEYS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1027,15 +1041,7 @@ def main():
         small = (synth.gauge_field(cs16["dims"], cs16["eps"], cs16["gauge_seed"]),
                  synth.source(cs16["dims"], cs16["src_seed"]), cs16)
         out["cpu_baseline"] = cpu_baseline(U, b, c, out["fp64_iterations"], small)
-    # the contract's fields first, then the mixed-vs-FP64 comparison, the
-    # roofline and CPU baseline objects, and after them the headline details
-    # and the side measurements
-    front = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
-             "scaling", "vs_baseline", "dtype", "data", "config", "time_to_1e10_ms", "iterations",
-             "fp64_time_to_1e10_ms", "fp64_iterations", "fp64_status", "speedup_mixed_vs_fp64",
-             "oracle_checked_relres", "roofline", "cpu_baseline"]
-    out = {**{k: out[k] for k in front if k in out}, **{k: v for k, v in out.items() if k not in front}}
-    print(json.dumps(out), flush=True)
+    print(json.dumps(ordered_line(out)), flush=True)
 
 
 if __name__ == "__main__":

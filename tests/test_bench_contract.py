@@ -1,6 +1,6 @@
 """bench.py's command-line contract, checked without a GPU: more than one
-GPU is refused with a message, and the sources that key the stored traffic
-record exist."""
+GPU is refused with a message, the sources that key the stored traffic
+record exist, and the JSON line leads with the contract's fields."""
 import os
 import subprocess
 import sys
@@ -22,3 +22,15 @@ def test_traffic_record_sources_exist():
     for name in bench.SAP_KERNEL_SOURCES:
         assert os.path.exists(os.path.join(csrc, name)), name
     assert len(bench.source_hash(bench.SAP_KERNEL_SOURCES)) == 16
+
+
+def test_line_leads_with_the_contract_fields():
+    sys.path.insert(0, ROOT)
+    import bench
+    out = {"next_rows": {}, "roofline": {"frac": 0.4}, "value": 6.0, "metric": "m", "cpu_baseline": {"value": 0.01},
+           "dslash": {}, "unit": "solves/s", "config": {"workload": "w"}, "fp64_time_to_1e10_ms": 437.0}
+    keys = list(bench.ordered_line(out))
+    assert keys[:3] == ["metric", "value", "unit"]
+    assert keys.index("config") < keys.index("fp64_time_to_1e10_ms") < keys.index("roofline")
+    assert keys.index("roofline") + 1 == keys.index("cpu_baseline")
+    assert keys[-2:] == ["next_rows", "dslash"] and len(keys) == len(out)

@@ -143,6 +143,14 @@ def test_graph_replay_equals_eager(case):
     c.op.gcr_solve(x2.zero_(), b1, cs.SolverParams(use_graph=True, **p16))
     torch.cuda.synchronize()
     assert torch.equal(x1, x2)
+    # the batch with a 16-bit basis (the tiled operator writes it directly)
+    eager16 = c.lat.new_field(cs.F64, NRHS).zero_()
+    c.op.gcr_solve(eager16, bd, cs.SolverParams(rhs_tile=4, use_graph=False, **p16), nrhs=NRHS)
+    for rep in range(2):
+        xg = c.lat.new_field(cs.F64, NRHS).zero_()
+        c.op.gcr_solve(xg, bd, cs.SolverParams(rhs_tile=4, use_graph=True, **p16), nrhs=NRHS)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, eager16), rep
 
 
 def test_batched_adjoint_solve(case):
