@@ -262,6 +262,16 @@ typedef struct {
                              paper's QWS smoother, see cs_sap_smooth_jacobi); 2 =
                              n_mr even-odd preconditioned MR steps (see
                              cs_sap_smooth_eo)                                   */
+    int rhs_groups;       /* 0 or 1: the nrhs right-hand sides advance as one
+                             lock-step batch.  G > 1 (nrhs > 1, not with the
+                             multigrid preconditioner): they are split into
+                             min(G, nrhs) contiguous groups of near-equal size,
+                             each solved as its own batch on its own workspace
+                             (kept with the clover handle), private stream and
+                             host thread, so the memory-bound level-1 kernels
+                             of one group overlap the smoother of another.
+                             Every column's result is bit-identical to its
+                             single-right-hand-side solve either way.         */
 } cs_solver_params;
 
 typedef struct {
@@ -273,7 +283,7 @@ typedef struct {
 
 /* Fill p with the defaults: restart 16, max_iter 2000, n_cy 2, n_mr 4,
  * tol 1e-10, inner CS_F32, basis CS_F32, reliable_delta 1e-5, rhs_tile 0,
- * use_graph 1. */
+ * use_graph 1, block_solver 0, rhs_groups 1. */
 void cs_solver_params_default(cs_solver_params* p);
 
 /* Solve D x = b by flexible GCR (outer arithmetic, reductions and the

@@ -34,7 +34,7 @@ class _Params(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iter", C.c_int), ("n_cy", C.c_int), ("n_mr", C.c_int),
                 ("tol", C.c_double), ("inner_prec", C.c_int), ("basis_prec", C.c_int),
                 ("reliable_delta", C.c_double), ("rhs_tile", C.c_int), ("use_graph", C.c_int),
-                ("block_solver", C.c_int)]
+                ("block_solver", C.c_int), ("rhs_groups", C.c_int)]
 
 
 class LaunchConfig(C.Structure):
@@ -532,11 +532,12 @@ class SolverParams:
     rhs_tile: int = 0
     use_graph: bool = True
     block_solver: int = 0     # 0: MR on D_BB; 1: Jacobi on (C^-1 D)_BB; 2: even-odd preconditioned MR (n_mr steps)
+    rhs_groups: int = 1       # > 1: the batch split into that many groups solved concurrently
 
     def to_c(self) -> _Params:
         return _Params(self.restart, self.max_iter, self.n_cy, self.n_mr, self.tol,
                        self.inner_prec, self.basis_prec, self.reliable_delta, self.rhs_tile,
-                       int(bool(self.use_graph)), int(self.block_solver))
+                       int(bool(self.use_graph)), int(self.block_solver), int(self.rhs_groups))
 
 
 def profile_enable(on: bool = True):

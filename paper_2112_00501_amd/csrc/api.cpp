@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/cloversap.h"
@@ -43,6 +44,7 @@ struct cs_clover_s {
     void* ci64 = nullptr;   // (1 + T)^-1
     void* ci32 = nullptr;
     std::unique_ptr<cs::GcrWork> work;
+    std::vector<std::unique_ptr<cs::GcrWork>> group_work;  // one per concurrent group of right-hand sides
     std::unique_ptr<cs::BicgWork> bicg;
     void* force_H = nullptr;   // insertion matrices of the force, 864 B/site
     void* dag_tmp = nullptr;   // FP64 fields for the adjoint solve
@@ -106,6 +108,7 @@ bool sap_geometry_ok(const cs::Geom& g) {
 
 struct ProfRec {
     std::string fam;
+    hipStream_t s;  // records of concurrent solves on other streams stay apart
     hipEvent_t a, b;
     bool closed;
 };
@@ -149,7 +152,7 @@ namespace cs {
 void prof_begin(const char* family, hipStream_t s) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_pm);
-    ProfRec r{family, take_event(), take_event(), false};
+    ProfRec r{family, s, take_event(), take_event(), false};
     if (!r.a || !r.b) return;
     hipEventRecord(r.a, s);
     g_pending.push_back(r);
@@ -159,7 +162,7 @@ void prof_end(const char* family, hipStream_t s) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_pm);
     for (auto it = g_pending.rbegin(); it != g_pending.rend(); ++it) {
-        if (!it->closed && it->fam == family) {
+        if (!it->closed && it->s == s && it->fam == family) {
             hipEventRecord(it->b, s);
             it->closed = true;
             break;
@@ -298,6 +301,7 @@ int cs_clover_create(cs_gauge g, double kappa, double csw, void* stream, cs_clov
 int cs_clover_destroy(cs_clover c) {
     if (!c) return ok();
     c->work.reset();
+    c->group_work.clear();
     if (c->force_H) hipFree(c->force_H);
     if (c->dag_tmp) hipFree(c->dag_tmp);
     if (c->c64) hipFree(c->c64);
@@ -521,6 +525,7 @@ void cs_solver_params_default(cs_solver_params* p) {
     p->rhs_tile = 0;
     p->use_graph = 1;
     p->block_solver = 0;
+    p->rhs_groups = 1;
 }
 
 static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* x, const void* b, int nrhs,
@@ -545,6 +550,7 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         return fail(CS_ERR_PRECISION, "the multigrid preconditioner takes basis_prec CS_F32 or CS_F64");
     if (nrhs < 1 || nrhs > 65535) return fail(CS_ERR_INVALID, "nrhs must be in 1..65535");
     if (p->rhs_tile < 0) return fail(CS_ERR_INVALID, "rhs_tile must be >= 0");
+    if (p->rhs_groups < 0) return fail(CS_ERR_INVALID, "rhs_groups must be >= 0");
     if ((p->n_cy > 0 || mg) && !sap_geometry_ok(g->g))
         return fail(CS_ERR_GEOMETRY, "the red/black block colouring needs an even number of blocks per direction");
     if (mg && (nrhs != 1 || p->inner_prec != CS_F32))
@@ -552,21 +558,6 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
     const size_t f64 = cs::spinor_bytes_per_site(cs::P_F64) * (size_t)g->g.V;
     if (overlap(b, x, f64 * nrhs)) return fail(CS_ERR_INVALID, "x and b overlap");
     hipStream_t s = (hipStream_t)stream;
-    cs::LaunchCfg sap_cfg, d_cfg;
-    if (nrhs > 1) {
-        if (p->rhs_tile == 0) {
-            st = autotune(g, c, p->inner_prec, nrhs, s, &sap_cfg, &d_cfg);
-            if (st) return st;
-        } else {
-            sap_cfg.rhs_tile = d_cfg.rhs_tile = p->rhs_tile;
-        }
-    }
-    if (!c->work) c->work.reset(new cs::GcrWork);
-    hipError_t e = c->work->ensure(g->g, p->restart, p->inner_prec, p->basis_prec, nrhs);
-    if (e != hipSuccess) {
-        c->work->release();
-        return fail(CS_ERR_ALLOC, "solver workspace: %s", hipGetErrorString(e));
-    }
     if (dagger && c->dag_tmp_nrhs < nrhs) {
         if (c->dag_tmp) hipFree(c->dag_tmp);
         c->dag_tmp = nullptr;
@@ -582,15 +573,63 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         std::lock_guard<std::mutex> lk(g_pm);
         prof = g_prof_on;
     }
-    cs::GcrParams gp{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
-                     p->reliable_delta, sap_cfg, d_cfg, p->use_graph != 0 && !prof, p->block_solver};
-    gp.mg = mg;
-    std::vector<cs::GcrResult> res(nrhs);
-    e = cs::gcr_solve(make_op(g, c), gp, *c->work, x, b, nrhs, dagger, c->dag_tmp, res.data(), s);
-    if (e != hipSuccess) {
-        c->work->drop_graphs();
-        return fail(CS_ERR_HIP, "solve: %s", hipGetErrorString(e));
+    // groups of right-hand sides: [first[q], first[q] + count[q]), each its
+    // own batch (one group: the whole batch on the handle's main workspace)
+    int G = p->rhs_groups > 1 && !mg ? (p->rhs_groups < nrhs ? p->rhs_groups : nrhs) : 1;
+    std::vector<int> first(G), count(G);
+    for (int q = 0, at = 0; q < G; ++q) {
+        count[q] = nrhs / G + (q < nrhs % G ? 1 : 0);
+        first[q] = at;
+        at += count[q];
     }
+    std::vector<cs::GcrParams> gps(G);
+    std::vector<cs::GcrWork*> works(G);
+    if (G > 1 && (int)c->group_work.size() < G) c->group_work.resize(G);
+    for (int q = 0; q < G; ++q) {
+        cs::LaunchCfg sap_cfg, d_cfg;
+        if (count[q] > 1) {
+            if (p->rhs_tile == 0) {
+                st = autotune(g, c, p->inner_prec, count[q], s, &sap_cfg, &d_cfg);
+                if (st) return st;
+            } else {
+                sap_cfg.rhs_tile = d_cfg.rhs_tile = p->rhs_tile;
+            }
+        }
+        std::unique_ptr<cs::GcrWork>& wp = G > 1 ? c->group_work[q] : c->work;
+        if (!wp) wp.reset(new cs::GcrWork);
+        hipError_t e = wp->ensure(g->g, p->restart, p->inner_prec, p->basis_prec, count[q]);
+        if (e != hipSuccess) {
+            wp->release();
+            return fail(CS_ERR_ALLOC, "solver workspace: %s", hipGetErrorString(e));
+        }
+        works[q] = wp.get();
+        gps[q] = cs::GcrParams{p->restart, p->max_iter, p->n_cy, p->n_mr, p->tol, p->inner_prec, p->basis_prec,
+                               p->reliable_delta, sap_cfg, d_cfg, p->use_graph != 0 && !prof, p->block_solver};
+        gps[q].mg = mg;
+    }
+    std::vector<cs::GcrResult> res(nrhs);
+    std::vector<hipError_t> errs(G, hipSuccess);
+    const cs::OpData op = make_op(g, c);
+    auto run = [&](int q) {
+        const size_t off = f64 * (size_t)first[q];
+        errs[q] = cs::gcr_solve(op, gps[q], *works[q], (char*)x + off, (const char*)b + off, count[q], dagger,
+                                dagger ? (char*)c->dag_tmp + off : nullptr, res.data() + first[q], s);
+    };
+    const auto t0 = std::chrono::steady_clock::now();
+    if (G == 1) {
+        run(0);
+    } else {
+        std::vector<std::thread> th;
+        for (int q = 0; q < G; ++q) th.emplace_back(run, q);
+        for (std::thread& t : th) t.join();
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (cs::GcrResult& r : res) r.seconds = secs;
+    }
+    for (int q = 0; q < G; ++q)
+        if (errs[q] != hipSuccess) {
+            for (cs::GcrWork* w : works) w->drop_graphs();
+            return fail(CS_ERR_HIP, "solve: %s", hipGetErrorString(errs[q]));
+        }
     int first_bad = CS_OK;
     for (int r = 0; r < nrhs; ++r) {
         if (stats) {
