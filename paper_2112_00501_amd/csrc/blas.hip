@@ -316,8 +316,9 @@ __global__ __launch_bounds__(TPB) void k_ortho(Geom g, char* W, size_t ws, int n
     const size_t vs = (size_t)nrhs * ws;
     cpx<double> acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
     for (int blk = blockIdx.x; blk < g.nblk; blk += gridDim.x) {
-        cpx<double> v[12];
+        cpx<double> v[12], rr[12];
         ld64<PB>(base + (size_t)k * vs, g.nblk, blk, threadIdx.x, v);
+        ld64<P_F64>(rr_base, g.nblk, blk, threadIdx.x, rr);
         for (int jb = 0; jb < k; jb += G) {
             cpx<RS> t[G][12];
 #pragma unroll
@@ -335,8 +336,6 @@ __global__ __launch_bounds__(TPB) void k_ortho(Geom g, char* W, size_t ws, int n
             }
         }
         if (k > 0) st64<PB>(base + (size_t)k * vs, g.nblk, blk, threadIdx.x, v);
-        cpx<double> rr[12];
-        ld64<P_F64>(rr_base, g.nblk, blk, threadIdx.x, rr);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             acc[0].re += v[c].re * v[c].re + v[c].im * v[c].im;
