@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -620,7 +621,12 @@ static int gcr_common(cs_gauge g, cs_clover c, const cs_solver_params* p, void* 
         run(0);
     } else {
         std::vector<std::thread> th;
-        for (int q = 0; q < G; ++q) th.emplace_back(run, q);
+        int q = 0;
+        try {
+            for (; q < G; ++q) th.emplace_back(run, q);
+        } catch (const std::system_error&) {
+            for (; q < G; ++q) run(q);  // no thread to be had: the rest on this one, one after another
+        }
         for (std::thread& t : th) t.join();
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         for (cs::GcrResult& r : res) r.seconds = secs;
